@@ -1,0 +1,113 @@
+/*
+ * roeam_oracle.h -- FP64 CPU oracle for the Roe-AM finite-volume Euler solver
+ * on structured 2-D grids (Li, Ren, Gu: "An Improved Roe Scheme for All
+ * Mach-Number Flows Simultaneously Curing Known Problems", arXiv 1711.09272).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that
+ * the GPU path is checked against.  It shares no code, header, table or
+ * constant with the HIP library.  Only tests/, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.
+ *
+ * Layout: conserved state q is [4][ny][nx] row-major FP64, rows (rho, rho*u,
+ * rho*v, rho*E).  Node coordinates are [ny+1][nx+1].
+ *
+ * Parity unpinned (documented readings, checked only oracle == GPU): the
+ * modified-entropy-fix / rotated-Riemann term of Eq. (86) (readings D6-D8),
+ * the expansion-shock weight of Eq. (92) (reading D2), MUSCL-minmod
+ * details, the slip-wall ghost rule and the time-step rule.
+ */
+#ifndef ROEAM_ORACLE_H
+#define ROEAM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary kinds (the paper names none; the test configurations do). */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_SLIPWALL = 2, ORC_BC_DIRICHLET = 3 };
+/* Sides. */
+enum { ORC_WEST = 0, ORC_EAST = 1, ORC_SOUTH = 2, ORC_NORTH = 3 };
+/* Numerical flux families. */
+enum { ORC_SCHEME_ROEAM = 0, ORC_SCHEME_ROE = 1, ORC_SCHEME_ROE_HARTEN = 2 };
+
+/* Variant bits: alternative readings of ambiguous passages and the paper's
+ * ablations of Sec. 7.  All zero = the Roe-AM scheme of Eqs. (85)-(109) with
+ * the default readings. */
+#define ORC_V_XI_UNGATED    (1u << 0) /* xi as printed in Eq. (86) instead of the Eq. (68) gate   */
+#define ORC_V_EXPFIX_F8     (1u << 1) /* f^8(Mbar) weight of Eq. (73) instead of f(Mbar), Eq. (92)  */
+#define ORC_V_CLAMP_UPRIME  (1u << 2) /* clamp |U|' at zero                                        */
+#define ORC_V_NO_EQ92       (1u << 3) /* |U|' = |U| (ablation of Fig. 3b / Fig. 8d)                */
+#define ORC_V_XI_ROE        (1u << 4) /* xi = |U| of Eq. (13) (Fig. 6d)                             */
+#define ORC_V_DUP_ROE       (1u << 5) /* dU_p of Eq. (17) (Fig. 6d, 6e, 11c)                        */
+#define ORC_V_XI_EQ46       (1u << 6) /* xi = |U_R+U_L|/2 of Eq. (46): no velocity positivity (6f)  */
+#define ORC_V_DUP_ZERO      (1u << 7) /* dU_p = 0 (Fig. 11b)                                        */
+
+typedef struct {
+    double gamma;     /* ratio of specific heats, Eq. (54)                       */
+    double cfl;       /* Courant number of the time-step rule                     */
+    double mach_ref;  /* global reference Mach number of Eq. (101)               */
+    double u_ref;     /* reference speed of Eq. (108)                             */
+    double eps1;      /* switch of Eq. (111), 0 or 1                              */
+    double eps2;      /* entropy-fix constant of Eq. (112)                        */
+    double eps_lambda;/* Harten constant of Eq. (115) (Roe + entropy fix only)   */
+    int s1_mode;      /* 0: detector of Eqs. (95)-(97); 1: s1 = 1 (Eq. 110)       */
+    int order;        /* 1: piecewise constant; 2: MUSCL-minmod                   */
+    int time_scheme;  /* 0: forward Euler; 1: SSP-RK3 (Shu-Osher)                 */
+    int scheme;       /* ORC_SCHEME_*                                             */
+    unsigned variant; /* ORC_V_* bits                                             */
+} orc_params;
+
+typedef struct {
+    int nx, ny;
+    int metric;            /* 0: uniform dx, dy; 1: node coordinates            */
+    double dx, dy;
+    const double *xn, *yn; /* metric 1: [ny+1][nx+1]                            */
+    int bc[4];             /* west, east, south, north                          */
+    double bc_state[4][4]; /* Dirichlet conserved state per side                */
+} orc_grid;
+
+/* Every intermediate of one face evaluation, for property tests. */
+typedef struct {
+    double UL, UR, U, dU, dp;          /* normal velocities and jumps            */
+    double rho, u, v, H, c;            /* Roe averages                           */
+    double M, Mbar, theta, ct, Ut;     /* Eqs. (93), (94), (101), (99), (100)    */
+    double absUp;                      /* |U|' of Eq. (92)                       */
+    double s1, fef, frr;               /* Eqs. (95), (102), (103)                */
+    double xi, dpp, dpu, dUp, dUuR, dUuL; /* Eqs. (86)-(91)                      */
+} orc_face_diag;
+
+typedef struct {
+    double t, dt_last, max_rate;
+    long steps;
+    int nonphys;
+    long neg_uprime_faces;  /* faces where |U|' < 0 was seen (reading D4)       */
+} orc_run_stats;
+
+/* Eq. (98). */
+double orc_f(double phi);
+/* Eq. (97): detector ratio of two neighbouring cells. */
+double orc_detector_P(double pA, double rhoA, double pB, double rhoB);
+/* One face: W = (rho, u, v, p) on each side, unit normal (nx, ny), switch s1.
+ * Writes the numerical flux per unit face length; diag may be NULL. */
+void orc_face_flux(const orc_params *prm, const double WL[4], const double WR[4],
+                   double nx, double ny, double s1, double F[4], orc_face_diag *diag);
+/* Physical face flux of Eq. (4) for one state. */
+void orc_physical_flux(double gamma, const double W[4], double nx, double ny, double F[4]);
+
+/* R = dQ/dt.  q, r: [4][ny][nx].  scale (nullable): per-cell sum over the
+ * four faces of |F_k| |S| / Omega, used by the cancellation-aware error norm.
+ * Returns 0, or -4 if a cell has rho <= 0, p <= 0 or a non-finite value. */
+int orc_residual(const orc_params *prm, const orc_grid *g, const double *q, double *r, double *scale);
+/* Largest explicit rate lambda over cells (time-step rule). */
+int orc_max_rate(const orc_params *prm, const orc_grid *g, const double *q, double *max_rate);
+/* Advance q in place: nsteps steps or until t reaches t_end (t_end <= 0: no
+ * clip).  Returns 0 or -4 (non-physical state: q undefined). */
+int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, double t_end,
+            orc_run_stats *stats);
+/* Cell areas [ny][nx] (shoelace); face vectors for tests. */
+void orc_cell_areas(const orc_grid *g, double *omega);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

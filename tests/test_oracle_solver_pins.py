@@ -1,0 +1,317 @@
+"""Grid-level pins of the CPU oracle: discrete invariants, exact Riemann
+solutions, the paper's printed states and the qualitative outcomes of Sec. 7."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_riemann as er
+import oracle
+import workloads
+from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
+
+G = 1.4
+
+
+def prim(q, g=G):
+    rho = q[0]
+    u, v = q[1] / rho, q[2] / rho
+    return rho, u, v, (g - 1) * (q[3] - 0.5 * rho * (u * u + v * v))
+
+
+def golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    out = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        out[parts[0]] = parts[1]
+    return out
+
+
+def uniform_case(nx, ny, bc, nodes=False, seed=0, **prm):
+    c = workloads.smooth_random_case(nx, ny, seed, bc=bc, nodes=nodes, **prm)
+    W = (1.3, 0.4, -0.25, 0.9)
+    c.q0 = np.ascontiguousarray(np.broadcast_to(workloads.conserved(G, *W)[:, None, None], (4, ny, nx)))
+    for s in range(4):
+        c.bc_state[s] = workloads.conserved(G, *W)
+    return c
+
+
+# --- Free-stream preservation --------------------------------------------------
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("bc", [(PERIODIC,) * 4, (TRANSMISSIVE,) * 4, (DIRICHLET, TRANSMISSIVE, PERIODIC, PERIODIC)])
+def test_free_stream_cartesian_exact(order, bc):
+    c = uniform_case(12, 9, bc, order=order, eps1=1.0)
+    r = oracle.residual(c)
+    assert np.all(r == 0.0)
+
+
+def test_free_stream_wall_parallel_flow():
+    c = uniform_case(10, 8, (PERIODIC, PERIODIC, SLIPWALL, SLIPWALL), order=2)
+    W = (1.0, 0.7, 0.0, 1.0)
+    c.q0 = np.ascontiguousarray(np.broadcast_to(workloads.conserved(G, *W)[:, None, None], (4, 8, 10)))
+    assert np.all(oracle.residual(c) == 0.0)
+
+
+def test_free_stream_perturbed_nodes():
+    c = uniform_case(14, 11, (PERIODIC,) * 4, nodes=True, seed=3, order=2, eps1=1.0)
+    r, sc = oracle.residual(c, with_scale=True)
+    assert np.abs(r).max() <= 1e-13 * sc.max()
+
+
+# --- Discrete conservation ------------------------------------------------------
+
+@pytest.mark.parametrize("nodes", [False, True])
+def test_conservation_periodic(nodes):
+    c = workloads.smooth_random_case(16, 12, 21, nodes=nodes, order=2, eps1=1.0)
+    r, sc = oracle.residual(c, with_scale=True)
+    om = oracle.cell_areas(c)
+    tot = (r * om[None]).sum(axis=(1, 2))
+    mag = (sc * om[None]).sum(axis=(1, 2))
+    assert np.all(np.abs(tot) <= 1e-13 * mag)
+
+
+def test_cell_areas_sum_to_domain():
+    c = workloads.smooth_random_case(16, 12, 4, nodes=True)
+    assert oracle.cell_areas(c).sum() == pytest.approx(1.0, rel=1e-13)
+
+
+# --- Symmetries -------------------------------------------------------------------
+
+def _rot90(q):
+    """Rotate a state field by +90 degrees on a square periodic grid:
+    cell (i, j) -> (n-1-j, i) and (u, v) -> (-v, u)."""
+    n = q.shape[1]
+    out = np.empty_like(q)
+    for j in range(n):
+        for i in range(n):
+            ii, jj = n - 1 - j, i
+            out[0, jj, ii] = q[0, j, i]
+            out[1, jj, ii] = -q[2, j, i]
+            out[2, jj, ii] = q[1, j, i]
+            out[3, jj, ii] = q[3, j, i]
+    return out
+
+
+@pytest.mark.parametrize("order,eps1,s1_mode", [(1, 0.0, 0), (2, 1.0, 0), (2, 1.0, 1)])
+def test_rotation_equivariance(order, eps1, s1_mode):
+    c = workloads.smooth_random_case(12, 12, 8, mach=0.7, amp=0.3, order=order, eps1=eps1,
+                                     s1_mode=s1_mode, mach_ref=0.05)
+    c.dx = c.dy = 1.0 / 12
+    r, sc = oracle.residual(c, with_scale=True)
+    c2 = workloads.smooth_random_case(12, 12, 8, order=order, eps1=eps1, s1_mode=s1_mode, mach_ref=0.05)
+    c2.q0 = _rot90(c.q0)
+    c2.dx = c2.dy = 1.0 / 12
+    r2 = oracle.residual(c2)
+    assert np.abs(r2 - _rot90(r)).max() <= 1e-13 * sc.max()
+
+
+def test_mirror_symmetry():
+    c = workloads.smooth_random_case(10, 8, 9, order=2, eps1=1.0, mach_ref=0.1)
+    r, sc = oracle.residual(c, with_scale=True)
+    qm = c.q0[:, :, ::-1].copy()
+    qm[1] *= -1
+    c.q0 = qm
+    rm = oracle.residual(c)
+    rr = r[:, :, ::-1].copy()
+    rr[1] *= -1
+    assert np.abs(rm - rr).max() <= 1e-13 * sc.max()
+
+
+# --- Shock tubes ----------------------------------------------------------------
+
+def test_exact_solver_sod_star_golden():
+    g = golden("sod_star.txt")
+    ps, us, rl, rr = er.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(ps - float(g["p_star"])) < 1e-5
+    assert abs(us - float(g["u_star"])) < 1e-5
+    assert abs(rl - float(g["rho_star_L"])) < 1e-5
+    assert abs(rr - float(g["rho_star_R"])) < 1e-5
+
+
+def test_sod_y_invariance_and_convergence():
+    errs = []
+    for nx in (100, 200, 400):
+        c = workloads.sod(nx=nx, ny=4)
+        q, st = oracle.run(c)
+        assert st["t"] == 0.2
+        for j in range(1, 4):  # transverse invariance: bitwise equal rows, v == 0
+            assert np.array_equal(q[:, j], q[:, 0])
+        assert np.all(q[2] == 0.0)
+        x = (np.arange(nx) + 0.5) / nx
+        ex = er.sample((1, 0, 1), (0.125, 0, 0.1), x, 0.5, 0.2)
+        errs.append(np.abs(q[0, 0] - ex[0]).mean())
+        if nx == 400:
+            rho, u, v, p = prim(q[:, 0])
+            # plateau between contact and shock: within 2% of the exact star values
+            sel = (x > 0.72) & (x < 0.82)
+            assert np.abs(p[sel] / 0.3031302 - 1).max() < 0.02
+            assert np.abs(u[sel] / 0.9274526 - 1).max() < 0.02
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert errs[-1] < 0.008
+    assert all(0.5 <= o <= 1.1 for o in orders), orders
+
+
+def _tube(case_fn, **over):
+    c = case_fn(nx=200, ny=2)
+    prm = dict(c.params)
+    prm.update(over)
+    return c, prm
+
+
+def test_expansion_shock_fig3():
+    """Sec. 7.1.1: Roe and Roe-AM without Eq. (92) keep an expansion shock at
+    x = 0.3; the full Roe-AM does not (proxy: the largest density jump between
+    neighbouring cells near x = 0.3, against the exact solution's)."""
+    x = (np.arange(200) + 0.5) / 200
+    ex = er.sample((3, 0.9, 3), (1, 0.9, 1), x, 0.3, 0.2)
+    exact_jump = np.abs(np.diff(ex[0]))[55:65].max()
+    jumps = {}
+    for name, over in (("roe", dict(scheme=oracle.SCHEME_ROE)), ("noeq92", dict(variant=oracle.V_NO_EQ92)),
+                       ("roeam", {})):
+        c, prm = _tube(workloads.expansion_shock_tube, **over)
+        q, st = oracle.run(c, params=prm)
+        jumps[name] = np.abs(np.diff(q[0, 0]))[55:65].max()
+    assert jumps["roe"] > 8 * exact_jump
+    assert jumps["noeq92"] > 8 * exact_jump
+    assert jumps["roeam"] < 3 * exact_jump
+
+
+def test_near_vacuum():
+    """Sec. 7.1.2: Roe fails (non-physical state), Roe-AM reaches t = 0.15."""
+    c, prm = _tube(workloads.near_vacuum_tube, scheme=oracle.SCHEME_ROE)
+    with pytest.raises(oracle.NonPhysical):
+        oracle.run(c, params=prm)
+    c, prm = _tube(workloads.near_vacuum_tube)
+    q, st = oracle.run(c, params=prm)
+    assert st["t"] == 0.15
+    rho, u, v, p = prim(q)
+    assert rho.min() > 0 and p.min() > 0
+
+
+def test_strong_shock():
+    """Sec. 7.1.3: Roe-AM finishes like Roe, with the same accuracy.
+
+    With the detector (Eqs. 95-97) the initial interface has U_L = U_R = 0, so
+    xi = 0 and s1 ~ 0 (no dU_p): no mass or energy flux on the first step and
+    the low-pressure cell turns negative unless the first step is small.  The
+    paper gives no CFL; we pin that CFL 0.02 finishes, and that s1 = 1
+    (Eq. 110) finishes at CFL 0.2."""
+    x = (np.arange(200) + 0.5) / 200
+    ex = er.sample((1, 0, 1000), (1, 0, 0.01), x, 0.5, 0.012)
+    c, prm = _tube(workloads.strong_shock_tube, scheme=oracle.SCHEME_ROE, cfl=0.2)
+    q, _ = oracle.run(c, params=prm)
+    e_roe = np.abs(q[0, 0] - ex[0]).mean()
+    c, prm = _tube(workloads.strong_shock_tube, s1_mode=1, cfl=0.2)
+    q, _ = oracle.run(c, params=prm)
+    assert np.abs(q[0, 0] - ex[0]).mean() < 1.05 * e_roe
+    c, prm = _tube(workloads.strong_shock_tube, cfl=0.02)
+    q, st = oracle.run(c, params=prm)
+    assert st["t"] == 0.012
+    assert np.abs(q[0, 0] - ex[0]).mean() < 1.05 * e_roe
+    c, prm = _tube(workloads.strong_shock_tube, cfl=0.2)
+    with pytest.raises(oracle.NonPhysical):
+        oracle.run(c, params=prm)
+
+
+# --- Printed states ----------------------------------------------------------------
+
+def test_moving_shock_rationals_golden():
+    g = golden("paper_states.txt")
+    rho2, u2, p2 = workloads.moving_shock_state(6, Fraction(g["mach6_rho_pre"]), Fraction(g["mach6_p_pre"]))
+    assert rho2 == Fraction(g["mach6_rho_post"])
+    assert p2 == Fraction(g["mach6_p_post"])
+    assert u2 == Fraction(g["mach6_u_post"])
+    rho2, u2, p2 = workloads.moving_shock_state(20)
+    assert (rho2, u2, p2) == (Fraction(224, 27), Fraction(133, 8), Fraction(933, 2))
+
+
+def test_corner_state_is_a_normal_shock():
+    """Sec. 7.3's left state is a moving normal shock into (1.4, 0, 1): find its Mach
+    number from the pressure ratio and check density and velocity to 5 digits."""
+    g = golden("paper_states.txt")
+    p2 = float(g["corner_p_post"])
+    Ms = math.sqrt((p2 - 1) * 2.4 / 2.8 + 1)
+    rho2, u2, pp = (float(v) for v in workloads.moving_shock_state(Fraction(Ms)))
+    assert pp == pytest.approx(p2, rel=1e-9)
+    assert rho2 == pytest.approx(float(g["corner_rho_post"]), rel=2e-5)
+    assert u2 == pytest.approx(float(g["corner_u_post"]), rel=2e-5)
+
+
+# --- Low Mach (Sec. 3.2, Sec. 7.6) ---------------------------------------------------
+
+def test_low_mach_residual_scaling():
+    """Eqs. (31)-(32): on a steady vortex the momentum residual of Roe-AM scales
+    with M^2, the classical Roe one with M."""
+    ratios = {}
+    for scheme in (oracle.SCHEME_ROEAM, oracle.SCHEME_ROE):
+        nrm = []
+        for mach in (0.01, 0.001):
+            c = workloads.vortex(n=32, mach=mach, stationary=True, checker_amp=0.0)
+            prm = dict(c.params)
+            prm["scheme"] = scheme
+            r = oracle.residual(c, params=prm)
+            nrm.append(np.sqrt((r[1] ** 2 + r[2] ** 2).mean()))
+        ratios[scheme] = nrm[0] / nrm[1]
+    assert 80 < ratios[oracle.SCHEME_ROEAM] < 120
+    assert 8 < ratios[oracle.SCHEME_ROE] < 12
+
+
+def _checker(q):
+    n = q.shape[1]
+    I, J = np.meshgrid(np.arange(q.shape[2]), np.arange(n))
+    _, _, _, p = prim(q)
+    return abs(np.sum(np.where((I + J) % 2 == 0, 1, -1) * (p - p.mean()))) / p.size
+
+
+def test_checkerboard_suppression_fig11():
+    """Fig. 11: the full Roe-AM removes the pressure checkerboard; dU_p = 0 keeps
+    it; dU_p of Eq. (17) removes it only slowly."""
+    c = workloads.vortex(n=32, mach=0.01)
+    c0 = _checker(c.q0)
+    out = {}
+    for name, var in (("roeam", 0), ("zero", oracle.V_DUP_ZERO), ("roe17", oracle.V_DUP_ROE)):
+        prm = dict(c.params)
+        prm["variant"] = var
+        q, _ = oracle.run(c, nsteps=20, params=prm)
+        out[name] = _checker(q) / c0
+    assert out["roeam"] < 1e-3
+    assert out["zero"] > 0.9
+    assert 0.3 < out["roe17"] < 0.99
+
+
+def test_low_mach_time_step_rule():
+    """The time-step rule uses c / sqrt(theta): the preconditioned dU_p acts as a
+    pressure diffusion of speed ~ c / M at low Mach.  An acoustic-rate step
+    (100x larger at M_ref = 0.01) is non-physical at once; the rule is stable."""
+    c = workloads.vortex(n=24, mach=0.01)
+    prm = dict(c.params)
+    prm["cfl"] = 40.0
+    with pytest.raises(oracle.NonPhysical):
+        oracle.run(c, nsteps=5, params=prm)
+    q, st = oracle.run(c, nsteps=40)
+    assert _checker(q) < 1e-3 * _checker(c.q0)
+
+
+# --- Odd-even decoupling (Sec. 7.2) --------------------------------------------------
+
+def test_odd_even_decoupling():
+    """Fig. 6a vs 6g/6i: Roe amplifies the odd-even grid perturbation behind the
+    moving shock; Roe-AM keeps it near its initial size."""
+    dev = {}
+    for name, over in (("roe", dict(scheme=oracle.SCHEME_ROE)), ("roeam0", dict(eps1=0.0)),
+                       ("roeam1", dict(eps1=1.0))):
+        c = workloads.odd_even(nx=120, ny=16, eps_y=0.1, seeded=False, shock_x=8.0, t_end=3.0)
+        prm = dict(c.params)
+        prm.update(over)
+        q, st = oracle.run(c, params=prm)
+        rho = q[0]
+        dev[name] = (rho.std(axis=0) / rho.mean(axis=0)).max()
+    assert dev["roe"] > 0.1
+    assert dev["roeam0"] < 0.02 and dev["roeam1"] < 0.02

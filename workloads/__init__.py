@@ -1,0 +1,380 @@
+"""Seeded synthetic inputs shaped like the paper's test cases (arXiv 1711.09272, Sec. 7).
+
+This module holds only input generation: grids, initial states, boundary
+specifications and request traces.  It contains none of the numerical
+method's arithmetic, so it can feed both the CPU oracle and the GPU library,
+which otherwise share no code.
+
+A :class:`Case` describes one structured 2-D grid:
+
+* ``q0``: conserved state, float64 array [4, ny, nx] (rho, rho u, rho v, rho E);
+* geometry: uniform ``dx``, ``dy`` or node coordinates ``xn``, ``yn`` [ny+1, nx+1];
+* ``bc``: boundary kinds for (west, east, south, north);
+* ``bc_state``: conserved Dirichlet state per side [4, 4];
+* ``params``: scheme parameters (gamma, CFL, M_ref, U_ref, eps1, eps2, s1 mode,
+  reconstruction order, time scheme);
+* ``nsteps`` / ``t_end``: run length.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from fractions import Fraction
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+SEED_BASE = 171109272
+
+PERIODIC, TRANSMISSIVE, SLIPWALL, DIRICHLET = 0, 1, 2, 3
+WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
+
+
+def default_params(**kw) -> Dict:
+    p = dict(gamma=1.4, cfl=0.4, mach_ref=1.0, u_ref=1.0, eps1=0.0, eps2=0.05,
+             eps_lambda=0.1, s1_mode=0, order=1, time_scheme=0, scheme=0, variant=0)
+    p.update(kw)
+    return p
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    q0: np.ndarray
+    params: Dict
+    bc: Tuple[int, int, int, int]
+    dx: float = 1.0
+    dy: float = 1.0
+    xn: Optional[np.ndarray] = None
+    yn: Optional[np.ndarray] = None
+    bc_state: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((4, 4)))
+    nsteps: int = 1
+    t_end: float = 0.0
+
+    @property
+    def ny(self) -> int:
+        return self.q0.shape[1]
+
+    @property
+    def nx(self) -> int:
+        return self.q0.shape[2]
+
+    @property
+    def metric(self) -> int:
+        return 0 if self.xn is None else 1
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+
+def conserved(gamma: float, rho, u, v, p) -> np.ndarray:
+    """Primitive (rho, u, v, p) -> conserved (rho, rho u, rho v, rho E), ideal gas."""
+    rho, u, v, p = (np.asarray(a, dtype=np.float64) for a in (rho, u, v, p))
+    rhoE = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack(np.broadcast_arrays(rho, rho * u, rho * v, rhoE)).astype(np.float64)
+
+
+def cell_centres(nx: int, ny: int, x0: float, y0: float, dx: float, dy: float):
+    x = x0 + (np.arange(nx) + 0.5) * dx
+    y = y0 + (np.arange(ny) + 0.5) * dy
+    return np.meshgrid(x, y)  # [ny, nx] each
+
+
+# --------------------------------------------------------------------------
+# Shock tubes (Sec. 7.1 and the Sod configuration)
+# --------------------------------------------------------------------------
+
+def shock_tube(left, right, x0: float, nx: int = 400, ny: int = 4, t_end: float = 0.2,
+               name: str = "shock_tube", **params) -> Case:
+    """1-D Riemann problem along x on [0,1] x [0, ny dx]; states are (rho, u, v, p).
+
+    Transmissive in x, periodic in y.  The paper runs its tubes on 200 x 10
+    cells with first-order space (Sec. 7.1)."""
+    dx = 1.0 / nx
+    X, _ = cell_centres(nx, ny, 0.0, 0.0, dx, dx)
+    gamma = params.get("gamma", 1.4)
+    st = [np.where(X < x0, left[k], right[k]) for k in range(4)]
+    q0 = conserved(gamma, *st)
+    prm = default_params(order=1, time_scheme=0, eps1=0.0, s1_mode=0, mach_ref=1.0, u_ref=1.0)
+    prm.update(params)
+    return Case(name=name, q0=q0, params=prm, bc=(TRANSMISSIVE, TRANSMISSIVE, PERIODIC, PERIODIC),
+                dx=dx, dy=dx, nsteps=100000, t_end=t_end)
+
+
+def sod(nx: int = 400, ny: int = 4, **params) -> Case:
+    """Sod tube: (1, 0, 0, 1) | (0.125, 0, 0, 0.1) at x = 0.5, first order, forward
+    Euler, CFL 0.4, to t = 0.2 (first test configuration)."""
+    return shock_tube((1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1), 0.5, nx, ny, 0.2,
+                      name=f"sod_{nx}x{ny}", **params)
+
+
+def expansion_shock_tube(nx: int = 200, ny: int = 4, **params) -> Case:
+    """Sec. 7.1.1: (3, 0.9, 0, 3) | (1, 0.9, 0, 1) at 0.3, t = 0.2."""
+    return shock_tube((3.0, 0.9, 0.0, 3.0), (1.0, 0.9, 0.0, 1.0), 0.3, nx, ny, 0.2,
+                      name="expansion_shock", **params)
+
+
+def near_vacuum_tube(nx: int = 200, ny: int = 4, **params) -> Case:
+    """Sec. 7.1.2: (1, -2, 0, 0.4) | (1, 2, 0, 0.4) at 0.5, t = 0.15."""
+    return shock_tube((1.0, -2.0, 0.0, 0.4), (1.0, 2.0, 0.0, 0.4), 0.5, nx, ny, 0.15,
+                      name="near_vacuum", **params)
+
+
+def strong_shock_tube(nx: int = 200, ny: int = 4, **params) -> Case:
+    """Sec. 7.1.3: (1, 0, 0, 1000) | (1, 0, 0, 0.01) at 0.5, t = 0.012."""
+    return shock_tube((1.0, 0.0, 0.0, 1000.0), (1.0, 0.0, 0.0, 0.01), 0.5, nx, ny, 0.012,
+                      name="strong_shock", **params)
+
+
+# --------------------------------------------------------------------------
+# Moving normal shock (Rankine-Hugoniot), exact rationals
+# --------------------------------------------------------------------------
+
+def moving_shock_state(mach, rho1=Fraction(7, 5), p1=Fraction(1), gamma=Fraction(7, 5)):
+    """Post-shock (rho2, u2, p2) of a normal shock of Mach ``mach`` moving into gas at rest.
+
+    Textbook normal-shock relations, evaluated in exact rational arithmetic when
+    the inputs are rationals (the Sec. 7.2 state is printed as rationals)."""
+    M2 = Fraction(mach) ** 2
+    g = Fraction(gamma)
+    p2 = p1 * (1 + 2 * g / (g + 1) * (M2 - 1))
+    rho2 = rho1 * (g + 1) * M2 / ((g - 1) * M2 + 2)
+    c1_sq = g * p1 / rho1
+    # u2 = Ms c1 (1 - rho1/rho2); c1 is rational here when c1^2 is a square.
+    num, den = c1_sq.numerator, c1_sq.denominator
+    rn, rd = math.isqrt(num), math.isqrt(den)
+    if rn * rn == num and rd * rd == den:
+        c1 = Fraction(rn, rd)
+    else:
+        c1 = Fraction(math.sqrt(float(c1_sq)))
+    u2 = Fraction(mach) * c1 * (1 - rho1 / rho2)
+    return rho2, u2, p2
+
+
+# --------------------------------------------------------------------------
+# Low-Mach isentropic vortex (second test configuration)
+# --------------------------------------------------------------------------
+
+def vortex(n: int = 256, mach: float = 0.01, stationary: bool = False, seed: Optional[int] = None,
+           checker_amp: float = 1e-6, nsteps: int = 1000, **params) -> Case:
+    """Isentropic vortex on [0,10]^2, periodic, rho_inf = p_inf = 1 (c_inf = sqrt(gamma)).
+
+    Free stream M c_inf (1,1)/sqrt(2), or at rest when ``stationary``.  Vortex
+    strength beta = 5 M c_inf so the pressure dip scales with M^2.  The
+    pressure is then multiplied by 1 + checker_amp (-1)^(i+j) u_ij with u_ij
+    uniform in [0.5, 1.5) from the seed: a seeded checkerboard."""
+    gamma = params.get("gamma", 1.4)
+    seed = SEED_BASE + 1 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = 10.0
+    dx = L / n
+    X, Y = cell_centres(n, n, 0.0, 0.0, dx, dx)
+    cinf = math.sqrt(gamma)
+    beta = 5.0 * mach * cinf
+    vinf = 0.0 if stationary else mach * cinf / math.sqrt(2.0)
+    xr, yr = X - 5.0, Y - 5.0
+    r2 = xr * xr + yr * yr
+    amp = beta / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    u = vinf - amp * yr
+    v = vinf + amp * xr
+    T = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    I, J = np.meshgrid(np.arange(n), np.arange(n))
+    chk = np.where((I + J) % 2 == 0, 1.0, -1.0)
+    p = p * (1.0 + checker_amp * chk * rng.uniform(0.5, 1.5, size=(n, n)))
+    q0 = conserved(gamma, rho, u, v, p)
+    u_ref = math.sqrt(2.0) * vinf if not stationary else mach * cinf
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=mach, u_ref=u_ref,
+                         eps1=1.0, eps2=0.05, s1_mode=0)
+    prm.update(params)
+    return Case(name=f"vortex_{n}_M{mach:g}{'_rest' if stationary else ''}", q0=q0, params=prm,
+                bc=(PERIODIC,) * 4, dx=dx, dy=dx, nsteps=nsteps, t_end=0.0)
+
+
+# --------------------------------------------------------------------------
+# Hypersonic odd-even decoupling (third test configuration; Sec. 7.2)
+# --------------------------------------------------------------------------
+
+def odd_even(nx: int = 800, ny: int = 80, mach: float = 20.0, eps_y: float = 1e-6,
+             seeded: bool = True, seed: Optional[int] = None, shock_x: float = 20.0,
+             t_end: float = 30.0, **params) -> Case:
+    """Planar Mach-``mach`` shock moving into (rho, p) = (1.4, 1) in an nx x ny
+    channel of unit cells.  The centreline node row is displaced by
+    +-eps_y cell heights: alternating in i as in Eq. (113), or with a seeded
+    sign per node column.  Left: Dirichlet post-shock inflow; right:
+    transmissive; top and bottom: slip walls."""
+    gamma = params.get("gamma", 1.4)
+    seed = SEED_BASE + 2 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs = np.arange(nx + 1, dtype=np.float64)
+    ys = np.arange(ny + 1, dtype=np.float64)
+    xn, yn = np.meshgrid(xs, ys)
+    jmid = ny // 2
+    if seeded:
+        s = rng.choice(np.array([-1.0, 1.0]), size=nx + 1)
+    else:
+        s = np.where(np.arange(nx + 1) % 2 == 0, 1.0, -1.0)
+    yn = yn.copy()
+    yn[jmid, :] = jmid + eps_y * s
+    rho2, u2, p2 = (float(v) for v in moving_shock_state(Fraction(mach).limit_denominator(10 ** 6)))
+    X, _ = cell_centres(nx, ny, 0.0, 0.0, 1.0, 1.0)
+    post = (rho2, u2, 0.0, p2)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    st = [np.where(X < shock_x, post[k], pre[k]) for k in range(4)]
+    q0 = conserved(gamma, *st)
+    bc_state = np.zeros((4, 4))
+    bc_state[WEST] = conserved(gamma, *post)
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=1.0, u_ref=u2,
+                         eps1=1.0, eps2=0.05, s1_mode=0)
+    prm.update(params)
+    return Case(name=f"odd_even_{nx}x{ny}_M{mach:g}", q0=q0, params=prm,
+                bc=(DIRICHLET, TRANSMISSIVE, SLIPWALL, SLIPWALL), xn=xn, yn=yn,
+                bc_state=bc_state, nsteps=100000, t_end=t_end)
+
+
+# --------------------------------------------------------------------------
+# Batched / serving family (fourth and fifth test configurations)
+# --------------------------------------------------------------------------
+
+def bump_state(n: int, rng: np.random.Generator, gamma: float = 1.4, mach_lo: float = 0.001,
+               mach_hi: float = 20.0):
+    """Uniform flow on [0,1]^2 (rho = 1, p = 1/gamma so c = 1), Mach ~ U(lo, hi),
+    direction ~ U(0, 2 pi), times 1-5 Gaussian bumps (minimum-image distance,
+    sigma ~ U(0.03, 0.1), amplitude ~ U(0.01, 0.2) with a random sign) applied
+    multiplicatively to rho, p or both."""
+    mach = rng.uniform(mach_lo, mach_hi)
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    dx = 1.0 / n
+    X, Y = cell_centres(n, n, 0.0, 0.0, dx, dx)
+    rho = np.ones((n, n))
+    p = np.full((n, n), 1.0 / gamma)
+    nb = int(rng.integers(1, 6))
+    for _ in range(nb):
+        cx, cy = rng.uniform(0.0, 1.0, size=2)
+        sig = rng.uniform(0.03, 0.1)
+        a = rng.uniform(0.01, 0.2) * rng.choice(np.array([-1.0, 1.0]))
+        target = int(rng.integers(0, 3))  # 0 rho, 1 p, 2 both
+        ddx = np.abs(X - cx)
+        ddx = np.minimum(ddx, 1.0 - ddx)
+        ddy = np.abs(Y - cy)
+        ddy = np.minimum(ddy, 1.0 - ddy)
+        bump = 1.0 + a * np.exp(-(ddx * ddx + ddy * ddy) / (2.0 * sig * sig))
+        if target in (0, 2):
+            rho = rho * bump
+        if target in (1, 2):
+            p = p * bump
+    u = np.full((n, n), mach * math.cos(ang))
+    v = np.full((n, n), mach * math.sin(ang))
+    return conserved(gamma, rho, u, v, p), mach
+
+
+def bump_case(n: int, rng: np.random.Generator, nsteps: int, name: str = "bump", **params) -> Case:
+    q0, mach = bump_state(n, rng)
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=min(mach, 1.0), u_ref=mach,
+                         eps1=1.0, eps2=0.05, s1_mode=0)
+    prm.update(params)
+    return Case(name=name, q0=q0, params=prm, bc=(PERIODIC,) * 4, dx=1.0 / n, dy=1.0 / n,
+                nsteps=nsteps, t_end=0.0)
+
+
+def batch_family(n_grids: int = 256, seed: Optional[int] = None, nsteps: int = 200,
+                 n_lo: int = 32, n_hi: int = 512, **params) -> List[Case]:
+    """Square grids with side round(exp(U(ln n_lo, ln n_hi)))."""
+    seed = SEED_BASE + 3 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for g in range(n_grids):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        out.append(bump_case(n, rng, nsteps, name=f"batch{g}_{n}", **params))
+    return out
+
+
+def serving_trace(rate: float, duration: float, seed: Optional[int] = None, n_lo: int = 64,
+                  n_hi: int = 2048, s_lo: int = 50, s_hi: int = 2000):
+    """Poisson arrivals at ``rate`` per second for ``duration`` seconds; each request
+    has a square grid side log-uniform in [n_lo, n_hi] and a step count
+    log-uniform in [s_lo, s_hi].  Returns a list of (arrival_s, side, steps, seed)."""
+    seed = SEED_BASE + 4 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        s = int(round(math.exp(rng.uniform(math.log(s_lo), math.log(s_hi)))))
+        out.append((t, n, s, int(rng.integers(0, 2 ** 31))))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Random face states and smooth fields for unit and parity tests
+# --------------------------------------------------------------------------
+
+def random_prim_pairs(n: int, seed: int, mach_lo: float = 1e-3, mach_hi: float = 5.0,
+                      jump: float = 0.5) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """n pairs of primitive states (rho, u, v, p) and unit normals [n, 2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = np.exp(rng.uniform(-1.0, 1.0, n))
+    p = np.exp(rng.uniform(-1.0, 1.0, n))
+    c = np.sqrt(1.4 * p / rho)
+    mach = np.exp(rng.uniform(math.log(mach_lo), math.log(mach_hi), n))
+    ang = rng.uniform(0, 2 * math.pi, n)
+    u, v = mach * c * np.cos(ang), mach * c * np.sin(ang)
+    WL = np.stack([rho, u, v, p], axis=1)
+    f = np.exp(rng.uniform(-jump, jump, (n, 4)))
+    WR = WL.copy()
+    WR[:, 0] *= f[:, 0]
+    WR[:, 3] *= f[:, 3]
+    WR[:, 1] += (f[:, 1] - 1.0) * c * mach
+    WR[:, 2] += (f[:, 2] - 1.0) * c * mach
+    th = rng.uniform(0, 2 * math.pi, n)
+    nrm = np.stack([np.cos(th), np.sin(th)], axis=1)
+    return WL, WR, nrm
+
+
+def smooth_random_case(nx: int, ny: int, seed: int, bc=(PERIODIC,) * 4, mach: float = 0.5,
+                       amp: float = 0.2, nodes: bool = False, **params) -> Case:
+    """A smooth random periodic-like field (sums of a few sines) with mild
+    density/pressure variation; optionally on a randomly perturbed node grid."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gamma = params.get("gamma", 1.4)
+    dx, dy = 1.0 / nx, 1.0 / ny
+    X, Y = cell_centres(nx, ny, 0.0, 0.0, dx, dy)
+
+    def field():
+        out = np.zeros_like(X)
+        for _ in range(3):
+            kx, ky = rng.integers(1, 4, size=2)
+            ph = rng.uniform(0, 2 * math.pi)
+            out += rng.uniform(-1, 1) * np.sin(2 * math.pi * (kx * X + ky * Y) + ph)
+        return out / 3.0
+
+    rho = 1.0 + amp * field()
+    p = 1.0 / gamma * (1.0 + amp * field())
+    u = mach * (1.0 + field())
+    v = mach * field()
+    q0 = conserved(gamma, rho, u, v, p)
+    xn = yn = None
+    if nodes:
+        xs = np.arange(nx + 1) * dx
+        ys = np.arange(ny + 1) * dy
+        xn, yn = np.meshgrid(xs, ys)
+        # node perturbation that repeats with the domain period, so opposite
+        # boundary faces coincide under the periodic index wrap
+        px = 0.15 * dx * rng.uniform(-1, 1, xn.shape)
+        py = 0.15 * dy * rng.uniform(-1, 1, yn.shape)
+        for a in (px, py):
+            a[:, -1] = a[:, 0]
+            a[-1, :] = a[0, :]
+        xn = xn + px
+        yn = yn + py
+    prm = default_params(order=2, time_scheme=1, mach_ref=0.1, u_ref=mach, eps1=1.0)
+    prm.update(params)
+    bc_state = np.zeros((4, 4))
+    for s in range(4):
+        bc_state[s] = conserved(gamma, 1.0, mach, 0.0, 1.0 / gamma)
+    return Case(name=f"smooth_{nx}x{ny}", q0=q0, params=prm, bc=tuple(bc), dx=dx, dy=dy,
+                xn=xn, yn=yn, bc_state=bc_state, nsteps=10, t_end=0.0)
