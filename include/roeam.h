@@ -1,0 +1,217 @@
+/*
+ * roeam.h -- C ABI of the MI355X (gfx950) Roe-AM finite-volume library.
+ *
+ * The library evaluates the Roe-AM numerical flux of Li, Ren and Gu
+ * ("An Improved Roe Scheme for All Mach-Number Flows Simultaneously Curing
+ * Known Problems", arXiv 1711.09272, Sec. 6.2, Eqs. 85-109) on every face of a
+ * structured 2-D grid, sums the face fluxes into the cell residual of a
+ * finite-volume method (Sec. 2.2, Eqs. 2-4) and advances the conserved state
+ * Q = (rho, rho u, rho v, rho E) of the Euler equations (Eq. 1, with w = 0)
+ * with an explicit Runge-Kutta method.  All arithmetic runs in HIP kernels on
+ * the GPU; nothing here falls back to the CPU.
+ *
+ * Conventions
+ *   - State arrays are device memory, FP64, structure of arrays:
+ *     q[k][j][i] at q + k*ny*pitch + j*pitch + i, k = 0..3 (rho, rho u,
+ *     rho v, rho E), j = 0..ny-1, i = 0..nx-1.  The row pitch (in elements)
+ *     is chosen by the library and read back with roeam_grid_layout(); pad
+ *     elements i >= nx are never read or written.
+ *   - Every function returns a roeam_status; no C++ exception crosses the
+ *     ABI.  Argument errors are reported synchronously.  Numerical failure
+ *     (a non-physical state) is detected on the device and reported with the
+ *     step statistics or by the batch poll.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *     a function says otherwise.  Caller-owned buffers must stay valid until
+ *     that stream has finished the work.
+ *   - A context must be used by one host thread at a time.
+ */
+#ifndef ROEAM_H
+#define ROEAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROEAM_OK = 0,
+    ROEAM_EINVAL = -1,    /* invalid argument (see each function)                  */
+    ROEAM_ENOMEM = -2,    /* device allocation failed or the arena is too small     */
+    ROEAM_EDEVICE = -3,   /* a HIP runtime call failed                              */
+    ROEAM_ENONPHYS = -4,  /* rho <= 0, p <= 0 or a non-finite value was produced     */
+    ROEAM_EBUSY = -5,     /* the request cannot be admitted now                     */
+    ROEAM_ENOTFOUND = -6  /* unknown batch ticket                                   */
+} roeam_status;
+
+typedef struct roeam_ctx roeam_ctx;   /* device, stream, kernel tables, batch engine      */
+typedef struct roeam_grid roeam_grid; /* immutable grid: sizes, metrics, boundary kinds    */
+
+/* Boundary kinds (the paper's Sec. 7 cases use inflow, outflow, walls and
+ * periodic directions; the ghost-cell rules themselves are not printed):
+ *   PERIODIC      wrap around;
+ *   TRANSMISSIVE  copy the nearest interior cell (zero gradient);
+ *   SLIPWALL      mirror the interior cells and reflect the velocity about the
+ *                 wall-face normal;
+ *   DIRICHLET     a fixed state supplied at grid creation.
+ * Two ghost layers are used.  Corner ghosts apply the x rule first and then
+ * the y rule. */
+typedef enum {
+    ROEAM_BC_PERIODIC = 0,
+    ROEAM_BC_TRANSMISSIVE = 1,
+    ROEAM_BC_SLIPWALL = 2,
+    ROEAM_BC_DIRICHLET = 3
+} roeam_bc;
+
+enum { ROEAM_WEST = 0, ROEAM_EAST = 1, ROEAM_SOUTH = 2, ROEAM_NORTH = 3 };
+
+/* Grid metrics: the face-normal vectors and face lengths of Eq. (4) and the
+ * cell areas of the finite-volume sum come from either a uniform spacing or
+ * the node coordinates of a structured grid.
+ *   kind 0: uniform, cell (i, j) = [i dx, (i+1) dx] x [j dy, (j+1) dy];
+ *   kind 1: node coordinates xn, yn, HOST pointers to (ny+1)*(nx+1) doubles,
+ *           row-major [j][i]; the library copies them.  The i-face between
+ *           cells (i-1, j) and (i, j) joins nodes (i, j) and (i, j+1); its
+ *           vector is (y(i,j+1) - y(i,j), -(x(i,j+1) - x(i,j))).  The j-face
+ *           between (i, j-1) and (i, j) joins nodes (i, j) and (i+1, j); its
+ *           vector is (-(y(i+1,j) - y(i,j)), x(i+1,j) - x(i,j)).  Cell areas
+ *           by the shoelace formula. */
+typedef struct {
+    int kind;
+    double dx, dy;
+    const double *xn, *yn;
+} roeam_metrics;
+
+/* Variant bits: alternative readings of ambiguous passages.  0 = the scheme
+ * of Eqs. (85)-(109) with the default readings. */
+#define ROEAM_V_XI_UNGATED   (1u << 0) /* xi as printed in Eq. (86), without the Eq. (68) gate */
+#define ROEAM_V_EXPFIX_F8    (1u << 1) /* f^8(Mbar) weight of Eq. (73) instead of f(Mbar)       */
+#define ROEAM_V_CLAMP_UPRIME (1u << 2) /* clamp |U|' of Eq. (92) at zero                        */
+#define ROEAM_V_SUPPORTED    (ROEAM_V_XI_UNGATED | ROEAM_V_EXPFIX_F8 | ROEAM_V_CLAMP_UPRIME)
+
+/* Scheme parameters.
+ *   gamma     ratio of specific heats (Eq. 54), > 1;
+ *   cfl       Courant number of the time-step rule, > 0 (roeam_step only);
+ *   mach_ref  global reference Mach number of Eq. (101), > 0;
+ *   u_ref     reference speed of Eq. (108), >= 0;
+ *   eps1      switch of Eq. (111): 0 or 1;
+ *   eps2      entropy-fix constant of Eq. (112), >= 0 (paper: 0.05);
+ *   s1_mode   0: pressure-density detector of Eqs. (95)-(97); 1: s1 = 1 (Eq. 110);
+ *   order     1: piecewise-constant face states (Sec. 7.1);
+ *             2: MUSCL-minmod on (rho, u, v, p);
+ *   time_scheme 0: forward Euler; 1: three-stage SSP Runge-Kutta;
+ *   precision 0: FP64 throughout;
+ *             1: flux coefficients in FP32, with the state, the jumps of
+ *                Eq. (85), the central term and the residual sum in FP64;
+ *   variant   ROEAM_V_* bits.
+ * Time step: dt = cfl / max over cells of
+ *   (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega,  ce = c / sqrt(theta_cell),
+ * with Si, Sj the means of opposite face vectors and theta_cell of Eq. (101)
+ * from the cell Mach number (ce bounds the speed of the low-Mach dU_p term
+ * of Eq. 89). */
+typedef struct {
+    double gamma, cfl, mach_ref, u_ref, eps1, eps2;
+    int s1_mode, order, time_scheme, precision;
+    unsigned variant;
+} roeam_params;
+
+typedef struct {
+    double t;        /* time reached                                             */
+    double dt_last;  /* last time step taken                                     */
+    double max_rate; /* max explicit rate that set dt_last                       */
+    long steps;      /* steps taken by this call                                 */
+    int nonphys;     /* nonzero if a non-physical state was produced              */
+} roeam_step_stats;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  EINVAL: bad device; EDEVICE. */
+roeam_status roeam_ctx_create(int device, void *hip_stream, roeam_ctx **out);
+roeam_status roeam_ctx_destroy(roeam_ctx *ctx);
+/* Rebind the stream used by later calls. */
+roeam_status roeam_ctx_set_stream(roeam_ctx *ctx, void *hip_stream);
+/* Text of the last error of this context (never NULL). */
+const char *roeam_last_error(const roeam_ctx *ctx);
+
+/* Create a grid of nx x ny cells (nx, ny >= 2).  bc[4] = kinds for west,
+ * east, south, north; a periodic kind must be used on both sides of its
+ * direction.  dirichlet_state: HOST array [4 sides][4] of conserved states,
+ * used by DIRICHLET sides (NULL allowed if none).  The grid owns device
+ * copies of its metrics and two stage buffers of the state size.
+ * EINVAL: sizes, kinds or metrics invalid (non-positive spacing or cell
+ * area); ENOMEM. */
+roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metrics *metrics,
+                               const int bc[4], const double *dirichlet_state, roeam_grid **out);
+roeam_status roeam_grid_destroy(roeam_grid *grid);
+/* Layout of state arrays: q[k][j][i] at k*ny*pitch + j*pitch + i. */
+roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *pitch);
+
+/* Residual R = dQ/dt = -(1/Omega) sum over the cell's faces of F.S, with F the
+ * Roe-AM flux of Eq. (85) (Sec. 2.2: finite-volume cell faces).
+ * q: device, state layout, read only; r: device, state layout, written.
+ * max_rate_out: nullable DEVICE pointer to one double that receives the
+ * largest explicit rate of q (time-step rule above).  Asynchronous.
+ * EINVAL: NULL q/r, bad params; EDEVICE. */
+roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params,
+                            const double *q, double *r, double *max_rate_out);
+
+/* Advance q (device, state layout) in place by up to nsteps steps of the
+ * chosen time scheme, stopping when t reaches t_end (t_end <= 0: no stop;
+ * the last step is shortened to land on t_end).  The step loop runs from
+ * device-resident dt and t (no host synchronisation inside) as captured HIP
+ * graphs.  If stats != NULL the call waits for the stream and fills it; a
+ * non-physical state then returns ROEAM_ENONPHYS (q undefined).  With
+ * stats == NULL the call is asynchronous; roeam_last_stats() reads them later.
+ * EINVAL: NULL q, nsteps < 0, bad params; EDEVICE. */
+roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params,
+                        double *q, long nsteps, double t0, double t_end, roeam_step_stats *stats);
+/* Wait for the grid's last roeam_step and read its statistics. */
+roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Batched and served solves                                                */
+/* ------------------------------------------------------------------------ */
+
+/* One solve: a grid, its parameters, an initial state and a run length.
+ * q0: HOST or DEVICE pointer (q0_on_device) in the grid's state layout, read
+ * at admission; q_out: HOST or DEVICE pointer (q_out_on_device) written when
+ * the solve completes.  Both caller-owned; they must stay valid until the
+ * ticket reports done. */
+typedef struct {
+    const roeam_grid *grid;
+    roeam_params params;
+    const double *q0;
+    int q0_on_device;
+    long nsteps;
+    double t_end;
+    double *q_out;
+    int q_out_on_device;
+} roeam_solve_desc;
+
+/* Reserve `arena_bytes` of device memory for resident batch state (three
+ * state copies per solve plus per-solve slots); must be called before the
+ * first submit.  ENOMEM if the allocation fails. */
+roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes);
+/* Bytes of arena a solve on this grid occupies while resident. */
+size_t roeam_batch_footprint(const roeam_grid *grid);
+/* Queue n solves; tickets_out[n] receives their tickets.  Solves are
+ * admitted when arena memory is free and then advance together, one step of
+ * every resident solve per scheduler iteration, with solves that arrive
+ * later joining at the next iteration (continuous batching).
+ * EINVAL: bad descriptor (validated before anything is queued). */
+roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *descs,
+                                uint64_t *tickets_out);
+/* Drive the scheduler for up to `iterations` iterations (0: only admit and
+ * retire; -1: until every queued solve is done).  Returns the number of
+ * solves still pending in *pending (nullable). */
+roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending);
+/* Non-blocking poll: *done = 1 once the solve's output is written; stats
+ * (nullable) then holds its statistics.  A solve that produced a
+ * non-physical state is done with return value ROEAM_ENONPHYS; the other
+ * solves are not affected.  ENOTFOUND: unknown ticket. */
+roeam_status roeam_batch_poll(roeam_ctx *ctx, uint64_t ticket, int *done, roeam_step_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROEAM_H */

@@ -1,0 +1,253 @@
+"""Python binding of the gfx950 Roe-AM library (``libroeam.so``, C ABI in include/roeam.h).
+
+Argument marshalling only: every step of the residual and time step runs in
+the library's HIP kernels.  PyTorch supplies device memory and streams.  The
+library must be built (``python -m paper_1711_09272_amd.build``); importing
+the binding without it raises ImportError -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libroeam.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
+V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
+
+EXPORTS = [
+    "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
+    "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_residual", "roeam_step",
+    "roeam_last_stats", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
+    "roeam_batch_run", "roeam_batch_poll",
+]
+
+
+class RoeamError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"roeam error {code}: {msg}")
+        self.code = code
+
+
+class NonPhysicalError(RoeamError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("mach_ref", ctypes.c_double),
+                ("u_ref", ctypes.c_double), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
+                ("s1_mode", ctypes.c_int), ("order", ctypes.c_int), ("time_scheme", ctypes.c_int),
+                ("precision", ctypes.c_int), ("variant", ctypes.c_uint)]
+
+
+class Metrics(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("xn", ctypes.POINTER(ctypes.c_double)), ("yn", ctypes.POINTER(ctypes.c_double))]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt_last", ctypes.c_double), ("max_rate", ctypes.c_double),
+                ("steps", ctypes.c_long), ("nonphys", ctypes.c_int)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("params", Params), ("q0", ctypes.c_void_p),
+                ("q0_on_device", ctypes.c_int), ("nsteps", ctypes.c_long), ("t_end", ctypes.c_double),
+                ("q_out", ctypes.c_void_p), ("q_out_on_device", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libroeam.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_09272_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "roeam_ctx_create": (i, [i, vp, ctypes.POINTER(vp)]),
+        "roeam_ctx_destroy": (i, [vp]),
+        "roeam_ctx_set_stream": (i, [vp, vp]),
+        "roeam_last_error": (ctypes.c_char_p, [vp]),
+        "roeam_grid_create": (i, [vp, i, i, ctypes.POINTER(Metrics), ctypes.POINTER(ctypes.c_int * 4), vp,
+                                  ctypes.POINTER(vp)]),
+        "roeam_grid_destroy": (i, [vp]),
+        "roeam_grid_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]),
+        "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
+        "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
+        "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
+        "roeam_batch_reserve": (i, [vp, ctypes.c_size_t]),
+        "roeam_batch_footprint": (ctypes.c_size_t, [vp]),
+        "roeam_batch_submit": (i, [vp, i, ctypes.POINTER(SolveDesc), ctypes.POINTER(ctypes.c_uint64)]),
+        "roeam_batch_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i)]),
+        "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def params(d: Dict) -> Params:
+    """Params from a dict with the keys of workloads.default_params."""
+    return Params(float(d.get("gamma", 1.4)), float(d.get("cfl", 0.4)), float(d.get("mach_ref", 1.0)),
+                  float(d.get("u_ref", 1.0)), float(d.get("eps1", 0.0)), float(d.get("eps2", 0.05)),
+                  int(d.get("s1_mode", 0)), int(d.get("order", 1)), int(d.get("time_scheme", 0)),
+                  int(d.get("precision", 0)), int(d.get("variant", 0)))
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """A library context on one device, bound to a HIP stream (torch stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        rc = lib().roeam_ctx_create(device, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h))
+        if rc != OK:
+            raise RoeamError(rc, "context creation failed")
+        self.h = h
+
+    def check(self, rc: int):
+        if rc == OK:
+            return
+        msg = lib().roeam_last_error(self.h).decode()
+        if rc == ENONPHYS:
+            raise NonPhysicalError(rc, msg)
+        raise RoeamError(rc, msg)
+
+    def set_stream(self, stream):
+        self.check(lib().roeam_ctx_set_stream(self.h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().roeam_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    """An immutable structured grid of the library (sizes, metrics, boundary kinds)."""
+
+    def __init__(self, ctx: Context, nx: int, ny: int, dx: float = None, dy: float = None,
+                 xn: Optional[np.ndarray] = None, yn: Optional[np.ndarray] = None,
+                 bc: Sequence[int] = (0, 0, 0, 0), bc_state: Optional[np.ndarray] = None):
+        self.ctx = ctx
+        m = Metrics()
+        self._keep = []
+        if xn is None:
+            m.kind, m.dx, m.dy = 0, float(dx), float(dy)
+        else:
+            xa = np.ascontiguousarray(xn, dtype=np.float64)
+            ya = np.ascontiguousarray(yn, dtype=np.float64)
+            assert xa.shape == (ny + 1, nx + 1) and ya.shape == (ny + 1, nx + 1)
+            self._keep += [xa, ya]
+            m.kind = 1
+            m.xn = xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            m.yn = ya.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        bca = (ctypes.c_int * 4)(*[int(b) for b in bc])
+        st = None
+        if bc_state is not None:
+            sa = np.ascontiguousarray(bc_state, dtype=np.float64).reshape(16)
+            self._keep.append(sa)
+            st = ctypes.c_void_p(sa.ctypes.data)
+        h = ctypes.c_void_p()
+        ctx.check(lib().roeam_grid_create(ctx.h, int(nx), int(ny), ctypes.byref(m), ctypes.byref(bca), st,
+                                          ctypes.byref(h)))
+        self.h = h
+        a, b, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+        lib().roeam_grid_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(p))
+        self.nx, self.ny, self.pitch = a.value, b.value, p.value
+
+    @classmethod
+    def from_case(cls, ctx: Context, case) -> "Grid":
+        return cls(ctx, case.nx, case.ny, dx=case.dx, dy=case.dy, xn=case.xn, yn=case.yn, bc=case.bc,
+                   bc_state=case.bc_state)
+
+    def empty_state(self):
+        import torch
+        return torch.zeros((4, self.ny, self.pitch), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+
+    def to_device(self, q: np.ndarray):
+        import torch
+        t = self.empty_state()
+        t[:, :, : self.nx] = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64))
+        return t
+
+    def from_device(self, t) -> np.ndarray:
+        return t[:, :, : self.nx].detach().cpu().numpy().copy()
+
+    def footprint(self) -> int:
+        return int(lib().roeam_batch_footprint(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().roeam_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_ptr(t, grid: Grid) -> ctypes.c_void_p:
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    assert tuple(t.shape) == (4, grid.ny, grid.pitch), (tuple(t.shape), (4, grid.ny, grid.pitch))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def residual(ctx: Context, grid: Grid, prm: Dict, q, r=None, rate_out=None):
+    """R = dQ/dt of state tensor q (device, [4, ny, pitch]); returns r.
+    rate_out: optional 1-element float64 device tensor for the max explicit rate."""
+    if r is None:
+        r = grid.empty_state()
+    p = params(prm)
+    rp = ctypes.c_void_p(rate_out.data_ptr()) if rate_out is not None else None
+    ctx.check(lib().roeam_residual(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), _dev_ptr(r, grid), rp))
+    return r
+
+
+def step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float = 0.0, t_end: float = 0.0,
+         sync: bool = True) -> Optional[Dict]:
+    """Advance q in place; returns the step statistics when sync (else None)."""
+    p = params(prm)
+    st = StepStats()
+    ctx.check(lib().roeam_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
+                               float(t_end), ctypes.byref(st) if sync else None))
+    return st.as_dict() if sync else None
+
+
+def last_stats(ctx: Context, grid: Grid) -> Dict:
+    st = StepStats()
+    ctx.check(lib().roeam_last_stats(ctx.h, grid.h, ctypes.byref(st)))
+    return st.as_dict()

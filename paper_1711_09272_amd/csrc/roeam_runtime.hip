@@ -1,0 +1,397 @@
+// roeam_runtime.hip -- host side of the C ABI in include/roeam.h: contexts,
+// immutable grids, the residual call, the graph-captured step loop and the
+// continuous-batching engine.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/roeam.h"
+#include "roeam_internal.hpp"
+
+using roeam::DevSolve;
+using roeam::Slot;
+
+namespace {
+
+constexpr int kStepsPerGraph = 50;
+
+struct GraphCache {
+    bool valid = false;
+    const double *q = nullptr;
+    roeam_params params{};
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int chunk = 0;
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+};
+
+} // namespace
+
+struct BatchEngine;
+
+struct roeam_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err = "no error";
+    BatchEngine *batch = nullptr;
+};
+
+struct roeam_grid {
+    roeam_ctx *ctx = nullptr;
+    int nx = 0, ny = 0;
+    long long pitch = 0;
+    int metric = 0;
+    double dx = 0, dy = 0;
+    double *d_xn = nullptr, *d_yn = nullptr;
+    int bc[4] = {0, 0, 0, 0};
+    double bcq[4][4] = {};
+    double *d_qa = nullptr, *d_qb = nullptr;
+    Slot *d_slot = nullptr;
+    Slot *h_slot = nullptr;  // pinned readback
+    GraphCache gc;
+};
+
+static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+static roeam_status hip_fail(roeam_ctx *ctx, hipError_t e, const char *where)
+{
+    return fail(ctx, ROEAM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+static roeam_status check_params(roeam_ctx *ctx, const roeam_params *p, bool need_cfl)
+{
+    if (!p) return fail(ctx, ROEAM_EINVAL, "params is NULL");
+    if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(ctx, ROEAM_EINVAL, "gamma must be > 1");
+    if (need_cfl && !(p->cfl > 0.0 && std::isfinite(p->cfl))) return fail(ctx, ROEAM_EINVAL, "cfl must be > 0");
+    if (!(p->mach_ref > 0.0) || !std::isfinite(p->mach_ref))
+        return fail(ctx, ROEAM_EINVAL, "mach_ref must be > 0 (theta of Eq. 101 divides dU_p)");
+    if (!(p->u_ref >= 0.0) || !std::isfinite(p->u_ref)) return fail(ctx, ROEAM_EINVAL, "u_ref must be >= 0");
+    if (p->eps1 != 0.0 && p->eps1 != 1.0) return fail(ctx, ROEAM_EINVAL, "eps1 must be 0 or 1 (Eq. 111)");
+    if (!(p->eps2 >= 0.0) || !std::isfinite(p->eps2)) return fail(ctx, ROEAM_EINVAL, "eps2 must be >= 0");
+    if (p->s1_mode != 0 && p->s1_mode != 1) return fail(ctx, ROEAM_EINVAL, "s1_mode must be 0 or 1");
+    if (p->order != 1 && p->order != 2) return fail(ctx, ROEAM_EINVAL, "order must be 1 or 2");
+    if (p->time_scheme != 0 && p->time_scheme != 1) return fail(ctx, ROEAM_EINVAL, "time_scheme must be 0 or 1");
+    if (p->precision != 0 && p->precision != 1) return fail(ctx, ROEAM_EINVAL, "precision must be 0 or 1");
+    if (p->variant & ~ROEAM_V_SUPPORTED) return fail(ctx, ROEAM_EINVAL, "unsupported variant bits");
+    return ROEAM_OK;
+}
+
+static void prim_of(double gamma, const double Q[4], double W[4])
+{
+    double rho = Q[0], u = Q[1] / rho, v = Q[2] / rho;
+    W[0] = rho;
+    W[1] = u;
+    W[2] = v;
+    W[3] = (gamma - 1.0) * (Q[3] - 0.5 * rho * (u * u + v * v));
+}
+
+static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q)
+{
+    DevSolve S;
+    std::memset(&S, 0, sizeof S);
+    S.nx = g->nx;
+    S.ny = g->ny;
+    S.pitch = g->pitch;
+    S.plane = (long long)g->ny * g->pitch;
+    S.metric = g->metric;
+    S.dx = g->dx;
+    S.dy = g->dy;
+    S.area = g->dx * g->dy;
+    S.xn = g->d_xn;
+    S.yn = g->d_yn;
+    for (int s = 0; s < 4; ++s) {
+        S.bc[s] = g->bc[s];
+        prim_of(p->gamma, g->bcq[s], S.bcw[s]);
+    }
+    S.gamma = p->gamma;
+    S.gm1 = p->gamma - 1.0;
+    S.mr2 = p->mach_ref * p->mach_ref;
+    S.u_ref = p->u_ref;
+    S.eps1 = p->eps1;
+    S.eps2 = p->eps2;
+    S.cfl = p->cfl;
+    S.s1_mode = p->s1_mode;
+    S.order = p->order;
+    S.precision = p->precision;
+    S.variant = p->variant;
+    S.q = q;
+    S.qa = g->d_qa;
+    S.qb = g->d_qb;
+    S.slot = g->d_slot;
+    int tx, ty;
+    roeam::tile_shape(p->order, &tx, &ty);
+    S.tiles_x = (g->nx + tx - 1) / tx;
+    S.tiles_y = (g->ny + ty - 1) / ty;
+    return S;
+}
+
+extern "C" {
+
+roeam_status roeam_ctx_create(int device, void *hip_stream, roeam_ctx **out)
+{
+    if (!out) return ROEAM_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ROEAM_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return ROEAM_EDEVICE;
+    roeam_ctx *c = new (std::nothrow) roeam_ctx;
+    if (!c) return ROEAM_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return ROEAM_OK;
+}
+
+void roeam_batch_release(roeam_ctx *ctx);  // defined with the batch engine
+
+roeam_status roeam_ctx_destroy(roeam_ctx *ctx)
+{
+    if (!ctx) return ROEAM_EINVAL;
+    roeam_batch_release(ctx);
+    delete ctx;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_ctx_set_stream(roeam_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return ROEAM_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return ROEAM_OK;
+}
+
+const char *roeam_last_error(const roeam_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+roeam_status roeam_grid_destroy(roeam_grid *g)
+{
+    if (!g) return ROEAM_EINVAL;
+    g->gc.release();
+    if (g->d_xn) (void)hipFree(g->d_xn);
+    if (g->d_yn) (void)hipFree(g->d_yn);
+    if (g->d_qa) (void)hipFree(g->d_qa);
+    if (g->d_qb) (void)hipFree(g->d_qb);
+    if (g->d_slot) (void)hipFree(g->d_slot);
+    if (g->h_slot) (void)hipHostFree(g->h_slot);
+    delete g;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metrics *m, const int bc[4],
+                               const double *dirichlet_state, roeam_grid **out)
+{
+    if (!ctx || !out || !m || !bc) return fail(ctx, ROEAM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (nx < 2 || ny < 2) return fail(ctx, ROEAM_EINVAL, "nx and ny must be >= 2");
+    if ((long long)nx * ny > (1ll << 31) - 1) return fail(ctx, ROEAM_EINVAL, "grid too large");
+    for (int s = 0; s < 4; ++s)
+        if (bc[s] < ROEAM_BC_PERIODIC || bc[s] > ROEAM_BC_DIRICHLET) return fail(ctx, ROEAM_EINVAL, "bad boundary kind");
+    if ((bc[0] == ROEAM_BC_PERIODIC) != (bc[1] == ROEAM_BC_PERIODIC) ||
+        (bc[2] == ROEAM_BC_PERIODIC) != (bc[3] == ROEAM_BC_PERIODIC))
+        return fail(ctx, ROEAM_EINVAL, "a periodic direction needs periodic kinds on both sides");
+    bool need_dir = false;
+    for (int s = 0; s < 4; ++s) need_dir |= bc[s] == ROEAM_BC_DIRICHLET;
+    if (need_dir && !dirichlet_state) return fail(ctx, ROEAM_EINVAL, "Dirichlet side without a state");
+    if (m->kind == 0) {
+        if (!(m->dx > 0.0) || !(m->dy > 0.0)) return fail(ctx, ROEAM_EINVAL, "dx, dy must be > 0");
+    } else if (m->kind == 1) {
+        if (!m->xn || !m->yn) return fail(ctx, ROEAM_EINVAL, "node arrays are NULL");
+        const long long nxn = nx + 1;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const double *x = m->xn, *y = m->yn;
+                long long r0 = (long long)j * nxn, r1 = r0 + nxn;
+                double a = 0.5 * ((x[r1 + i + 1] - x[r0 + i]) * (y[r1 + i] - y[r0 + i + 1]) -
+                                  (x[r1 + i] - x[r0 + i + 1]) * (y[r1 + i + 1] - y[r0 + i]));
+                if (!(a > 0.0)) return fail(ctx, ROEAM_EINVAL, "non-positive cell area in node grid");
+            }
+    } else {
+        return fail(ctx, ROEAM_EINVAL, "metrics kind must be 0 or 1");
+    }
+    if (need_dir) {
+        for (int s = 0; s < 4; ++s) {
+            if (bc[s] != ROEAM_BC_DIRICHLET) continue;
+            const double *Q = dirichlet_state + 4 * s;
+            if (!(Q[0] > 0.0)) return fail(ctx, ROEAM_EINVAL, "Dirichlet density must be > 0");
+            for (int k = 0; k < 4; ++k)
+                if (!std::isfinite(Q[k])) return fail(ctx, ROEAM_EINVAL, "non-finite Dirichlet state");
+        }
+    }
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    roeam_grid *g = new (std::nothrow) roeam_grid;
+    if (!g) return fail(ctx, ROEAM_ENOMEM, "host allocation");
+    g->ctx = ctx;
+    g->nx = nx;
+    g->ny = ny;
+    g->pitch = ((long long)nx + 15) & ~15ll;
+    g->metric = m->kind;
+    g->dx = m->kind == 0 ? m->dx : 0.0;
+    g->dy = m->kind == 0 ? m->dy : 0.0;
+    for (int s = 0; s < 4; ++s) {
+        g->bc[s] = bc[s];
+        for (int k = 0; k < 4; ++k) g->bcq[s][k] = (bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_state[4 * s + k] : 0.0;
+    }
+    const size_t state_bytes = sizeof(double) * 4 * (size_t)ny * (size_t)g->pitch;
+    hipError_t e = hipMalloc(&g->d_qa, state_bytes);
+    if (e == hipSuccess) e = hipMalloc(&g->d_qb, state_bytes);
+    if (e == hipSuccess) e = hipMalloc(&g->d_slot, sizeof(Slot));
+    if (e == hipSuccess) e = hipHostMalloc(&g->h_slot, sizeof(Slot), hipHostMallocDefault);
+    if (e == hipSuccess && m->kind == 1) {
+        const size_t nb = sizeof(double) * (size_t)(nx + 1) * (size_t)(ny + 1);
+        e = hipMalloc(&g->d_xn, nb);
+        if (e == hipSuccess) e = hipMalloc(&g->d_yn, nb);
+        if (e == hipSuccess) e = hipMemcpy(g->d_xn, m->xn, nb, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g->d_yn, m->yn, nb, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemset(g->d_slot, 0, sizeof(Slot));
+    if (e != hipSuccess) {
+        roeam_grid_destroy(g);
+        return e == hipErrorOutOfMemory ? fail(ctx, ROEAM_ENOMEM, "device allocation") : hip_fail(ctx, e, "grid create");
+    }
+    std::memset(g->h_slot, 0, sizeof(Slot));
+    *out = g;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid_layout(const roeam_grid *g, int *nx, int *ny, long *pitch)
+{
+    if (!g) return ROEAM_EINVAL;
+    if (nx) *nx = g->nx;
+    if (ny) *ny = g->ny;
+    if (pitch) *pitch = (long)g->pitch;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *g, const roeam_params *p, const double *q, double *r,
+                            double *max_rate_out)
+{
+    if (!ctx || !g) return fail(ctx, ROEAM_EINVAL, "NULL context or grid");
+    if (!q || !r) return fail(ctx, ROEAM_EINVAL, "q and r must be device pointers");
+    if (g->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    roeam_status st = check_params(ctx, p, false);
+    if (st) return st;
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    DevSolve S = make_solve(g, p, const_cast<double *>(q));
+    if (max_rate_out) HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 0, ctx->stream));
+    HIP_OK(ctx, roeam::launch_stage_single(S, 0, max_rate_out ? 1 : 0, r, ctx->stream));
+    if (max_rate_out) HIP_OK(ctx, roeam::launch_rate_out(g->d_slot, max_rate_out, ctx->stream));
+    return ROEAM_OK;
+}
+
+// One time step: the dt kernel, then the stage kernels of the scheme.
+static hipError_t enqueue_step(const DevSolve &S, int time_scheme, hipStream_t st)
+{
+    hipError_t e = roeam::launch_dt(S.slot, 1, 0, st);
+    if (e != hipSuccess) return e;
+    if (time_scheme == 0) {
+        e = roeam::launch_stage_single(S, 1, 1, nullptr, st);
+        if (e == hipSuccess) e = roeam::launch_copy_back(S, st);
+        return e;
+    }
+    e = roeam::launch_stage_single(S, 1, 0, nullptr, st);
+    if (e == hipSuccess) e = roeam::launch_stage_single(S, 2, 0, nullptr, st);
+    if (e == hipSuccess) e = roeam::launch_stage_single(S, 3, 1, nullptr, st);
+    return e;
+}
+
+static roeam_status fill_stats(roeam_ctx *ctx, const roeam_grid *g, roeam_step_stats *stats)
+{
+    HIP_OK(ctx, hipMemcpyAsync(g->h_slot, g->d_slot, sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    const Slot &z = *g->h_slot;
+    stats->t = z.t;
+    stats->dt_last = z.dt_last;
+    stats->max_rate = z.rate_last;
+    stats->steps = (long)z.steps;
+    stats->nonphys = z.nonphys;
+    return z.nonphys ? fail(ctx, ROEAM_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite)") : ROEAM_OK;
+}
+
+roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params *p, double *q, long nsteps,
+                        double t0, double t_end, roeam_step_stats *stats)
+{
+    if (!ctx || !gc) return fail(ctx, ROEAM_EINVAL, "NULL context or grid");
+    if (!q) return fail(ctx, ROEAM_EINVAL, "q must be a device pointer");
+    if (nsteps < 0) return fail(ctx, ROEAM_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(t0) || !std::isfinite(t_end)) return fail(ctx, ROEAM_EINVAL, "non-finite time");
+    if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    roeam_status st = check_params(ctx, p, true);
+    if (st) return st;
+    roeam_grid *g = const_cast<roeam_grid *>(gc);
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    const DevSolve S = make_solve(g, p, q);
+    hipStream_t s = ctx->stream;
+    // The slot holds t, t_end and the step budget, so one captured graph of
+    // kStepsPerGraph steps serves any nsteps: steps past the budget or past
+    // t_end are inactive and their kernels exit at once.
+    HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, t0, t_end, p->cfl, nsteps, s));
+    HIP_OK(ctx, roeam::launch_rate(S, s));
+    const bool use_graph = s != nullptr && nsteps > 1;
+    if (!use_graph) {
+        for (long k = 0; k < nsteps; ++k) HIP_OK(ctx, enqueue_step(S, p->time_scheme, s));
+    } else {
+        const int chunk = (int)(nsteps < kStepsPerGraph ? nsteps : kStepsPerGraph);
+        GraphCache &G = g->gc;
+        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || std::memcmp(&G.params, p, sizeof *p) != 0) {
+            G.release();
+            HIP_OK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < chunk && e == hipSuccess; ++k) e = enqueue_step(S, p->time_scheme, s);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &graph);
+            if (e != hipSuccess) return hip_fail(ctx, e, "capture step");
+            if (e2 != hipSuccess) return hip_fail(ctx, e2, "hipStreamEndCapture");
+            G.graph = graph;
+            HIP_OK(ctx, hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0));
+            G.valid = true;
+            G.q = q;
+            G.stream = s;
+            G.chunk = chunk;
+            G.params = *p;
+        }
+        const long launches = (nsteps + chunk - 1) / chunk;
+        for (long k = 0; k < launches; ++k) {
+            HIP_OK(ctx, hipGraphLaunch(G.exec, s));
+            if (t_end > 0.0 && (k & 1)) {
+                // stop launching once the run has reached t_end
+                HIP_OK(ctx, hipMemcpyAsync(g->h_slot, g->d_slot, sizeof(Slot), hipMemcpyDeviceToHost, s));
+                HIP_OK(ctx, hipStreamSynchronize(s));
+                if (g->h_slot->done) break;
+            }
+        }
+    }
+    HIP_OK(ctx, roeam::launch_dt(g->d_slot, 1, 1, s));
+    if (stats) return fill_stats(ctx, g, stats);
+    return ROEAM_OK;
+}
+
+roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *g, roeam_step_stats *stats)
+{
+    if (!ctx || !g || !stats) return fail(ctx, ROEAM_EINVAL, "NULL argument");
+    return fill_stats(ctx, g, stats);
+}
+
+} // extern "C"

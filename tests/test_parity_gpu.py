@@ -1,0 +1,184 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances (cancellation-aware, see gpu_util.residual_error):
+  * FP64 residual: max |dR_k| / max_ij sum_faces |F_k| |S| / Omega <= 1e-12;
+  * FP32-flux residual (precision 1): <= 1e-5;
+  * states after n steps: max |dQ| / max |Q| <= 1e-12 (FP64).
+Sizes span several 32 x 15 tiles with ragged tails; the full-size cases are
+the test configurations' own grids (400 x 4, 256^2, 800 x 80).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import ctx, gpu_residual, gpu_run, residual_error, say, state_error
+from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    return ctx()
+
+
+def rough_case(nx, ny, seed, bc=(PERIODIC,) * 4, **prm):
+    """Cell-by-cell random states: density and pressure over two decades, Mach up
+    to 3 in random directions; exercises limiter, detector and supersonic branches."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = workloads.smooth_random_case(nx, ny, seed, bc=bc, **prm)
+    rho = np.exp(rng.uniform(-2.3, 2.3, (ny, nx)))
+    p = np.exp(rng.uniform(-2.3, 2.3, (ny, nx)))
+    cs = np.sqrt(1.4 * p / rho)
+    M = rng.uniform(0, 3, (ny, nx))
+    th = rng.uniform(0, 2 * np.pi, (ny, nx))
+    c.q0 = workloads.conserved(1.4, rho, M * cs * np.cos(th), M * cs * np.sin(th), p)
+    return c
+
+
+def residual_cases():
+    yield "smooth_periodic_75x37", workloads.smooth_random_case(75, 37, 1, order=2, eps1=1.0, mach_ref=0.05)
+    yield "smooth_nodes_70x33", workloads.smooth_random_case(70, 33, 2, nodes=True, order=2, eps1=1.0)
+    yield "bcmix_walls_nodes", workloads.smooth_random_case(40, 20, 3, bc=(TRANSMISSIVE, DIRICHLET, SLIPWALL, SLIPWALL),
+                                                            nodes=True, order=2, eps1=1.0)
+    yield "bcmix2_order1", workloads.smooth_random_case(33, 16, 4, bc=(DIRICHLET, TRANSMISSIVE, TRANSMISSIVE, SLIPWALL),
+                                                        order=1, eps1=0.0)
+    yield "min_2x2_periodic", workloads.smooth_random_case(2, 2, 5, order=2, eps1=1.0)
+    yield "min_2x2_walls", workloads.smooth_random_case(2, 3, 6, bc=(SLIPWALL, TRANSMISSIVE, SLIPWALL, DIRICHLET), order=2)
+    yield "rough_periodic_65x31", rough_case(65, 31, 7, order=2, eps1=1.0, mach_ref=0.01)
+    yield "rough_s1_one", rough_case(40, 17, 8, order=2, eps1=1.0, s1_mode=1)
+    yield "rough_order1", rough_case(41, 18, 9, order=1, eps1=0.0)
+    yield "rough_xi_ungated", rough_case(33, 16, 10, order=2, eps1=1.0, variant=1)
+    yield "rough_expfix_f8_clamp", rough_case(33, 16, 11, order=2, eps1=1.0, variant=2 | 4)
+    yield "sod_400x4", workloads.sod()
+    yield "vortex_256_M0.01", workloads.vortex(256, 0.01)
+    yield "vortex_256_M0.001", workloads.vortex(256, 0.001)
+    yield "odd_even_800x80", workloads.odd_even()
+
+
+@pytest.mark.parametrize("name,case", list(residual_cases()), ids=[n for n, _ in residual_cases()])
+def test_residual_fp64(C, name, case):
+    say(f"[residual fp64] {name} {case.nx}x{case.ny}")
+    r_or, scale = oracle.residual(case, with_scale=True)
+    r_gpu, rate = gpu_residual(C, case, rate=True)
+    err = residual_error(r_gpu, r_or, scale)
+    say(f"    err per row {err}")
+    assert np.all(err <= TOL64), err
+    rate_or = oracle.max_rate(case)
+    assert abs(rate - rate_or) <= 1e-14 * rate_or
+
+
+@pytest.mark.parametrize("name,case", [c for c in residual_cases() if c[0] in
+                                       ("smooth_periodic_75x37", "rough_periodic_65x31", "vortex_256_M0.001",
+                                        "odd_even_800x80", "smooth_nodes_70x33")],
+                         ids=lambda v: v if isinstance(v, str) else "")
+def test_residual_fp32_flux(C, name, case):
+    say(f"[residual fp32-flux] {name}")
+    r_or, scale = oracle.residual(case, with_scale=True)
+    prm = dict(case.params)
+    prm["precision"] = 1
+    r_gpu = gpu_residual(C, case, params=prm)
+    err = residual_error(r_gpu, r_or, scale)
+    say(f"    err per row {err}")
+    assert np.all(err <= TOL32), err
+
+
+def test_sod_full_run(C):
+    """First configuration: Sod 400 x 4, first order, forward Euler, CFL 0.4 to t = 0.2."""
+    case = workloads.sod()
+    say("[step] sod 400x4 to t=0.2")
+    q_or, st_or = oracle.run(case)
+    q_gpu, st = gpu_run(C, case)
+    say(f"    oracle {st_or}  gpu {st}  err {state_error(q_gpu, q_or):.3e}")
+    assert st["steps"] == st_or["steps"] and st["t"] == st_or["t"] == 0.2
+    assert state_error(q_gpu, q_or) <= TOL64
+
+
+@pytest.mark.parametrize("mach,n,steps", [(0.01, 256, 6), (0.001, 64, 60)])
+def test_vortex_steps(C, mach, n, steps):
+    """Second configuration (MUSCL + SSP-RK3), full 256^2 size for a few steps
+    and a smaller grid for more steps."""
+    case = workloads.vortex(n, mach)
+    say(f"[step] vortex {n} M={mach} {steps} steps")
+    q_or, st_or = oracle.run(case, nsteps=steps)
+    q_gpu, st = gpu_run(C, case, nsteps=steps)
+    say(f"    oracle t={st_or['t']:.6e} gpu t={st['t']:.6e} err {state_error(q_gpu, q_or):.3e}")
+    assert st["steps"] == steps
+    assert abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
+    assert state_error(q_gpu, q_or) <= TOL64
+
+
+def test_odd_even_first_steps(C):
+    """Third configuration at full size (800 x 80 node grid, Dirichlet inflow,
+    transmissive outflow, slip walls): the first 20 steps."""
+    case = workloads.odd_even()
+    say("[step] odd-even 800x80, 20 steps")
+    q_or, st_or = oracle.run(case, nsteps=20)
+    q_gpu, st = gpu_run(C, case, nsteps=20)
+    say(f"    err {state_error(q_gpu, q_or):.3e}")
+    assert state_error(q_gpu, q_or) <= TOL64
+
+
+def test_odd_even_small_50_steps(C):
+    case = workloads.odd_even(nx=200, ny=40, shock_x=10.0)
+    say("[step] odd-even 200x40, 50 steps")
+    q_or, _ = oracle.run(case, nsteps=50)
+    q_gpu, _ = gpu_run(C, case, nsteps=50)
+    assert state_error(q_gpu, q_or) <= TOL64
+
+
+def test_step_is_deterministic(C):
+    case = workloads.vortex(96, 0.01)
+    a, _ = gpu_run(C, case, nsteps=7)
+    b, _ = gpu_run(C, case, nsteps=7)
+    assert np.array_equal(a, b)
+
+
+def test_t_end_stops_and_clips(C):
+    case = workloads.sod(nx=100, ny=2)
+    q_or, st_or = oracle.run(case, nsteps=100000, t_end=0.05)
+    q_gpu, st = gpu_run(C, case, nsteps=100000, t_end=0.05)
+    assert st["t"] == 0.05 and st["steps"] == st_or["steps"]
+    assert state_error(q_gpu, q_or) <= TOL64
+
+
+def test_nonphysical_state_is_reported(C):
+    import paper_1711_09272_amd as P
+    case = workloads.smooth_random_case(20, 10, 3, order=2)
+    q0 = case.q0.copy()
+    q0[3, 4, 7] = 0.0  # rho E = 0: negative pressure
+    with pytest.raises(P.NonPhysicalError):
+        gpu_run(C, case, nsteps=3, q0=q0)
+
+
+def test_near_vacuum_roe_am_survives(C):
+    """Sec. 7.1.2 on the GPU path: Roe-AM keeps rho, p > 0 to t = 0.15."""
+    case = workloads.near_vacuum_tube(nx=200, ny=2)
+    q_or, st_or = oracle.run(case)
+    q_gpu, st = gpu_run(C, case)
+    assert st["nonphys"] == 0 and st["t"] == 0.15
+    assert state_error(q_gpu, q_or) <= 1e-10
+
+
+def test_invalid_arguments(C):
+    import paper_1711_09272_amd as P
+    case = workloads.smooth_random_case(8, 8, 1)
+    g = P.Grid.from_case(C, case)
+    q = g.to_device(case.q0)
+    bad = dict(case.params)
+    bad["mach_ref"] = 0.0
+    with pytest.raises(P.RoeamError) as e:
+        P.residual(C, g, bad, q)
+    assert e.value.code == P.EINVAL
+    bad = dict(case.params)
+    bad["order"] = 3
+    with pytest.raises(P.RoeamError):
+        P.step(C, g, bad, q, 1)
+    with pytest.raises(P.RoeamError):
+        P.Grid(C, 1, 5, dx=0.1, dy=0.1)
+    with pytest.raises(P.RoeamError):
+        P.Grid(C, 5, 5, dx=0.1, dy=0.1, bc=(PERIODIC, TRANSMISSIVE, PERIODIC, PERIODIC))
