@@ -165,6 +165,15 @@ roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *grid, const roeam_
  * EINVAL: NULL q, nsteps < 0, bad params; EDEVICE. */
 roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params,
                         double *q, long nsteps, double t0, double t_end, roeam_step_stats *stats);
+/* Profiling aid (same arithmetic as roeam_step): advance q by nsteps steps
+ * launching every kernel directly, with HIP events recorded on the context
+ * stream around each stage kernel.  Waits for the stream, then writes the
+ * mean duration in milliseconds of the stage kernels into stage_ms[0..2]
+ * (first, second and third stage; forward Euler fills stage_ms[0] only) and
+ * the number of timed launches into *launches (nullable).
+ * EINVAL as roeam_step; EDEVICE. */
+roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params, double *q,
+                                long nsteps, double t0, double stage_ms[3], long *launches);
 /* Wait for the grid's last roeam_step and read its statistics. */
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step_stats *stats);
 

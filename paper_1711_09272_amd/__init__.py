@@ -23,7 +23,7 @@ V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
     "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_residual", "roeam_step",
-    "roeam_last_stats", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
+    "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_poll",
 ]
 
@@ -88,6 +88,8 @@ def lib():
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
+        "roeam_profile_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d,
+                                   ctypes.POINTER(ctypes.c_double * 3), ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_reserve": (i, [vp, ctypes.c_size_t]),
         "roeam_batch_footprint": (ctypes.c_size_t, [vp]),
         "roeam_batch_submit": (i, [vp, i, ctypes.POINTER(SolveDesc), ctypes.POINTER(ctypes.c_uint64)]),
@@ -251,3 +253,14 @@ def last_stats(ctx: Context, grid: Grid) -> Dict:
     st = StepStats()
     ctx.check(lib().roeam_last_stats(ctx.h, grid.h, ctypes.byref(st)))
     return st.as_dict()
+
+
+def profile_step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float = 0.0):
+    """Advance q by nsteps steps with HIP events around every stage kernel; returns
+    (mean ms of the stage-1, stage-2, stage-3 kernels, number of timed launches)."""
+    p = params(prm)
+    out = (ctypes.c_double * 3)()
+    n = ctypes.c_long()
+    ctx.check(lib().roeam_profile_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
+                                       ctypes.byref(out), ctypes.byref(n)))
+    return list(out), n.value

@@ -388,6 +388,50 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
     return ROEAM_OK;
 }
 
+roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params *p, double *q, long nsteps,
+                                double t0, double stage_ms[3], long *launches)
+{
+    if (!ctx || !gc || !q || !stage_ms || nsteps < 1) return fail(ctx, ROEAM_EINVAL, "bad argument");
+    if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    roeam_status st = check_params(ctx, p, true);
+    if (st) return st;
+    roeam_grid *g = const_cast<roeam_grid *>(gc);
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    const DevSolve S = make_solve(g, p, q);
+    hipStream_t s = ctx->stream;
+    const int nst = p->time_scheme == 0 ? 1 : 3;
+    std::vector<hipEvent_t> ev((size_t)(2 * nst * nsteps));
+    for (auto &e : ev) HIP_OK(ctx, hipEventCreate(&e));
+    roeam_status rc = ROEAM_OK;
+    hipError_t e = roeam::launch_slot_init(g->d_slot, 1, t0, 0.0, p->cfl, nsteps, s);
+    if (e == hipSuccess) e = roeam::launch_rate(S, s);
+    for (long k = 0; k < nsteps && e == hipSuccess; ++k) {
+        e = roeam::launch_dt(S.slot, 1, 0, s);
+        for (int stg = 1; stg <= nst && e == hipSuccess; ++stg) {
+            hipEvent_t *pair = &ev[(size_t)(2 * (k * nst + stg - 1))];
+            e = hipEventRecord(pair[0], s);
+            const int want_rate = (stg == nst) ? 1 : 0;
+            if (e == hipSuccess) e = roeam::launch_stage_single(S, stg, want_rate, nullptr, s);
+            if (e == hipSuccess) e = hipEventRecord(pair[1], s);
+        }
+        if (e == hipSuccess && nst == 1) e = roeam::launch_copy_back(S, s);
+    }
+    if (e == hipSuccess) e = roeam::launch_dt(g->d_slot, 1, 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(ctx, e, "profile step");
+    double sum[3] = {0, 0, 0};
+    for (long k = 0; k < nsteps && rc == ROEAM_OK; ++k)
+        for (int stg = 0; stg < nst; ++stg) {
+            float ms = 0.f;
+            hipEvent_t *pair = &ev[(size_t)(2 * (k * nst + stg))];
+            if (hipEventElapsedTime(&ms, pair[0], pair[1]) == hipSuccess) sum[stg] += ms;
+        }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    for (int stg = 0; stg < 3; ++stg) stage_ms[stg] = stg < nst ? sum[stg] / (double)nsteps : 0.0;
+    if (launches) *launches = nsteps * nst;
+    return rc;
+}
+
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *g, roeam_step_stats *stats)
 {
     if (!ctx || !g || !stats) return fail(ctx, ROEAM_EINVAL, "NULL argument");
