@@ -136,6 +136,7 @@ def main():
     if st["nonphys"] or st["steps"] != args.steps:
         raise SystemExit(f"bench run failed: {st}")
     ms_per_step = gpu_ms / args.steps
+    shape = grid.tile_shape(prm)
     value = cells * 3 * args.steps / (gpu_ms / 1e3) / 1e9
 
     # roofline of the stage kernel: HIP events around every stage launch
@@ -174,6 +175,7 @@ def main():
                         "MUSCL-minmod + SSP-RK3, Roe-AM (detector, eps1=1, eps2=0.05), CFL 0.4",
             "cells": cells,
             "stages_per_step": 3,
+            "tile_shape": ["32x15", "16x15", "8x7"][shape] if shape >= 0 else None,
             "wall_s": round(wall, 4),
         },
         "roofline": roofline,

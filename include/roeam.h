@@ -145,6 +145,14 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
 roeam_status roeam_grid_destroy(roeam_grid *grid);
 /* Layout of state arrays: q[k][j][i] at k*ny*pitch + j*pitch + i. */
 roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *pitch);
+/* Tile shape of the stage kernel for this grid: 0 = 32x15 cells per
+ * workgroup, 1 = 16x15, 2 = 8x7, or -1 (default) = chosen by the autotuner,
+ * which times every shape on the grid at its first roeam_step and keeps the
+ * fastest per (order, precision).  Every shape computes the same result.
+ * EINVAL: shape outside -1..2. */
+roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
+/* The shape in use for these parameters (-1 if not tuned yet). */
+roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *params, int *shape);
 
 /* Residual R = dQ/dt = -(1/Omega) sum over the cell's faces of F.S, with F the
  * Roe-AM flux of Eq. (85) (Sec. 2.2: finite-volume cell faces).

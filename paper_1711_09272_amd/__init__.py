@@ -22,7 +22,8 @@ V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
-    "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_residual", "roeam_step",
+    "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_grid_set_tile_shape",
+    "roeam_grid_tile_shape", "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_poll",
 ]
@@ -85,6 +86,8 @@ def lib():
                                   ctypes.POINTER(vp)]),
         "roeam_grid_destroy": (i, [vp]),
         "roeam_grid_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]),
+        "roeam_grid_set_tile_shape": (i, [vp, i]),
+        "roeam_grid_tile_shape": (i, [vp, ctypes.POINTER(Params), ctypes.POINTER(i)]),
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
@@ -205,6 +208,16 @@ class Grid:
 
     def from_device(self, t) -> np.ndarray:
         return t[:, :, : self.nx].detach().cpu().numpy().copy()
+
+    def set_tile_shape(self, shape: int):
+        """0 = 32x15, 1 = 16x15, 2 = 8x7 cells per workgroup; -1 = autotune."""
+        self.ctx.check(lib().roeam_grid_set_tile_shape(self.h, int(shape)))
+
+    def tile_shape(self, prm: Dict) -> int:
+        out = ctypes.c_int()
+        p = params(prm)
+        self.ctx.check(lib().roeam_grid_tile_shape(self.h, ctypes.byref(p), ctypes.byref(out)))
+        return out.value
 
     def footprint(self) -> int:
         return int(lib().roeam_batch_footprint(self.h))

@@ -14,18 +14,33 @@ enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_SLIPWALL = 2, BC_DIRICHLET = 3 }
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum : unsigned { V_XI_UNGATED = 1u, V_EXPFIX_F8 = 2u, V_CLAMP_UPRIME = 4u };
 
-// Per-solve time-integration state, resident in device memory.  Written only
-// by the single-thread dt kernel, except rate_bits (atomicMax from stage
-// kernels) and nonphys (atomicOr).
+// Per-solve time-integration state, resident in device memory.  The step
+// state is double-buffered by step parity p: the first stage kernel of a step
+// reads st[p] (time, step count and the explicit rate reduced over the state
+// at the start of the step), every block derives the same dt from it, and
+// block 0 writes st[1-p] for the next step.  No separate dt kernel runs.
+// The max explicit rate of a state is reduced into kRateSlots words (workgroup
+// id modulo kRateSlots) so that thousands of workgroups do not serialize on
+// one device-scope atomic; readers take the max over the words.  Each word is
+// the bit pattern of a non-negative double, which atomicMax on the unsigned
+// 64-bit integer orders correctly.
+constexpr int kRateSlots = 64;
+
+struct StepState {
+    double t;                      // time of the state at this parity
+    double dt;                     // dt of the step that produced this state
+    long long steps;               // steps taken so far
+    long long pad;
+};
+
 struct alignas(64) Slot {
-    double t, dt, t_next, t_end, cfl;
-    double rate_last, dt_last;
-    unsigned long long rate_bits;  // bit pattern of a non-negative double: atomicMax orders it
-    long long steps, max_steps;
-    int active;
-    int nonphys;
-    int done;                      // t reached t_end or a non-physical state
-    int pad;
+    unsigned long long rate_bits[2][kRateSlots];  // per parity
+    StepState st[2];
+    double t_end, cfl;
+    long long max_steps;
+    double dt_last, rate_last;     // of the last step taken
+    int nonphys;                   // set (atomicOr) when a stage produces rho <= 0, p <= 0 or NaN
+    int pad[3];
 };
 
 // Everything a stage kernel needs about one solve.  Passed by value as a
@@ -40,7 +55,7 @@ struct DevSolve {
     int bc[4];
     double bcw[4][4];           // Dirichlet states, primitive (rho, u, v, p)
     // scheme
-    double gamma, gm1, mr2, u_ref, eps1, eps2, cfl;
+    double gamma, gm1, g_gm1, mr2, u_ref, dv_min2, eps1, eps2, cfl, inv_area;
     int s1_mode, order, precision;
     unsigned variant;
     // state
@@ -56,20 +71,49 @@ template <typename R> __device__ __forceinline__ R sgn(R x) { return (R)((x > (R
 template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 
-// Division and square root in the flux-coefficient precision.  FP64 uses the
-// correctly rounded operators; FP32 uses the hardware reciprocal and square
-// root (about 1 ulp), enough for coefficients whose error budget is 1e-5.
-__device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
-__device__ __forceinline__ double rsqrt_(double a) { return sqrt(a); }
-__device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ float rsqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
+// Reciprocal, quotient and reciprocal square root.  FP64: Newton-Raphson
+// refinement (two iterations) of the hardware estimates v_rcp_f64 and
+// v_rsq_f64, a few ulp from the exact value for the normal-range operands
+// of this solver.  FP32: the hardware instructions (about 1 ulp).
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double div_nr(double a, double b)
+{
+    const double r = rcp_nr(b);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    double e = fma(-hx * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-hx * y, y, 0.5);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rcpR(double b) { return rcp_nr(b); }
+__device__ __forceinline__ double rsqR(double x) { return rsq_nr(x); }
+__device__ __forceinline__ double sqrtR(double x) { return sqrt(x); }
+__device__ __forceinline__ float rcpR(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float rsqR(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Eq. (98): f(phi) = min(phi sqrt(4 + (1 - phi^2)^2) / (1 + phi^2), 1).
+// Eq. (98): f(phi) = min(phi sqrt(4 + (1 - phi^2)^2) / (1 + phi^2), 1), with
+// sqrt(A) / B evaluated as A rsq(A B^2).
 template <typename R> __device__ __forceinline__ R fswitch(R phi)
 {
-    R one_minus = (R)1 - phi * phi;
-    R val = rdiv(phi * rsqrt_((R)4 + one_minus * one_minus), (R)1 + phi * phi);
-    return rmin(val, (R)1);
+    const R p2 = phi * phi;
+    const R om = (R)1 - p2;
+    const R A = (R)4 + om * om;
+    const R B = (R)1 + p2;
+    return rmin(phi * A * rsqR(A * B * B), (R)1);
 }
 // f^8 as the eighth power (repeated squaring).
 template <typename R> __device__ __forceinline__ R pow8(R x)
@@ -83,9 +127,7 @@ template <typename R> __device__ __forceinline__ R pow8(R x)
 // density ratios, each taken below one.
 __device__ __forceinline__ double detector_P(double pA, double rA, double pB, double rB)
 {
-    double a = rmin(pA, pB) / rmax(pA, pB);
-    double b = rmin(rA, rB) / rmax(rA, rB);
-    return rmin(a, b);
+    return rmin(div_nr(rmin(pA, pB), rmax(pA, pB)), div_nr(rmin(rA, rB), rmax(rA, rB)));
 }
 
 // ---------------------------------------------------------------------------
@@ -94,7 +136,8 @@ __device__ __forceinline__ double detector_P(double pA, double rA, double pB, do
 __device__ __forceinline__ void to_prim(double gm1, double q0, double q1, double q2, double q3, double W[4])
 {
     double rho = q0;
-    double u = q1 / rho, v = q2 / rho;
+    const double ir = rcp_nr(rho);
+    double u = q1 * ir, v = q2 * ir;
     W[0] = rho;
     W[1] = u;
     W[2] = v;
@@ -163,10 +206,12 @@ __device__ __forceinline__ void reflect(double W[4], double nx, double ny)
 __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
 {
     if (i >= 0 && i < S.nx) { load_prim(S, q, i, j, W); return; }
-    int side = i < 0 ? SIDE_W : SIDE_E;
-    int kind = S.bc[side];
+    // constant-index selects keep the by-value kernel argument out of scratch
+    const bool west = i < 0;
+    const int kind = west ? S.bc[SIDE_W] : S.bc[SIDE_E];
     if (kind == BC_DIRICHLET) {
-        for (int k = 0; k < 4; ++k) W[k] = S.bcw[side][k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) W[k] = west ? S.bcw[SIDE_W][k] : S.bcw[SIDE_E][k];
         return;
     }
     int is;
@@ -187,10 +232,11 @@ __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__
 __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
 {
     if (j >= 0 && j < S.ny) { fetch_prim_x(S, q, i, j, W); return; }
-    int side = j < 0 ? SIDE_S : SIDE_N;
-    int kind = S.bc[side];
+    const bool south = j < 0;
+    const int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
     if (kind == BC_DIRICHLET) {
-        for (int k = 0; k < 4; ++k) W[k] = S.bcw[side][k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) W[k] = south ? S.bcw[SIDE_S][k] : S.bcw[SIDE_N][k];
         return;
     }
     int js;
@@ -209,91 +255,85 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
 
 // ---------------------------------------------------------------------------
 // Roe-AM numerical flux, Eqs. (85)-(109), per unit face length.
-// R is the precision of the dissipation coefficients; the central term, the
-// jumps of Eq. (85) and the final assembly stay in FP64.
+// R is the precision of the dissipation coefficients; the side quantities,
+// the central term, the jumps of Eq. (85) and the final assembly stay FP64.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4], const double WR[4], double nx,
                                            double ny, double s1d, double F[4])
 {
-    const double g = S.gamma;
     const double rL = WL[0], uL = WL[1], vL = WL[2], pL = WL[3];
     const double rR = WR[0], uR = WR[1], vR = WR[2], pR = WR[3];
 
-    // side quantities, Eq. (4)
-    double UL = nx * uL + ny * vL;
-    double UR = nx * uR + ny * vR;
-    double HL = (pL / S.gm1 + 0.5 * rL * (uL * uL + vL * vL) + pL) / rL;
-    double HR = (pR / S.gm1 + 0.5 * rR * (uR * uR + vR * vR) + pR) / rR;
-    double PsiL[4] = {rL, rL * uL, rL * vL, rL * HL};
-    double PsiR[4] = {rR, rR * uR, rR * vR, rR * HR};
-    double FbL[4] = {UL * rL, UL * PsiL[1] + pL * nx, UL * PsiL[2] + pL * ny, UL * PsiL[3]};
-    double FbR[4] = {UR * rR, UR * PsiR[1] + pR * nx, UR * PsiR[2] + pR * ny, UR * PsiR[3]};
+    // side quantities, Eq. (4); H = gamma/(gamma-1) p/rho + |V|^2/2
+    const double iL = rcp_nr(rL), iR = rcp_nr(rR);
+    const double qL = uL * uL + vL * vL, qR = uR * uR + vR * vR;
+    const double UL = nx * uL + ny * vL, UR = nx * uR + ny * vR;
+    const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
+    const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
+    const double PsiL1 = rL * uL, PsiL2 = rL * vL, PsiL3 = rL * HL;
+    const double PsiR1 = rR * uR, PsiR2 = rR * vR, PsiR3 = rR * HR;
 
     // jumps stay FP64 (low-Mach pressure differences cancel otherwise)
-    double dUd = UR - UL;
-    double dpd = pR - pL;
-    double dPsi[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) dPsi[k] = PsiR[k] - PsiL[k];
+    const double dUd = UR - UL, dpd = pR - pL;
 
     // Roe averages (sqrt(rho) weights)
-    const R rr = rsqrt_((R)rdiv((R)rR, (R)rL));
-    const R inv1r = rdiv((R)1, (R)1 + rr);
+    const R rr = sqrtR((R)(rR * iL));
+    const R w1 = rcpR((R)1 + rr);
     const R rho = rr * (R)rL;
-    const R u = ((R)uL + rr * (R)uR) * inv1r;
-    const R v = ((R)vL + rr * (R)vR) * inv1r;
-    const R H = ((R)HL + rr * (R)HR) * inv1r;
-    const R c = rsqrt_((R)S.gm1 * (H - (R)0.5 * (u * u + v * v)));
+    const R u = ((R)uL + rr * (R)uR) * w1;
+    const R v = ((R)vL + rr * (R)vR) * w1;
+    const R H = ((R)HL + rr * (R)HR) * w1;
+    const R c2 = (R)S.gm1 * (H - (R)0.5 * (u * u + v * v));
+    const R ic = rsqR(c2);
+    const R c = c2 * ic;
     const R U = (R)nx * u + (R)ny * v;
     const R dU = (R)dUd, dp = (R)dpd;
     const R s1 = (R)s1d;
 
-    // Mach numbers, Eqs. (93)-(94); f, f^8 of Eq. (98)
-    const R cL = rsqrt_(rdiv((R)g * (R)pL, (R)rL)), cR = rsqrt_(rdiv((R)g * (R)pR, (R)rR));
-    const R M = (R)0.5 * (rdiv(rsqrt_((R)(uL * uL + vL * vL)), cL) + rdiv(rsqrt_((R)(uR * uR + vR * vR)), cR));
+    // Mach numbers, Eqs. (93)-(94): M_K = |V_K| / c_K, c_K^2 = gamma p_K / rho_K
+    const R c2L = (R)(S.gamma * pL * iL), c2R = (R)(S.gamma * pR * iR);
+    const R icLR = rcpR(c2L * c2R);
+    const R M = (R)0.5 * (sqrtR((R)qL * c2R * icLR) + sqrtR((R)qR * c2L * icLR));
     const R absU = U < (R)0 ? -U : U;
-    const R Mbar = rdiv(absU, c);
+    const R Mbar = absU * ic;
     const R fM = fswitch(M), f8M = pow8(fM);
     const R fMbar = fswitch(Mbar), f8Mbar = pow8(fMbar);
 
     // preconditioning, Eqs. (99)-(101)
     const R theta = rmin(rmax((R)S.mr2, M * M), (R)1);
     const R omt = (R)1 - theta;
-    const R ct = (R)0.5 * rsqrt_((R)4 * c * c * theta + omt * omt * U * U);
+    const R X = (R)4 * c2 * theta + omt * omt * U * U;
+    const R rX = rsqR(X);
+    const R ct = (R)0.5 * X * rX;  // c~ of Eq. (99)
+    const R U_2ct = U * rX;        // U / (2 c~)
     const R Ut = (R)0.5 * ((R)1 + theta) * U;
 
     // expansion-shock fix, Eq. (92)
-    const R w = (S.variant & V_EXPFIX_F8) ? f8Mbar : fMbar;
-    R absUp = absU - w * (sgn(U + c) - sgn(U - c)) * rmax((R)0, dU) / (R)4;
+    const R wexp = (S.variant & V_EXPFIX_F8) ? f8Mbar : fMbar;
+    R absUp = absU - wexp * (sgn(U + c) - sgn(U - c)) * rmax((R)0, dU) * (R)0.25;
     if (S.variant & V_CLAMP_UPRIME) absUp = rmax(absUp, (R)0);
 
     // basic upwind dissipation xi, Eq. (86) with the Eq. (68) gate
     const R gate = (S.variant & V_XI_UNGATED) ? (R)1 : (R)1 - f8Mbar;
     const R ULR = (R)(0.5 * (UR + UL));
     const R xi_pos = (ULR < (R)0 ? -ULR : ULR) + gate * ((R)0.5 * dU);
-    R xi = xi_pos;
+    R xi;
     if (S.eps1 != 0.0) {
         // modified entropy fix f_ef (Eq. 102) and rotated speed f_rr (Eqs. 103-109)
         const R fef = (R)S.eps2 * c;
         const R du = (R)(uR - uL), dv = (R)(vR - vL);
-        const R dV = rsqrt_(du * du + dv * dv);
+        const R dV2 = du * du + dv * dv;
         R n1x = (R)nx, n1y = (R)ny;
-        if (!(dV < (R)(1e-5 * S.u_ref) || dV == (R)0)) {
-            const R idV = rdiv((R)1, dV);
+        if (!(dV2 < (R)S.dv_min2 || dV2 == (R)0)) {
+            const R idV = rsqR(dV2);
             n1x = du * idV;
             n1y = dv * idV;
         }
-        const R alpha1 = n1x * (R)nx + n1y * (R)ny;
-        const R U1 = n1x * u + n1y * v;
+        const R a1U1 = (n1x * (R)nx + n1y * (R)ny) * (n1x * u + n1y * v);
+        // unit n2 along (n1 x n) x n1 = s (-n1y, n1x): alpha2 U2 = |s| (n1x v - n1y u) up to sign
         const R sz = n1x * (R)ny - n1y * (R)nx;
-        R a2U2 = (R)0;
-        if (sz != (R)0) {
-            const R sg = sgn(sz);
-            const R n2x = -sg * n1y, n2y = sg * n1x;
-            a2U2 = (n2x * (R)nx + n2y * (R)ny) * (n2x * u + n2y * v);
-        }
-        const R a1U1 = alpha1 * U1;
+        const R a2U2 = sz * (n1x * v - n1y * u);
         const R frr = (a1U1 < (R)0 ? -a1U1 : a1U1) + (a2U2 < (R)0 ? -a2U2 : a2U2);
         const R xi_fix = (R)S.eps1 * ((R)1 - f8Mbar) * f8M * rmin(fef, frr);
         xi = rmax(xi_pos, xi_fix);
@@ -302,36 +342,34 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     }
 
     // Eqs. (87)-(91)
-    const R ic = rdiv((R)1, c);
     const R sU = sgn(U);
     const R mUc = rmin(absUp, c);
     const R dpp = sU * mUc * dp * ic;
     const R dpu = ((R)1 - s1 + s1 * fM) * rmax((R)0, c - absUp) * rho * dU;
-    const R bracket = rmax((R)0, ct - absUp)
-                    + omt * (absUp - rdiv(U, (R)2 * ct) * sgn(Ut) * rmin(Ut < (R)0 ? -Ut : Ut, ct));
-    const R dUp = rdiv(s1 * ((R)1 - f8M) * bracket * dp, rho * theta * c * c);
+    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(Ut < (R)0 ? -Ut : Ut, ct));
+    const R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
     const R dUu = (R)0.5 * sU * mUc * dU * ic;
 
     // Eq. (85): F = central - (1/2){xi dPsi + (dpp + dpu)(0, n, 0) + dUp PsiHat + dUu (Psi_R + Psi_L)}
-    const double xid = (double)xi, dpd_ = (double)(dpp + dpu), dUpd = (double)dUp, dUud = (double)dUu;
+    const double xid = (double)xi, pd = (double)(dpp + dpu), dUpd = (double)dUp, dUud = (double)dUu;
     const double rhod = (double)rho;
-    const double Ph[4] = {rhod, rhod * (double)u, rhod * (double)v, rhod * (double)H};
-    const double pv[4] = {0.0, nx, ny, 0.0};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double diss = xid * dPsi[k] + dpd_ * pv[k] + dUpd * Ph[k] + dUud * PsiR[k] + dUud * PsiL[k];
-        F[k] = 0.5 * (FbL[k] + FbR[k]) - 0.5 * diss;
-    }
+    F[0] = 0.5 * (UL * rL + UR * rR) - 0.5 * (xid * (rR - rL) + dUpd * rhod + dUud * (rR + rL));
+    F[1] = 0.5 * ((UL * PsiL1 + pL * nx) + (UR * PsiR1 + pR * nx))
+         - 0.5 * (xid * (PsiR1 - PsiL1) + pd * nx + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
+    F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
+         - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+    F[3] = 0.5 * (UL * PsiL3 + UR * PsiR3)
+         - 0.5 * (xid * (PsiR3 - PsiL3) + dUpd * (rhod * (double)H) + dUud * (PsiR3 + PsiL3));
 }
 
 // Explicit rate of one cell for the time-step rule:
 // (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega, ce = c / sqrt(theta_cell).
 __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4], int i, int j)
 {
-    double c = sqrt(S.gamma * W[3] / W[0]);
-    double M = sqrt(W[1] * W[1] + W[2] * W[2]) / c;
-    double theta = rmin(rmax(S.mr2, M * M), 1.0);
-    double ce = c / sqrt(theta);
+    const double c2 = S.gamma * W[3] * rcp_nr(W[0]);
+    const double M2 = (W[1] * W[1] + W[2] * W[2]) * rcp_nr(c2);
+    const double theta = rmin(rmax(S.mr2, M2), 1.0);
+    const double ce = sqrt(c2 * rcp_nr(theta));
     double six, siy, sjx, sjy, li, lj;
     if (S.metric == 0) {
         six = S.dy; siy = 0.0; sjx = 0.0; sjy = S.dx; li = S.dy; lj = S.dx;
@@ -346,8 +384,8 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
         li = sqrt(six * six + siy * siy);
         lj = sqrt(sjx * sjx + sjy * sjy);
     }
-    double sum = fabs(W[1] * six + W[2] * siy) + ce * li + fabs(W[1] * sjx + W[2] * sjy) + ce * lj;
-    return sum / cell_area(S, i, j);
+    const double sum = fabs(W[1] * six + W[2] * siy) + ce * li + fabs(W[1] * sjx + W[2] * sjy) + ce * lj;
+    return S.metric == 0 ? sum * S.inv_area : sum / cell_area(S, i, j);
 }
 
 __device__ __forceinline__ bool physical(const double W[4])

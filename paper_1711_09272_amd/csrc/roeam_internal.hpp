@@ -13,14 +13,18 @@ struct TileEntry {
     int solve, tx, ty, pad;
 };
 
-void tile_shape(int order, int *tx, int *ty);
-hipError_t launch_stage_single(const DevSolve &S, int stage, int want_rate, double *r_out, hipStream_t st);
+// Tile shapes of the stage kernel: 0 = 32x15 cells / 256 threads,
+// 1 = 16x15 / 128, 2 = 8x7 / 64.
+void tile_shape(int shape, int *tx, int *ty);
+int tile_shape_count();
+// dS: the descriptor in device memory (read by the kernel); S: its host copy.
+hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                               double *r_out, hipStream_t st);
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int stage, int want_rate, hipStream_t st);
+                              int shape, int stage, int p, int last, hipStream_t st);
 hipError_t launch_rate(const DevSolve &S, hipStream_t st);
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
-hipError_t launch_dt(Slot *s, int n, int commit_only, hipStream_t st);
-hipError_t launch_copy_back(const DevSolve &S, hipStream_t st);
+hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
 
 } // namespace roeam

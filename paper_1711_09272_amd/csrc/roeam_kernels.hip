@@ -3,21 +3,18 @@
 // One fused stage kernel per Runge-Kutta stage.  A workgroup owns a tile of
 // TX x TY cells: it stages the tile plus its halo as primitives in LDS, builds
 // the pressure-density detector ratios of Eq. (97) for every face the tile
-// touches, evaluates every face flux of the tile exactly once (Eq. 85), forms
-// the conservative residual of each cell and applies the stage update, the
-// positivity check and the explicit-rate reduction for the next time step.
+// touches, evaluates every face flux of the tile exactly once (Eq. 85; the
+// i-faces, then the j-faces through the same LDS buffer), forms the
+// conservative residual of each cell in registers and applies the stage
+// update, the positivity check and the explicit-rate reduction that sets the
+// next time step.  The first stage of a step also derives dt from the
+// double-buffered step state, so a step is exactly one kernel per stage.
 #include <type_traits>
 
 #include "roeam_device.hpp"
 #include "roeam_internal.hpp"
 
 namespace roeam {
-
-template <int ORDER, int PREC> struct Tile {
-    static constexpr int TX = 32, TY = 15, NT = 256, HL = ORDER;
-    static constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL;
-    static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
-};
 
 __device__ __forceinline__ double minmod(double a, double b)
 {
@@ -41,43 +38,109 @@ __device__ __forceinline__ void reconstruct(const double m2[4], const double m1[
     }
 }
 
+template <int NT>
 __device__ __forceinline__ double block_max(double v, double *red)
 {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    if (NT == 64) return v;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    double m = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = rmax(m, red[w]);
-    }
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) m = rmax(m, red[w]);
     return m;
 }
 
-// The tile body.  stage: 0 residual only (r_out), 1 Q + dt R into qa,
-// 2 SSP-RK3 second stage into qb, 3 SSP-RK3 third stage into q.
-// want_rate: reduce the explicit rate of the produced state (or of the input
-// for stage 0) into the solve's slot.
-template <int ORDER, int PREC>
-__device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int want_rate,
-                                           double *__restrict__ r_out)
+// Max explicit rate of the state at parity p: lane k of every wave reads rate
+// word k, then a wave max.  Every lane of every wave ends with the same value.
+__device__ __forceinline__ double read_rate(const Slot &z, int p)
 {
-    using T = Tile<ORDER, PREC>;
+    static_assert(kRateSlots == 64, "one rate word per lane");
+    const int lane = threadIdx.x & 63;
+    double v = __longlong_as_double((long long)z.rate_bits[p][lane]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
+{
+    atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
+}
+
+// Time-step logic shared by all stage kernels of a step with parity p.
+// Returns whether the step is active and its dt.
+__device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, double &dt, double &t_next,
+                                            double &rate)
+{
+    const StepState &s = z.st[p];
+    if (stage >= 2) {
+        // the first stage has already decided: the step ran iff it advanced the count
+        const StepState &n = z.st[p ^ 1];
+        dt = n.dt;
+        return n.steps != s.steps;
+    }
+    rate = read_rate(z, p);
+    if (z.nonphys || (z.t_end > 0.0 && s.t >= z.t_end) || s.steps >= z.max_steps || !(rate > 0.0)) return false;
+    dt = z.cfl / rate;
+    t_next = s.t + dt;
+    if (z.t_end > 0.0 && s.t + dt >= z.t_end) {
+        dt = z.t_end - s.t;
+        t_next = z.t_end;
+    }
+    return true;
+}
+
+// The tile body.  stage: 0 residual only (r_out), 1 Q + dt R into qa (forward
+// Euler, or the first SSP-RK3 stage), 2 SSP-RK3 second stage into qb, 3 third
+// stage into q.  p: step parity.  last: this stage ends the step (reduce the
+// rate of the new state into st[p^1]); for stage 0 the rate of the input is
+// reduced into st[0].
+template <int ORDER, int PREC, int TX, int TY, int NT>
+__device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int p, int last,
+                                           int first_block, double *__restrict__ r_out)
+{
     using R = typename std::conditional<PREC == 0, double, float>::type;
-    constexpr int TX = T::TX, TY = T::TY, HL = T::HL, LX = T::LX, LY = T::LY;
+    constexpr int HL = ORDER;
+    constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL;
+    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    constexpr int NFB = NFX > NFY ? NFX : NFY;
+    constexpr int CPT = (TX * TY + NT - 1) / NT;  // cells per thread
     __shared__ double sW[4][LY][LX];
     __shared__ double sPx[TY + 2][TX + 1];
     __shared__ double sPy[TY + 1][TX + 2];
-    __shared__ double sFx[4][TY][TX + 1];
-    __shared__ double sFy[4][TY + 1][TX];
-    __shared__ double sRed[T::NT / 64];
+    __shared__ double sF[4][NFB];
+    __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
 
     const int tid = threadIdx.x;
-    double dt = 0.0;
+    Slot &z = *S.slot;
+    double dt = 0.0, t_next = 0.0, rate = 0.0;
     if (stage > 0) {
-        if (!S.slot->active) return;
-        dt = S.slot->dt;
+        const bool active = step_active(z, p, stage, dt, t_next, rate);
+        if (stage == 1 && first_block) {
+            // block 0 publishes the next step state
+            if (tid == 0) {
+                const StepState &s = z.st[p];
+                StepState &n = z.st[p ^ 1];
+                if (active) {
+                    n.t = t_next;
+                    n.dt = dt;
+                    n.steps = s.steps + 1;
+                    z.dt_last = dt;
+                    z.rate_last = rate;
+                } else {
+                    n.t = s.t;
+                    n.dt = 0.0;
+                    n.steps = s.steps;
+                }
+            }
+            // SSP-RK3: the third stage reduces into parity p^1; forward Euler
+            // reduces in this kernel, so its words were cleared earlier.
+            if (!last && tid < kRateSlots) z.rate_bits[p ^ 1][tid] = 0ull;
+        }
+        if (!active) return;
     }
     const double *__restrict__ qin = (stage <= 1) ? S.q : (stage == 2 ? S.qa : S.qb);
     const int i0 = tx * TX, j0 = ty * TY;
@@ -85,7 +148,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 
     // 1. tile + halo -> primitives in LDS
     const bool interior = (i0 - HL >= 0) && (i0 + TX + HL <= nx) && (j0 - HL >= 0) && (j0 + TY + HL <= ny);
-    for (int e = tid; e < LX * LY; e += T::NT) {
+    for (int e = tid; e < LX * LY; e += NT) {
         const int ly = e / LX, lx = e - ly * LX;
         int gi = i0 - HL + lx, gj = j0 - HL + ly;
         double W[4];
@@ -104,100 +167,118 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 
     // 2. detector ratios, Eq. (97), from cell-centre values
     if (S.s1_mode == 0) {
-        for (int e = tid; e < (TY + 2) * (TX + 1); e += T::NT) {
+        for (int e = tid; e < (TY + 2) * (TX + 1); e += NT) {
             const int r = e / (TX + 1), fi = e - r * (TX + 1);
             const int ly = r - 1 + HL;
             sPx[r][fi] = detector_P(sW[3][ly][fi - 1 + HL], sW[0][ly][fi - 1 + HL], sW[3][ly][fi + HL], sW[0][ly][fi + HL]);
         }
-        for (int e = tid; e < (TY + 1) * (TX + 2); e += T::NT) {
+        for (int e = tid; e < (TY + 1) * (TX + 2); e += NT) {
             const int fr = e / (TX + 2), cc = e - fr * (TX + 2);
             const int lx = cc - 1 + HL;
             sPy[fr][cc] = detector_P(sW[3][fr - 1 + HL][lx], sW[0][fr - 1 + HL][lx], sW[3][fr + HL][lx], sW[0][fr + HL][lx]);
         }
+        __syncthreads();
     }
-    __syncthreads();
 
-    // 3. every face of the tile once
-    for (int f = tid; f < T::NFX + T::NFY; f += T::NT) {
+    // 3. i-faces of the tile, once each
+    for (int f = tid; f < NFX; f += NT) {
+        const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+        const int gi = i0 + fi, gj = j0 + fj;
+        if (gi > nx || gj >= ny) continue;
         double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4];
-        double sx, sy, nxv, nyv, len, s1 = 1.0;
-        if (f < T::NFX) {
-            const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
-            const int gi = i0 + fi, gj = j0 + fj;
-            if (gi > nx || gj >= ny) continue;
-            const int ly = fj + HL, lx = fi + HL;
+        const int ly = fj + HL, lx = fi + HL;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                m1[k] = sW[k][ly][lx - 1];
-                p0[k] = sW[k][ly][lx];
-                if (ORDER == 2) {
-                    m2[k] = sW[k][ly][lx - 2];
-                    p1[k] = sW[k][ly][lx + 1];
-                }
+        for (int k = 0; k < 4; ++k) {
+            m1[k] = sW[k][ly][lx - 1];
+            p0[k] = sW[k][ly][lx];
+            if (ORDER == 2) {
+                m2[k] = sW[k][ly][lx - 2];
+                p1[k] = sW[k][ly][lx + 1];
             }
-            if (S.s1_mode == 0) {
-                double a = sPx[fj + 1][fi];
-                a = rmin(a, sPy[fj][fi]);
-                a = rmin(a, sPy[fj + 1][fi]);
-                a = rmin(a, sPy[fj][fi + 1]);
-                a = rmin(a, sPy[fj + 1][fi + 1]);
-                s1 = pow8(fswitch(a));
-            }
-            reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
-            xface_vec(S, gi, gj, sx, sy);
-            unit_normal(S, sx, sy, nxv, nyv, len);
-            roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) sFx[k][fj][fi] = F[k] * len;
-        } else {
-            const int g = f - T::NFX;
-            const int fr = g / TX, fi = g - fr * TX;
-            const int gi = i0 + fi, gj = j0 + fr;
-            if (gi >= nx || gj > ny) continue;
-            const int ly = fr + HL, lx = fi + HL;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                m1[k] = sW[k][ly - 1][lx];
-                p0[k] = sW[k][ly][lx];
-                if (ORDER == 2) {
-                    m2[k] = sW[k][ly - 2][lx];
-                    p1[k] = sW[k][ly + 1][lx];
-                }
-            }
-            if (S.s1_mode == 0) {
-                double a = sPy[fr][fi + 1];
-                a = rmin(a, sPx[fr][fi]);
-                a = rmin(a, sPx[fr][fi + 1]);
-                a = rmin(a, sPx[fr + 1][fi]);
-                a = rmin(a, sPx[fr + 1][fi + 1]);
-                s1 = pow8(fswitch(a));
-            }
-            reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
-            yface_vec(S, gi, gj, sx, sy);
-            unit_normal(S, sx, sy, nxv, nyv, len);
-            roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) sFy[k][fr][fi] = F[k] * len;
         }
+        double s1 = 1.0;
+        if (S.s1_mode == 0) {
+            double a = sPx[fj + 1][fi];
+            a = rmin(a, sPy[fj][fi]);
+            a = rmin(a, sPy[fj + 1][fi]);
+            a = rmin(a, sPy[fj][fi + 1]);
+            a = rmin(a, sPy[fj + 1][fi + 1]);
+            s1 = pow8(fswitch(a));
+        }
+        reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
+        double sx, sy, nxv, nyv, len;
+        xface_vec(S, gi, gj, sx, sy);
+        unit_normal(S, sx, sy, nxv, nyv, len);
+        roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
     }
     __syncthreads();
 
-    // 4. conservative residual and the stage update
-    double lmax = 0.0;
-    for (int c = tid; c < TX * TY; c += T::NT) {
+    // i-direction part of the residual, kept in registers
+    double dfx[CPT][4];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * NT;
         const int cj = c / TX, ci = c - cj * TX;
-        const int gi = i0 + ci, gj = j0 + cj;
-        if (gi >= nx || gj >= ny) continue;
-        const double omega = cell_area(S, gi, gj);
-        double Rv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            Rv[k] = -((sFx[k][cj][ci + 1] - sFx[k][cj][ci]) + (sFy[k][cj + 1][ci] - sFy[k][cj][ci])) / omega;
+            dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
+    }
+    __syncthreads();
+
+    // 4. j-faces of the tile, once each, through the same LDS buffer
+    for (int f = tid; f < NFY; f += NT) {
+        const int fr = f / TX, fi = f - fr * TX;
+        const int gi = i0 + fi, gj = j0 + fr;
+        if (gi >= nx || gj > ny) continue;
+        double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4];
+        const int ly = fr + HL, lx = fi + HL;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m1[k] = sW[k][ly - 1][lx];
+            p0[k] = sW[k][ly][lx];
+            if (ORDER == 2) {
+                m2[k] = sW[k][ly - 2][lx];
+                p1[k] = sW[k][ly + 1][lx];
+            }
+        }
+        double s1 = 1.0;
+        if (S.s1_mode == 0) {
+            double a = sPy[fr][fi + 1];
+            a = rmin(a, sPx[fr][fi]);
+            a = rmin(a, sPx[fr][fi + 1]);
+            a = rmin(a, sPx[fr + 1][fi]);
+            a = rmin(a, sPx[fr + 1][fi + 1]);
+            s1 = pow8(fswitch(a));
+        }
+        reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
+        double sx, sy, nxv, nyv, len;
+        yface_vec(S, gi, gj, sx, sy);
+        unit_normal(S, sx, sy, nxv, nyv, len);
+        roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
+    }
+    __syncthreads();
+
+    // 5. conservative residual R = -((F_e - F_w) + (G_n - G_s)) / Omega and the stage update
+    double lmax = 0.0;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * NT;
+        const int cj = c / TX, ci = c - cj * TX;
+        const int gi = i0 + ci, gj = j0 + cj;
+        if (c >= TX * TY || gi >= nx || gj >= ny) continue;
+        const double iom = S.metric == 0 ? S.inv_area : rcp_nr(cell_area(S, gi, gj));
+        double Rv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sF[k][(cj + 1) * TX + ci] - sF[k][cj * TX + ci])) * iom;
         const long long idx = (long long)gj * S.pitch + gi;
         if (stage == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) r_out[k * S.plane + idx] = Rv[k];
-            if (want_rate) {
+            if (last) {
                 double W[4] = {sW[0][cj + HL][ci + HL], sW[1][cj + HL][ci + HL], sW[2][cj + HL][ci + HL],
                                sW[3][cj + HL][ci + HL]};
                 lmax = rmax(lmax, cell_rate(S, W, gi, gj));
@@ -222,14 +303,14 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         double W[4];
         to_prim(S.gm1, Qn[0], Qn[1], Qn[2], Qn[3], W);
         if (!physical(W)) {
-            atomicOr(&S.slot->nonphys, 1);
-        } else if (want_rate) {
+            atomicOr(&z.nonphys, 1);
+        } else if (last) {
             lmax = rmax(lmax, cell_rate(S, W, gi, gj));
         }
     }
-    if (want_rate) {
-        const double m = block_max(lmax, sRed);
-        if (tid == 0 && m > 0.0) atomicMax(&S.slot->rate_bits, (unsigned long long)__double_as_longlong(m));
+    if (last) {
+        const double mx = block_max<NT>(lmax, sRed);
+        if (tid == 0 && mx > 0.0) reduce_rate(z, stage == 0 ? 0 : (p ^ 1), mx);
     }
 }
 
@@ -242,26 +323,31 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return (b & 7) * chunk + (b >> 3);
 }
 
-template <int ORDER, int PREC>
-__global__ __launch_bounds__(256) void k_stage_single(DevSolve S, int stage, int want_rate, double *r_out)
+template <int ORDER, int PREC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
+                                                     double *r_out)
 {
-    const int nt = S.tiles_x * S.tiles_y;
+    const DevSolve &S = *Sp;
+    const int txs = (S.nx + TX - 1) / TX, tys = (S.ny + TY - 1) / TY;
+    const int nt = txs * tys;
     const int t = xcd_tile(blockIdx.x, nt);
     if (t >= nt) return;
-    stage_tile<ORDER, PREC>(S, t % S.tiles_x, t / S.tiles_x, stage, want_rate, r_out);
+    stage_tile<ORDER, PREC, TX, TY, NT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
 }
 
-template <int ORDER, int PREC>
-__global__ __launch_bounds__(256) void k_stage_batch(const DevSolve *__restrict__ solves, const TileEntry *__restrict__ tiles,
-                                                     int ntiles, int stage, int want_rate)
+template <int ORDER, int PREC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__ solves,
+                                                    const TileEntry *__restrict__ tiles, int ntiles, int stage,
+                                                    int p, int last)
 {
     const int t = xcd_tile(blockIdx.x, ntiles);
     if (t >= ntiles) return;
     const TileEntry te = tiles[t];
-    stage_tile<ORDER, PREC>(solves[te.solve], te.tx, te.ty, stage, want_rate, nullptr);
+    stage_tile<ORDER, PREC, TX, TY, NT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
+                                        nullptr);
 }
 
-// Explicit rate of a state (time step of the first step of a run).
+// Explicit rate of a state (sets dt of the first step of a run) into st[0].
 __global__ __launch_bounds__(256) void k_rate(DevSolve S)
 {
     __shared__ double sRed[4];
@@ -274,8 +360,8 @@ __global__ __launch_bounds__(256) void k_rate(DevSolve S)
         if (!physical(W)) atomicOr(&S.slot->nonphys, 1);
         else lmax = rmax(lmax, cell_rate(S, W, i, j));
     }
-    const double m = block_max(lmax, sRed);
-    if (threadIdx.x == 0 && m > 0.0) atomicMax(&S.slot->rate_bits, (unsigned long long)__double_as_longlong(m));
+    const double m = block_max<256>(lmax, sRed);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, 0, m);
 }
 
 __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps)
@@ -283,47 +369,29 @@ __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl,
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     Slot &z = s[k];
-    z.t = t0; z.dt = 0.0; z.t_next = t0; z.t_end = t_end; z.cfl = cfl;
-    z.rate_last = 0.0; z.dt_last = 0.0; z.rate_bits = 0ull; z.steps = 0; z.max_steps = max_steps;
-    z.active = 0; z.nonphys = 0; z.done = 0; z.pad = 0;
+    for (int q = 0; q < 2; ++q) {
+        z.st[q].t = t0;
+        z.st[q].dt = 0.0;
+        z.st[q].steps = 0;
+        z.st[q].pad = 0;
+        for (int w = 0; w < kRateSlots; ++w) z.rate_bits[q][w] = 0ull;
+    }
+    z.t_end = t_end;
+    z.cfl = cfl;
+    z.max_steps = max_steps;
+    z.dt_last = 0.0;
+    z.rate_last = 0.0;
+    z.nonphys = 0;
 }
 
-// Per solve: commit the previous step, then choose the next dt from the
-// rate reduced over the current state (or mark the solve done).
-__global__ void k_dt(Slot *s, int n, int commit_only)
+// Forward Euler: copy the stage result back into q when the step ran, and
+// clear the rate accumulator that the next step's stage will use.
+__global__ void k_copy_back(DevSolve S, int p)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    Slot &z = s[k];
-    if (z.active) {
-        z.t = z.t_next;
-        z.steps += 1;
-        z.dt_last = z.dt;
-        z.active = 0;
-    }
-    if (commit_only) return;
-    const double rate = __longlong_as_double((long long)z.rate_bits);
-    z.rate_bits = 0ull;
-    if (z.nonphys || (z.t_end > 0.0 && z.t >= z.t_end) || z.steps >= z.max_steps || !(rate > 0.0)) {
-        z.dt = 0.0;
-        z.done = 1;
-        return;
-    }
-    z.rate_last = rate;
-    double dt = z.cfl / rate;
-    bool last = false;
-    if (z.t_end > 0.0 && z.t + dt >= z.t_end) {
-        dt = z.t_end - z.t;
-        last = true;
-    }
-    z.dt = dt;
-    z.t_next = last ? z.t_end : z.t + dt;
-    z.active = 1;
-}
-
-__global__ void k_copy_back(DevSolve S)
-{
-    if (!S.slot->active) return;
+    Slot &z = *S.slot;
+    const bool ran = z.st[p ^ 1].steps != z.st[p].steps;
+    if (blockIdx.x == 0 && threadIdx.x < kRateSlots) z.rate_bits[p][threadIdx.x] = 0ull;
+    if (!ran) return;
     const long long n = (long long)S.nx * S.ny;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(c / S.nx), i = (int)(c - (long long)j * S.nx);
@@ -335,45 +403,78 @@ __global__ void k_copy_back(DevSolve S)
 
 __global__ void k_rate_out(const Slot *s, double *out)
 {
-    if (threadIdx.x == 0) *out = __longlong_as_double((long long)s->rate_bits);
+    const double v = read_rate(*s, 0);
+    if (threadIdx.x == 0) *out = v;
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-static int tile_count(const DevSolve &S) { return S.tiles_x * S.tiles_y; }
+struct TileShape {
+    int tx, ty, nt;
+};
+static const TileShape kShapes[3] = {{32, 15, 256}, {16, 15, 128}, {8, 7, 64}};
 
-void tile_shape(int /*order*/, int *tx, int *ty)
+void tile_shape(int shape, int *tx, int *ty)
 {
-    *tx = Tile<2, 0>::TX;
-    *ty = Tile<2, 0>::TY;
+    const TileShape &s = kShapes[shape < 0 || shape > 2 ? 0 : shape];
+    *tx = s.tx;
+    *ty = s.ty;
 }
 
-hipError_t launch_stage_single(const DevSolve &S, int stage, int want_rate, double *r_out, hipStream_t st)
+int tile_shape_count() { return 3; }
+
+template <int ORDER, int PREC>
+static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                                double *r_out, hipStream_t st)
 {
-    const int nt = tile_count(S);
+    const TileShape &sh = kShapes[shape];
+    const int nt = ((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty);
     const int blocks = ((nt + 7) >> 3) << 3;
+    switch (shape) {
+    case 0: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, dS, stage, p, last, r_out); break;
+    case 1: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, dS, stage, p, last, r_out); break;
+    default: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, dS, stage, p, last, r_out); break;
+    }
+}
+
+hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                               double *r_out, hipStream_t st)
+{
+    if (shape < 0 || shape > 2) return hipErrorInvalidValue;
     if (S.order == 1) {
-        if (S.precision == 0) hipLaunchKernelGGL((k_stage_single<1, 0>), dim3(blocks), dim3(256), 0, st, S, stage, want_rate, r_out);
-        else hipLaunchKernelGGL((k_stage_single<1, 1>), dim3(blocks), dim3(256), 0, st, S, stage, want_rate, r_out);
+        if (S.precision == 0) launch_single_shape<1, 0>(dS, S, shape, stage, p, last, r_out, st);
+        else launch_single_shape<1, 1>(dS, S, shape, stage, p, last, r_out, st);
     } else {
-        if (S.precision == 0) hipLaunchKernelGGL((k_stage_single<2, 0>), dim3(blocks), dim3(256), 0, st, S, stage, want_rate, r_out);
-        else hipLaunchKernelGGL((k_stage_single<2, 1>), dim3(blocks), dim3(256), 0, st, S, stage, want_rate, r_out);
+        if (S.precision == 0) launch_single_shape<2, 0>(dS, S, shape, stage, p, last, r_out, st);
+        else launch_single_shape<2, 1>(dS, S, shape, stage, p, last, r_out, st);
     }
     return hipGetLastError();
 }
 
+template <int ORDER, int PREC>
+static void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int stage, int p,
+                               int last, hipStream_t st)
+{
+    const int blocks = ((ntiles + 7) >> 3) << 3;
+    switch (shape) {
+    case 0: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    case 1: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    default: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    }
+}
+
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int stage, int want_rate, hipStream_t st)
+                              int shape, int stage, int p, int last, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    const int blocks = ((ntiles + 7) >> 3) << 3;
+    if (shape < 0 || shape > 2) return hipErrorInvalidValue;
     if (order == 1) {
-        if (precision == 0) hipLaunchKernelGGL((k_stage_batch<1, 0>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, want_rate);
-        else hipLaunchKernelGGL((k_stage_batch<1, 1>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, want_rate);
+        if (precision == 0) launch_batch_shape<1, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
+        else launch_batch_shape<1, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
     } else {
-        if (precision == 0) hipLaunchKernelGGL((k_stage_batch<2, 0>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, want_rate);
-        else hipLaunchKernelGGL((k_stage_batch<2, 1>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, want_rate);
+        if (precision == 0) launch_batch_shape<2, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
+        else launch_batch_shape<2, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
     }
     return hipGetLastError();
 }
@@ -396,15 +497,9 @@ hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl,
     return hipGetLastError();
 }
 
-hipError_t launch_dt(Slot *s, int n, int commit_only, hipStream_t st)
+hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dt, dim3((n + 63) / 64), dim3(64), 0, st, s, n, commit_only);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_back(const DevSolve &S, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_copy_back, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_copy_back, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, p);
     return hipGetLastError();
 }
 

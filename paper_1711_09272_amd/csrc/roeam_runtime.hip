@@ -30,6 +30,7 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int chunk = 0;
+    int shape = 0;
     void release()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -64,6 +65,12 @@ struct roeam_grid {
     Slot *d_slot = nullptr;
     Slot *h_slot = nullptr;  // pinned readback
     GraphCache gc;
+    int shape_forced = -1;   // tile shape set by the caller, or -1
+    int shape_tuned[2][2] = {{-1, -1}, {-1, -1}};  // autotuned shape per [order-1][precision]
+    int final_parity = 0;    // parity of the step state after the last roeam_step
+    DevSolve *d_solve = nullptr;  // descriptor read by the single-grid kernels
+    DevSolve *h_solve = nullptr;  // pinned staging copy of the last descriptor sent
+    bool solve_valid = false;
 };
 
 static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg)
@@ -130,8 +137,11 @@ static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q
     }
     S.gamma = p->gamma;
     S.gm1 = p->gamma - 1.0;
+    S.g_gm1 = p->gamma / (p->gamma - 1.0);
     S.mr2 = p->mach_ref * p->mach_ref;
     S.u_ref = p->u_ref;
+    S.dv_min2 = (1e-5 * p->u_ref) * (1e-5 * p->u_ref);
+    S.inv_area = g->metric == 0 ? 1.0 / (g->dx * g->dy) : 0.0;
     S.eps1 = p->eps1;
     S.eps2 = p->eps2;
     S.cfl = p->cfl;
@@ -143,11 +153,21 @@ static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q
     S.qa = g->d_qa;
     S.qb = g->d_qb;
     S.slot = g->d_slot;
-    int tx, ty;
-    roeam::tile_shape(p->order, &tx, &ty);
-    S.tiles_x = (g->nx + tx - 1) / tx;
-    S.tiles_y = (g->ny + ty - 1) / ty;
     return S;
+}
+
+// Make the grid's device descriptor equal to S.  Work already queued may
+// still read the old descriptor, so a change waits for the stream first.
+static hipError_t upload_solve(roeam_grid *g, const DevSolve &S, hipStream_t s)
+{
+    if (g->solve_valid && std::memcmp(g->h_solve, &S, sizeof S) == 0) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::memcpy(g->h_solve, &S, sizeof S);
+    e = hipMemcpyAsync(g->d_solve, g->h_solve, sizeof S, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    g->solve_valid = true;
+    return hipSuccess;
 }
 
 extern "C" {
@@ -196,6 +216,8 @@ roeam_status roeam_grid_destroy(roeam_grid *g)
     if (g->d_qb) (void)hipFree(g->d_qb);
     if (g->d_slot) (void)hipFree(g->d_slot);
     if (g->h_slot) (void)hipHostFree(g->h_slot);
+    if (g->d_solve) (void)hipFree(g->d_solve);
+    if (g->h_solve) (void)hipHostFree(g->h_solve);
     delete g;
     return ROEAM_OK;
 }
@@ -259,6 +281,8 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
     if (e == hipSuccess) e = hipMalloc(&g->d_qb, state_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_slot, sizeof(Slot));
     if (e == hipSuccess) e = hipHostMalloc(&g->h_slot, sizeof(Slot), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&g->d_solve, sizeof(DevSolve));
+    if (e == hipSuccess) e = hipHostMalloc(&g->h_solve, sizeof(DevSolve), hipHostMallocDefault);
     if (e == hipSuccess && m->kind == 1) {
         const size_t nb = sizeof(double) * (size_t)(nx + 1) * (size_t)(ny + 1);
         e = hipMalloc(&g->d_xn, nb);
@@ -285,6 +309,74 @@ roeam_status roeam_grid_layout(const roeam_grid *g, int *nx, int *ny, long *pitc
     return ROEAM_OK;
 }
 
+// Tile shape for a grid: the caller's choice, else the autotuned one.  The
+// autotuner times the first-stage kernel of every shape on the grid (stage 1
+// only reads q and writes the grid's own stage buffer, so it leaves q
+// untouched) and keeps the fastest, per (order, precision), in the grid and in
+// a process-wide table keyed by the grid size.
+struct TuneKey {
+    int nx, ny, order, precision, metric;
+    bool operator==(const TuneKey &o) const
+    {
+        return nx == o.nx && ny == o.ny && order == o.order && precision == o.precision && metric == o.metric;
+    }
+};
+struct TuneKeyHash {
+    size_t operator()(const TuneKey &k) const
+    {
+        return ((size_t)k.nx * 1000003u) ^ ((size_t)k.ny * 7919u) ^ (size_t)(k.order * 31 + k.precision * 7 + k.metric);
+    }
+};
+static std::unordered_map<TuneKey, int, TuneKeyHash> g_tuned;
+
+static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_params *p, const DevSolve &S, int *shape)
+{
+    if (g->shape_forced >= 0) {
+        *shape = g->shape_forced;
+        return ROEAM_OK;
+    }
+    int &cached = g->shape_tuned[p->order - 1][p->precision];
+    if (cached >= 0) {
+        *shape = cached;
+        return ROEAM_OK;
+    }
+    const TuneKey key{g->nx, g->ny, p->order, p->precision, g->metric};
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        cached = it->second;
+        *shape = cached;
+        return ROEAM_OK;
+    }
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    HIP_OK(ctx, hipEventCreate(&e0));
+    HIP_OK(ctx, hipEventCreate(&e1));
+    HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 1, s));
+    HIP_OK(ctx, roeam::launch_rate(S, s));
+    int best = 0;
+    float best_ms = 1e30f;
+    const int reps = 4;
+    for (int sh = 0; sh < roeam::tile_shape_count(); ++sh) {
+        HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, sh, 1, 0, 0, nullptr, s));  // warm-up
+        HIP_OK(ctx, hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, sh, 1, 0, 0, nullptr, s));
+        HIP_OK(ctx, hipEventRecord(e1, s));
+        HIP_OK(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OK(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cached = best;
+    g_tuned[key] = best;
+    *shape = best;
+    return ROEAM_OK;
+}
+
 roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *g, const roeam_params *p, const double *q, double *r,
                             double *max_rate_out)
 {
@@ -295,25 +387,30 @@ roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *g, const roeam_par
     if (st) return st;
     HIP_OK(ctx, hipSetDevice(ctx->device));
     DevSolve S = make_solve(g, p, const_cast<double *>(q));
+    const int shape = g->shape_forced >= 0 ? g->shape_forced : 0;
+    roeam_grid *gm = const_cast<roeam_grid *>(g);
+    HIP_OK(ctx, upload_solve(gm, S, ctx->stream));
     if (max_rate_out) HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 0, ctx->stream));
-    HIP_OK(ctx, roeam::launch_stage_single(S, 0, max_rate_out ? 1 : 0, r, ctx->stream));
+    HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, shape, 0, 0, max_rate_out ? 1 : 0, r, ctx->stream));
     if (max_rate_out) HIP_OK(ctx, roeam::launch_rate_out(g->d_slot, max_rate_out, ctx->stream));
     return ROEAM_OK;
 }
 
-// One time step: the dt kernel, then the stage kernels of the scheme.
-static hipError_t enqueue_step(const DevSolve &S, int time_scheme, hipStream_t st)
+// One time step with parity p: one kernel per stage (the first stage also
+// sets dt), plus the copy back for forward Euler.
+static hipError_t enqueue_step(const roeam_grid *g, const DevSolve &S, int shape, int time_scheme, int p,
+                               hipStream_t st)
 {
-    hipError_t e = roeam::launch_dt(S.slot, 1, 0, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    const DevSolve *d = g->d_solve;
     if (time_scheme == 0) {
-        e = roeam::launch_stage_single(S, 1, 1, nullptr, st);
-        if (e == hipSuccess) e = roeam::launch_copy_back(S, st);
+        e = roeam::launch_stage_single(d, S, shape, 1, p, 1, nullptr, st);
+        if (e == hipSuccess) e = roeam::launch_copy_back(S, p, st);
         return e;
     }
-    e = roeam::launch_stage_single(S, 1, 0, nullptr, st);
-    if (e == hipSuccess) e = roeam::launch_stage_single(S, 2, 0, nullptr, st);
-    if (e == hipSuccess) e = roeam::launch_stage_single(S, 3, 1, nullptr, st);
+    e = roeam::launch_stage_single(d, S, shape, 1, p, 0, nullptr, st);
+    if (e == hipSuccess) e = roeam::launch_stage_single(d, S, shape, 2, p, 0, nullptr, st);
+    if (e == hipSuccess) e = roeam::launch_stage_single(d, S, shape, 3, p, 1, nullptr, st);
     return e;
 }
 
@@ -322,10 +419,11 @@ static roeam_status fill_stats(roeam_ctx *ctx, const roeam_grid *g, roeam_step_s
     HIP_OK(ctx, hipMemcpyAsync(g->h_slot, g->d_slot, sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
     const Slot &z = *g->h_slot;
-    stats->t = z.t;
+    const roeam::StepState &s = z.st[g->final_parity];
+    stats->t = s.t;
     stats->dt_last = z.dt_last;
     stats->max_rate = z.rate_last;
-    stats->steps = (long)z.steps;
+    stats->steps = (long)s.steps;
     stats->nonphys = z.nonphys;
     return z.nonphys ? fail(ctx, ROEAM_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite)") : ROEAM_OK;
 }
@@ -344,22 +442,30 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
     HIP_OK(ctx, hipSetDevice(ctx->device));
     const DevSolve S = make_solve(g, p, q);
     hipStream_t s = ctx->stream;
+    HIP_OK(ctx, upload_solve(g, S, s));
+    int shape = 0;
+    st = choose_shape(ctx, g, p, S, &shape);
+    if (st) return st;
     // The slot holds t, t_end and the step budget, so one captured graph of
-    // kStepsPerGraph steps serves any nsteps: steps past the budget or past
-    // t_end are inactive and their kernels exit at once.
+    // an even number of steps serves any nsteps: steps past the budget or
+    // past t_end are inactive and their kernels exit at once.
     HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, t0, t_end, p->cfl, nsteps, s));
     HIP_OK(ctx, roeam::launch_rate(S, s));
     const bool use_graph = s != nullptr && nsteps > 1;
+    long launched = 0;
     if (!use_graph) {
-        for (long k = 0; k < nsteps; ++k) HIP_OK(ctx, enqueue_step(S, p->time_scheme, s));
+        for (long k = 0; k < nsteps; ++k) HIP_OK(ctx, enqueue_step(g, S, shape, p->time_scheme, (int)(k & 1), s));
+        launched = nsteps;
     } else {
-        const int chunk = (int)(nsteps < kStepsPerGraph ? nsteps : kStepsPerGraph);
+        int chunk = (int)(nsteps < kStepsPerGraph ? nsteps : kStepsPerGraph);
+        chunk += chunk & 1;  // even: every launch of the graph starts at parity 0
         GraphCache &G = g->gc;
-        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || std::memcmp(&G.params, p, sizeof *p) != 0) {
+        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || G.shape != shape ||
+            std::memcmp(&G.params, p, sizeof *p) != 0) {
             G.release();
             HIP_OK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             hipError_t e = hipSuccess;
-            for (int k = 0; k < chunk && e == hipSuccess; ++k) e = enqueue_step(S, p->time_scheme, s);
+            for (int k = 0; k < chunk && e == hipSuccess; ++k) e = enqueue_step(g, S, shape, p->time_scheme, k & 1, s);
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(s, &graph);
             if (e != hipSuccess) return hip_fail(ctx, e, "capture step");
@@ -370,20 +476,23 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
             G.q = q;
             G.stream = s;
             G.chunk = chunk;
+            G.shape = shape;
             G.params = *p;
         }
         const long launches = (nsteps + chunk - 1) / chunk;
         for (long k = 0; k < launches; ++k) {
             HIP_OK(ctx, hipGraphLaunch(G.exec, s));
+            launched += chunk;
             if (t_end > 0.0 && (k & 1)) {
                 // stop launching once the run has reached t_end
                 HIP_OK(ctx, hipMemcpyAsync(g->h_slot, g->d_slot, sizeof(Slot), hipMemcpyDeviceToHost, s));
                 HIP_OK(ctx, hipStreamSynchronize(s));
-                if (g->h_slot->done) break;
+                const Slot &z = *g->h_slot;
+                if (z.nonphys || z.st[0].t >= t_end || z.st[0].steps >= nsteps) break;
             }
         }
     }
-    HIP_OK(ctx, roeam::launch_dt(g->d_slot, 1, 1, s));
+    g->final_parity = (int)(launched & 1);
     if (stats) return fill_stats(ctx, g, stats);
     return ROEAM_OK;
 }
@@ -399,6 +508,10 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     HIP_OK(ctx, hipSetDevice(ctx->device));
     const DevSolve S = make_solve(g, p, q);
     hipStream_t s = ctx->stream;
+    HIP_OK(ctx, upload_solve(g, S, s));
+    int shape = 0;
+    st = choose_shape(ctx, g, p, S, &shape);
+    if (st) return st;
     const int nst = p->time_scheme == 0 ? 1 : 3;
     std::vector<hipEvent_t> ev((size_t)(2 * nst * nsteps));
     for (auto &e : ev) HIP_OK(ctx, hipEventCreate(&e));
@@ -406,17 +519,16 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     hipError_t e = roeam::launch_slot_init(g->d_slot, 1, t0, 0.0, p->cfl, nsteps, s);
     if (e == hipSuccess) e = roeam::launch_rate(S, s);
     for (long k = 0; k < nsteps && e == hipSuccess; ++k) {
-        e = roeam::launch_dt(S.slot, 1, 0, s);
+        const int par = (int)(k & 1);
         for (int stg = 1; stg <= nst && e == hipSuccess; ++stg) {
             hipEvent_t *pair = &ev[(size_t)(2 * (k * nst + stg - 1))];
             e = hipEventRecord(pair[0], s);
-            const int want_rate = (stg == nst) ? 1 : 0;
-            if (e == hipSuccess) e = roeam::launch_stage_single(S, stg, want_rate, nullptr, s);
+            if (e == hipSuccess) e = roeam::launch_stage_single(g->d_solve, S, shape, stg, par, stg == nst ? 1 : 0, nullptr, s);
             if (e == hipSuccess) e = hipEventRecord(pair[1], s);
         }
-        if (e == hipSuccess && nst == 1) e = roeam::launch_copy_back(S, s);
+        if (e == hipSuccess && nst == 1) e = roeam::launch_copy_back(S, par, s);
     }
-    if (e == hipSuccess) e = roeam::launch_dt(g->d_slot, 1, 1, s);
+    g->final_parity = (int)(nsteps & 1);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(ctx, e, "profile step");
     double sum[3] = {0, 0, 0};
@@ -430,6 +542,21 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     for (int stg = 0; stg < 3; ++stg) stage_ms[stg] = stg < nst ? sum[stg] / (double)nsteps : 0.0;
     if (launches) *launches = nsteps * nst;
     return rc;
+}
+
+roeam_status roeam_grid_set_tile_shape(roeam_grid *g, int shape)
+{
+    if (!g || shape < -1 || shape >= roeam::tile_shape_count()) return ROEAM_EINVAL;
+    g->shape_forced = shape;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid_tile_shape(const roeam_grid *g, const roeam_params *p, int *shape)
+{
+    if (!g || !p || !shape || (p->order != 1 && p->order != 2) || (p->precision != 0 && p->precision != 1))
+        return ROEAM_EINVAL;
+    *shape = g->shape_forced >= 0 ? g->shape_forced : g->shape_tuned[p->order - 1][p->precision];
+    return ROEAM_OK;
 }
 
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *g, roeam_step_stats *stats)

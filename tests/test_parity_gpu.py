@@ -182,3 +182,61 @@ def test_invalid_arguments(C):
         P.Grid(C, 1, 5, dx=0.1, dy=0.1)
     with pytest.raises(P.RoeamError):
         P.Grid(C, 5, 5, dx=0.1, dy=0.1, bc=(PERIODIC, TRANSMISSIVE, PERIODIC, PERIODIC))
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_each_tile_shape_matches_oracle(C, shape):
+    """Every tile shape of the stage kernel (32x15, 16x15, 8x7 cells per
+    workgroup) against the oracle, on a ragged grid with walls and Dirichlet
+    sides, for the residual and for SSP-RK3 steps."""
+    import torch
+    import paper_1711_09272_amd as P
+    case = workloads.smooth_random_case(45, 29, 12, bc=(DIRICHLET, TRANSMISSIVE, SLIPWALL, SLIPWALL), nodes=True,
+                                        order=2, eps1=1.0, mach_ref=0.05)
+    say(f"[shape {shape}] residual + 5 steps on 45x29")
+    g = P.Grid.from_case(C, case)
+    g.set_tile_shape(shape)
+    r = g.from_device(P.residual(C, g, case.params, g.to_device(case.q0)))
+    r_or, scale = oracle.residual(case, with_scale=True)
+    assert np.all(residual_error(r, r_or, scale) <= TOL64)
+    q = g.to_device(case.q0)
+    st = P.step(C, g, case.params, q, 5)
+    torch.cuda.synchronize()
+    assert g.tile_shape(case.params) == shape and st["steps"] == 5
+    q_or, _ = oracle.run(case, nsteps=5)
+    assert state_error(g.from_device(q), q_or) <= TOL64
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_shapes_are_bitwise_identical(C, precision):
+    """Each face flux is a pure function of its stencil and the residual sum
+    order is fixed, so every tile shape must give the same bits: a check for
+    races and halo-indexing mistakes."""
+    import torch
+    import paper_1711_09272_amd as P
+    case = rough_case(97, 61, 13, order=2, eps1=1.0, mach_ref=0.01)
+    prm = dict(case.params)
+    prm["precision"] = precision
+    prm["cfl"] = 0.1  # this field has two-decade jumps between neighbours
+    outs = []
+    for shape in (0, 1, 2):
+        g = P.Grid.from_case(C, case)
+        g.set_tile_shape(shape)
+        r = g.from_device(P.residual(C, g, prm, g.to_device(case.q0)))
+        q = g.to_device(case.q0)
+        P.step(C, g, prm, q, 3)
+        torch.cuda.synchronize()
+        outs.append((r, g.from_device(q)))
+    for r, q in outs[1:]:
+        assert np.array_equal(r, outs[0][0])
+        assert np.array_equal(q, outs[0][1])
+
+
+def test_autotuner_picks_a_shape(C):
+    import paper_1711_09272_amd as P
+    case = workloads.vortex(128, 0.01)
+    g = P.Grid.from_case(C, case)
+    assert g.tile_shape(case.params) == -1
+    q = g.to_device(case.q0)
+    P.step(C, g, case.params, q, 2)
+    assert g.tile_shape(case.params) in (0, 1, 2)
