@@ -277,3 +277,77 @@ def profile_step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float 
     ctx.check(lib().roeam_profile_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
                                        ctypes.byref(out), ctypes.byref(n)))
     return list(out), n.value
+
+
+# ---------------------------------------------------------------------------
+# batched and served solves
+# ---------------------------------------------------------------------------
+
+class Solve:
+    """One batched solve: grid, parameters, initial state, run length and output.
+
+    q0 / q_out: numpy arrays (host) or torch tensors (device) of shape
+    [4, ny, pitch]; they must stay alive until the ticket reports done."""
+
+    def __init__(self, grid: Grid, prm: Dict, q0, nsteps: int, t_end: float = 0.0, q_out=None):
+        self.grid, self.prm, self.nsteps, self.t_end = grid, prm, int(nsteps), float(t_end)
+        self.q0 = q0
+        if q_out is None:
+            q_out = np.zeros((4, grid.ny, grid.pitch))
+        self.q_out = q_out
+        self.ticket = None
+
+    @staticmethod
+    def _ptr(a, grid):
+        if isinstance(a, np.ndarray):
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (4, grid.ny, grid.pitch)
+            return ctypes.c_void_p(a.ctypes.data), 0
+        return _dev_ptr(a, grid), 1
+
+    def desc(self) -> SolveDesc:
+        d = SolveDesc()
+        d.grid = self.grid.h
+        d.params = params(self.prm)
+        d.q0, d.q0_on_device = self._ptr(self.q0, self.grid)
+        d.nsteps = self.nsteps
+        d.t_end = self.t_end
+        d.q_out, d.q_out_on_device = self._ptr(self.q_out, self.grid)
+        return d
+
+
+def padded(grid: Grid, q: np.ndarray) -> np.ndarray:
+    """Host state [4, ny, nx] -> the grid's padded layout [4, ny, pitch]."""
+    out = np.zeros((4, grid.ny, grid.pitch))
+    out[:, :, : grid.nx] = q
+    return out
+
+
+def batch_reserve(ctx: Context, nbytes: int):
+    ctx.check(lib().roeam_batch_reserve(ctx.h, int(nbytes)))
+
+
+def batch_submit(ctx: Context, solves) -> list:
+    solves = list(solves)
+    arr = (SolveDesc * len(solves))(*[s.desc() for s in solves])
+    tk = (ctypes.c_uint64 * len(solves))()
+    ctx.check(lib().roeam_batch_submit(ctx.h, len(solves), arr, tk))
+    for s, t in zip(solves, tk):
+        s.ticket = int(t)
+    return [int(t) for t in tk]
+
+
+def batch_run(ctx: Context, iterations: int = -1) -> int:
+    pend = ctypes.c_int()
+    ctx.check(lib().roeam_batch_run(ctx.h, int(iterations), ctypes.byref(pend)))
+    return pend.value
+
+
+def batch_poll(ctx: Context, ticket: int):
+    """(done, stats dict or None, status code); a solve that went non-physical
+    is done with code ENONPHYS."""
+    done = ctypes.c_int()
+    st = StepStats()
+    rc = lib().roeam_batch_poll(ctx.h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(st))
+    if rc not in (OK, ENONPHYS):
+        ctx.check(rc)
+    return bool(done.value), (st.as_dict() if done.value else None), rc

@@ -13,6 +13,13 @@ struct TileEntry {
     int solve, tx, ty, pad;
 };
 
+// Compact per-solve status copied to the host after batched iterations.
+struct SolveStatus {
+    double t, dt_last, rate_last;
+    long long steps;
+    int nonphys, done;
+};
+
 // Tile shapes of the stage kernel: 0 = 32x15 cells / 256 threads,
 // 1 = 16x15 / 128, 2 = 8x7 / 64.
 void tile_shape(int shape, int *tx, int *ty);
@@ -22,7 +29,10 @@ hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape,
                                double *r_out, hipStream_t st);
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
                               int shape, int stage, int p, int last, hipStream_t st);
-hipError_t launch_rate(const DevSolve &S, hipStream_t st);
+hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st);
+hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipStream_t st);
+hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,
+                                  hipStream_t st);
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
 hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);

@@ -347,8 +347,9 @@ __global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__
                                         nullptr);
 }
 
-// Explicit rate of a state (sets dt of the first step of a run) into st[0].
-__global__ __launch_bounds__(256) void k_rate(DevSolve S)
+// Explicit rate of a state (sets dt of the first step of a run) into the
+// rate words of parity p.
+__global__ __launch_bounds__(256) void k_rate(DevSolve S, int p)
 {
     __shared__ double sRed[4];
     double lmax = 0.0;
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(256) void k_rate(DevSolve S)
         else lmax = rmax(lmax, cell_rate(S, W, i, j));
     }
     const double m = block_max<256>(lmax, sRed);
-    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, 0, m);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, p, m);
 }
 
 __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps)
@@ -485,9 +486,71 @@ static int small_grid(long long n)
     return (int)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
 }
 
-hipError_t launch_rate(const DevSolve &S, hipStream_t st)
+hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rate, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_rate, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, p);
+    return hipGetLastError();
+}
+
+// Batched runs: per-solve status of the state at parity p, for the host's
+// retire decisions.
+__global__ void k_status(const Slot *__restrict__ slots, int n, int p, SolveStatus *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const Slot &z = slots[k];
+    const StepState &s = z.st[p];
+    SolveStatus o;
+    o.t = s.t;
+    o.steps = s.steps;
+    o.dt_last = z.dt_last;
+    o.rate_last = z.rate_last;
+    o.nonphys = z.nonphys;
+    o.done = z.nonphys || s.steps >= z.max_steps || (z.t_end > 0.0 && s.t >= z.t_end);
+    out[k] = o;
+}
+
+hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_status, dim3((n + 63) / 64), dim3(64), 0, st, slots, n, p, out);
+    return hipGetLastError();
+}
+
+// Forward Euler in a batch: copy each tile of qa back into q when the solve's
+// step ran; the rate words of parity p are cleared by each solve's first tile.
+template <int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_copy_back_batch(const DevSolve *__restrict__ solves,
+                                                        const TileEntry *__restrict__ tiles, int ntiles, int p)
+{
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    if (t >= ntiles) return;
+    const TileEntry te = tiles[t];
+    const DevSolve &S = solves[te.solve];
+    Slot &z = *S.slot;
+    const bool ran = z.st[p ^ 1].steps != z.st[p].steps;
+    if (te.tx == 0 && te.ty == 0 && threadIdx.x < kRateSlots) z.rate_bits[p][threadIdx.x] = 0ull;
+    if (!ran) return;
+    for (int c = threadIdx.x; c < TX * TY; c += NT) {
+        const int cj = c / TX, ci = c - cj * TX;
+        const int gi = te.tx * TX + ci, gj = te.ty * TY + cj;
+        if (gi >= S.nx || gj >= S.ny) continue;
+        const long long idx = (long long)gj * S.pitch + gi;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
+    }
+}
+
+hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,
+                                  hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int blocks = ((ntiles + 7) >> 3) << 3;
+    switch (shape) {
+    case 0: hipLaunchKernelGGL((k_copy_back_batch<32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, p); break;
+    case 1: hipLaunchKernelGGL((k_copy_back_batch<16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, p); break;
+    default: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, p); break;
+    }
     return hipGetLastError();
 }
 

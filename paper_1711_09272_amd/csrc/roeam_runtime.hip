@@ -12,72 +12,15 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/roeam.h"
-#include "roeam_internal.hpp"
+#include "roeam_host.hpp"
 
-using roeam::DevSolve;
-using roeam::Slot;
-
-namespace {
-
-constexpr int kStepsPerGraph = 50;
-
-struct GraphCache {
-    bool valid = false;
-    const double *q = nullptr;
-    roeam_params params{};
-    hipStream_t stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int chunk = 0;
-    int shape = 0;
-    void release()
-    {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-        valid = false;
-    }
-};
-
-} // namespace
-
-struct BatchEngine;
-
-struct roeam_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err = "no error";
-    BatchEngine *batch = nullptr;
-};
-
-struct roeam_grid {
-    roeam_ctx *ctx = nullptr;
-    int nx = 0, ny = 0;
-    long long pitch = 0;
-    int metric = 0;
-    double dx = 0, dy = 0;
-    double *d_xn = nullptr, *d_yn = nullptr;
-    int bc[4] = {0, 0, 0, 0};
-    double bcq[4][4] = {};
-    double *d_qa = nullptr, *d_qb = nullptr;
-    Slot *d_slot = nullptr;
-    Slot *h_slot = nullptr;  // pinned readback
-    GraphCache gc;
-    int shape_forced = -1;   // tile shape set by the caller, or -1
-    int shape_tuned[2][2] = {{-1, -1}, {-1, -1}};  // autotuned shape per [order-1][precision]
-    int final_parity = 0;    // parity of the step state after the last roeam_step
-    DevSolve *d_solve = nullptr;  // descriptor read by the single-grid kernels
-    DevSolve *h_solve = nullptr;  // pinned staging copy of the last descriptor sent
-    bool solve_valid = false;
-};
-
-static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg)
+roeam_status roeam_fail(roeam_ctx *ctx, roeam_status st, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
     return st;
 }
+
+static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg) { return roeam_fail(ctx, st, msg); }
 
 static roeam_status hip_fail(roeam_ctx *ctx, hipError_t e, const char *where)
 {
@@ -90,7 +33,7 @@ static roeam_status hip_fail(roeam_ctx *ctx, hipError_t e, const char *where)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
     } while (0)
 
-static roeam_status check_params(roeam_ctx *ctx, const roeam_params *p, bool need_cfl)
+roeam_status roeam_check_params(roeam_ctx *ctx, const roeam_params *p, bool need_cfl)
 {
     if (!p) return fail(ctx, ROEAM_EINVAL, "params is NULL");
     if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(ctx, ROEAM_EINVAL, "gamma must be > 1");
@@ -117,7 +60,7 @@ static void prim_of(double gamma, const double Q[4], double W[4])
     W[3] = (gamma - 1.0) * (Q[3] - 0.5 * rho * (u * u + v * v));
 }
 
-static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q)
+DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q, double *qa, double *qb, Slot *slot)
 {
     DevSolve S;
     std::memset(&S, 0, sizeof S);
@@ -150,10 +93,20 @@ static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q
     S.precision = p->precision;
     S.variant = p->variant;
     S.q = q;
-    S.qa = g->d_qa;
-    S.qb = g->d_qb;
-    S.slot = g->d_slot;
+    S.qa = qa;
+    S.qb = qb;
+    S.slot = slot;
     return S;
+}
+
+static roeam_status check_params(roeam_ctx *ctx, const roeam_params *p, bool need_cfl)
+{
+    return roeam_check_params(ctx, p, need_cfl);
+}
+
+static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q)
+{
+    return roeam_make_solve(g, p, q, g->d_qa, g->d_qb, g->d_slot);
 }
 
 // Make the grid's device descriptor equal to S.  Work already queued may
@@ -352,7 +305,7 @@ static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_para
     HIP_OK(ctx, hipEventCreate(&e0));
     HIP_OK(ctx, hipEventCreate(&e1));
     HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 1, s));
-    HIP_OK(ctx, roeam::launch_rate(S, s));
+    HIP_OK(ctx, roeam::launch_rate(S, 0, s));
     int best = 0;
     float best_ms = 1e30f;
     const int reps = 4;
@@ -450,7 +403,7 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
     // an even number of steps serves any nsteps: steps past the budget or
     // past t_end are inactive and their kernels exit at once.
     HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, t0, t_end, p->cfl, nsteps, s));
-    HIP_OK(ctx, roeam::launch_rate(S, s));
+    HIP_OK(ctx, roeam::launch_rate(S, 0, s));
     const bool use_graph = s != nullptr && nsteps > 1;
     long launched = 0;
     if (!use_graph) {
@@ -517,7 +470,7 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     for (auto &e : ev) HIP_OK(ctx, hipEventCreate(&e));
     roeam_status rc = ROEAM_OK;
     hipError_t e = roeam::launch_slot_init(g->d_slot, 1, t0, 0.0, p->cfl, nsteps, s);
-    if (e == hipSuccess) e = roeam::launch_rate(S, s);
+    if (e == hipSuccess) e = roeam::launch_rate(S, 0, s);
     for (long k = 0; k < nsteps && e == hipSuccess; ++k) {
         const int par = (int)(k & 1);
         for (int stg = 1; stg <= nst && e == hipSuccess; ++stg) {

@@ -1,0 +1,150 @@
+"""Batched and continuously batched solves on the GPU: every result must be
+bitwise equal to the same solve run alone through roeam_step (same kernels,
+same tile shape), whatever else shares the launches, and a solve that goes
+non-physical must not disturb the others."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import ctx, say, state_error
+from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    return ctx()
+
+
+def family():
+    """Uneven grids, all boundary kinds, both orders, both time schemes and
+    both precisions (so several work-list groups run side by side)."""
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 50))
+    cases = []
+    for n, steps in ((40, 9), (67, 14), (33, 5), (90, 11)):
+        cases.append(workloads.bump_case(n, rng, steps))
+    c = workloads.smooth_random_case(45, 29, 3, bc=(DIRICHLET, TRANSMISSIVE, SLIPWALL, SLIPWALL), nodes=True,
+                                     order=2, eps1=1.0, mach_ref=0.05)
+    c.nsteps = 7
+    cases.append(c)
+    c = workloads.sod(nx=120, ny=3)  # forward Euler, first order, stops at t_end
+    c.t_end = 0.05
+    cases.append(c)
+    c = workloads.bump_case(50, rng, 8)
+    c.params["precision"] = 1
+    cases.append(c)
+    return cases
+
+
+def run_alone(C, case):
+    import torch
+    import paper_1711_09272_amd as P
+    g = P.Grid.from_case(C, case)
+    g.set_tile_shape(0)
+    q = g.to_device(case.q0)
+    st = P.step(C, g, case.params, q, case.nsteps, 0.0, case.t_end)
+    torch.cuda.synchronize()
+    return g.from_device(q), st
+
+
+def submit_all(C, cases, grids=None):
+    import paper_1711_09272_amd as P
+    grids = grids or [P.Grid.from_case(C, c) for c in cases]
+    solves = [P.Solve(g, c.params, P.padded(g, c.q0), c.nsteps, c.t_end) for g, c in zip(grids, cases)]
+    P.batch_submit(C, solves)
+    return grids, solves
+
+
+def collect(C, solves):
+    import paper_1711_09272_amd as P
+    out = []
+    for s in solves:
+        done, st, rc = P.batch_poll(C, s.ticket)
+        assert done, s.ticket
+        out.append((s.q_out[:, :, : s.grid.nx].copy(), st, rc))
+    return out
+
+
+def test_batch_equals_single_runs(C):
+    import paper_1711_09272_amd as P
+    cases = family()
+    P.batch_reserve(C, 256 << 20)
+    say(f"[batch] {len(cases)} solves in one batch")
+    _, solves = submit_all(C, cases)
+    assert P.batch_run(C, -1) == 0
+    res = collect(C, solves)
+    for c, (q, st, rc) in zip(cases, res):
+        qa, sta = run_alone(C, c)
+        say(f"    {c.name}: steps {st['steps']} t {st['t']:.4e}")
+        assert rc == P.OK and st["steps"] == sta["steps"] and st["t"] == sta["t"]
+        assert np.array_equal(q, qa), c.name
+
+
+def test_batch_member_matches_oracle(C):
+    import paper_1711_09272_amd as P
+    cases = family()[:2]
+    P.batch_reserve(C, 64 << 20)
+    _, solves = submit_all(C, cases)
+    P.batch_run(C, -1)
+    for c, (q, st, rc) in zip(cases, collect(C, solves)):
+        q_or, st_or = oracle.run(c)
+        assert st["steps"] == st_or["steps"]
+        assert state_error(q, q_or) <= 1e-12
+
+
+def test_continuous_admission_and_arena_pressure(C):
+    """Solves submitted while others run join at the next iteration; an arena
+    that holds only two solves at a time still completes every solve, and each
+    result is bitwise the solve run alone."""
+    import paper_1711_09272_amd as P
+    cases = family()
+    grids = [P.Grid.from_case(C, c) for c in cases]
+    big = max(g.footprint() for g in grids)
+    P.batch_reserve(C, 2 * big + 4096)
+    _, first = submit_all(C, cases[:3], grids[:3])
+    P.batch_run(C, 3)
+    _, second = submit_all(C, cases[3:], grids[3:])
+    P.batch_run(C, 2)
+    _, third = submit_all(C, cases[:2], grids[:2])  # the same solves again, mid-flight
+    assert P.batch_run(C, -1) == 0
+    res = collect(C, first + second + third)
+    alone = [run_alone(C, c)[0] for c in cases]
+    for k, (q, st, rc) in enumerate(res):
+        ref = alone[k] if k < len(cases) else alone[k - len(cases)]
+        assert rc == P.OK
+        assert np.array_equal(q, ref), k
+
+
+def test_poisoned_request_is_isolated(C):
+    import paper_1711_09272_amd as P
+    cases = family()[:4]
+    bad = workloads.bump_case(40, np.random.Generator(np.random.PCG64(7)), 6)
+    bad.q0 = bad.q0.copy()
+    bad.q0[3, 5, 5] = -1.0  # negative energy: p < 0
+    P.batch_reserve(C, 128 << 20)
+    _, solves = submit_all(C, cases + [bad])
+    P.batch_run(C, -1)
+    res = collect(C, solves)
+    assert res[-1][2] == P.ENONPHYS and res[-1][1]["nonphys"]
+    for c, (q, st, rc) in zip(cases, res[:-1]):
+        assert rc == P.OK and np.array_equal(q, run_alone(C, c)[0])
+
+
+def test_batch_errors(C):
+    import paper_1711_09272_amd as P
+    case = workloads.bump_case(64, np.random.Generator(np.random.PCG64(1)), 3)
+    g = P.Grid.from_case(C, case)
+    P.batch_reserve(C, g.footprint() // 2)
+    with pytest.raises(P.RoeamError) as e:
+        P.batch_submit(C, [P.Solve(g, case.params, P.padded(g, case.q0), 3)])
+    assert e.value.code == P.ENOMEM
+    P.batch_reserve(C, 16 << 20)
+    bad = dict(case.params)
+    bad["cfl"] = -1.0
+    with pytest.raises(P.RoeamError):
+        P.batch_submit(C, [P.Solve(g, bad, P.padded(g, case.q0), 3)])
+    with pytest.raises(P.RoeamError) as e:
+        P.batch_poll(C, 999999)
+    assert e.value.code == P.ENOTFOUND
