@@ -101,6 +101,9 @@ def main():
                     help="steps timed kernel by kernel with HIP events for the roofline object")
     ap.add_argument("--cpu-sample-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="for rocprofv3 --pmc: only --profile-steps steps of directly launched stage "
+                         "kernels, then a plain 256 MiB device copy as the counter reference; no timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the Roe-AM step here is a single-GPU build "
@@ -117,6 +120,16 @@ def main():
     q = grid.to_device(case.q0)
     prm = case.params
     stream = torch.cuda.current_stream()
+
+    if args.counter_run:
+        P.profile_step(ctx, grid, prm, q, args.profile_steps)
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": args.workload, "cells": cells, "profile_steps": args.profile_steps,
+                          "copy_bytes": src.numel() * 8, "tile_shape": grid.tile_shape(prm)}), flush=True)
+        return
 
     # warmup (also captures the step graphs)
     P.step(ctx, grid, prm, q, args.warmup, sync=True)

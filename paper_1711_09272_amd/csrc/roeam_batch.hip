@@ -97,7 +97,7 @@ struct Request {
 };
 
 struct Group {
-    int order = 2, precision = 0, time_scheme = 1, shape = 0;
+    int order = 2, precision = 0, time_scheme = 1, metric = 0, shape = 0;
     std::vector<TileEntry> tiles;
     TileEntry *d_tiles = nullptr;
     TileEntry *h_tiles = nullptr;  // pinned staging of the last upload
@@ -129,14 +129,17 @@ struct BatchEngine {
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
     long iter = 0;
-    Group groups[8];                // (order-1, precision, time_scheme)
+    Group groups[16];               // (order-1, precision, time_scheme, metric)
     bool set_changed = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
 };
 
-static int group_id(const roeam_params &p) { return (p.order - 1) * 4 + p.precision * 2 + p.time_scheme; }
+static int group_id(const roeam_params &p, int metric)
+{
+    return (p.order - 1) * 8 + p.precision * 4 + p.time_scheme * 2 + metric;
+}
 
 static void release_engine(BatchEngine *b)
 {
@@ -312,12 +315,12 @@ static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
         if (!n) continue;
         hipError_t e;
         if (G.time_scheme == 0) {
-            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.shape, 1, p, 1, s);
+            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 1, p, 1, s);
             if (e == hipSuccess) e = roeam::launch_copy_back_batch(b->d_solves, G.d_tiles, n, G.shape, p, s);
         } else {
-            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.shape, 1, p, 0, s);
-            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.shape, 2, p, 0, s);
-            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.shape, 3, p, 1, s);
+            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 1, p, 0, s);
+            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 2, p, 0, s);
+            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 3, p, 1, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -393,11 +396,12 @@ roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes)
     b->alloc.reset(arena_bytes);
     b->by_idx.assign(kMaxSolves, 0);
     for (int i = kMaxSolves - 1; i >= 0; --i) b->free_idx.push_back(i);
-    for (int gidx = 0; gidx < 8; ++gidx) {
+    for (int gidx = 0; gidx < 16; ++gidx) {
         Group &G = b->groups[gidx];
-        G.order = gidx / 4 + 1;
-        G.precision = (gidx / 2) & 1;
-        G.time_scheme = gidx & 1;
+        G.order = gidx / 8 + 1;
+        G.precision = (gidx / 4) & 1;
+        G.time_scheme = (gidx / 2) & 1;
+        G.metric = gidx & 1;
         G.shape = 0;
     }
     ctx->batch = b;
@@ -424,7 +428,7 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
         Request r;
         r.d = descs[i];
         r.bytes = roeam_batch_footprint(descs[i].grid);
-        r.group = group_id(descs[i].params);
+        r.group = group_id(descs[i].params, descs[i].grid->metric);
         b->reqs.emplace(tk, r);
         b->queue.push_back(tk);
         tickets_out[i] = tk;

@@ -67,9 +67,15 @@ struct DevSolve {
 // ---------------------------------------------------------------------------
 // scalar helpers
 // ---------------------------------------------------------------------------
-template <typename R> __device__ __forceinline__ R sgn(R x) { return (R)((x > (R)0) - (x < (R)0)); }
-template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
-template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+template <typename R> __device__ __forceinline__ R sgn(R x) { return x > (R)0 ? (R)1 : (x < (R)0 ? (R)-1 : (R)0); }
+// min/max/abs map to single instructions (v_min_f64, v_max_f64, source
+// modifiers); the operands here are never NaN.
+__device__ __forceinline__ double rmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ double rmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float rmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float rmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double rabs(double a) { return fabs(a); }
+__device__ __forceinline__ float rabs(float a) { return fabsf(a); }
 
 // Reciprocal, quotient and reciprocal square root.  FP64: Newton-Raphson
 // refinement (two iterations) of the hardware estimates v_rcp_f64 and
@@ -100,10 +106,14 @@ __device__ __forceinline__ double rsq_nr(double x)
 }
 __device__ __forceinline__ double rcpR(double b) { return rcp_nr(b); }
 __device__ __forceinline__ double rsqR(double x) { return rsq_nr(x); }
-__device__ __forceinline__ double sqrtR(double x) { return sqrt(x); }
+// square root of a positive operand as x rsq(x)
+__device__ __forceinline__ double sqrtR(double x) { return x * rsq_nr(x); }
 __device__ __forceinline__ float rcpR(float b) { return __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ float rsqR(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
+// square root of a non-negative operand (zero allowed)
+__device__ __forceinline__ double sqrt0R(double x) { return x > 0.0 ? x * rsq_nr(x) : 0.0; }
+__device__ __forceinline__ float sqrt0R(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Eq. (98): f(phi) = min(phi sqrt(4 + (1 - phi^2)^2) / (1 + phi^2), 1), with
 // sqrt(A) / B evaluated as A rsq(A B^2).
@@ -127,7 +137,10 @@ template <typename R> __device__ __forceinline__ R pow8(R x)
 // density ratios, each taken below one.
 __device__ __forceinline__ double detector_P(double pA, double rA, double pB, double rB)
 {
-    return rmin(div_nr(rmin(pA, pB), rmax(pA, pB)), div_nr(rmin(rA, rB), rmax(rA, rB)));
+    // the smaller of the two ratios, chosen by cross-multiplication, one division
+    const double pn = rmin(pA, pB), pd = rmax(pA, pB), rn = rmin(rA, rB), rd = rmax(rA, rB);
+    const bool use_p = pn * rd <= rn * pd;
+    return div_nr(use_p ? pn : rn, use_p ? pd : rd);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,18 +163,20 @@ __device__ __forceinline__ void load_prim(const DevSolve &S, const double *__res
     to_prim(S.gm1, q[idx], q[S.plane + idx], q[2 * S.plane + idx], q[3 * S.plane + idx], W);
 }
 
+template <int METRIC>
 __device__ __forceinline__ void xface_vec(const DevSolve &S, int i, int j, double &sx, double &sy)
 {
-    if (S.metric == 0) { sx = S.dy; sy = 0.0; return; }
+    if (METRIC == 0) { sx = S.dy; sy = 0.0; return; }
     long long nxn = S.nx + 1;
     double ddx = S.xn[(long long)(j + 1) * nxn + i] - S.xn[(long long)j * nxn + i];
     double ddy = S.yn[(long long)(j + 1) * nxn + i] - S.yn[(long long)j * nxn + i];
     sx = ddy;
     sy = -ddx;
 }
+template <int METRIC>
 __device__ __forceinline__ void yface_vec(const DevSolve &S, int i, int j, double &sx, double &sy)
 {
-    if (S.metric == 0) { sx = 0.0; sy = S.dx; return; }
+    if (METRIC == 0) { sx = 0.0; sy = S.dx; return; }
     long long nxn = S.nx + 1;
     double ddx = S.xn[(long long)j * nxn + i + 1] - S.xn[(long long)j * nxn + i];
     double ddy = S.yn[(long long)j * nxn + i + 1] - S.yn[(long long)j * nxn + i];
@@ -170,9 +185,10 @@ __device__ __forceinline__ void yface_vec(const DevSolve &S, int i, int j, doubl
 }
 // Unit normal and length of a face vector; axis-aligned faces of uniform
 // grids are exact.
+template <int METRIC>
 __device__ __forceinline__ void unit_normal(const DevSolve &S, double sx, double sy, double &nx, double &ny, double &len)
 {
-    if (S.metric == 0) {
+    if (METRIC == 0) {
         if (sy == 0.0) { nx = 1.0; ny = 0.0; len = sx; }
         else { nx = 0.0; ny = 1.0; len = sy; }
         return;
@@ -181,9 +197,10 @@ __device__ __forceinline__ void unit_normal(const DevSolve &S, double sx, double
     nx = sx / len;
     ny = sy / len;
 }
+template <int METRIC>
 __device__ __forceinline__ double cell_area(const DevSolve &S, int i, int j)
 {
-    if (S.metric == 0) return S.area;
+    if (METRIC == 0) return S.area;
     long long nxn = S.nx + 1;
     const double *x = S.xn, *y = S.yn;
     long long r0 = (long long)j * nxn, r1 = (long long)(j + 1) * nxn;
@@ -203,6 +220,7 @@ __device__ __forceinline__ void reflect(double W[4], double nx, double ny)
 
 // Primitive state of cell (i, j) where j is inside the grid and i may lie in
 // the two ghost columns on either side.
+template <int METRIC>
 __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
 {
     if (i >= 0 && i < S.nx) { load_prim(S, q, i, j, W); return; }
@@ -221,17 +239,18 @@ __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__
     load_prim(S, q, is, j, W);
     if (kind == BC_SLIPWALL) {
         double sx, sy, nx, ny, len;
-        xface_vec(S, i < 0 ? 0 : S.nx, j, sx, sy);
-        unit_normal(S, sx, sy, nx, ny, len);
+        xface_vec<METRIC>(S, i < 0 ? 0 : S.nx, j, sx, sy);
+        unit_normal<METRIC>(S, sx, sy, nx, ny, len);
         reflect(W, nx, ny);
     }
 }
 
 // Primitive state of any cell within two layers of the grid: the x rule, then
 // the y rule (which also defines the corners).
+template <int METRIC>
 __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
 {
-    if (j >= 0 && j < S.ny) { fetch_prim_x(S, q, i, j, W); return; }
+    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC>(S, q, i, j, W); return; }
     const bool south = j < 0;
     const int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
     if (kind == BC_DIRICHLET) {
@@ -243,12 +262,12 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
     if (kind == BC_PERIODIC) js = j < 0 ? j + S.ny : j - S.ny;
     else if (kind == BC_TRANSMISSIVE) js = j < 0 ? 0 : S.ny - 1;
     else js = j < 0 ? -j - 1 : 2 * S.ny - 1 - j;
-    fetch_prim_x(S, q, i, js, W);
+    fetch_prim_x<METRIC>(S, q, i, js, W);
     if (kind == BC_SLIPWALL) {
         int ic = i < 0 ? 0 : (i > S.nx - 1 ? S.nx - 1 : i);
         double sx, sy, nx, ny, len;
-        yface_vec(S, ic, j < 0 ? 0 : S.ny, sx, sy);
-        unit_normal(S, sx, sy, nx, ny, len);
+        yface_vec<METRIC>(S, ic, j < 0 ? 0 : S.ny, sx, sy);
+        unit_normal<METRIC>(S, sx, sy, nx, ny, len);
         reflect(W, nx, ny);
     }
 }
@@ -294,8 +313,8 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     // Mach numbers, Eqs. (93)-(94): M_K = |V_K| / c_K, c_K^2 = gamma p_K / rho_K
     const R c2L = (R)(S.gamma * pL * iL), c2R = (R)(S.gamma * pR * iR);
     const R icLR = rcpR(c2L * c2R);
-    const R M = (R)0.5 * (sqrtR((R)qL * c2R * icLR) + sqrtR((R)qR * c2L * icLR));
-    const R absU = U < (R)0 ? -U : U;
+    const R M = (R)0.5 * (sqrt0R((R)qL * c2R * icLR) + sqrt0R((R)qR * c2L * icLR));
+    const R absU = rabs(U);
     const R Mbar = absU * ic;
     const R fM = fswitch(M), f8M = pow8(fM);
     const R fMbar = fswitch(Mbar), f8Mbar = pow8(fMbar);
@@ -309,32 +328,30 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     const R U_2ct = U * rX;        // U / (2 c~)
     const R Ut = (R)0.5 * ((R)1 + theta) * U;
 
-    // expansion-shock fix, Eq. (92)
+    // expansion-shock fix, Eq. (92); sign(U + c) - sign(U - c) is 2 for |U| < c,
+    // 1 for |U| = c and 0 otherwise (the sums are exact near their zeros)
     const R wexp = (S.variant & V_EXPFIX_F8) ? f8Mbar : fMbar;
-    R absUp = absU - wexp * (sgn(U + c) - sgn(U - c)) * rmax((R)0, dU) * (R)0.25;
+    const R quarter_term = absU < c ? (R)0.5 : (absU == c ? (R)0.25 : (R)0);
+    R absUp = absU - wexp * rmax((R)0, dU) * quarter_term;
     if (S.variant & V_CLAMP_UPRIME) absUp = rmax(absUp, (R)0);
 
     // basic upwind dissipation xi, Eq. (86) with the Eq. (68) gate
     const R gate = (S.variant & V_XI_UNGATED) ? (R)1 : (R)1 - f8Mbar;
-    const R ULR = (R)(0.5 * (UR + UL));
-    const R xi_pos = (ULR < (R)0 ? -ULR : ULR) + gate * ((R)0.5 * dU);
+    const R xi_pos = (R)rabs(0.5 * (UR + UL)) + gate * ((R)0.5 * dU);
     R xi;
     if (S.eps1 != 0.0) {
         // modified entropy fix f_ef (Eq. 102) and rotated speed f_rr (Eqs. 103-109)
         const R fef = (R)S.eps2 * c;
         const R du = (R)(uR - uL), dv = (R)(vR - vL);
         const R dV2 = du * du + dv * dv;
-        R n1x = (R)nx, n1y = (R)ny;
-        if (!(dV2 < (R)S.dv_min2 || dV2 == (R)0)) {
-            const R idV = rsqR(dV2);
-            n1x = du * idV;
-            n1y = dv * idV;
-        }
+        const bool use_n = dV2 < (R)S.dv_min2 || dV2 == (R)0;
+        const R idV = rsqR(use_n ? (R)1 : dV2);
+        const R n1x = use_n ? (R)nx : du * idV, n1y = use_n ? (R)ny : dv * idV;
         const R a1U1 = (n1x * (R)nx + n1y * (R)ny) * (n1x * u + n1y * v);
         // unit n2 along (n1 x n) x n1 = s (-n1y, n1x): alpha2 U2 = |s| (n1x v - n1y u) up to sign
         const R sz = n1x * (R)ny - n1y * (R)nx;
         const R a2U2 = sz * (n1x * v - n1y * u);
-        const R frr = (a1U1 < (R)0 ? -a1U1 : a1U1) + (a2U2 < (R)0 ? -a2U2 : a2U2);
+        const R frr = rabs(a1U1) + rabs(a2U2);
         const R xi_fix = (R)S.eps1 * ((R)1 - f8Mbar) * f8M * rmin(fef, frr);
         xi = rmax(xi_pos, xi_fix);
     } else {
@@ -346,7 +363,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     const R mUc = rmin(absUp, c);
     const R dpp = sU * mUc * dp * ic;
     const R dpu = ((R)1 - s1 + s1 * fM) * rmax((R)0, c - absUp) * rho * dU;
-    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(Ut < (R)0 ? -Ut : Ut, ct));
+    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(rabs(Ut), ct));
     const R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
     const R dUu = (R)0.5 * sU * mUc * dU * ic;
 
@@ -364,6 +381,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
 
 // Explicit rate of one cell for the time-step rule:
 // (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega, ce = c / sqrt(theta_cell).
+template <int METRIC>
 __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4], int i, int j)
 {
     const double c2 = S.gamma * W[3] * rcp_nr(W[0]);
@@ -371,21 +389,21 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
     const double theta = rmin(rmax(S.mr2, M2), 1.0);
     const double ce = sqrt(c2 * rcp_nr(theta));
     double six, siy, sjx, sjy, li, lj;
-    if (S.metric == 0) {
+    if (METRIC == 0) {
         six = S.dy; siy = 0.0; sjx = 0.0; sjy = S.dx; li = S.dy; lj = S.dx;
     } else {
         double ax, ay, bx, by;
-        xface_vec(S, i, j, ax, ay);
-        xface_vec(S, i + 1, j, bx, by);
+        xface_vec<METRIC>(S, i, j, ax, ay);
+        xface_vec<METRIC>(S, i + 1, j, bx, by);
         six = 0.5 * (ax + bx); siy = 0.5 * (ay + by);
-        yface_vec(S, i, j, ax, ay);
-        yface_vec(S, i, j + 1, bx, by);
+        yface_vec<METRIC>(S, i, j, ax, ay);
+        yface_vec<METRIC>(S, i, j + 1, bx, by);
         sjx = 0.5 * (ax + bx); sjy = 0.5 * (ay + by);
         li = sqrt(six * six + siy * siy);
         lj = sqrt(sjx * sjx + sjy * sjy);
     }
     const double sum = fabs(W[1] * six + W[2] * siy) + ce * li + fabs(W[1] * sjx + W[2] * sjy) + ce * lj;
-    return S.metric == 0 ? sum * S.inv_area : sum / cell_area(S, i, j);
+    return METRIC == 0 ? sum * S.inv_area : sum / cell_area<METRIC>(S, i, j);
 }
 
 __device__ __forceinline__ bool physical(const double W[4])

@@ -28,7 +28,7 @@ int tile_shape_count();
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                double *r_out, hipStream_t st);
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int shape, int stage, int p, int last, hipStream_t st);
+                              int metric, int shape, int stage, int p, int last, hipStream_t st);
 hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipStream_t st);
 hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,

@@ -16,10 +16,11 @@
 
 namespace roeam {
 
+// minmod(a, b): 0 when the slopes differ in sign, else the one nearer zero,
+// written as max(0, min(a, b)) + min(0, max(a, b)) (four min/max and an add).
 __device__ __forceinline__ double minmod(double a, double b)
 {
-    if (a * b <= 0.0) return 0.0;
-    return sgn(a) * rmin(fabs(a), fabs(b));
+    return rmax(0.0, rmin(a, b)) + rmin(0.0, rmax(a, b));
 }
 
 template <int ORDER>
@@ -32,8 +33,9 @@ __device__ __forceinline__ void reconstruct(const double m2[4], const double m1[
             WL[k] = m1[k];
             WR[k] = p0[k];
         } else {
-            WL[k] = m1[k] + 0.5 * minmod(m1[k] - m2[k], p0[k] - m1[k]);
-            WR[k] = p0[k] - 0.5 * minmod(p0[k] - m1[k], p1[k] - p0[k]);
+            const double d1 = p0[k] - m1[k];
+            WL[k] = m1[k] + 0.5 * minmod(m1[k] - m2[k], d1);
+            WR[k] = p0[k] - 0.5 * minmod(d1, p1[k] - p0[k]);
         }
     }
 }
@@ -98,7 +100,7 @@ __device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, dou
 // stage into q.  p: step parity.  last: this stage ends the step (reduce the
 // rate of the new state into st[p^1]); for stage 0 the rate of the input is
 // reduced into st[0].
-template <int ORDER, int PREC, int TX, int TY, int NT>
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
 __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int p, int last,
                                            int first_block, double *__restrict__ r_out)
 {
@@ -158,7 +160,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             // cells past the ghost layers of a ragged tile feed no valid face
             gi = gi > nx + 1 ? nx + 1 : gi;
             gj = gj > ny + 1 ? ny + 1 : gj;
-            fetch_prim(S, qin, gi, gj, W);
+            fetch_prim<METRIC>(S, qin, gi, gj, W);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) sW[k][ly][lx] = W[k];
@@ -207,8 +209,8 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
         reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
         double sx, sy, nxv, nyv, len;
-        xface_vec(S, gi, gj, sx, sy);
-        unit_normal(S, sx, sy, nxv, nyv, len);
+        xface_vec<METRIC>(S, gi, gj, sx, sy);
+        unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
         roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
 #pragma unroll
         for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
@@ -254,8 +256,8 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
         reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
         double sx, sy, nxv, nyv, len;
-        yface_vec(S, gi, gj, sx, sy);
-        unit_normal(S, sx, sy, nxv, nyv, len);
+        yface_vec<METRIC>(S, gi, gj, sx, sy);
+        unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
         roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
 #pragma unroll
         for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
@@ -270,7 +272,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         const int cj = c / TX, ci = c - cj * TX;
         const int gi = i0 + ci, gj = j0 + cj;
         if (c >= TX * TY || gi >= nx || gj >= ny) continue;
-        const double iom = S.metric == 0 ? S.inv_area : rcp_nr(cell_area(S, gi, gj));
+        const double iom = METRIC == 0 ? S.inv_area : rcp_nr(cell_area<METRIC>(S, gi, gj));
         double Rv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sF[k][(cj + 1) * TX + ci] - sF[k][cj * TX + ci])) * iom;
@@ -281,7 +283,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             if (last) {
                 double W[4] = {sW[0][cj + HL][ci + HL], sW[1][cj + HL][ci + HL], sW[2][cj + HL][ci + HL],
                                sW[3][cj + HL][ci + HL]};
-                lmax = rmax(lmax, cell_rate(S, W, gi, gj));
+                lmax = rmax(lmax, cell_rate<METRIC>(S, W, gi, gj));
             }
             continue;
         }
@@ -305,7 +307,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         if (!physical(W)) {
             atomicOr(&z.nonphys, 1);
         } else if (last) {
-            lmax = rmax(lmax, cell_rate(S, W, gi, gj));
+            lmax = rmax(lmax, cell_rate<METRIC>(S, W, gi, gj));
         }
     }
     if (last) {
@@ -323,7 +325,7 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return (b & 7) * chunk + (b >> 3);
 }
 
-template <int ORDER, int PREC, int TX, int TY, int NT>
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
                                                      double *r_out)
 {
@@ -332,10 +334,10 @@ __global__ __launch_bounds__(NT) void k_stage_single(const DevSolve *__restrict_
     const int nt = txs * tys;
     const int t = xcd_tile(blockIdx.x, nt);
     if (t >= nt) return;
-    stage_tile<ORDER, PREC, TX, TY, NT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
+    stage_tile<ORDER, PREC, METRIC, TX, TY, NT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
 }
 
-template <int ORDER, int PREC, int TX, int TY, int NT>
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__ solves,
                                                     const TileEntry *__restrict__ tiles, int ntiles, int stage,
                                                     int p, int last)
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__
     const int t = xcd_tile(blockIdx.x, ntiles);
     if (t >= ntiles) return;
     const TileEntry te = tiles[t];
-    stage_tile<ORDER, PREC, TX, TY, NT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
+    stage_tile<ORDER, PREC, METRIC, TX, TY, NT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
                                         nullptr);
 }
 
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(256) void k_rate(DevSolve S, int p)
         double W[4];
         load_prim(S, S.q, i, j, W);
         if (!physical(W)) atomicOr(&S.slot->nonphys, 1);
-        else lmax = rmax(lmax, cell_rate(S, W, i, j));
+        else lmax = rmax(lmax, S.metric == 0 ? cell_rate<0>(S, W, i, j) : cell_rate<1>(S, W, i, j));
     }
     const double m = block_max<256>(lmax, sRed);
     if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, p, m);
@@ -425,7 +427,7 @@ void tile_shape(int shape, int *tx, int *ty)
 
 int tile_shape_count() { return 3; }
 
-template <int ORDER, int PREC>
+template <int ORDER, int PREC, int METRIC>
 static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                 double *r_out, hipStream_t st)
 {
@@ -433,10 +435,18 @@ static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape
     const int nt = ((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty);
     const int blocks = ((nt + 7) >> 3) << 3;
     switch (shape) {
-    case 0: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, dS, stage, p, last, r_out); break;
-    case 1: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, dS, stage, p, last, r_out); break;
-    default: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, dS, stage, p, last, r_out); break;
+    case 0: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, dS, stage, p, last, r_out); break;
+    case 1: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, dS, stage, p, last, r_out); break;
+    default: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, dS, stage, p, last, r_out); break;
     }
+}
+
+template <int ORDER, int PREC>
+static void launch_single_metric(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                                 double *r_out, hipStream_t st)
+{
+    if (S.metric == 0) launch_single_shape<ORDER, PREC, 0>(dS, S, shape, stage, p, last, r_out, st);
+    else launch_single_shape<ORDER, PREC, 1>(dS, S, shape, stage, p, last, r_out, st);
 }
 
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
@@ -444,38 +454,46 @@ hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape,
 {
     if (shape < 0 || shape > 2) return hipErrorInvalidValue;
     if (S.order == 1) {
-        if (S.precision == 0) launch_single_shape<1, 0>(dS, S, shape, stage, p, last, r_out, st);
-        else launch_single_shape<1, 1>(dS, S, shape, stage, p, last, r_out, st);
+        if (S.precision == 0) launch_single_metric<1, 0>(dS, S, shape, stage, p, last, r_out, st);
+        else launch_single_metric<1, 1>(dS, S, shape, stage, p, last, r_out, st);
     } else {
-        if (S.precision == 0) launch_single_shape<2, 0>(dS, S, shape, stage, p, last, r_out, st);
-        else launch_single_shape<2, 1>(dS, S, shape, stage, p, last, r_out, st);
+        if (S.precision == 0) launch_single_metric<2, 0>(dS, S, shape, stage, p, last, r_out, st);
+        else launch_single_metric<2, 1>(dS, S, shape, stage, p, last, r_out, st);
     }
     return hipGetLastError();
 }
 
-template <int ORDER, int PREC>
+template <int ORDER, int PREC, int METRIC>
 static void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int stage, int p,
                                int last, hipStream_t st)
 {
     const int blocks = ((ntiles + 7) >> 3) << 3;
     switch (shape) {
-    case 0: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, p, last); break;
-    case 1: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, stage, p, last); break;
-    default: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    case 0: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    case 1: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, stage, p, last); break;
+    default: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, stage, p, last); break;
     }
 }
 
+template <int ORDER, int PREC>
+static void launch_batch_metric(const DevSolve *solves, const TileEntry *tiles, int ntiles, int metric, int shape,
+                                int stage, int p, int last, hipStream_t st)
+{
+    if (metric == 0) launch_batch_shape<ORDER, PREC, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
+    else launch_batch_shape<ORDER, PREC, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
+}
+
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int shape, int stage, int p, int last, hipStream_t st)
+                              int metric, int shape, int stage, int p, int last, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     if (shape < 0 || shape > 2) return hipErrorInvalidValue;
     if (order == 1) {
-        if (precision == 0) launch_batch_shape<1, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
-        else launch_batch_shape<1, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
+        if (precision == 0) launch_batch_metric<1, 0>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
+        else launch_batch_metric<1, 1>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
     } else {
-        if (precision == 0) launch_batch_shape<2, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
-        else launch_batch_shape<2, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
+        if (precision == 0) launch_batch_metric<2, 0>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
+        else launch_batch_metric<2, 1>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
     }
     return hipGetLastError();
 }
