@@ -1,16 +1,18 @@
 #!/usr/bin/env python
 """Throughput of the Roe-AM step on one MI355X: Gcell-updates/s per RK stage.
 
-Workload (default): the low-Mach isentropic vortex on a 256 x 256 periodic
-grid, free-stream Mach 0.01, FP64, MUSCL-minmod + SSP-RK3, full Roe-AM
-(detector on, eps1 = 1, eps2 = 0.05), CFL 0.4 with the c / sqrt(theta)
-time-step rule; seeded +-1e-6 pressure checkerboard.  One bench step is one
-SSP-RK3 time step (three fused stage kernels plus the on-device dt kernel) of
-the whole grid, launched from captured HIP graphs.  Inputs are resident in
-HBM before the timed region.
+Default workload (the low-Mach vortex configuration): two 256 x 256 periodic
+grids, free-stream Mach 0.01 and 0.001, FP64, MUSCL-minmod + SSP-RK3, full
+Roe-AM (detector on, eps1 = 1, eps2 = 0.05), CFL 0.4 with the c / sqrt(theta)
+time-step rule, seeded +-1e-6 pressure checkerboard.  Both grids advance
+together through the batch engine (one batched stage kernel per RK stage, each
+grid with its own dt); one bench step is one SSP-RK3 step of both grids.
+Inputs are resident in HBM before the timed region.  `--workload vortexN`
+runs one N x N grid (M = 0.01) through roeam_step instead.
 
-Prints one JSON line.  Extra legs: the roofline of the stage kernel (HIP
-events around each stage launch), and the CPU oracle on a bounded sample.
+Prints one JSON line.  Extra legs: the roofline of the stage kernel (HIP events
+around each stage launch of the same grid launched alone), and the CPU oracle
+on a bounded sample.
 """
 from __future__ import annotations
 
@@ -61,33 +63,73 @@ def measured_traffic(workload: str):
         return None
 
 
-def make_case(workload: str, precision: int):
+def make_cases(workload: str, precision: int):
+    """The grids of a workload (list) and whether they run as one batch."""
     import workloads
-    if workload == "vortex256":
-        case = workloads.vortex(256, 0.01)
+    if workload == "vortex256pair":
+        cases = [workloads.vortex(256, 0.01), workloads.vortex(256, 0.001)]
+        batched = True
     elif workload.startswith("vortex"):
-        n = int(workload[len("vortex"):])
-        case = workloads.vortex(n, 0.01)
+        cases = [workloads.vortex(int(workload[len("vortex"):]), 0.01)]
+        batched = False
     else:
         raise SystemExit(f"unknown workload {workload}")
-    case.params["precision"] = precision
-    return case
+    for c in cases:
+        c.params["precision"] = precision
+    return cases, batched
 
 
-def cpu_baseline(case, sample_steps: int):
+def cpu_baseline(cases, sample_steps: int):
     import oracle
     t0 = time.perf_counter()
-    _, st = oracle.run(case, nsteps=sample_steps)
+    updates = 0
+    for case in cases:
+        _, st = oracle.run(case, nsteps=sample_steps)
+        updates += case.nx * case.ny * 3 * st["steps"]
     dt = time.perf_counter() - t0
-    cells = case.nx * case.ny
+    names = " + ".join(f"{c.nx}x{c.ny} M={c.params['mach_ref']:g}" for c in cases)
     return {
-        "value": cells * 3 * st["steps"] / dt / 1e9,
+        "value": updates / dt / 1e9,
         "unit": "Gcell-updates/s per RK stage",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"first {st['steps']} SSP-RK3 steps of the same {case.nx}x{case.ny} case "
-                  f"({cells * 3 * st['steps']} cell-stage updates, {dt:.1f} s, single thread)",
+        "sample": f"first {sample_steps} SSP-RK3 steps of each grid of the same workload ({names}; "
+                  f"{updates} cell-stage updates, {dt:.1f} s, single thread)",
     }
+
+
+def timed_batch(ctx, grids, cases, steps, warmup, stream):
+    """Advance every grid `steps` steps together through the batch engine;
+    returns GPU ms between events around submission and completion."""
+    import torch
+    import paper_1711_09272_amd as P
+    # tune the tile shape on the first grid (a zero-step run); the batch uses it
+    P.step(ctx, grids[0], cases[0].params, grids[0].to_device(cases[0].q0), 0)
+    q0 = [g.to_device(c.q0) for g, c in zip(grids, cases)]
+    qout = [g.empty_state() for g in grids]
+    P.batch_reserve(ctx, sum(g.footprint() for g in grids) + (1 << 20))
+
+    def run(n):
+        solves = [P.Solve(g, c.params, q, n, 0.0, o) for g, c, q, o in zip(grids, cases, q0, qout)]
+        P.batch_submit(ctx, solves)
+        P.batch_run(ctx, -1)
+        return solves
+
+    run(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solves = run(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s in solves:
+        done, st, rc = P.batch_poll(ctx, s.ticket)
+        if not done or rc != P.OK or st["steps"] != steps:
+            raise SystemExit(f"bench batch run failed: {done} {st} {rc}")
+    return ev0.elapsed_time(ev1), wall
 
 
 def main():
@@ -95,11 +137,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="vortex256")
+    ap.add_argument("--workload", default="vortex256pair",
+                    help="vortex256pair (both Mach numbers, batched) or vortexN (one N x N grid)")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps timed kernel by kernel with HIP events for the roofline object")
-    ap.add_argument("--cpu-sample-steps", type=int, default=150)
+    ap.add_argument("--cpu-sample-steps", type=int, default=75)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counter-run", action="store_true",
                     help="for rocprofv3 --pmc: only --profile-steps steps of directly launched stage "
@@ -113,10 +156,11 @@ def main():
     import torch
     import paper_1711_09272_amd as P
 
-    case = make_case(args.workload, args.precision)
-    cells = case.nx * case.ny
+    cases, batched = make_cases(args.workload, args.precision)
+    cells = sum(c.nx * c.ny for c in cases)
     ctx = P.Context(0)
-    grid = P.Grid.from_case(ctx, case)
+    grids = [P.Grid.from_case(ctx, c) for c in cases]
+    case, grid = cases[0], grids[0]
     q = grid.to_device(case.q0)
     prm = case.params
     stream = torch.cuda.current_stream()
@@ -127,35 +171,38 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"counter_run": args.workload, "cells": cells, "profile_steps": args.profile_steps,
-                          "copy_bytes": src.numel() * 8, "tile_shape": grid.tile_shape(prm)}), flush=True)
+        print(json.dumps({"counter_run": args.workload, "cells": case.nx * case.ny,
+                          "profile_steps": args.profile_steps, "copy_bytes": src.numel() * 8,
+                          "tile_shape": grid.tile_shape(prm)}), flush=True)
         return
 
-    # warmup (also captures the step graphs)
-    P.step(ctx, grid, prm, q, args.warmup, sync=True)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    P.step(ctx, grid, prm, q, args.steps, t0=0.0, t_end=0.0, sync=False)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    st = P.last_stats(ctx, grid)
-    if st["nonphys"] or st["steps"] != args.steps:
-        raise SystemExit(f"bench run failed: {st}")
+    if batched:
+        gpu_ms, wall = timed_batch(ctx, grids, cases, args.steps, args.warmup, stream)
+    else:
+        # warmup (also tunes the tile shape and captures the step graphs)
+        P.step(ctx, grid, prm, q, args.warmup, sync=True)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        P.step(ctx, grid, prm, q, args.steps, t0=0.0, t_end=0.0, sync=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        st = P.last_stats(ctx, grid)
+        if st["nonphys"] or st["steps"] != args.steps:
+            raise SystemExit(f"bench run failed: {st}")
     ms_per_step = gpu_ms / args.steps
-    shape = grid.tile_shape(prm)
     value = cells * 3 * args.steps / (gpu_ms / 1e3) / 1e9
 
-    # roofline of the stage kernel: HIP events around every stage launch
+    # roofline of the stage kernel: HIP events around every stage launch of the
+    # first grid launched alone (the same kernel code the batch runs)
     stage_ms, launches = P.profile_step(ctx, grid, prm, q, args.profile_steps)
+    shape = grid.tile_shape(prm)
     mean_ms = sum(stage_ms) / 3.0
-    bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
+    bytes_per_launch = case.nx * case.ny * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
     achieved = bytes_per_launch / (mean_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload)
     roofline = {
@@ -165,7 +212,9 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 5),
         "traffic": traffic,
-        "kernel": "k_stage_single<2,%d>" % args.precision,
+        "kernel": "k_stage_single<order 2, FP%s, uniform, %s>" % ("64" if args.precision == 0 else "32-coef",
+                                                                  P.SHAPES[shape] if shape >= 0 else "?"),
+        "kernel_grid": f"{case.nx}x{case.ny}",
         "stage_ms": [round(x, 5) for x in stage_ms],
         "algorithmic_bytes_per_launch": bytes_per_launch,
     }
@@ -184,17 +233,20 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f32-flux/f64-state",
         "data": "synthetic",
         "config": {
-            "workload": f"low-Mach isentropic vortex {case.nx}x{case.ny} periodic, M=0.01, "
-                        "MUSCL-minmod + SSP-RK3, Roe-AM (detector, eps1=1, eps2=0.05), CFL 0.4",
+            "workload": ("low-Mach isentropic vortex, two 256x256 periodic grids (M=0.01 and M=0.001) "
+                         "advanced together as one batch" if batched else
+                         f"low-Mach isentropic vortex {case.nx}x{case.ny} periodic, M=0.01")
+                        + ", FP64 state, MUSCL-minmod + SSP-RK3, Roe-AM (detector, eps1=1, eps2=0.05), CFL 0.4",
             "cells": cells,
+            "grids": len(cases),
             "stages_per_step": 3,
-            "tile_shape": ["32x15", "16x15", "8x7"][shape] if shape >= 0 else None,
+            "tile_shape": P.SHAPES[shape] if shape >= 0 else None,
             "wall_s": round(wall, 4),
         },
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
 
 

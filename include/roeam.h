@@ -145,11 +145,12 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
 roeam_status roeam_grid_destroy(roeam_grid *grid);
 /* Layout of state arrays: q[k][j][i] at k*ny*pitch + j*pitch + i. */
 roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *pitch);
-/* Tile shape of the stage kernel for this grid: 0 = 32x15 cells per
- * workgroup, 1 = 16x15, 2 = 8x7, or -1 (default) = chosen by the autotuner,
- * which times every shape on the grid at its first roeam_step and keeps the
- * fastest per (order, precision).  Every shape computes the same result.
- * EINVAL: shape outside -1..2. */
+/* Tile shape of the stage kernel for this grid (cells per workgroup /
+ * threads): 0 = 32x15/256, 1 = 16x15/128, 2 = 8x7/64 (about two faces per
+ * thread), 3 = 8x7/128, 4 = 16x15/512, 5 = 32x7/512 (one face per thread),
+ * or -1 (default) = chosen by the autotuner, which times every shape on the
+ * grid at its first roeam_step and keeps the fastest per (order, precision).
+ * Every shape computes bitwise the same result.  EINVAL: shape outside -1..5. */
 roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
 /* The shape in use for these parameters (-1 if not tuned yet). */
 roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *params, int *shape);

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libroeam.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
+# stage-kernel tile shapes: cells x cells / threads per workgroup
+SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512"]
 
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
@@ -210,7 +212,7 @@ class Grid:
         return t[:, :, : self.nx].detach().cpu().numpy().copy()
 
     def set_tile_shape(self, shape: int):
-        """0 = 32x15, 1 = 16x15, 2 = 8x7 cells per workgroup; -1 = autotune."""
+        """Tile shape (see SHAPES); -1 = autotune."""
         self.ctx.check(lib().roeam_grid_set_tile_shape(self.h, int(shape)))
 
     def tile_shape(self, prm: Dict) -> int:

@@ -264,8 +264,15 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
                                  r.d.q0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
         BHIP(ctx, roeam::launch_slot_init(&b->d_slots[idx], 1, 0.0, r.d.t_end, r.d.params.cfl, r.d.nsteps, ctx->stream));
         BHIP(ctx, roeam::launch_rate(S, p, ctx->stream));
-        // tiles of the solve join its group's work list
+        // tiles of the solve join its group's work list; an empty group takes
+        // the tile shape of its first solve's grid (set, autotuned, or by size)
         Group &G = b->groups[r.group];
+        if (G.tiles.empty()) {
+            int sh = g->shape_forced >= 0 ? g->shape_forced : g->shape_tuned[r.d.params.order - 1][r.d.params.precision];
+            if (sh < 0) sh = (long long)g->nx * g->ny >= (1ll << 20) ? 0 : 3;
+            if (sh != G.shape) b->graph_valid = false;
+            G.shape = sh;
+        }
         int tx, ty;
         roeam::tile_shape(G.shape, &tx, &ty);
         const int ntx = (g->nx + tx - 1) / tx, nty = (g->ny + ty - 1) / ty;

@@ -95,25 +95,81 @@ __device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, dou
     return true;
 }
 
-// The tile body.  stage: 0 residual only (r_out), 1 Q + dt R into qa (forward
-// Euler, or the first SSP-RK3 stage), 2 SSP-RK3 second stage into qb, 3 third
-// stage into q.  p: step parity.  last: this stage ends the step (reduce the
-// rate of the new state into st[p^1]); for stage 0 the rate of the input is
-// reduced into st[0].
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
-__device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int p, int last,
-                                           int first_block, double *__restrict__ r_out)
+// One i-face (between local cells (fi-1, fj) and (fi, fj)) or j-face (between
+// (fi, fr-1) and (fi, fr)) of a tile: stencil from the LDS primitives, the
+// detector minimum over the face and its four transverse neighbours, and the
+// flux times the face length.
+template <int ORDER, int PREC, int METRIC, int TX, int TY, bool XDIR>
+__device__ __forceinline__ void tile_face(const DevSolve &S, const double (&sW)[4][TY + 2 * ORDER][TX + 2 * ORDER],
+                                          const double (&sPx)[TY + 2][TX + 1], const double (&sPy)[TY + 1][TX + 2],
+                                          int fi, int fj, int gi, int gj, double F[4])
 {
     using R = typename std::conditional<PREC == 0, double, float>::type;
     constexpr int HL = ORDER;
+    double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4];
+    const int ly = fj + HL, lx = fi + HL;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (XDIR) {
+            m1[k] = sW[k][ly][lx - 1];
+            p0[k] = sW[k][ly][lx];
+            if (ORDER == 2) {
+                m2[k] = sW[k][ly][lx - 2];
+                p1[k] = sW[k][ly][lx + 1];
+            }
+        } else {
+            m1[k] = sW[k][ly - 1][lx];
+            p0[k] = sW[k][ly][lx];
+            if (ORDER == 2) {
+                m2[k] = sW[k][ly - 2][lx];
+                p1[k] = sW[k][ly + 1][lx];
+            }
+        }
+    }
+    double s1 = 1.0;
+    if (S.s1_mode == 0) {
+        double a;
+        if (XDIR) {
+            a = rmin(rmin(sPx[fj + 1][fi], sPy[fj][fi]), rmin(sPy[fj + 1][fi], rmin(sPy[fj][fi + 1], sPy[fj + 1][fi + 1])));
+        } else {
+            a = rmin(rmin(sPy[fj][fi + 1], sPx[fj][fi]), rmin(sPx[fj][fi + 1], rmin(sPx[fj + 1][fi], sPx[fj + 1][fi + 1])));
+        }
+        s1 = pow8(fswitch(a));
+    }
+    reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
+    double sx, sy, nxv, nyv, len;
+    if (XDIR) xface_vec<METRIC>(S, gi, gj, sx, sy);
+    else yface_vec<METRIC>(S, gi, gj, sx, sy);
+    unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
+    roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F[k] *= len;
+}
+
+// The tile body.  stage: 0 residual only (r_out), 1 Q + dt R into qa (forward
+// Euler, or the first SSP-RK3 stage), 2 SSP-RK3 second stage into qb, 3 third
+// stage into q.  p: step parity.  last: this stage ends the step (reduce the
+// rate of the new state into parity p^1); for stage 0 the rate of the input is
+// reduced into parity 0.
+// SPLIT = false: NT threads sweep the i-faces, then the j-faces through one
+// LDS buffer (about two faces per thread).  SPLIT = true: one face per thread,
+// i-faces on the first ceil(NFX/64) waves and j-faces on the rest, in one pass.
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
+__device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int p, int last,
+                                           int first_block, double *__restrict__ r_out)
+{
+    constexpr int HL = ORDER;
     constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL;
     constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
-    constexpr int NFB = NFX > NFY ? NFX : NFY;
+    constexpr int NFXR = (NFX + 63) / 64 * 64;  // i-face threads in SPLIT mode
+    static_assert(!SPLIT || NFXR + NFY <= NT, "split shape must give every face a thread");
+    constexpr int NFB = SPLIT ? NFX : (NFX > NFY ? NFX : NFY);
     constexpr int CPT = (TX * TY + NT - 1) / NT;  // cells per thread
     __shared__ double sW[4][LY][LX];
     __shared__ double sPx[TY + 2][TX + 1];
     __shared__ double sPy[TY + 1][TX + 2];
     __shared__ double sF[4][NFB];
+    __shared__ double sG[4][SPLIT ? NFY : 1];
     __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
 
     const int tid = threadIdx.x;
@@ -182,89 +238,71 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         __syncthreads();
     }
 
-    // 3. i-faces of the tile, once each
-    for (int f = tid; f < NFX; f += NT) {
-        const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
-        const int gi = i0 + fi, gj = j0 + fj;
-        if (gi > nx || gj >= ny) continue;
-        double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4];
-        const int ly = fj + HL, lx = fi + HL;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            m1[k] = sW[k][ly][lx - 1];
-            p0[k] = sW[k][ly][lx];
-            if (ORDER == 2) {
-                m2[k] = sW[k][ly][lx - 2];
-                p1[k] = sW[k][ly][lx + 1];
-            }
-        }
-        double s1 = 1.0;
-        if (S.s1_mode == 0) {
-            double a = sPx[fj + 1][fi];
-            a = rmin(a, sPy[fj][fi]);
-            a = rmin(a, sPy[fj + 1][fi]);
-            a = rmin(a, sPy[fj][fi + 1]);
-            a = rmin(a, sPy[fj + 1][fi + 1]);
-            s1 = pow8(fswitch(a));
-        }
-        reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
-        double sx, sy, nxv, nyv, len;
-        xface_vec<METRIC>(S, gi, gj, sx, sy);
-        unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
-        roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
-    }
-    __syncthreads();
-
-    // i-direction part of the residual, kept in registers
+    // 3. every face of the tile exactly once
     double dfx[CPT][4];
+    if (SPLIT) {
+        if (tid < NFXR) {
+            const int f = tid;
+            const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+            if (f < NFX && i0 + fi <= nx && j0 + fj < ny) {
+                double F[4];
+                tile_face<ORDER, PREC, METRIC, TX, TY, true>(S, sW, sPx, sPy, fi, fj, i0 + fi, j0 + fj, F);
 #pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-        const int c = tid + m * NT;
-        const int cj = c / TX, ci = c - cj * TX;
+                for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
+            }
+        } else {
+            const int f = tid - NFXR;
+            const int fr = f / TX, fi = f - fr * TX;
+            if (f < NFY && i0 + fi < nx && j0 + fr <= ny) {
+                double F[4];
+                tile_face<ORDER, PREC, METRIC, TX, TY, false>(S, sW, sPx, sPy, fi, fr, i0 + fi, j0 + fr, F);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
-    }
-    __syncthreads();
-
-    // 4. j-faces of the tile, once each, through the same LDS buffer
-    for (int f = tid; f < NFY; f += NT) {
-        const int fr = f / TX, fi = f - fr * TX;
-        const int gi = i0 + fi, gj = j0 + fr;
-        if (gi >= nx || gj > ny) continue;
-        double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4];
-        const int ly = fr + HL, lx = fi + HL;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            m1[k] = sW[k][ly - 1][lx];
-            p0[k] = sW[k][ly][lx];
-            if (ORDER == 2) {
-                m2[k] = sW[k][ly - 2][lx];
-                p1[k] = sW[k][ly + 1][lx];
+                for (int k = 0; k < 4; ++k) sG[k][f] = F[k];
             }
         }
-        double s1 = 1.0;
-        if (S.s1_mode == 0) {
-            double a = sPy[fr][fi + 1];
-            a = rmin(a, sPx[fr][fi]);
-            a = rmin(a, sPx[fr][fi + 1]);
-            a = rmin(a, sPx[fr + 1][fi]);
-            a = rmin(a, sPx[fr + 1][fi + 1]);
-            s1 = pow8(fswitch(a));
-        }
-        reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
-        double sx, sy, nxv, nyv, len;
-        yface_vec<METRIC>(S, gi, gj, sx, sy);
-        unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
-        roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
+        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sF[k][f] = F[k] * len;
+        for (int m = 0; m < CPT; ++m) {
+            const int c = tid + m * NT;
+            const int cj = c / TX, ci = c - cj * TX;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
+        }
+    } else {
+        for (int f = tid; f < NFX; f += NT) {
+            const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+            if (i0 + fi > nx || j0 + fj >= ny) continue;
+            double F[4];
+            tile_face<ORDER, PREC, METRIC, TX, TY, true>(S, sW, sPx, sPy, fi, fj, i0 + fi, j0 + fj, F);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
+        }
+        __syncthreads();
+        // i-direction part of the residual, kept in registers
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const int c = tid + m * NT;
+            const int cj = c / TX, ci = c - cj * TX;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
+        }
+        __syncthreads();
+        // j-faces through the same LDS buffer
+        for (int f = tid; f < NFY; f += NT) {
+            const int fr = f / TX, fi = f - fr * TX;
+            if (i0 + fi >= nx || j0 + fr > ny) continue;
+            double F[4];
+            tile_face<ORDER, PREC, METRIC, TX, TY, false>(S, sW, sPx, sPy, fi, fr, i0 + fi, j0 + fr, F);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    const double(&sJ)[4][SPLIT ? NFY : NFB] = *reinterpret_cast<const double(*)[4][SPLIT ? NFY : NFB]>(SPLIT ? &sG[0][0] : &sF[0][0]);
 
-    // 5. conservative residual R = -((F_e - F_w) + (G_n - G_s)) / Omega and the stage update
+    // 4. conservative residual R = -((F_e - F_w) + (G_n - G_s)) / Omega and the stage update
     double lmax = 0.0;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -275,7 +313,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         const double iom = METRIC == 0 ? S.inv_area : rcp_nr(cell_area<METRIC>(S, gi, gj));
         double Rv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sF[k][(cj + 1) * TX + ci] - sF[k][cj * TX + ci])) * iom;
+        for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sJ[k][(cj + 1) * TX + ci] - sJ[k][cj * TX + ci])) * iom;
         const long long idx = (long long)gj * S.pitch + gi;
         if (stage == 0) {
 #pragma unroll
@@ -325,7 +363,7 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return (b & 7) * chunk + (b >> 3);
 }
 
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
                                                      double *r_out)
 {
@@ -334,10 +372,10 @@ __global__ __launch_bounds__(NT) void k_stage_single(const DevSolve *__restrict_
     const int nt = txs * tys;
     const int t = xcd_tile(blockIdx.x, nt);
     if (t >= nt) return;
-    stage_tile<ORDER, PREC, METRIC, TX, TY, NT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
+    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
 }
 
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT>
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__ solves,
                                                     const TileEntry *__restrict__ tiles, int ntiles, int stage,
                                                     int p, int last)
@@ -345,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_stage_batch(const DevSolve *__restrict__
     const int t = xcd_tile(blockIdx.x, ntiles);
     if (t >= ntiles) return;
     const TileEntry te = tiles[t];
-    stage_tile<ORDER, PREC, METRIC, TX, TY, NT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
+    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
                                         nullptr);
 }
 
@@ -416,16 +454,29 @@ __global__ void k_rate_out(const Slot *s, double *out)
 struct TileShape {
     int tx, ty, nt;
 };
-static const TileShape kShapes[3] = {{32, 15, 256}, {16, 15, 128}, {8, 7, 64}};
+// 0-2: about two faces per thread; 3-5: one face per thread (split)
+static const TileShape kShapes[6] = {{32, 15, 256}, {16, 15, 128}, {8, 7, 64},
+                                     {8, 7, 128},   {16, 15, 512}, {32, 7, 512}};
+constexpr int kNumShapes = 6;
 
 void tile_shape(int shape, int *tx, int *ty)
 {
-    const TileShape &s = kShapes[shape < 0 || shape > 2 ? 0 : shape];
+    const TileShape &s = kShapes[shape < 0 || shape >= kNumShapes ? 0 : shape];
     *tx = s.tx;
     *ty = s.ty;
 }
 
-int tile_shape_count() { return 3; }
+int tile_shape_count() { return kNumShapes; }
+
+#define ROEAM_SHAPE_SWITCH(KERNEL, ...)                                                                                  \
+    switch (shape) {                                                                                                     \
+    case 0: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 32, 15, 256, false>), dim3(blocks), dim3(256), 0, st, __VA_ARGS__); break; \
+    case 1: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 16, 15, 128, false>), dim3(blocks), dim3(128), 0, st, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 8, 7, 64, false>), dim3(blocks), dim3(64), 0, st, __VA_ARGS__); break;    \
+    case 3: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 8, 7, 128, true>), dim3(blocks), dim3(128), 0, st, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 16, 15, 512, true>), dim3(blocks), dim3(512), 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 32, 7, 512, true>), dim3(blocks), dim3(512), 0, st, __VA_ARGS__); break; \
+    }
 
 template <int ORDER, int PREC, int METRIC>
 static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
@@ -434,11 +485,7 @@ static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape
     const TileShape &sh = kShapes[shape];
     const int nt = ((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty);
     const int blocks = ((nt + 7) >> 3) << 3;
-    switch (shape) {
-    case 0: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, dS, stage, p, last, r_out); break;
-    case 1: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, dS, stage, p, last, r_out); break;
-    default: hipLaunchKernelGGL((k_stage_single<ORDER, PREC, METRIC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, dS, stage, p, last, r_out); break;
-    }
+    ROEAM_SHAPE_SWITCH(k_stage_single, dS, stage, p, last, r_out)
 }
 
 template <int ORDER, int PREC>
@@ -452,7 +499,7 @@ static void launch_single_metric(const DevSolve *dS, const DevSolve &S, int shap
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                double *r_out, hipStream_t st)
 {
-    if (shape < 0 || shape > 2) return hipErrorInvalidValue;
+    if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
     if (S.order == 1) {
         if (S.precision == 0) launch_single_metric<1, 0>(dS, S, shape, stage, p, last, r_out, st);
         else launch_single_metric<1, 1>(dS, S, shape, stage, p, last, r_out, st);
@@ -468,11 +515,7 @@ static void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, i
                                int last, hipStream_t st)
 {
     const int blocks = ((ntiles + 7) >> 3) << 3;
-    switch (shape) {
-    case 0: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, stage, p, last); break;
-    case 1: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, stage, p, last); break;
-    default: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, 8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, stage, p, last); break;
-    }
+    ROEAM_SHAPE_SWITCH(k_stage_batch, solves, tiles, ntiles, stage, p, last)
 }
 
 template <int ORDER, int PREC>
@@ -487,7 +530,7 @@ hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, in
                               int metric, int shape, int stage, int p, int last, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (shape < 0 || shape > 2) return hipErrorInvalidValue;
+    if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
     if (order == 1) {
         if (precision == 0) launch_batch_metric<1, 0>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
         else launch_batch_metric<1, 1>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
@@ -567,7 +610,10 @@ hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles
     switch (shape) {
     case 0: hipLaunchKernelGGL((k_copy_back_batch<32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, p); break;
     case 1: hipLaunchKernelGGL((k_copy_back_batch<16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, p); break;
-    default: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, p); break;
+    case 2: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, p); break;
+    case 3: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, p); break;
+    case 4: hipLaunchKernelGGL((k_copy_back_batch<16, 15, 512>), dim3(blocks), dim3(512), 0, st, solves, tiles, ntiles, p); break;
+    default: hipLaunchKernelGGL((k_copy_back_batch<32, 7, 512>), dim3(blocks), dim3(512), 0, st, solves, tiles, ntiles, p); break;
     }
     return hipGetLastError();
 }
