@@ -125,17 +125,32 @@ def _stream_ptr(stream) -> int:
 
 
 class Context:
-    """A library context on one device, bound to a HIP stream (torch stream)."""
+    """A library context on one device.
+
+    The library enqueues on its own non-null torch stream (the null stream
+    cannot be captured into HIP graphs).  Every call below first makes that
+    stream wait for the caller's current torch stream and afterwards makes the
+    current stream wait for it, so library calls are ordered with the caller's
+    torch work exactly as if they ran on the current stream."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch
         self.device = device
         torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = ctypes.c_void_p()
-        rc = lib().roeam_ctx_create(device, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h))
+        rc = lib().roeam_ctx_create(device, ctypes.c_void_p(_stream_ptr(self.stream)), ctypes.byref(h))
         if rc != OK:
             raise RoeamError(rc, "context creation failed")
         self.h = h
+
+    def enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def leave(self):
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def check(self, rc: int):
         if rc == OK:
@@ -147,6 +162,7 @@ class Context:
 
     def set_stream(self, stream):
         self.check(lib().roeam_ctx_set_stream(self.h, ctypes.c_void_p(_stream_ptr(stream))))
+        self.stream = stream
 
     def close(self):
         if getattr(self, "h", None):
@@ -250,7 +266,11 @@ def residual(ctx: Context, grid: Grid, prm: Dict, q, r=None, rate_out=None):
         r = grid.empty_state()
     p = params(prm)
     rp = ctypes.c_void_p(rate_out.data_ptr()) if rate_out is not None else None
-    ctx.check(lib().roeam_residual(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), _dev_ptr(r, grid), rp))
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_residual(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), _dev_ptr(r, grid), rp))
+    finally:
+        ctx.leave()
     return r
 
 
@@ -259,14 +279,19 @@ def step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float = 0.0, t
     """Advance q in place; returns the step statistics when sync (else None)."""
     p = params(prm)
     st = StepStats()
-    ctx.check(lib().roeam_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
-                               float(t_end), ctypes.byref(st) if sync else None))
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
+                                   float(t_end), ctypes.byref(st) if sync else None))
+    finally:
+        ctx.leave()
     return st.as_dict() if sync else None
 
 
 def last_stats(ctx: Context, grid: Grid) -> Dict:
     st = StepStats()
     ctx.check(lib().roeam_last_stats(ctx.h, grid.h, ctypes.byref(st)))
+    ctx.leave()
     return st.as_dict()
 
 
@@ -276,8 +301,12 @@ def profile_step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float 
     p = params(prm)
     out = (ctypes.c_double * 3)()
     n = ctypes.c_long()
-    ctx.check(lib().roeam_profile_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps), float(t0),
-                                       ctypes.byref(out), ctypes.byref(n)))
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_profile_step(ctx.h, grid.h, ctypes.byref(p), _dev_ptr(q, grid), int(nsteps),
+                                           float(t0), ctypes.byref(out), ctypes.byref(n)))
+    finally:
+        ctx.leave()
     return list(out), n.value
 
 
@@ -332,6 +361,7 @@ def batch_submit(ctx: Context, solves) -> list:
     solves = list(solves)
     arr = (SolveDesc * len(solves))(*[s.desc() for s in solves])
     tk = (ctypes.c_uint64 * len(solves))()
+    ctx.enter()  # initial states written by the caller's stream are read at admission
     ctx.check(lib().roeam_batch_submit(ctx.h, len(solves), arr, tk))
     for s, t in zip(solves, tk):
         s.ticket = int(t)
@@ -340,7 +370,11 @@ def batch_submit(ctx: Context, solves) -> list:
 
 def batch_run(ctx: Context, iterations: int = -1) -> int:
     pend = ctypes.c_int()
-    ctx.check(lib().roeam_batch_run(ctx.h, int(iterations), ctypes.byref(pend)))
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_batch_run(ctx.h, int(iterations), ctypes.byref(pend)))
+    finally:
+        ctx.leave()
     return pend.value
 
 
@@ -352,4 +386,6 @@ def batch_poll(ctx: Context, ticket: int):
     rc = lib().roeam_batch_poll(ctx.h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(st))
     if rc not in (OK, ENONPHYS):
         ctx.check(rc)
+    if done.value:
+        ctx.leave()  # outputs written by the library's stream are read after this
     return bool(done.value), (st.as_dict() if done.value else None), rc

@@ -31,6 +31,7 @@ namespace {
 constexpr int kMaxSolves = 4096;
 constexpr size_t kAlign = 256;
 constexpr int kGraphIters = 16;  // even
+constexpr int kStatusEvery = 8;  // iterations between status snapshots without a graph
 
 size_t align_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
 
@@ -129,6 +130,7 @@ struct BatchEngine {
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
     long iter = 0;
+    long since_status = 0;          // iterations since the last status snapshot
     Group groups[16];               // (order-1, precision, time_scheme, metric)
     bool set_changed = true;
     hipGraph_t graph = nullptr;
@@ -498,10 +500,17 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         }
         b->iter += ran;
         done_iters += ran;
-        // snapshot the status; the buffer's previous snapshot (two back) is read first
-        const int which = (int)(b->status_seq++ & 1);
-        if ((rc = process_status(ctx, b, which, true))) return rc;
-        if ((rc = enqueue_status(ctx, b, which))) return rc;
+        b->since_status += ran;
+        // snapshot the status after every graph, or every kStatusEvery single
+        // iterations, or when the caller's iteration budget ends; the buffer's
+        // previous snapshot (two back) is read first
+        const bool budget_end = iterations >= 0 && done_iters >= iterations;
+        if (ran > 1 || b->since_status >= kStatusEvery || budget_end) {
+            const int which = (int)(b->status_seq++ & 1);
+            if ((rc = process_status(ctx, b, which, true))) return rc;
+            if ((rc = enqueue_status(ctx, b, which))) return rc;
+            b->since_status = 0;
+        }
     }
     if (iterations < 0) {
         // drain: retire everything still reported

@@ -173,6 +173,31 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
 
     const int tid = threadIdx.x;
+    const double *__restrict__ qin = (stage <= 1) ? S.q : (stage == 2 ? S.qa : S.qb);
+    const int i0 = tx * TX, j0 = ty * TY;
+    const int nx = S.nx, ny = S.ny;
+
+    // Own cells' stage input (and Q^n for stages 2-3) are loaded first so their
+    // latency is hidden behind the face work; cells outside the grid load cell
+    // (0, 0) and are never stored.
+    double Qs[CPT][4], Q0[CPT][4];
+    long long cidx[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * NT;
+        const int cj = c / TX, ci = c - cj * TX;
+        const bool ok = c < TX * TY && i0 + ci < nx && j0 + cj < ny;
+        cidx[m] = ok ? (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
+        if (stage > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
+        }
+        if (stage >= 2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
+        }
+    }
+
     Slot &z = *S.slot;
     double dt = 0.0, t_next = 0.0, rate = 0.0;
     if (stage > 0) {
@@ -200,13 +225,14 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
         if (!active) return;
     }
-    const double *__restrict__ qin = (stage <= 1) ? S.q : (stage == 2 ? S.qa : S.qb);
-    const int i0 = tx * TX, j0 = ty * TY;
-    const int nx = S.nx, ny = S.ny;
 
-    // 1. tile + halo -> primitives in LDS
+    // 1. tile + halo -> primitives in LDS (fully unrolled: all loads in flight)
     const bool interior = (i0 - HL >= 0) && (i0 + TX + HL <= nx) && (j0 - HL >= 0) && (j0 + TY + HL <= ny);
-    for (int e = tid; e < LX * LY; e += NT) {
+    constexpr int NLOAD = (LX * LY + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < NLOAD; ++it) {
+        const int e = tid + it * NT;
+        if (e >= LX * LY) break;
         const int ly = e / LX, lx = e - ly * LX;
         int gi = i0 - HL + lx, gj = j0 - HL + ly;
         double W[4];
@@ -314,7 +340,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         double Rv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sJ[k][(cj + 1) * TX + ci] - sJ[k][cj * TX + ci])) * iom;
-        const long long idx = (long long)gj * S.pitch + gi;
+        const long long idx = cidx[m];
         if (stage == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) r_out[k * S.plane + idx] = Rv[k];
@@ -328,13 +354,11 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         double Qn[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double Qs = qin[k * S.plane + idx];
             if (stage == 1) {
-                Qn[k] = Qs + dt * Rv[k];
+                Qn[k] = Qs[m][k] + dt * Rv[k];
             } else {
-                const double Q0 = S.q[k * S.plane + idx];
-                Qn[k] = (stage == 2) ? 0.75 * Q0 + 0.25 * (Qs + dt * Rv[k])
-                                     : (1.0 / 3.0) * Q0 + (2.0 / 3.0) * (Qs + dt * Rv[k]);
+                Qn[k] = (stage == 2) ? 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k])
+                                     : (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]);
             }
         }
         double *__restrict__ qo = (stage == 1) ? S.qa : (stage == 2 ? S.qb : S.q);
