@@ -132,14 +132,194 @@ def timed_batch(ctx, grids, cases, steps, warmup, stream):
     return ev0.elapsed_time(ev1), wall
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def one_at_a_time(ctx, items, precision):
+    """Run each (grid, params, q0_tensor, steps) alone through roeam_step in
+    order; returns per-item GPU-serial completion times (s from start) and total."""
+    import torch
+    import paper_1711_09272_amd as P
+    # tune tile shapes first (zero-step runs), outside the timing
+    for g, prm, q0, n in items:
+        p = dict(prm)
+        p["precision"] = precision
+        P.step(ctx, g, p, q0.clone(), 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = []
+    for g, prm, q0, n in items:
+        p = dict(prm)
+        p["precision"] = precision
+        q = q0.clone()
+        P.step(ctx, g, p, q, n, sync=True)
+        done.append(time.perf_counter() - t0)
+    return done, time.perf_counter() - t0
+
+
+def bench_batch(args):
+    """Fourth configuration: 256 seeded grids of sides log-uniform 32..512, 200
+    SSP-RK3 steps each, FP32 coefficients / FP64 state, all submitted at once
+    and advanced together (graph-replayed batched stage kernels)."""
+    import torch
+    import paper_1711_09272_amd as P
+    import workloads
+    prec = 1 if args.precision is None else args.precision
+    cases = workloads.batch_family(args.batch_grids, nsteps=args.steps, precision=prec)
+    ctx = P.Context(0)
+    grids = [P.Grid.from_case(ctx, c) for c in cases]
+    if args.batch_shape >= 0:
+        for g in grids:
+            g.set_tile_shape(args.batch_shape)
+    q0 = [g.to_device(c.q0) for g, c in zip(grids, cases)]
+    cells = sum(c.nx * c.ny for c in cases)
+    P.batch_reserve(ctx, sum(g.footprint() for g in grids) + (64 << 20))
+
+    def run(nsteps):
+        outs = [g.empty_state() for g in grids]
+        solves = [P.Solve(g, c.params, q, nsteps, 0.0, o) for g, c, q, o in zip(grids, cases, q0, outs)]
+        t0 = time.perf_counter()
+        P.batch_submit(ctx, solves)
+        fin = {}
+        while len(fin) < len(solves):
+            P.batch_run(ctx, 16)
+            now = time.perf_counter()
+            for s in solves:
+                if s.ticket not in fin:
+                    done, st, rc = P.batch_poll(ctx, s.ticket)
+                    if done:
+                        if rc != P.OK or st["steps"] != nsteps:
+                            raise SystemExit(f"batched solve failed: {st} {rc}")
+                        fin[s.ticket] = now - t0
+        return [fin[s.ticket] for s in solves]
+
+    run(2)  # warm-up: kernels, graphs
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ev0.record(stream)
+    lat = run(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    updates = cells * 3 * args.steps
+    items = [(g, c.params, q, args.steps) for g, c, q in zip(grids, cases, q0)]
+    alone64, total64 = one_at_a_time(ctx, items, 0)
+    aloneP, totalP = (alone64, total64) if prec == 0 else one_at_a_time(ctx, items, prec)
+    out = {
+        "metric": "Gcell-updates/s per RK stage (batched)",
+        "value": round(updates / gpu_s / 1e9, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64" if prec == 0 else "f32-flux/f64-state",
+        "data": "synthetic",
+        "config": {"workload": f"{len(cases)} bump-family grids, sides log-uniform 32..512, "
+                               f"{args.steps} SSP-RK3 steps each, submitted together",
+                   "cells": cells, "cell_stage_updates": updates, "tile_shape": args.batch_shape},
+        "makespan_s": round(gpu_s, 4),
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+        "one_at_a_time": {
+            "same_precision": {"value": round(updates / totalP / 1e9, 4), "makespan_s": round(totalP, 4),
+                               "p50_s": percentile(aloneP, 50), "p99_s": percentile(aloneP, 99)},
+            "fp64": {"value": round(updates / total64 / 1e9, 4), "makespan_s": round(total64, 4),
+                     "p50_s": percentile(alone64, 50), "p99_s": percentile(alone64, 99)},
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Fifth configuration: Poisson arrivals (rates swept) of solves with grid
+    sides log-uniform 64..2048 and 50..2000 steps, bump-family states built on
+    the device; served with continuous batching vs one at a time (FP64)."""
+    import torch
+    import paper_1711_09272_amd as P
+    import workloads
+    from paper_1711_09272_amd.serving import Server
+    prec = 0 if args.precision is None else args.precision
+    ctx = P.Context(0)
+    grid_cache = {}
+
+    def grid(n):
+        if n not in grid_cache:
+            grid_cache[n] = P.Grid(ctx, n, n, dx=1.0 / n, dy=1.0 / n, bc=(0, 0, 0, 0))
+        return grid_cache[n]
+
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        trace = workloads.serving_trace(rate, args.duration)
+        server = Server(ctx, args.arena_gb << 30)
+        t0 = time.perf_counter()
+        k = 0
+        reqs = []
+        while k < len(trace) or server.outstanding:
+            now = time.perf_counter() - t0
+            while k < len(trace) and trace[k]["arrival_s"] <= now:
+                tr = trace[k]
+                g = grid(tr["n"])
+                q0 = workloads.bump_state_device(tr["n"], tr["spec"], g.pitch)
+                prm = workloads.bump_params(tr["spec"]["mach"], precision=prec)
+                r = server.submit(g, prm, q0, tr["steps"], tag=k)
+                r.arrival = t0 + tr["arrival_s"]
+                reqs.append(r)
+                k += 1
+            if server.outstanding:
+                for r in server.pump(8):
+                    r.solve.q0 = r.solve.q_out = None  # release device memory
+            else:
+                time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        lat = [r.finished - r.arrival for r in reqs]
+        updates = sum(r.cells * 3 * r.solve.nsteps for r in reqs)
+        span = max(r.finished for r in reqs) - (t0 + trace[0]["arrival_s"])
+        # one at a time, FIFO, in real time: each request runs alone when the previous finished
+        t1 = time.perf_counter()
+        lat1 = []
+        for tr in trace:
+            wait = t1 + tr["arrival_s"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            g = grid(tr["n"])
+            q = workloads.bump_state_device(tr["n"], tr["spec"], g.pitch)
+            P.step(ctx, g, workloads.bump_params(tr["spec"]["mach"], precision=0), q, tr["steps"], sync=True)
+            lat1.append(time.perf_counter() - (t1 + tr["arrival_s"]))
+        span1 = time.perf_counter() - (t1 + trace[0]["arrival_s"])
+        results.append({
+            "rate_per_s": rate, "requests": len(trace), "duration_s": args.duration,
+            "served": {"gcell_updates_per_s": round(updates / span / 1e9, 4), "p50_s": percentile(lat, 50),
+                       "p99_s": percentile(lat, 99), "wall_s": round(wall, 3)},
+            "one_at_a_time_fp64": {"gcell_updates_per_s": round(updates / span1 / 1e9, 4),
+                                   "p50_s": percentile(lat1, 50), "p99_s": percentile(lat1, 99)},
+        })
+        print(json.dumps({"serve_rate": rate, **results[-1]}), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+    out = {"metric": "served p50/p99 latency and Gcell-updates/s", "n_gpus": 1,
+           "dtype": "f64" if prec == 0 else "f32-flux/f64-state", "data": "synthetic",
+           "config": {"workload": "Poisson requests, sides log-uniform 64..2048, steps log-uniform 50..2000, "
+                                  "bump-family states, SSP-RK3 + MUSCL, continuous batching",
+                      "arena_gb": args.arena_gb},
+           "rates": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="vortex256pair",
-                    help="vortex256pair (both Mach numbers, batched) or vortexN (one N x N grid)")
-    ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
+                    help="vortex256pair (both Mach numbers, batched; the default line), vortexN (one "
+                         "N x N grid), batch256 (fourth configuration), serve (fifth configuration)")
+    ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
+                    help="0 FP64, 1 FP32 coefficients (default: 0; batch256 defaults to 1)")
+    ap.add_argument("--batch-grids", type=int, default=256)
+    ap.add_argument("--batch-shape", type=int, default=-1)
+    ap.add_argument("--rates", default="2,5,10")
+    ap.add_argument("--duration", type=float, default=15.0)
+    ap.add_argument("--arena-gb", type=int, default=48)
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps timed kernel by kernel with HIP events for the roofline object")
     ap.add_argument("--cpu-sample-steps", type=int, default=75)
@@ -152,6 +332,13 @@ def main():
         print("bench.py runs on one GPU only: the Roe-AM step here is a single-GPU build "
               "(multi-GPU sharding is described, not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch256":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.precision is None:
+        args.precision = 0
 
     import torch
     import paper_1711_09272_amd as P

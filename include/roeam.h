@@ -137,7 +137,8 @@ const char *roeam_last_error(const roeam_ctx *ctx);
  * east, south, north; a periodic kind must be used on both sides of its
  * direction.  dirichlet_state: HOST array [4 sides][4] of conserved states,
  * used by DIRICHLET sides (NULL allowed if none).  The grid owns device
- * copies of its metrics and two stage buffers of the state size.
+ * copies of its metrics and, from its first roeam_step on, two stage
+ * buffers of the state size (batched solves use the batch arena instead).
  * EINVAL: sizes, kinds or metrics invalid (non-positive spacing or cell
  * area); ENOMEM. */
 roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metrics *metrics,

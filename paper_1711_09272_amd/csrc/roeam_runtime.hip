@@ -109,6 +109,21 @@ static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q
     return roeam_make_solve(g, p, q, g->d_qa, g->d_qb, g->d_slot);
 }
 
+// The grid's own stage buffers are allocated at its first single-grid step
+// (batched solves keep theirs in the batch arena).
+static roeam_status ensure_stage_buffers(roeam_ctx *ctx, roeam_grid *g)
+{
+    if (g->d_qa && g->d_qb) return ROEAM_OK;
+    const size_t bytes = sizeof(double) * 4 * (size_t)g->ny * (size_t)g->pitch;
+    hipError_t e = g->d_qa ? hipSuccess : hipMalloc(&g->d_qa, bytes);
+    if (e == hipSuccess && !g->d_qb) e = hipMalloc(&g->d_qb, bytes);
+    if (e != hipSuccess)
+        return roeam_fail(ctx, e == hipErrorOutOfMemory ? ROEAM_ENOMEM : ROEAM_EDEVICE,
+                          std::string("stage buffers: ") + hipGetErrorString(e));
+    g->solve_valid = false;
+    return ROEAM_OK;
+}
+
 // Make the grid's device descriptor equal to S.  Work already queued may
 // still read the old descriptor, so a change waits for the stream first.
 static hipError_t upload_solve(roeam_grid *g, const DevSolve &S, hipStream_t s)
@@ -229,10 +244,7 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
         g->bc[s] = bc[s];
         for (int k = 0; k < 4; ++k) g->bcq[s][k] = (bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_state[4 * s + k] : 0.0;
     }
-    const size_t state_bytes = sizeof(double) * 4 * (size_t)ny * (size_t)g->pitch;
-    hipError_t e = hipMalloc(&g->d_qa, state_bytes);
-    if (e == hipSuccess) e = hipMalloc(&g->d_qb, state_bytes);
-    if (e == hipSuccess) e = hipMalloc(&g->d_slot, sizeof(Slot));
+    hipError_t e = hipMalloc(&g->d_slot, sizeof(Slot));
     if (e == hipSuccess) e = hipHostMalloc(&g->h_slot, sizeof(Slot), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&g->d_solve, sizeof(DevSolve));
     if (e == hipSuccess) e = hipHostMalloc(&g->h_solve, sizeof(DevSolve), hipHostMallocDefault);
@@ -393,6 +405,7 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
     if (st) return st;
     roeam_grid *g = const_cast<roeam_grid *>(gc);
     HIP_OK(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_stage_buffers(ctx, g))) return st;
     const DevSolve S = make_solve(g, p, q);
     hipStream_t s = ctx->stream;
     HIP_OK(ctx, upload_solve(g, S, s));
@@ -459,6 +472,7 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     if (st) return st;
     roeam_grid *g = const_cast<roeam_grid *>(gc);
     HIP_OK(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_stage_buffers(ctx, g))) return st;
     const DevSolve S = make_solve(g, p, q);
     hipStream_t s = ctx->stream;
     HIP_OK(ctx, upload_solve(g, S, s));

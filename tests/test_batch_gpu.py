@@ -148,3 +148,36 @@ def test_batch_errors(C):
     with pytest.raises(P.RoeamError) as e:
         P.batch_poll(C, 999999)
     assert e.value.code == P.ENOTFOUND
+
+
+def test_server_staggered_requests(C):
+    """The request server: requests with device-built initial states submitted
+    while earlier ones run each finish with the result of the same solve run
+    alone, with completion times recorded."""
+    import torch
+    import paper_1711_09272_amd as P
+    from paper_1711_09272_amd.serving import Server
+    trace = workloads.serving_trace(50.0, 0.2, n_lo=24, n_hi=96, s_lo=3, s_hi=30)
+    assert len(trace) >= 4
+    srv = Server(C, 256 << 20)
+    grids, reqs, refs = {}, [], []
+    for k, tr in enumerate(trace):
+        n = tr["n"]
+        if n not in grids:
+            grids[n] = P.Grid(C, n, n, dx=1.0 / n, dy=1.0 / n, bc=(PERIODIC,) * 4)
+            grids[n].set_tile_shape(0)
+        g = grids[n]
+        prm = workloads.bump_params(tr["spec"]["mach"])
+        q0 = workloads.bump_state_device(n, tr["spec"], g.pitch)
+        q_ref = q0.clone()
+        reqs.append(srv.submit(g, prm, q0, tr["steps"], tag=k))
+        refs.append((g, prm, q_ref, tr["steps"]))
+        if k % 2 == 1:
+            srv.pump(2)
+    srv.drain()
+    assert not srv.outstanding and len(srv.done) == len(reqs)
+    for r, (g, prm, q, n) in zip(reqs, refs):
+        assert r.code == P.OK and r.stats["steps"] == n and r.latency >= 0.0
+        P.step(C, g, prm, q, n)
+        torch.cuda.synchronize()
+        assert torch.equal(r.solve.q_out[:, :, : g.nx], q[:, :, : g.nx]), r.tag

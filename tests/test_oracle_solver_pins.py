@@ -315,3 +315,15 @@ def test_odd_even_decoupling():
         dev[name] = (rho.std(axis=0) / rho.mean(axis=0)).max()
     assert dev["roe"] > 0.1
     assert dev["roeam0"] < 0.02 and dev["roeam1"] < 0.02
+
+
+def test_bump_state_device_matches_host_recipe():
+    """The torch-built bump-family state (used by the served workload) equals the
+    numpy recipe that the batch family uses, in the padded layout."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(5))
+    spec = workloads.bump_spec(rng)
+    q_host = workloads.conserved(1.4, *workloads.bump_fields(37, spec))
+    q_dev = workloads.bump_state_device(37, spec, 40, device="cpu").numpy()
+    assert q_dev.shape == (4, 37, 40) and not q_dev[:, :, 37:].any()
+    assert np.allclose(q_dev[:, :, :37], q_host, rtol=1e-14, atol=1e-14)

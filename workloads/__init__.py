@@ -238,45 +238,77 @@ def odd_even(nx: int = 800, ny: int = 80, mach: float = 20.0, eps_y: float = 1e-
 # Batched / serving family (fourth and fifth test configurations)
 # --------------------------------------------------------------------------
 
-def bump_state(n: int, rng: np.random.Generator, gamma: float = 1.4, mach_lo: float = 0.001,
-               mach_hi: float = 20.0):
-    """Uniform flow on [0,1]^2 (rho = 1, p = 1/gamma so c = 1), Mach ~ U(lo, hi),
-    direction ~ U(0, 2 pi), times 1-5 Gaussian bumps (minimum-image distance,
-    sigma ~ U(0.03, 0.1), amplitude ~ U(0.01, 0.2) with a random sign) applied
-    multiplicatively to rho, p or both."""
+def bump_spec(rng: np.random.Generator, mach_lo: float = 0.001, mach_hi: float = 20.0) -> Dict:
+    """Seeded parameters of one bump-family state: Mach ~ U(lo, hi), direction ~
+    U(0, 2 pi), 1-5 Gaussian bumps (centre, sigma ~ U(0.03, 0.1), amplitude ~
+    U(0.01, 0.2) with a random sign, target 0 = rho, 1 = p, 2 = both)."""
     mach = rng.uniform(mach_lo, mach_hi)
     ang = rng.uniform(0.0, 2.0 * math.pi)
-    dx = 1.0 / n
-    X, Y = cell_centres(n, n, 0.0, 0.0, dx, dx)
-    rho = np.ones((n, n))
-    p = np.full((n, n), 1.0 / gamma)
-    nb = int(rng.integers(1, 6))
-    for _ in range(nb):
+    bumps = []
+    for _ in range(int(rng.integers(1, 6))):
         cx, cy = rng.uniform(0.0, 1.0, size=2)
         sig = rng.uniform(0.03, 0.1)
         a = rng.uniform(0.01, 0.2) * rng.choice(np.array([-1.0, 1.0]))
-        target = int(rng.integers(0, 3))  # 0 rho, 1 p, 2 both
-        ddx = np.abs(X - cx)
-        ddx = np.minimum(ddx, 1.0 - ddx)
-        ddy = np.abs(Y - cy)
-        ddy = np.minimum(ddy, 1.0 - ddy)
-        bump = 1.0 + a * np.exp(-(ddx * ddx + ddy * ddy) / (2.0 * sig * sig))
+        bumps.append((float(cx), float(cy), float(sig), float(a), int(rng.integers(0, 3))))
+    return {"mach": float(mach), "angle": float(ang), "bumps": bumps}
+
+
+def bump_fields(n: int, spec: Dict, xp=np, device=None, gamma: float = 1.4):
+    """Primitive fields of a bump-family state on [0,1]^2 (rho = 1, p = 1/gamma,
+    so c = 1), with xp = numpy or torch (device arrays)."""
+    kw = {} if xp is np else {"device": device, "dtype": xp.float64}
+    dx = 1.0 / n
+    c = (xp.arange(n, **kw) + 0.5) * dx
+    Y, X = xp.meshgrid(c, c, indexing="ij")
+    rho = xp.ones((n, n), **kw)
+    p = xp.full((n, n), 1.0 / gamma, **kw)
+    for cx, cy, sig, a, target in spec["bumps"]:
+        ddx = xp.abs(X - cx)
+        ddx = xp.minimum(ddx, 1.0 - ddx)
+        ddy = xp.abs(Y - cy)
+        ddy = xp.minimum(ddy, 1.0 - ddy)
+        bump = 1.0 + a * xp.exp(-(ddx * ddx + ddy * ddy) / (2.0 * sig * sig))
         if target in (0, 2):
             rho = rho * bump
         if target in (1, 2):
             p = p * bump
-    u = np.full((n, n), mach * math.cos(ang))
-    v = np.full((n, n), mach * math.sin(ang))
-    return conserved(gamma, rho, u, v, p), mach
+    u = xp.full((n, n), spec["mach"] * math.cos(spec["angle"]), **kw)
+    v = xp.full((n, n), spec["mach"] * math.sin(spec["angle"]), **kw)
+    return rho, u, v, p
+
+
+def bump_state(n: int, rng: np.random.Generator, gamma: float = 1.4, mach_lo: float = 0.001,
+               mach_hi: float = 20.0):
+    """Uniform flow on [0,1]^2 (rho = 1, p = 1/gamma so c = 1) times 1-5
+    multiplicative Gaussian bumps (minimum-image distance); see bump_spec."""
+    spec = bump_spec(rng, mach_lo, mach_hi)
+    return conserved(gamma, *bump_fields(n, spec, gamma=gamma)), spec["mach"]
+
+
+def bump_state_device(n: int, spec: Dict, pitch: int, device="cuda", gamma: float = 1.4):
+    """The same state built directly on the GPU with torch, in a padded
+    [4, n, pitch] layout (for serving traces with large grids)."""
+    import torch
+    rho, u, v, p = bump_fields(n, spec, xp=torch, device=device, gamma=gamma)
+    out = torch.zeros((4, n, pitch), dtype=torch.float64, device=device)
+    out[0, :, :n] = rho
+    out[1, :, :n] = rho * u
+    out[2, :, :n] = rho * v
+    out[3, :, :n] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return out
+
+
+def bump_params(spec_mach: float, **params) -> Dict:
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=min(spec_mach, 1.0), u_ref=spec_mach,
+                         eps1=1.0, eps2=0.05, s1_mode=0)
+    prm.update(params)
+    return prm
 
 
 def bump_case(n: int, rng: np.random.Generator, nsteps: int, name: str = "bump", **params) -> Case:
     q0, mach = bump_state(n, rng)
-    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=min(mach, 1.0), u_ref=mach,
-                         eps1=1.0, eps2=0.05, s1_mode=0)
-    prm.update(params)
-    return Case(name=name, q0=q0, params=prm, bc=(PERIODIC,) * 4, dx=1.0 / n, dy=1.0 / n,
-                nsteps=nsteps, t_end=0.0)
+    return Case(name=name, q0=q0, params=bump_params(mach, **params), bc=(PERIODIC,) * 4, dx=1.0 / n,
+                dy=1.0 / n, nsteps=nsteps, t_end=0.0)
 
 
 def batch_family(n_grids: int = 256, seed: Optional[int] = None, nsteps: int = 200,
@@ -294,8 +326,9 @@ def batch_family(n_grids: int = 256, seed: Optional[int] = None, nsteps: int = 2
 def serving_trace(rate: float, duration: float, seed: Optional[int] = None, n_lo: int = 64,
                   n_hi: int = 2048, s_lo: int = 50, s_hi: int = 2000):
     """Poisson arrivals at ``rate`` per second for ``duration`` seconds; each request
-    has a square grid side log-uniform in [n_lo, n_hi] and a step count
-    log-uniform in [s_lo, s_hi].  Returns a list of (arrival_s, side, steps, seed)."""
+    has a square grid side log-uniform in [n_lo, n_hi], a step count log-uniform
+    in [s_lo, s_hi] and a bump-family state (bump_spec).  Returns a list of
+    dicts (arrival_s, n, steps, spec)."""
     seed = SEED_BASE + 4 if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     t, out = 0.0, []
@@ -305,7 +338,7 @@ def serving_trace(rate: float, duration: float, seed: Optional[int] = None, n_lo
             break
         n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
         s = int(round(math.exp(rng.uniform(math.log(s_lo), math.log(s_hi)))))
-        out.append((t, n, s, int(rng.integers(0, 2 ** 31))))
+        out.append({"arrival_s": t, "n": n, "steps": s, "spec": bump_spec(rng)})
     return out
 
 
