@@ -44,10 +44,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, precision: int):
     """HBM bytes per stage launch from committed rocprofv3 counter summaries,
     or None when missing or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"stage_kernel_{workload}_traffic.txt")
+    tag = workload + ("_fp32coef" if precision else "")
+    path = os.path.join(ROOT, "profiles", f"stage_kernel_{tag}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -130,6 +131,21 @@ def timed_batch(ctx, grids, cases, steps, warmup, stream):
         if not done or rc != P.OK or st["steps"] != steps:
             raise SystemExit(f"bench batch run failed: {done} {st} {rc}")
     return ev0.elapsed_time(ev1), wall
+
+
+def profile_batch(ctx, grids, cases, steps):
+    """The same batch again for `steps` steps with HIP events around every
+    batched stage launch (on the library's stream); (stage ms, launches)."""
+    import paper_1711_09272_amd as P
+    q0 = [g.to_device(c.q0) for g, c in zip(grids, cases)]
+    solves = [P.Solve(g, c.params, q, steps, 0.0, g.empty_state()) for g, c, q in zip(grids, cases, q0)]
+    P.batch_submit(ctx, solves)
+    stage_ms, launches = P.batch_profile_run(ctx, -1)
+    for s in solves:
+        done, st, rc = P.batch_poll(ctx, s.ticket)
+        if not done or rc != P.OK or st["steps"] != steps:
+            raise SystemExit(f"bench batch profile run failed: {done} {st} {rc}")
+    return stage_ms, launches
 
 
 def percentile(xs, q):
@@ -315,6 +331,8 @@ def main():
                          "N x N grid), batch256 (fourth configuration), serve (fifth configuration)")
     ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
                     help="0 FP64, 1 FP32 coefficients (default: 0; batch256 defaults to 1)")
+    ap.add_argument("--tile-shape", type=int, default=-1,
+                    help="stage-kernel tile shape index for the vortex workloads (-1: autotune)")
     ap.add_argument("--batch-grids", type=int, default=256)
     ap.add_argument("--batch-shape", type=int, default=-1)
     ap.add_argument("--rates", default="2,5,10")
@@ -347,18 +365,26 @@ def main():
     cells = sum(c.nx * c.ny for c in cases)
     ctx = P.Context(0)
     grids = [P.Grid.from_case(ctx, c) for c in cases]
+    if args.tile_shape >= 0:
+        for g in grids:
+            g.set_tile_shape(args.tile_shape)
     case, grid = cases[0], grids[0]
     q = grid.to_device(case.q0)
     prm = case.params
     stream = torch.cuda.current_stream()
 
     if args.counter_run:
-        P.profile_step(ctx, grid, prm, q, args.profile_steps)
+        if batched:
+            P.step(ctx, grid, prm, grid.to_device(case.q0), 0)  # tile-shape tuning, as in the timed run
+            P.batch_reserve(ctx, sum(g.footprint() for g in grids) + (1 << 20))
+            profile_batch(ctx, grids, cases, args.profile_steps)
+        else:
+            P.profile_step(ctx, grid, prm, q, args.profile_steps)
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"counter_run": args.workload, "cells": case.nx * case.ny,
+        print(json.dumps({"counter_run": args.workload, "cells": cells,
                           "profile_steps": args.profile_steps, "copy_bytes": src.numel() * 8,
                           "tile_shape": grid.tile_shape(prm)}), flush=True)
         return
@@ -384,14 +410,25 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = cells * 3 * args.steps / (gpu_ms / 1e3) / 1e9
 
-    # roofline of the stage kernel: HIP events around every stage launch of the
-    # first grid launched alone (the same kernel code the batch runs)
-    stage_ms, launches = P.profile_step(ctx, grid, prm, q, args.profile_steps)
+    # roofline of the stage kernel that ran: HIP events around every stage
+    # launch, on the library's stream
+    if batched:
+        stage_ms, launches = profile_batch(ctx, grids, cases, args.profile_steps)
+        kname = "k_stage_batch"
+        kgrid = " + ".join(f"{c.nx}x{c.ny}" for c in cases)
+    else:
+        stage_ms, launches = P.profile_step(ctx, grid, prm, q, args.profile_steps)
+        kname = "k_stage_single"
+        kgrid = f"{case.nx}x{case.ny}"
     shape = grid.tile_shape(prm)
-    mean_ms = sum(stage_ms) / 3.0
-    bytes_per_launch = case.nx * case.ny * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
-    achieved = bytes_per_launch / (mean_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload)
+    # average stage-launch duration over the timed region: its GPU time over
+    # its stage launches (inter-kernel gaps and the batch engine's status
+    # kernels count against the kernel, so this errs low); the event-bracketed
+    # per-launch times above overstate kernels of ~10 us by the events' own cost
+    launch_ms = gpu_ms / (3 * args.steps)
+    bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, args.precision)
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
@@ -399,10 +436,13 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 5),
         "traffic": traffic,
-        "kernel": "k_stage_single<order 2, FP%s, uniform, %s>" % ("64" if args.precision == 0 else "32-coef",
-                                                                  P.SHAPES[shape] if shape >= 0 else "?"),
-        "kernel_grid": f"{case.nx}x{case.ny}",
-        "stage_ms": [round(x, 5) for x in stage_ms],
+        "kernel": "%s<order 2, FP%s, uniform, %s>" % (kname, "64" if args.precision == 0 else "32-coef",
+                                                      P.SHAPES[shape] if shape >= 0 else "?"),
+        "kernel_grid": kgrid,
+        "launch_ms": round(launch_ms, 6),
+        "timed_region_launches": 3 * args.steps,
+        "event_bracketed_stage_ms": [round(x, 5) for x in stage_ms],
+        "event_bracketed_launches": launches,
         "algorithmic_bytes_per_launch": bytes_per_launch,
     }
 

@@ -224,6 +224,16 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
  * retire; -1: until every queued solve is done).  Returns the number of
  * solves still pending in *pending (nullable). */
 roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending);
+/* Profiling aid (same arithmetic as roeam_batch_run): drive the scheduler
+ * with every kernel launched directly (no graphs), HIP events recorded on
+ * the context stream around each batched stage kernel, and the status read
+ * after every iteration (a host wait per iteration), so that finished solves
+ * leave at once and no timed launch is an idle one.  Waits for the stream, then writes the mean duration in
+ * milliseconds of the batched stage kernels into stage_ms[0..2] (first,
+ * second and third stage; a stage that never ran reads 0) and the number of
+ * timed launches into *launches (nullable).  Errors as roeam_batch_run. */
+roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[3],
+                                     long *launches);
 /* Non-blocking poll: *done = 1 once the solve's output is written; stats
  * (nullable) then holds its statistics.  A solve that produced a
  * non-physical state is done with return value ROEAM_ENONPHYS; the other

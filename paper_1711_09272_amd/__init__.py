@@ -27,7 +27,7 @@ EXPORTS = [
     "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_grid_set_tile_shape",
     "roeam_grid_tile_shape", "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
-    "roeam_batch_run", "roeam_batch_poll",
+    "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll",
 ]
 
 
@@ -99,6 +99,8 @@ def lib():
         "roeam_batch_footprint": (ctypes.c_size_t, [vp]),
         "roeam_batch_submit": (i, [vp, i, ctypes.POINTER(SolveDesc), ctypes.POINTER(ctypes.c_uint64)]),
         "roeam_batch_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i)]),
+        "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 3),
+                                        ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
     }
     for name, (res, args) in sig.items():
@@ -376,6 +378,21 @@ def batch_run(ctx: Context, iterations: int = -1) -> int:
     finally:
         ctx.leave()
     return pend.value
+
+
+def batch_profile_run(ctx: Context, iterations: int = -1):
+    """batch_run with HIP events around every batched stage kernel; returns
+    (mean ms of the stage-1, -2, -3 launches, number of timed launches)."""
+    pend = ctypes.c_int()
+    out = (ctypes.c_double * 3)()
+    n = ctypes.c_long()
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_batch_profile_run(ctx.h, int(iterations), ctypes.byref(pend), ctypes.byref(out),
+                                                ctypes.byref(n)))
+    finally:
+        ctx.leave()
+    return list(out), n.value
 
 
 def batch_poll(ctx: Context, ticket: int):

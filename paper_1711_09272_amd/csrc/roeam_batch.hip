@@ -136,6 +136,11 @@ struct BatchEngine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
+    // profiling: event pairs around each stage launch (stage number beside)
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_stage;
+    size_t prof_used = 0;
 };
 
 static int group_id(const roeam_params &p, int metric)
@@ -146,6 +151,7 @@ static int group_id(const roeam_params &p, int metric)
 static void release_engine(BatchEngine *b)
 {
     if (!b) return;
+    for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (auto &kv : b->reqs)
@@ -317,6 +323,30 @@ static roeam_status upload_tiles(roeam_ctx *ctx, BatchEngine *b)
     return ROEAM_OK;
 }
 
+// One batched stage launch, bracketed by profiling events when profiling.
+static hipError_t stage_launch(BatchEngine *b, const Group &G, int n, int stage, int p, int last, hipStream_t s)
+{
+    if (!b->profiling)
+        return roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, stage,
+                                         p, last, s);
+    hipError_t e = hipSuccess;
+    while (e == hipSuccess && b->prof_ev.size() < b->prof_used + 2) {
+        hipEvent_t ev;
+        e = hipEventCreate(&ev);
+        if (e == hipSuccess) b->prof_ev.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used], s);
+    if (e == hipSuccess)
+        e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, stage, p,
+                                      last, s);
+    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used + 1], s);
+    if (e == hipSuccess) {
+        b->prof_stage.push_back(stage);
+        b->prof_used += 2;
+    }
+    return e;
+}
+
 static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
 {
     for (auto &G : b->groups) {
@@ -324,12 +354,12 @@ static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
         if (!n) continue;
         hipError_t e;
         if (G.time_scheme == 0) {
-            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 1, p, 1, s);
+            e = stage_launch(b, G, n, 1, p, 1, s);
             if (e == hipSuccess) e = roeam::launch_copy_back_batch(b->d_solves, G.d_tiles, n, G.shape, p, s);
         } else {
-            e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 1, p, 0, s);
-            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 2, p, 0, s);
-            if (e == hipSuccess) e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, 3, p, 1, s);
+            e = stage_launch(b, G, n, 1, p, 0, s);
+            if (e == hipSuccess) e = stage_launch(b, G, n, 2, p, 0, s);
+            if (e == hipSuccess) e = stage_launch(b, G, n, 3, p, 1, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -473,7 +503,7 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         const bool stable = !b->set_changed && b->queue.empty() && (b->iter & 1) == 0 &&
                             (iterations < 0 || iterations - done_iters >= kGraphIters);
         long ran;
-        if (stable && s != nullptr) {
+        if (stable && s != nullptr && !b->profiling) {
             if (!b->graph_valid) {
                 if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
                 if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -505,10 +535,13 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         // iterations, or when the caller's iteration budget ends; the buffer's
         // previous snapshot (two back) is read first
         const bool budget_end = iterations >= 0 && done_iters >= iterations;
-        if (ran > 1 || b->since_status >= kStatusEvery || budget_end) {
+        // (profiling snapshots and reads the status after every iteration, so
+        // finished solves leave at once and no timed launch is an idle one)
+        if (ran > 1 || b->since_status >= kStatusEvery || budget_end || b->profiling) {
             const int which = (int)(b->status_seq++ & 1);
             if ((rc = process_status(ctx, b, which, true))) return rc;
             if ((rc = enqueue_status(ctx, b, which))) return rc;
+            if (b->profiling && (rc = process_status(ctx, b, which, true))) return rc;
             b->since_status = 0;
         }
     }
@@ -522,6 +555,33 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         for (auto &kv : b->reqs) n += kv.second.state == QUEUED || kv.second.state == RESIDENT;
         *pending = n;
     }
+    return ROEAM_OK;
+}
+
+roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[3],
+                                     long *launches)
+{
+    if (!ctx || !stage_ms) return roeam_fail(ctx, ROEAM_EINVAL, "bad argument");
+    BatchEngine *b = ctx->batch;
+    if (!b) return roeam_fail(ctx, ROEAM_EINVAL, "call roeam_batch_reserve first");
+    b->profiling = true;
+    b->prof_used = 0;
+    b->prof_stage.clear();
+    roeam_status rc = roeam_batch_run(ctx, iterations, pending);
+    b->profiling = false;
+    if (rc) return rc;
+    BHIP(ctx, hipStreamSynchronize(ctx->stream));
+    double sum[3] = {0.0, 0.0, 0.0};
+    long cnt[3] = {0, 0, 0};
+    for (size_t k = 0; k < b->prof_stage.size(); ++k) {
+        float ms = 0.f;
+        BHIP(ctx, hipEventElapsedTime(&ms, b->prof_ev[2 * k], b->prof_ev[2 * k + 1]));
+        const int st = b->prof_stage[k] - 1;
+        sum[st] += ms;
+        cnt[st] += 1;
+    }
+    for (int k = 0; k < 3; ++k) stage_ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    if (launches) *launches = (long)b->prof_stage.size();
     return ROEAM_OK;
 }
 

@@ -181,3 +181,21 @@ def test_server_staggered_requests(C):
         P.step(C, g, prm, q, n)
         torch.cuda.synchronize()
         assert torch.equal(r.solve.q_out[:, :, : g.nx], q[:, :, : g.nx]), r.tag
+
+
+def test_batch_profile_run_matches_batch_run(C):
+    """The profiling driver runs the same kernels: bitwise the same results, one
+    timed launch per stage per group per iteration, positive mean durations."""
+    import paper_1711_09272_amd as P
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 51))
+    cases = [workloads.bump_case(n, rng, 6) for n in (48, 70)]
+    P.batch_reserve(C, 64 << 20)
+    _, a = submit_all(C, cases)
+    P.batch_run(C, -1)
+    ra = collect(C, a)
+    _, b = submit_all(C, cases)
+    stage_ms, launches = P.batch_profile_run(C, -1)
+    rb = collect(C, b)
+    assert launches == 3 * 6 and all(t > 0.0 for t in stage_ms), (stage_ms, launches)
+    for (qa, sa, ca), (qb, sb, cb) in zip(ra, rb):
+        assert ca == cb == P.OK and sa == sb and np.array_equal(qa, qb)
