@@ -83,12 +83,24 @@ typedef struct {
     const double *xn, *yn;
 } roeam_metrics;
 
-/* Variant bits: alternative readings of ambiguous passages.  0 = the scheme
- * of Eqs. (85)-(109) with the default readings. */
+/* Variant bits of the Roe-AM scheme: alternative readings of ambiguous
+ * passages (bits 0-2) and the ablations the paper compares in Sec. 7 (bits
+ * 3-7).  0 = the scheme of Eqs. (85)-(109) with the default readings.  When
+ * both bits 4 and 6 are set bit 4 wins; when both 5 and 7 are set bit 7 wins. */
 #define ROEAM_V_XI_UNGATED   (1u << 0) /* xi as printed in Eq. (86), without the Eq. (68) gate */
 #define ROEAM_V_EXPFIX_F8    (1u << 1) /* f^8(Mbar) weight of Eq. (73) instead of f(Mbar)       */
 #define ROEAM_V_CLAMP_UPRIME (1u << 2) /* clamp |U|' of Eq. (92) at zero                        */
-#define ROEAM_V_SUPPORTED    (ROEAM_V_XI_UNGATED | ROEAM_V_EXPFIX_F8 | ROEAM_V_CLAMP_UPRIME)
+#define ROEAM_V_NO_EQ92      (1u << 3) /* |U|' = |U|: no expansion-shock fix                    */
+#define ROEAM_V_XI_ROE       (1u << 4) /* xi = |U| of classical Roe, Eq. (13)                   */
+#define ROEAM_V_DUP_ROE      (1u << 5) /* dU_p of classical Roe, Eq. (17)                       */
+#define ROEAM_V_XI_EQ46      (1u << 6) /* xi = |U_R + U_L| / 2 of Eq. (46)                      */
+#define ROEAM_V_DUP_ZERO     (1u << 7) /* dU_p = 0                                              */
+#define ROEAM_V_SUPPORTED    0xffu
+
+/* Flux scheme. */
+#define ROEAM_SCHEME_ROEAM      0 /* Roe-AM, Eqs. (85)-(109)                                   */
+#define ROEAM_SCHEME_ROE        1 /* classical Roe, Eq. (7) with Eqs. (8)-(12)                 */
+#define ROEAM_SCHEME_ROE_HARTEN 2 /* classical Roe with Harten's entropy fix, Eqs. (114)-(115) */
 
 /* Scheme parameters.
  *   gamma     ratio of specific heats (Eq. 54), > 1;
@@ -104,7 +116,11 @@ typedef struct {
  *   precision 0: FP64 throughout;
  *             1: flux coefficients in FP32, with the state, the jumps of
  *                Eq. (85), the central term and the residual sum in FP64;
- *   variant   ROEAM_V_* bits.
+ *   variant   ROEAM_V_* bits (Roe-AM scheme only);
+ *   scheme    ROEAM_SCHEME_*; the classical schemes ignore mach_ref, u_ref,
+ *             eps1, eps2, s1_mode and variant in the flux (mach_ref still
+ *             enters the time-step rule below);
+ *   eps_lambda threshold factor of Harten's fix, Eq. (115), >= 0.
  * Time step: dt = cfl / max over cells of
  *   (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega,  ce = c / sqrt(theta_cell),
  * with Si, Sj the means of opposite face vectors and theta_cell of Eq. (101)
@@ -114,6 +130,8 @@ typedef struct {
     double gamma, cfl, mach_ref, u_ref, eps1, eps2;
     int s1_mode, order, time_scheme, precision;
     unsigned variant;
+    int scheme;
+    double eps_lambda;
 } roeam_params;
 
 typedef struct {
@@ -147,11 +165,12 @@ roeam_status roeam_grid_destroy(roeam_grid *grid);
 /* Layout of state arrays: q[k][j][i] at k*ny*pitch + j*pitch + i. */
 roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *pitch);
 /* Tile shape of the stage kernel for this grid (cells per workgroup /
- * threads): 0 = 32x15/256, 1 = 16x15/128, 2 = 8x7/64 (about two faces per
- * thread), 3 = 8x7/128, 4 = 16x15/512, 5 = 32x7/512 (one face per thread),
- * or -1 (default) = chosen by the autotuner, which times every shape on the
- * grid at its first roeam_step and keeps the fastest per (order, precision).
- * Every shape computes bitwise the same result.  EINVAL: shape outside -1..5. */
+ * threads): 0 = 32x15/256, 1 = 16x15/128, 2 = 8x7/64, 6 = 16x15/256,
+ * 7 = 32x7/256 (one or two faces per thread), 3 = 8x7/128, 4 = 16x15/512,
+ * 5 = 32x7/512 (one face per thread), or -1 (default) = chosen by the
+ * autotuner, which times every shape on the grid at its first roeam_step and
+ * keeps the fastest per (order, precision).  Every shape computes bitwise the
+ * same result.  EINVAL: shape outside -1..7. */
 roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
 /* The shape in use for these parameters (-1 if not tuned yet). */
 roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *params, int *shape);

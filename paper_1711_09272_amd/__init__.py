@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5,
 BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 # stage-kernel tile shapes: cells x cells / threads per workgroup
-SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512"]
+SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512", "16x15/256", "32x7/256"]
 
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
@@ -45,7 +45,8 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("mach_ref", ctypes.c_double),
                 ("u_ref", ctypes.c_double), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
                 ("s1_mode", ctypes.c_int), ("order", ctypes.c_int), ("time_scheme", ctypes.c_int),
-                ("precision", ctypes.c_int), ("variant", ctypes.c_uint)]
+                ("precision", ctypes.c_int), ("variant", ctypes.c_uint), ("scheme", ctypes.c_int),
+                ("eps_lambda", ctypes.c_double)]
 
 
 class Metrics(ctypes.Structure):
@@ -116,7 +117,8 @@ def params(d: Dict) -> Params:
     return Params(float(d.get("gamma", 1.4)), float(d.get("cfl", 0.4)), float(d.get("mach_ref", 1.0)),
                   float(d.get("u_ref", 1.0)), float(d.get("eps1", 0.0)), float(d.get("eps2", 0.05)),
                   int(d.get("s1_mode", 0)), int(d.get("order", 1)), int(d.get("time_scheme", 0)),
-                  int(d.get("precision", 0)), int(d.get("variant", 0)))
+                  int(d.get("precision", 0)), int(d.get("variant", 0)), int(d.get("scheme", 0)),
+                  float(d.get("eps_lambda", 0.1)))
 
 
 def _stream_ptr(stream) -> int:

@@ -12,7 +12,11 @@ namespace roeam {
 
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_SLIPWALL = 2, BC_DIRICHLET = 3 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
-enum : unsigned { V_XI_UNGATED = 1u, V_EXPFIX_F8 = 2u, V_CLAMP_UPRIME = 4u };
+enum : unsigned {
+    V_XI_UNGATED = 1u, V_EXPFIX_F8 = 2u, V_CLAMP_UPRIME = 4u, V_NO_EQ92 = 8u,
+    V_XI_ROE = 16u, V_DUP_ROE = 32u, V_XI_EQ46 = 64u, V_DUP_ZERO = 128u
+};
+enum { SCHEME_ROEAM = 0, SCHEME_ROE = 1, SCHEME_ROE_HARTEN = 2 };
 
 // Per-solve time-integration state, resident in device memory.  The step
 // state is double-buffered by step parity p: the first stage kernel of a step
@@ -55,8 +59,8 @@ struct DevSolve {
     int bc[4];
     double bcw[4][4];           // Dirichlet states, primitive (rho, u, v, p)
     // scheme
-    double gamma, gm1, g_gm1, mr2, u_ref, dv_min2, eps1, eps2, cfl, inv_area;
-    int s1_mode, order, precision;
+    double gamma, gm1, g_gm1, igm1, mr2, u_ref, dv_min2, eps1, eps2, eps_lambda, cfl, inv_area;
+    int s1_mode, order, precision, scheme;
     unsigned variant;
     // state
     double *q, *qa, *qb;
@@ -273,6 +277,66 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
 }
 
 // ---------------------------------------------------------------------------
+// Classical Roe flux in the scale form of Eq. (7) with the coefficients of
+// Eqs. (8)-(12) and the eigenvalues |U|, |U - c|, |U + c| of Eq. (6), with
+// Harten's fix of Eqs. (114)-(115) for SCHEME_ROE_HARTEN: an eigenvalue
+// below h = eps_lambda max(eigenvalues) becomes (l^2 / h + h) / 2.  The jump
+// multiplied by xi is the conserved one (energy row rho E) and the pressure
+// vector is (0, n, U), as Eq. (7) has them.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void roe_classic(const DevSolve &S, const double WL[4], const double WR[4], double nx,
+                                            double ny, double F[4])
+{
+    const double rL = WL[0], uL = WL[1], vL = WL[2], pL = WL[3];
+    const double rR = WR[0], uR = WR[1], vR = WR[2], pR = WR[3];
+    const double iL = rcp_nr(rL), iR = rcp_nr(rR);
+    const double qL = uL * uL + vL * vL, qR = uR * uR + vR * vR;
+    const double UL = nx * uL + ny * vL, UR = nx * uR + ny * vR;
+    const double HL = S.g_gm1 * pL * iL + 0.5 * qL, HR = S.g_gm1 * pR * iR + 0.5 * qR;
+    const double dUd = UR - UL, dpd = pR - pL;
+
+    const R rr = sqrtR((R)(rR * iL));
+    const R w1 = rcpR((R)1 + rr);
+    const R rho = rr * (R)rL;
+    const R u = ((R)uL + rr * (R)uR) * w1;
+    const R v = ((R)vL + rr * (R)vR) * w1;
+    const R H = ((R)HL + rr * (R)HR) * w1;
+    const R c2 = (R)S.gm1 * (H - (R)0.5 * (u * u + v * v));
+    const R ic = rsqR(c2);
+    const R c = c2 * ic;
+    const R U = (R)nx * u + (R)ny * v;
+    const R dU = (R)dUd, dp = (R)dpd;
+
+    R l1 = rabs(U), l4 = rabs(U - c), l5 = rabs(U + c);
+    if (S.scheme == SCHEME_ROE_HARTEN) {
+        const R h = (R)S.eps_lambda * rmax(l1, rmax(l4, l5));
+        if (h > (R)0) {
+            const R ih = rcpR(h);
+            l1 = l1 < h ? (R)0.5 * (l1 * l1 * ih + h) : l1;
+            l4 = l4 < h ? (R)0.5 * (l4 * l4 * ih + h) : l4;
+            l5 = l5 < h ? (R)0.5 * (l5 * l5 * ih + h) : l5;
+        }
+    }
+    const R a = (R)0.5 * (l5 + l4) - l1;  // Eqs. (9) and (12)
+    const R b = (R)0.5 * (l5 - l4);       // Eqs. (10) and (11)
+    const double xid = (double)l1;        // Eq. (8)
+    const double pd = (double)(a * rho * dU + b * dp * ic);
+    const double Ud = (double)((b * dU + a * dp * rcpR(rho * c)) * ic);
+    const double rhod = (double)rho;
+    // conserved jumps, energy row with rho E = p / (gamma - 1) + rho |V|^2 / 2
+    const double rEL = pL * S.igm1 + 0.5 * rL * qL;
+    const double rER = pR * S.igm1 + 0.5 * rR * qR;
+    const double PsiL1 = rL * uL, PsiL2 = rL * vL, PsiR1 = rR * uR, PsiR2 = rR * vR;
+    F[0] = 0.5 * (UL * rL + UR * rR) - 0.5 * (xid * (rR - rL) + Ud * rhod);
+    F[1] = 0.5 * ((UL * PsiL1 + pL * nx) + (UR * PsiR1 + pR * nx))
+         - 0.5 * (xid * (PsiR1 - PsiL1) + pd * nx + Ud * (rhod * (double)u));
+    F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
+         - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + Ud * (rhod * (double)v));
+    F[3] = 0.5 * (UL * (rL * HL) + UR * (rR * HR)) - 0.5 * (xid * (rER - rEL) + pd * (double)U + Ud * (rhod * (double)H));
+}
+
+// ---------------------------------------------------------------------------
 // Roe-AM numerical flux, Eqs. (85)-(109), per unit face length.
 // R is the precision of the dissipation coefficients; the side quantities,
 // the central term, the jumps of Eq. (85) and the final assembly stay FP64.
@@ -281,6 +345,10 @@ template <typename R>
 __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4], const double WR[4], double nx,
                                            double ny, double s1d, double F[4])
 {
+    if (__builtin_expect(S.scheme != SCHEME_ROEAM, 0)) {
+        roe_classic<R>(S, WL, WR, nx, ny, F);
+        return;
+    }
     const double rL = WL[0], uL = WL[1], vL = WL[2], pL = WL[3];
     const double rR = WR[0], uR = WR[1], vR = WR[2], pR = WR[3];
 
@@ -310,6 +378,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     const R dU = (R)dUd, dp = (R)dpd;
     const R s1 = (R)s1d;
 
+
     // Mach numbers, Eqs. (93)-(94): M_K = |V_K| / c_K, c_K^2 = gamma p_K / rho_K
     const R c2L = (R)(S.gamma * pL * iL), c2R = (R)(S.gamma * pR * iR);
     const R icLR = rcpR(c2L * c2R);
@@ -333,7 +402,10 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     const R wexp = (S.variant & V_EXPFIX_F8) ? f8Mbar : fMbar;
     const R quarter_term = absU < c ? (R)0.5 : (absU == c ? (R)0.25 : (R)0);
     R absUp = absU - wexp * rmax((R)0, dU) * quarter_term;
-    if (S.variant & V_CLAMP_UPRIME) absUp = rmax(absUp, (R)0);
+    if (__builtin_expect((S.variant & (V_NO_EQ92 | V_CLAMP_UPRIME)) != 0, 0)) {
+        if (S.variant & V_NO_EQ92) absUp = absU;
+        if (S.variant & V_CLAMP_UPRIME) absUp = rmax(absUp, (R)0);
+    }
 
     // basic upwind dissipation xi, Eq. (86) with the Eq. (68) gate
     const R gate = (S.variant & V_XI_UNGATED) ? (R)1 : (R)1 - f8Mbar;
@@ -364,7 +436,15 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
     const R dpp = sU * mUc * dp * ic;
     const R dpu = ((R)1 - s1 + s1 * fM) * rmax((R)0, c - absUp) * rho * dU;
     const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(rabs(Ut), ct));
-    const R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
+    R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
+    // ablations of Sec. 7: xi of Eq. (46) (no velocity positivity) or of
+    // Eq. (13); dU_p of classical Roe, Eq. (17), or none
+    if (__builtin_expect((S.variant & (V_XI_EQ46 | V_XI_ROE | V_DUP_ROE | V_DUP_ZERO)) != 0, 0)) {
+        if (S.variant & V_XI_EQ46) xi = (R)rabs(0.5 * (UR + UL));
+        if (S.variant & V_XI_ROE) xi = absU;
+        if (S.variant & V_DUP_ROE) dUp = rmax((R)0, c - absU) * dp * rcpR(rho * c2);
+        if (S.variant & V_DUP_ZERO) dUp = (R)0;
+    }
     const R dUu = (R)0.5 * sU * mUc * dU * ic;
 
     // Eq. (85): F = central - (1/2){xi dPsi + (dpp + dpu)(0, n, 0) + dUp PsiHat + dUu (Psi_R + Psi_L)}

@@ -127,7 +127,7 @@ __device__ __forceinline__ void tile_face(const DevSolve &S, const double (&sW)[
         }
     }
     double s1 = 1.0;
-    if (S.s1_mode == 0) {
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
         double a;
         if (XDIR) {
             a = rmin(rmin(sPx[fj + 1][fi], sPy[fj][fi]), rmin(sPy[fj + 1][fi], rmin(sPy[fj][fi + 1], sPy[fj + 1][fi + 1])));
@@ -250,7 +250,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     __syncthreads();
 
     // 2. detector ratios, Eq. (97), from cell-centre values
-    if (S.s1_mode == 0) {
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
         for (int e = tid; e < (TY + 2) * (TX + 1); e += NT) {
             const int r = e / (TX + 1), fi = e - r * (TX + 1);
             const int ly = r - 1 + HL;
@@ -478,10 +478,24 @@ __global__ void k_rate_out(const Slot *s, double *out)
 struct TileShape {
     int tx, ty, nt;
 };
-// 0-2: about two faces per thread; 3-5: one face per thread (split)
-static const TileShape kShapes[6] = {{32, 15, 256}, {16, 15, 128}, {8, 7, 64},
-                                     {8, 7, 128},   {16, 15, 512}, {32, 7, 512}};
-constexpr int kNumShapes = 6;
+// Tile shapes: id, TX, TY, threads, split.  Non-split shapes sweep the faces
+// in one or two passes per direction; split shapes give every face a thread.
+// 6 and 7 cover each face direction in one pass of 256 threads, so that a
+// pair of 256x256 grids fits the chip in one round of workgroups.
+#define ROEAM_SHAPES(X)               \
+    X(0, 32, 15, 256, false)          \
+    X(1, 16, 15, 128, false)          \
+    X(2, 8, 7, 64, false)             \
+    X(3, 8, 7, 128, true)             \
+    X(4, 16, 15, 512, true)           \
+    X(5, 32, 7, 512, true)            \
+    X(6, 16, 15, 256, false)          \
+    X(7, 32, 7, 256, false)
+
+#define ROEAM_SHAPE_ENTRY(ID, TX, TY, NT, SPLIT) {TX, TY, NT},
+static const TileShape kShapes[] = {ROEAM_SHAPES(ROEAM_SHAPE_ENTRY)};
+#undef ROEAM_SHAPE_ENTRY
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 void tile_shape(int shape, int *tx, int *ty)
 {
@@ -492,15 +506,9 @@ void tile_shape(int shape, int *tx, int *ty)
 
 int tile_shape_count() { return kNumShapes; }
 
-#define ROEAM_SHAPE_SWITCH(KERNEL, ...)                                                                                  \
-    switch (shape) {                                                                                                     \
-    case 0: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 32, 15, 256, false>), dim3(blocks), dim3(256), 0, st, __VA_ARGS__); break; \
-    case 1: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 16, 15, 128, false>), dim3(blocks), dim3(128), 0, st, __VA_ARGS__); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 8, 7, 64, false>), dim3(blocks), dim3(64), 0, st, __VA_ARGS__); break;    \
-    case 3: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 8, 7, 128, true>), dim3(blocks), dim3(128), 0, st, __VA_ARGS__); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 16, 15, 512, true>), dim3(blocks), dim3(512), 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KERNEL<ORDER, PREC, METRIC, 32, 7, 512, true>), dim3(blocks), dim3(512), 0, st, __VA_ARGS__); break; \
-    }
+#define ROEAM_SHAPE_CASE(ID, TX, TY, NT, SPLIT)                                                              \
+    case ID: hipLaunchKernelGGL((ROEAM_KERNEL<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>), dim3(blocks), dim3(NT), 0, st, \
+                                ROEAM_ARGS); break;
 
 template <int ORDER, int PREC, int METRIC>
 static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
@@ -509,7 +517,11 @@ static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape
     const TileShape &sh = kShapes[shape];
     const int nt = ((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty);
     const int blocks = ((nt + 7) >> 3) << 3;
-    ROEAM_SHAPE_SWITCH(k_stage_single, dS, stage, p, last, r_out)
+#define ROEAM_KERNEL k_stage_single
+#define ROEAM_ARGS dS, stage, p, last, r_out
+    switch (shape) { ROEAM_SHAPES(ROEAM_SHAPE_CASE) }
+#undef ROEAM_KERNEL
+#undef ROEAM_ARGS
 }
 
 template <int ORDER, int PREC>
@@ -539,7 +551,11 @@ static void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, i
                                int last, hipStream_t st)
 {
     const int blocks = ((ntiles + 7) >> 3) << 3;
-    ROEAM_SHAPE_SWITCH(k_stage_batch, solves, tiles, ntiles, stage, p, last)
+#define ROEAM_KERNEL k_stage_batch
+#define ROEAM_ARGS solves, tiles, ntiles, stage, p, last
+    switch (shape) { ROEAM_SHAPES(ROEAM_SHAPE_CASE) }
+#undef ROEAM_KERNEL
+#undef ROEAM_ARGS
 }
 
 template <int ORDER, int PREC>
@@ -631,14 +647,11 @@ hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles
 {
     if (ntiles <= 0) return hipSuccess;
     const int blocks = ((ntiles + 7) >> 3) << 3;
-    switch (shape) {
-    case 0: hipLaunchKernelGGL((k_copy_back_batch<32, 15, 256>), dim3(blocks), dim3(256), 0, st, solves, tiles, ntiles, p); break;
-    case 1: hipLaunchKernelGGL((k_copy_back_batch<16, 15, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, p); break;
-    case 2: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 64>), dim3(blocks), dim3(64), 0, st, solves, tiles, ntiles, p); break;
-    case 3: hipLaunchKernelGGL((k_copy_back_batch<8, 7, 128>), dim3(blocks), dim3(128), 0, st, solves, tiles, ntiles, p); break;
-    case 4: hipLaunchKernelGGL((k_copy_back_batch<16, 15, 512>), dim3(blocks), dim3(512), 0, st, solves, tiles, ntiles, p); break;
-    default: hipLaunchKernelGGL((k_copy_back_batch<32, 7, 512>), dim3(blocks), dim3(512), 0, st, solves, tiles, ntiles, p); break;
-    }
+#define ROEAM_COPY_CASE(ID, TX, TY, NT, SPLIT)                                                                 \
+    case ID: hipLaunchKernelGGL((k_copy_back_batch<TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, solves, tiles, ntiles, \
+                                p); break;
+    switch (shape) { ROEAM_SHAPES(ROEAM_COPY_CASE) }
+#undef ROEAM_COPY_CASE
     return hipGetLastError();
 }
 

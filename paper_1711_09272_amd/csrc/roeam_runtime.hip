@@ -48,6 +48,10 @@ roeam_status roeam_check_params(roeam_ctx *ctx, const roeam_params *p, bool need
     if (p->time_scheme != 0 && p->time_scheme != 1) return fail(ctx, ROEAM_EINVAL, "time_scheme must be 0 or 1");
     if (p->precision != 0 && p->precision != 1) return fail(ctx, ROEAM_EINVAL, "precision must be 0 or 1");
     if (p->variant & ~ROEAM_V_SUPPORTED) return fail(ctx, ROEAM_EINVAL, "unsupported variant bits");
+    if (p->scheme != ROEAM_SCHEME_ROEAM && p->scheme != ROEAM_SCHEME_ROE && p->scheme != ROEAM_SCHEME_ROE_HARTEN)
+        return fail(ctx, ROEAM_EINVAL, "scheme must be ROEAM_SCHEME_ROEAM, _ROE or _ROE_HARTEN");
+    if (!(p->eps_lambda >= 0.0) || !std::isfinite(p->eps_lambda))
+        return fail(ctx, ROEAM_EINVAL, "eps_lambda must be >= 0 (Eq. 115)");
     return ROEAM_OK;
 }
 
@@ -81,6 +85,7 @@ DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q,
     S.gamma = p->gamma;
     S.gm1 = p->gamma - 1.0;
     S.g_gm1 = p->gamma / (p->gamma - 1.0);
+    S.igm1 = 1.0 / (p->gamma - 1.0);
     S.mr2 = p->mach_ref * p->mach_ref;
     S.u_ref = p->u_ref;
     S.dv_min2 = (1e-5 * p->u_ref) * (1e-5 * p->u_ref);
@@ -92,6 +97,8 @@ DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q,
     S.order = p->order;
     S.precision = p->precision;
     S.variant = p->variant;
+    S.scheme = p->scheme;
+    S.eps_lambda = p->eps_lambda;
     S.q = q;
     S.qa = qa;
     S.qb = qb;
