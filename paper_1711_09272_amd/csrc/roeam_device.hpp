@@ -81,10 +81,14 @@ __device__ __forceinline__ float rmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double rabs(double a) { return fabs(a); }
 __device__ __forceinline__ float rabs(float a) { return fabsf(a); }
 
-// Reciprocal, quotient and reciprocal square root.  FP64: Newton-Raphson
-// refinement (two iterations) of the hardware estimates v_rcp_f64 and
-// v_rsq_f64, a few ulp from the exact value for the normal-range operands
-// of this solver.  FP32: the hardware instructions (about 1 ulp).
+// Reciprocal, quotient and reciprocal square root.  The hardware estimates
+// v_rcp_f64 and v_rsq_f64 are good to about 2^-24 relative.  Two Newton steps
+// (rcp_nr, rsq_nr) reach a correctly rounded or 1-ulp result: used for the
+// primitives of the cell states, the side quantities of the central flux and
+// the time-step rule.  One step (rcp_nr1, rsq_nr1: within about 20 ulp) is
+// used for the dissipation coefficients of the flux (the R functions below
+// for R = double), whose error is scaled by the jumps of Eq. (85).  FP32: the
+// hardware instructions (about 1 ulp).
 __device__ __forceinline__ double rcp_nr(double b)
 {
     double r = __builtin_amdgcn_rcp(b);
@@ -93,9 +97,15 @@ __device__ __forceinline__ double rcp_nr(double b)
     e = fma(-b, r, 1.0);
     return fma(r, e, r);
 }
-__device__ __forceinline__ double div_nr(double a, double b)
+__device__ __forceinline__ double rcp_nr1(double b)
 {
-    const double r = rcp_nr(b);
+    const double r = __builtin_amdgcn_rcp(b);
+    return fma(r, fma(-b, r, 1.0), r);
+}
+// a / b: one residual correction of a * (1/b)
+__device__ __forceinline__ double div_nr1(double a, double b)
+{
+    const double r = rcp_nr1(b);
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
 }
@@ -108,15 +118,20 @@ __device__ __forceinline__ double rsq_nr(double x)
     e = fma(-hx * y, y, 0.5);
     return fma(y, e, y);
 }
-__device__ __forceinline__ double rcpR(double b) { return rcp_nr(b); }
-__device__ __forceinline__ double rsqR(double x) { return rsq_nr(x); }
+__device__ __forceinline__ double rsq_nr1(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(y, fma(-0.5 * x * y, y, 0.5), y);
+}
+__device__ __forceinline__ double rcpR(double b) { return rcp_nr1(b); }
+__device__ __forceinline__ double rsqR(double x) { return rsq_nr1(x); }
 // square root of a positive operand as x rsq(x)
-__device__ __forceinline__ double sqrtR(double x) { return x * rsq_nr(x); }
+__device__ __forceinline__ double sqrtR(double x) { return x * rsq_nr1(x); }
 __device__ __forceinline__ float rcpR(float b) { return __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ float rsqR(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
 // square root of a non-negative operand (zero allowed)
-__device__ __forceinline__ double sqrt0R(double x) { return x > 0.0 ? x * rsq_nr(x) : 0.0; }
+__device__ __forceinline__ double sqrt0R(double x) { return x > 0.0 ? x * rsq_nr1(x) : 0.0; }
 __device__ __forceinline__ float sqrt0R(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Eq. (98): f(phi) = min(phi sqrt(4 + (1 - phi^2)^2) / (1 + phi^2), 1), with
@@ -144,7 +159,7 @@ __device__ __forceinline__ double detector_P(double pA, double rA, double pB, do
     // the smaller of the two ratios, chosen by cross-multiplication, one division
     const double pn = rmin(pA, pB), pd = rmax(pA, pB), rn = rmin(rA, rB), rd = rmax(rA, rB);
     const bool use_p = pn * rd <= rn * pd;
-    return div_nr(use_p ? pn : rn, use_p ? pd : rd);
+    return div_nr1(use_p ? pn : rn, use_p ? pd : rd);
 }
 
 // ---------------------------------------------------------------------------
