@@ -251,15 +251,26 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 
     // 2. detector ratios, Eq. (97), from cell-centre values
     if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
-        for (int e = tid; e < (TY + 2) * (TX + 1); e += NT) {
-            const int r = e / (TX + 1), fi = e - r * (TX + 1);
-            const int ly = r - 1 + HL;
-            sPx[r][fi] = detector_P(sW[3][ly][fi - 1 + HL], sW[0][ly][fi - 1 + HL], sW[3][ly][fi + HL], sW[0][ly][fi + HL]);
-        }
-        for (int e = tid; e < (TY + 1) * (TX + 2); e += NT) {
-            const int fr = e / (TX + 2), cc = e - fr * (TX + 2);
-            const int lx = cc - 1 + HL;
-            sPy[fr][cc] = detector_P(sW[3][fr - 1 + HL][lx], sW[0][fr - 1 + HL][lx], sW[3][fr + HL][lx], sW[0][fr + HL][lx]);
+        // one sweep over the i-face ratios then the j-face ratios, so that
+        // the threads stay busy across the two arrays
+        constexpr int NPX = (TY + 2) * (TX + 1), NPY = (TY + 1) * (TX + 2);
+        for (int e = tid; e < NPX + NPY; e += NT) {
+            int a, b;  // LDS cell offsets (within one plane of sW) of the two cells
+            double *dst;
+            if (e < NPX) {
+                const int r = e / (TX + 1), fi = e - r * (TX + 1);
+                a = (r - 1 + HL) * LX + fi - 1 + HL;
+                b = a + 1;
+                dst = &sPx[r][fi];
+            } else {
+                const int f = e - NPX;
+                const int fr = f / (TX + 2), cc = f - fr * (TX + 2);
+                a = (fr - 1 + HL) * LX + cc - 1 + HL;
+                b = a + LX;
+                dst = &sPy[fr][cc];
+            }
+            const double *p3 = &sW[3][0][0], *p0 = &sW[0][0][0];
+            *dst = detector_P(p3[a], p0[a], p3[b], p0[b]);
         }
         __syncthreads();
     }
