@@ -240,6 +240,23 @@ static roeam_status process_status(roeam_ctx *ctx, BatchEngine *b, int which, bo
     return ROEAM_OK;
 }
 
+// Tile shape of a group that forms with no forced or tuned shape on its
+// first grid, from the cells the group is about to hold (every queued solve
+// of the group): one-face-per-thread 8x7 tiles for small totals, where the
+// launch is latency-bound and needs many short workgroups; 16x15 tiles with
+// one face per thread and direction pass above about 200k cells, where fewer
+// halo cells per tile cell pay off (measured crossover on MI355X).
+static int untuned_shape(const BatchEngine *b, int group)
+{
+    long long cells = 0;
+    for (uint64_t tk : b->queue) {
+        auto it = b->reqs.find(tk);
+        if (it != b->reqs.end() && it->second.group == group)
+            cells += (long long)it->second.d.grid->nx * it->second.d.grid->ny;
+    }
+    return cells >= 200000 ? 6 : 3;
+}
+
 // Admit queued solves that fit (first fit in submission order).
 static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
 {
@@ -277,7 +294,7 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         Group &G = b->groups[r.group];
         if (G.tiles.empty()) {
             int sh = g->shape_forced >= 0 ? g->shape_forced : g->shape_tuned[r.d.params.order - 1][r.d.params.precision];
-            if (sh < 0) sh = (long long)g->nx * g->ny >= (1ll << 20) ? 0 : 3;
+            if (sh < 0) sh = untuned_shape(b, r.group);
             if (sh != G.shape) b->graph_valid = false;
             G.shape = sh;
         }
