@@ -212,9 +212,11 @@ __device__ __forceinline__ void unit_normal(const DevSolve &S, double sx, double
         else { nx = 0.0; ny = 1.0; len = sy; }
         return;
     }
-    len = sqrt(sx * sx + sy * sy);
-    nx = sx / len;
-    ny = sy / len;
+    const double s2 = sx * sx + sy * sy;
+    const double il = rsq_nr(s2);
+    len = s2 * il;
+    nx = sx * il;
+    ny = sy * il;
 }
 template <int METRIC>
 __device__ __forceinline__ double cell_area(const DevSolve &S, int i, int j)
@@ -482,7 +484,8 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
     const double c2 = S.gamma * W[3] * rcp_nr(W[0]);
     const double M2 = (W[1] * W[1] + W[2] * W[2]) * rcp_nr(c2);
     const double theta = rmin(rmax(S.mr2, M2), 1.0);
-    const double ce = sqrt(c2 * rcp_nr(theta));
+    const double ce2 = c2 * rcp_nr(theta);
+    const double ce = ce2 * rsq_nr(ce2);
     double six, siy, sjx, sjy, li, lj;
     if (METRIC == 0) {
         six = S.dy; siy = 0.0; sjx = 0.0; sjy = S.dx; li = S.dy; lj = S.dx;
@@ -494,11 +497,12 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
         yface_vec<METRIC>(S, i, j, ax, ay);
         yface_vec<METRIC>(S, i, j + 1, bx, by);
         sjx = 0.5 * (ax + bx); sjy = 0.5 * (ay + by);
-        li = sqrt(six * six + siy * siy);
-        lj = sqrt(sjx * sjx + sjy * sjy);
+        const double li2 = six * six + siy * siy, lj2 = sjx * sjx + sjy * sjy;
+        li = li2 * rsq_nr(li2);
+        lj = lj2 * rsq_nr(lj2);
     }
     const double sum = fabs(W[1] * six + W[2] * siy) + ce * li + fabs(W[1] * sjx + W[2] * sjy) + ce * lj;
-    return METRIC == 0 ? sum * S.inv_area : sum / cell_area<METRIC>(S, i, j);
+    return METRIC == 0 ? sum * S.inv_area : sum * rcp_nr(cell_area<METRIC>(S, i, j));
 }
 
 __device__ __forceinline__ bool physical(const double W[4])
