@@ -44,11 +44,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: int):
-    """HBM bytes per stage launch from committed rocprofv3 counter summaries,
-    or None when missing or taken on a different kernel source."""
+def counter_summary(workload: str, precision: int, kind: str, key: str):
+    """One figure of a committed rocprofv3 counter summary (profiles/), or None
+    when it is missing or was taken on a different kernel source."""
     tag = workload + ("_fp32coef" if precision else "")
-    path = os.path.join(ROOT, "profiles", f"stage_kernel_{tag}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"stage_kernel_{tag}_{kind}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -59,9 +59,25 @@ def measured_traffic(workload: str, precision: int):
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(workload: str, precision: int):
+    """HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE passes, scaled)."""
+    return counter_summary(workload, precision, "traffic", "hbm_bytes_per_launch")
+
+
+def measured_valu(workload: str, precision: int):
+    """VALU lane-instructions per cell-stage (SQ_INSTS_VALU x 64 / cells)."""
+    return counter_summary(workload, precision, "valu", "valu_lane_instr_per_cell_stage")
+
+
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (one
+# wave64 VALU instruction per SIMD every 4 clocks; an FP64 FMA is one such
+# instruction, which is where 78.6 TFLOP/s FP64 comes from).
+PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 
 
 def make_cases(workload: str, precision: int):
@@ -429,6 +445,13 @@ def main():
     bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload, args.precision)
+    valu = measured_valu(args.workload, args.precision)
+    alu = None
+    if valu is not None:
+        lane_rate = valu * cells / (launch_ms / 1e3)
+        alu = {"bound": "alu", "achieved": round(lane_rate / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 3),
+               "unit": "T VALU lane-instr/s", "frac": round(lane_rate / PEAK_VALU_LANE_INSTR, 4),
+               "valu_lane_instr_per_cell_stage": valu}
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
@@ -436,6 +459,8 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 5),
         "traffic": traffic,
+        "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
+        "alu": alu,
         "kernel": "%s<order 2, FP%s, uniform, %s>" % (kname, "64" if args.precision == 0 else "32-coef",
                                                       P.SHAPES[shape] if shape >= 0 else "?"),
         "kernel_grid": kgrid,
