@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -95,6 +96,7 @@ struct Request {
     roeam_status rc = ROEAM_OK;
     roeam_step_stats stats{};
     hipEvent_t out_ev = nullptr;
+    long done_iter = 0;  // scheduler iteration after which its step budget is spent
 };
 
 struct Group {
@@ -274,6 +276,7 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         r.idx = idx;
         r.off = off;
         r.state = RESIDENT;
+        r.done_iter = b->iter + r.d.nsteps;
         b->by_idx[idx] = *it;
         b->hw = std::max(b->hw, idx + 1);
         const roeam_grid *g = r.d.grid;
@@ -516,9 +519,16 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
             return roeam_fail(ctx, ROEAM_ENOMEM, "queued solve does not fit the arena");
         }
         // iterations of the resident set; a stable set with nothing waiting runs
-        // kGraphIters iterations from one captured graph
+        // kGraphIters iterations from one captured graph, unless a resident
+        // solve spends its step budget sooner: then single iterations run up to
+        // that iteration and the status is snapshot right after it, so the
+        // solve leaves without waiting for the regular snapshot cadence
+        long next_done = LONG_MAX;
+        for (int i = 0; i < b->hw; ++i)
+            if (b->by_idx[i]) next_done = std::min(next_done, b->reqs[b->by_idx[i]].done_iter);
         const bool stable = !b->set_changed && b->queue.empty() && (b->iter & 1) == 0 &&
-                            (iterations < 0 || iterations - done_iters >= kGraphIters);
+                            (iterations < 0 || iterations - done_iters >= kGraphIters) &&
+                            next_done - b->iter >= kGraphIters;
         long ran;
         if (stable && s != nullptr && !b->profiling) {
             if (!b->graph_valid) {
@@ -554,7 +564,8 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         const bool budget_end = iterations >= 0 && done_iters >= iterations;
         // (profiling snapshots and reads the status after every iteration, so
         // finished solves leave at once and no timed launch is an idle one)
-        if (ran > 1 || b->since_status >= kStatusEvery || budget_end || b->profiling) {
+        const bool budget_spent = b->iter == next_done;
+        if (ran > 1 || b->since_status >= kStatusEvery || budget_end || budget_spent || b->profiling) {
             const int which = (int)(b->status_seq++ & 1);
             if ((rc = process_status(ctx, b, which, true))) return rc;
             if ((rc = enqueue_status(ctx, b, which))) return rc;
