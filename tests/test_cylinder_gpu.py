@@ -1,0 +1,101 @@
+"""Body-fitted O-grids on the GPU (Secs. 7.5 and 7.6): the Mach-20 carbuncle
+configuration (upstream half O-grid, curved slip wall, free-stream far field,
+transmissive cuts) and the low-Mach cylinder (100 x 72 O-grid, stretched,
+potential-flow start).  Parity with the oracle at the usual bars, then the
+physical checks of the oracle pins on the GPU's own results."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import ctx, gpu_residual, gpu_run, residual_error, say, state_error
+from test_oracle_solver_pins import _ring_case, prim
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module")
+def C():
+    return ctx()
+
+
+def cases():
+    yield "ring_free_stream", _ring_case()
+    yield "carbuncle_roeam_o1", workloads.cylinder_carbuncle()
+    yield "carbuncle_roe_o1", workloads.cylinder_carbuncle(scheme=1)
+    yield "carbuncle_roeam_o2_jitter", workloads.cylinder_carbuncle(order=2, time_scheme=1, eps1=1.0, jitter=0.01)
+    yield "cylinder_M0.01", workloads.cylinder_low_mach(mach=0.01)
+    yield "cylinder_M0.001_roe", workloads.cylinder_low_mach(mach=0.001, scheme=1)
+
+
+CASES = list(cases())
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[n for n, _ in CASES])
+def test_ogrid_residual_fp64(C, name, case):
+    say(f"[o-grid residual fp64] {name} {case.nx}x{case.ny}")
+    r_or, scale = oracle.residual(case, with_scale=True)
+    err = residual_error(gpu_residual(C, case), r_or, scale)
+    say(f"    err per row {err}")
+    assert np.all(err <= TOL64), err
+
+
+@pytest.mark.parametrize("name,case", [c for c in CASES if c[0] in ("carbuncle_roeam_o1", "cylinder_M0.01")],
+                         ids=lambda v: v if isinstance(v, str) else "")
+def test_ogrid_residual_fp32_flux(C, name, case):
+    r_or, scale = oracle.residual(case, with_scale=True)
+    prm = dict(case.params)
+    prm["precision"] = 1
+    err = residual_error(gpu_residual(C, case, params=prm), r_or, scale)
+    say(f"[o-grid residual fp32-flux] {name} err {err}")
+    assert np.all(err <= TOL32), err
+
+
+@pytest.mark.parametrize("name,case,steps", [("carbuncle_roeam_o1", workloads.cylinder_carbuncle(), 200),
+                                             ("carbuncle_roe_o1", workloads.cylinder_carbuncle(scheme=1), 200),
+                                             ("cylinder_M0.01", workloads.cylinder_low_mach(mach=0.01), 20)],
+                         ids=lambda v: v if isinstance(v, str) else "")
+def test_ogrid_steps(C, name, case, steps):
+    q_or, st_or = oracle.run(case, nsteps=steps)
+    q_gpu, st = gpu_run(C, case, nsteps=steps)
+    err = state_error(q_gpu, q_or)
+    say(f"[o-grid steps] {name} {steps} steps err {err:.3e} t {st['t']:.6e} / {st_or['t']:.6e}")
+    assert st["steps"] == steps and abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
+    assert err <= TOL64
+
+
+def test_gpu_bow_shock_standoff_billig(C):
+    """The oracle pin's physics on the GPU's own run: 3000 forward-Euler steps
+    of the Mach-20 configuration put the bow shock on the stagnation line within
+    one radial cell of Billig's correlation."""
+    c = workloads.cylinder_carbuncle()
+    q, st = gpu_run(C, c, nsteps=3000)
+    assert st["nonphys"] == 0 and st["steps"] == 3000
+    _, _, _, p = prim(q)
+    X, Y = workloads._node_centres(c.xn, c.yn)
+    R = np.hypot(X, Y)
+    billig = 1.0 + 0.386 * math.exp(4.67 / 400.0)
+    for i in (c.nx // 2 - 1, c.nx // 2):
+        j = np.where(p[:, i] > 100.0)[0].max()
+        assert p[j + 1, i] < 10.0
+        shock = 0.5 * (R[j, i] + R[j + 1, i])
+        say(f"    ray {i}: shock at r = {shock:.4f} (Billig {billig:.4f})")
+        assert abs(shock - billig) <= 0.05
+
+
+def test_gpu_low_mach_residual_scaling(C):
+    """Fig. 12's M^2 (Roe-AM) against M (Roe) scaling on the GPU's residuals."""
+    ratios = {}
+    for scheme in (0, 1):
+        nrm = []
+        for mach in (0.01, 0.001):
+            c = workloads.cylinder_low_mach(mach=mach, scheme=scheme)
+            r = gpu_residual(C, c)
+            nrm.append(np.sqrt((r[1] ** 2 + r[2] ** 2).mean()))
+        ratios[scheme] = nrm[0] / nrm[1]
+    say(f"    residual ratio per decade of M: Roe-AM {ratios[0]:.2f}, Roe {ratios[1]:.2f}")
+    assert 80 < ratios[0] < 120 and 8 < ratios[1] < 12

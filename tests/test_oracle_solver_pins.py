@@ -327,3 +327,74 @@ def test_bump_state_device_matches_host_recipe():
     q_dev = workloads.bump_state_device(37, spec, 40, device="cpu").numpy()
     assert q_dev.shape == (4, 37, 40) and not q_dev[:, :, 37:].any()
     assert np.allclose(q_dev[:, :, :37], q_host, rtol=1e-14, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Body-fitted O-grids (Secs. 7.5 and 7.6)
+# --------------------------------------------------------------------------
+
+def _ring_case(n_circ=64, n_rad=16, mach=0.5, angle=0.5):
+    xn, yn = workloads.cylinder_ogrid(n_circ, n_rad, 1.0, 5.0, ratio=1.1)
+    gamma = 1.4
+    u, v = mach * math.cos(angle), mach * math.sin(angle)
+    fs = workloads.conserved(gamma, 1.0, u, v, 1.0 / gamma)
+    q0 = np.stack([np.full((n_rad, n_circ), fs[k]) for k in range(4)])
+    bc_state = np.zeros((4, 4))
+    bc_state[workloads.SOUTH] = bc_state[workloads.NORTH] = fs
+    prm = workloads.default_params(order=2, eps1=1.0, mach_ref=mach, u_ref=mach)
+    return workloads.Case(name="ring", q0=q0, params=prm, bc=(PERIODIC, PERIODIC, DIRICHLET, DIRICHLET),
+                          xn=xn, yn=yn, bc_state=bc_state)
+
+
+def test_ogrid_cell_areas_and_free_stream():
+    """A full O-grid ring: every cell positively oriented, the areas sum to the
+    area between the two inscribed polygons (the shoelace formula is exact for
+    them), and a uniform flow has zero residual to rounding (closed cells: the
+    face vectors of each cell sum to zero)."""
+    c = _ring_case()
+    om = oracle.cell_areas(c)
+    assert om.min() > 0.0
+    n = c.nx
+    poly = 0.5 * n * math.sin(2.0 * math.pi / n) * (5.0 ** 2 - 1.0)
+    assert abs(om.sum() - poly) <= 1e-12 * poly
+    r, scale = oracle.residual(c, with_scale=True)
+    for k in range(4):
+        assert np.abs(r[k]).max() <= 1e-13 * scale[k].max()
+
+
+def test_cylinder_bow_shock_standoff_billig():
+    """Sec. 7.5 configuration (Mach 20, upstream half O-grid, slip wall, first
+    order, forward Euler): after the start-up transient (t ~ 1, 3000 steps) the
+    bow shock on the stagnation line stands where Billig's correlation for
+    cylinders puts it, Delta / R = 0.386 exp(4.67 / M^2) = 0.3905, to within one
+    radial cell (0.05 R)."""
+    c = workloads.cylinder_carbuncle()
+    q, st = oracle.run(c, nsteps=3000)
+    assert st["nonphys"] == 0
+    _, _, _, p = prim(q)
+    X, Y = workloads._node_centres(c.xn, c.yn)
+    R = np.hypot(X, Y)
+    billig = 1.0 + 0.386 * math.exp(4.67 / 400.0)
+    for i in (c.nx // 2 - 1, c.nx // 2):  # the two rays next to the stagnation line
+        j = np.where(p[:, i] > 100.0)[0].max()  # last compressed cell (post-shock p ~ 400-500)
+        assert p[j + 1, i] < 10.0  # the next cell is still free stream (p = 1)
+        shock = 0.5 * (R[j, i] + R[j + 1, i])
+        assert abs(shock - billig) <= 0.05, (shock, billig)
+
+
+def test_cylinder_low_mach_residual_scaling_fig12():
+    """Sec. 7.6 / Fig. 12 on the 100 x 72 O-grid: for the incompressible
+    potential flow (pressure fluctuation ~ M^2) the momentum residual of Roe-AM
+    scales with M^2 and that of classical Roe with M, as Eqs. (31)-(32) predict."""
+    ratios = {}
+    for scheme in (oracle.SCHEME_ROEAM, oracle.SCHEME_ROE):
+        nrm = []
+        for mach in (0.01, 0.001):
+            c = workloads.cylinder_low_mach(mach=mach)
+            prm = dict(c.params)
+            prm["scheme"] = scheme
+            r = oracle.residual(c, params=prm)
+            nrm.append(np.sqrt((r[1] ** 2 + r[2] ** 2).mean()))
+        ratios[scheme] = nrm[0] / nrm[1]
+    assert 80 < ratios[oracle.SCHEME_ROEAM] < 120
+    assert 8 < ratios[oracle.SCHEME_ROE] < 12

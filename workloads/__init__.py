@@ -235,6 +235,109 @@ def odd_even(nx: int = 800, ny: int = 80, mach: float = 20.0, eps_y: float = 1e-
 
 
 # --------------------------------------------------------------------------
+# Body-fitted O-grids around a circular cylinder (Secs. 7.5 and 7.6)
+# --------------------------------------------------------------------------
+
+def cylinder_ogrid(n_circ: int, n_rad: int, r_in: float = 1.0, r_out: float = 4.0, ratio: float = 1.0,
+                   half: bool = False):
+    """Nodes of an O-grid around a cylinder of radius r_in centred at the origin:
+    i runs clockwise around the circumference (n_circ cells; node column n_circ
+    coincides with column 0, so the i direction is periodic), j outward
+    (n_rad cells) with radial spacing growing geometrically by ``ratio`` per
+    cell.  Clockwise i and outward j make the cells positively oriented for the
+    face-vector convention of the solver.  half=True: only the upstream half
+    (x <= 0), from the bottom (theta = -90 deg) clockwise to the top.  Returns
+    xn, yn of shape (n_rad + 1, n_circ + 1)."""
+    if ratio == 1.0:
+        w = np.arange(n_rad + 1, dtype=np.float64) / n_rad
+    else:
+        w = (ratio ** np.arange(n_rad + 1, dtype=np.float64) - 1.0) / (ratio ** n_rad - 1.0)
+    r = r_in + (r_out - r_in) * w
+    if half:
+        th = -0.5 * math.pi - math.pi * np.arange(n_circ + 1, dtype=np.float64) / n_circ
+    else:
+        th = -2.0 * math.pi * np.arange(n_circ + 1, dtype=np.float64) / n_circ
+    R, TH = np.meshgrid(r, th, indexing="ij")
+    xn, yn = R * np.cos(TH), R * np.sin(TH)
+    if half:
+        xn[:, 0] = xn[:, -1] = 0.0  # the cut along the y axis, exactly
+    else:
+        xn[:, -1], yn[:, -1] = xn[:, 0], yn[:, 0]  # close the ring exactly
+    return xn, yn
+
+
+def _node_centres(xn, yn):
+    return 0.25 * (xn[:-1, :-1] + xn[:-1, 1:] + xn[1:, :-1] + xn[1:, 1:]), \
+        0.25 * (yn[:-1, :-1] + yn[:-1, 1:] + yn[1:, :-1] + yn[1:, 1:])
+
+
+def cylinder_carbuncle(n_circ: int = 160, n_rad: int = 20, mach: float = 20.0, r_out: float = 2.0,
+                       jitter: float = 0.0, seed: Optional[int] = None, **params) -> Case:
+    """Sec. 7.5: Mach-20 flow (rho = 1.4, p = 1, so c = 1) past a unit cylinder on
+    160 x 20 cells (circumference x radius) of the upstream half O-grid (the
+    bow-shock region; the near-vacuum wake is outside the domain, as in the
+    usual form of this test); slip wall on the cylinder, free-stream Dirichlet
+    state on the outer arc, transmissive (supersonic outflow) cuts at the top
+    and bottom; impulsive start from the free stream.  First order, forward
+    Euler (the paper's shock tests use a first-order space discretisation)."""
+    gamma = params.get("gamma", 1.4)
+    xn, yn = cylinder_ogrid(n_circ, n_rad, 1.0, r_out, half=True)
+    if jitter:
+        # seeded displacement of the interior nodes along the radius, a fraction
+        # ``jitter`` of the radial spacing (the seed of a shock instability)
+        rng = np.random.Generator(np.random.PCG64(SEED_BASE + 5 if seed is None else seed))
+        f = 1.0 + jitter * (r_out - 1.0) / n_rad * rng.uniform(-1.0, 1.0, xn.shape) / np.hypot(xn, yn)
+        f[0, :] = f[-1, :] = 1.0
+        xn, yn = xn * f, yn * f
+    ny, nx = n_rad, n_circ
+    fs = (1.4, mach, 0.0, 1.0)
+    q0 = conserved(gamma, *[np.full((ny, nx), v) for v in fs])
+    bc_state = np.zeros((4, 4))
+    bc_state[NORTH] = conserved(gamma, *fs)
+    prm = default_params(order=1, time_scheme=0, cfl=0.4, mach_ref=1.0, u_ref=mach, eps1=0.0, eps2=0.05,
+                         s1_mode=0)
+    prm.update(params)
+    return Case(name=f"carbuncle_{nx}x{ny}", q0=q0, params=prm, bc=(TRANSMISSIVE, TRANSMISSIVE, SLIPWALL, DIRICHLET),
+                xn=xn, yn=yn, bc_state=bc_state, nsteps=1000, t_end=0.0)
+
+
+def cylinder_potential_state(xn, yn, mach: float, gamma: float = 1.4):
+    """Incompressible potential flow past the unit cylinder, free stream along +x
+    (rho = 1, p = 1/gamma, so c = 1 and U = mach), pressure from Bernoulli's
+    law, evaluated at the cell centres of the O-grid."""
+    X, Y = _node_centres(xn, yn)
+    r2 = X * X + Y * Y
+    th = np.arctan2(Y, X)
+    ur = mach * (1.0 - 1.0 / r2) * np.cos(th)
+    ut = -mach * (1.0 + 1.0 / r2) * np.sin(th)
+    u = ur * np.cos(th) - ut * np.sin(th)
+    v = ur * np.sin(th) + ut * np.cos(th)
+    rho = np.ones_like(u)
+    p = 1.0 / gamma + 0.5 * (mach * mach - (u * u + v * v))
+    return conserved(gamma, rho, u, v, p)
+
+
+def cylinder_low_mach(n_circ: int = 100, n_rad: int = 72, mach: float = 0.01, r_out: float = 20.0,
+                      ratio: float = 1.06, **params) -> Case:
+    """Sec. 7.6: low-Mach inviscid flow past a unit cylinder on a 100 x 72 O-grid
+    (circumference x radius, radial spacing stretched), slip wall on the
+    cylinder, free-stream Dirichlet state on the outer circle, started from
+    the incompressible potential flow.  MUSCL + SSP-RK3, M_ref = the inlet
+    Mach number."""
+    gamma = params.get("gamma", 1.4)
+    xn, yn = cylinder_ogrid(n_circ, n_rad, 1.0, r_out, ratio)
+    q0 = cylinder_potential_state(xn, yn, mach, gamma)
+    bc_state = np.zeros((4, 4))
+    bc_state[NORTH] = conserved(gamma, 1.0, mach, 0.0, 1.0 / gamma)
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=mach, u_ref=mach, eps1=1.0, eps2=0.05,
+                         s1_mode=0)
+    prm.update(params)
+    return Case(name=f"cylinder_{n_circ}x{n_rad}_M{mach:g}", q0=q0, params=prm,
+                bc=(PERIODIC, PERIODIC, SLIPWALL, DIRICHLET), xn=xn, yn=yn, bc_state=bc_state, nsteps=100,
+                t_end=0.0)
+
+
+# --------------------------------------------------------------------------
 # Batched / serving family (fourth and fifth test configurations)
 # --------------------------------------------------------------------------
 
