@@ -574,7 +574,7 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
 {
     int rc = check_args(prm, g);
     if (rc) return rc;
-    if (!(prm->cfl > 0.0) || (prm->time_scheme != 0 && prm->time_scheme != 1)) return ORC_EINVAL;
+    if (!(prm->cfl > 0.0) || prm->time_scheme < 0 || prm->time_scheme > 2) return ORC_EINVAL;
     const size_t n = 4 * (size_t)g->nx * g->ny;
     double *r = (double *)malloc(sizeof(double) * n);
     double *q1 = (double *)malloc(sizeof(double) * n);
@@ -596,6 +596,20 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
             rc = residual_impl(prm, g, q, r, NULL, &neg);
             if (rc) break;
             for (size_t m = 0; m < n; ++m) q[m] = q[m] + dt * r[m];
+        } else if (prm->time_scheme == 2) {
+            /* Four-stage Runge-Kutta (the paper's time scheme, Sec. 7.1; reading:
+             * the low-storage form of Jameson, Schmidt and Turkel):
+             * Q^(k) = Q^n + alpha_k dt R(Q^(k-1)), alpha = 1/4, 1/3, 1/2, 1. */
+            const double alpha[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+            const double *in = q;
+            for (int k = 0; k < 4 && !rc; ++k) {
+                rc = residual_impl(prm, g, in, r, NULL, &neg);
+                if (rc) break;
+                double *out = (k == 3) ? q : (k == 1 ? q2 : q1);
+                for (size_t m = 0; m < n; ++m) out[m] = q[m] + alpha[k] * dt * r[m];
+                in = out;
+            }
+            if (rc) break;
         } else {
             /* SSP-RK3 (Shu-Osher form) */
             rc = residual_impl(prm, g, q, r, NULL, &neg);

@@ -52,7 +52,7 @@ typedef struct {
     double eps_lambda;/* Harten constant of Eq. (115) (Roe + entropy fix only)   */
     int s1_mode;      /* 0: detector of Eqs. (95)-(97); 1: s1 = 1 (Eq. 110)       */
     int order;        /* 1: piecewise constant; 2: MUSCL-minmod                   */
-    int time_scheme;  /* 0: forward Euler; 1: SSP-RK3 (Shu-Osher)                 */
+    int time_scheme;  /* 0: forward Euler; 1: SSP-RK3 (Shu-Osher); 2: four-stage RK */
     int scheme;       /* ORC_SCHEME_*                                             */
     unsigned variant; /* ORC_V_* bits                                             */
 } orc_params;

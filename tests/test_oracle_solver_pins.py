@@ -398,3 +398,32 @@ def test_cylinder_low_mach_residual_scaling_fig12():
         ratios[scheme] = nrm[0] / nrm[1]
     assert 80 < ratios[oracle.SCHEME_ROEAM] < 120
     assert 8 < ratios[oracle.SCHEME_ROE] < 12
+
+
+# --------------------------------------------------------------------------
+# Time schemes
+# --------------------------------------------------------------------------
+
+def _acoustic_case(time_scheme, cfl, nx=32, amp=1e-5, mach=0.5):
+    x = (np.arange(nx) + 0.5) / nx
+    s = np.sin(2.0 * np.pi * x)[None, :].repeat(2, 0)
+    q = workloads.conserved(G, 1.0 + amp * s, mach + amp * s, np.zeros((2, nx)), (1.0 + G * amp * s) / G)
+    prm = workloads.default_params(order=1, eps1=0.0, mach_ref=1.0, u_ref=mach, time_scheme=time_scheme, cfl=cfl)
+    return workloads.Case(name="acoustic", q0=q, params=prm, bc=(PERIODIC,) * 4, dx=1.0 / nx, dy=1.0 / nx,
+                          nsteps=10 ** 6, t_end=0.3)
+
+
+@pytest.mark.parametrize("time_scheme,lo,hi", [(0, 1.8, 2.5), (1, 7.0, 9.0), (2, 14.0, 18.0)])
+def test_time_scheme_order_on_small_acoustics(time_scheme, lo, hi):
+    """Temporal order of the three time schemes on a 1e-5 acoustic wave (the
+    linear regime of the first-order operator, which is smooth there): halving
+    dt divides the error at t = 0.3 by 2 (forward Euler), 8 (SSP-RK3: third
+    order) and 16 for the four-stage scheme, whose amplification polynomial on
+    a linear problem is the fourth-degree Taylor polynomial of exp(z)."""
+    sol = {}
+    for cfl in (0.8, 0.4, 0.2, 0.0125):
+        sol[cfl], st = oracle.run(_acoustic_case(time_scheme, cfl))
+        assert st["t"] == 0.3
+    e = [np.abs(sol[c] - sol[0.0125]).max() for c in (0.8, 0.4, 0.2)]
+    for k in range(2):
+        assert lo <= e[k] / e[k + 1] <= hi, e
