@@ -113,6 +113,9 @@ typedef struct {
  *   order     1: piecewise-constant face states (Sec. 7.1);
  *             2: MUSCL-minmod on (rho, u, v, p);
  *   time_scheme 0: forward Euler; 1: three-stage SSP Runge-Kutta;
+ *             2: the four-stage Runge-Kutta of Sec. 7.1 (read as the
+ *                low-storage form Q^(k) = Q^n + a_k dt R(Q^(k-1)),
+ *                a = 1/4, 1/3, 1/2, 1);
  *   precision 0: FP64 throughout;
  *             1: flux coefficients in FP32, with the state, the jumps of
  *                Eq. (85), the central term and the residual sum in FP64;
@@ -197,12 +200,13 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *grid, const roeam_para
 /* Profiling aid (same arithmetic as roeam_step): advance q by nsteps steps
  * launching every kernel directly, with HIP events recorded on the context
  * stream around each stage kernel.  Waits for the stream, then writes the
- * mean duration in milliseconds of the stage kernels into stage_ms[0..2]
- * (first, second and third stage; forward Euler fills stage_ms[0] only) and
+ * mean duration in milliseconds of the stage kernels into stage_ms[0..3]
+ * (first to fourth stage of a step; forward Euler fills stage_ms[0] only,
+ * SSP-RK3 stage_ms[0..2]) and
  * the number of timed launches into *launches (nullable).
  * EINVAL as roeam_step; EDEVICE. */
 roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params, double *q,
-                                long nsteps, double t0, double stage_ms[3], long *launches);
+                                long nsteps, double t0, double stage_ms[4], long *launches);
 /* Wait for the grid's last roeam_step and read its statistics. */
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step_stats *stats);
 
@@ -248,10 +252,10 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending);
  * the context stream around each batched stage kernel, and the status read
  * after every iteration (a host wait per iteration), so that finished solves
  * leave at once and no timed launch is an idle one.  Waits for the stream, then writes the mean duration in
- * milliseconds of the batched stage kernels into stage_ms[0..2] (first,
- * second and third stage; a stage that never ran reads 0) and the number of
+ * milliseconds of the batched stage kernels into stage_ms[0..3] (first to
+ * fourth stage of a step; a stage that never ran reads 0) and the number of
  * timed launches into *launches (nullable).  Errors as roeam_batch_run. */
-roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[3],
+roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[4],
                                      long *launches);
 /* Non-blocking poll: *done = 1 once the solve's output is written; stats
  * (nullable) then holds its statistics.  A solve that produced a

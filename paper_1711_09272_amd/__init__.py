@@ -95,12 +95,12 @@ def lib():
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
         "roeam_profile_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d,
-                                   ctypes.POINTER(ctypes.c_double * 3), ctypes.POINTER(ctypes.c_long)]),
+                                   ctypes.POINTER(ctypes.c_double * 4), ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_reserve": (i, [vp, ctypes.c_size_t]),
         "roeam_batch_footprint": (ctypes.c_size_t, [vp]),
         "roeam_batch_submit": (i, [vp, i, ctypes.POINTER(SolveDesc), ctypes.POINTER(ctypes.c_uint64)]),
         "roeam_batch_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i)]),
-        "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 3),
+        "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 4),
                                         ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
     }
@@ -301,9 +301,9 @@ def last_stats(ctx: Context, grid: Grid) -> Dict:
 
 def profile_step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float = 0.0):
     """Advance q by nsteps steps with HIP events around every stage kernel; returns
-    (mean ms of the stage-1, stage-2, stage-3 kernels, number of timed launches)."""
+    (mean ms of the first to fourth stage kernels of a step, number of timed launches)."""
     p = params(prm)
-    out = (ctypes.c_double * 3)()
+    out = (ctypes.c_double * 4)()
     n = ctypes.c_long()
     ctx.enter()
     try:
@@ -384,9 +384,9 @@ def batch_run(ctx: Context, iterations: int = -1) -> int:
 
 def batch_profile_run(ctx: Context, iterations: int = -1):
     """batch_run with HIP events around every batched stage kernel; returns
-    (mean ms of the stage-1, -2, -3 launches, number of timed launches)."""
+    (mean ms of the first to fourth stage launches of a step, number of timed launches)."""
     pend = ctypes.c_int()
-    out = (ctypes.c_double * 3)()
+    out = (ctypes.c_double * 4)()
     n = ctypes.c_long()
     ctx.enter()
     try:

@@ -32,6 +32,7 @@ namespace {
 constexpr int kMaxSolves = 4096;
 constexpr size_t kAlign = 256;
 constexpr int kGraphIters = 16;  // even
+constexpr int kGroups = 24;      // order (2) x precision (2) x time scheme (3) x metric (2)
 constexpr int kStatusEvery = 8;  // iterations between status snapshots without a graph
 
 size_t align_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
@@ -133,7 +134,7 @@ struct BatchEngine {
     uint64_t next_ticket = 1;
     long iter = 0;
     long since_status = 0;          // iterations since the last status snapshot
-    Group groups[16];               // (order-1, precision, time_scheme, metric)
+    Group groups[kGroups];          // (order-1, precision, time_scheme, metric)
     bool set_changed = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -147,7 +148,7 @@ struct BatchEngine {
 
 static int group_id(const roeam_params &p, int metric)
 {
-    return (p.order - 1) * 8 + p.precision * 4 + p.time_scheme * 2 + metric;
+    return ((p.order - 1) * 2 + p.precision) * 6 + p.time_scheme * 2 + metric;
 }
 
 static void release_engine(BatchEngine *b)
@@ -377,9 +378,9 @@ static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
             e = stage_launch(b, G, n, 1, p, 1, s);
             if (e == hipSuccess) e = roeam::launch_copy_back_batch(b->d_solves, G.d_tiles, n, G.shape, p, s);
         } else {
-            e = stage_launch(b, G, n, 1, p, 0, s);
-            if (e == hipSuccess) e = stage_launch(b, G, n, 2, p, 0, s);
-            if (e == hipSuccess) e = stage_launch(b, G, n, 3, p, 1, s);
+            const int first = G.time_scheme == 1 ? 1 : 4, nst = G.time_scheme == 1 ? 3 : 4;
+            e = hipSuccess;
+            for (int k = 0; k < nst && e == hipSuccess; ++k) e = stage_launch(b, G, n, first + k, p, k == nst - 1, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -455,11 +456,11 @@ roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes)
     b->alloc.reset(arena_bytes);
     b->by_idx.assign(kMaxSolves, 0);
     for (int i = kMaxSolves - 1; i >= 0; --i) b->free_idx.push_back(i);
-    for (int gidx = 0; gidx < 16; ++gidx) {
+    for (int gidx = 0; gidx < kGroups; ++gidx) {
         Group &G = b->groups[gidx];
-        G.order = gidx / 8 + 1;
-        G.precision = (gidx / 4) & 1;
-        G.time_scheme = (gidx / 2) & 1;
+        G.order = gidx / 12 + 1;
+        G.precision = (gidx / 6) & 1;
+        G.time_scheme = (gidx / 2) % 3;
         G.metric = gidx & 1;
         G.shape = 0;
     }
@@ -586,7 +587,7 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
     return ROEAM_OK;
 }
 
-roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[3],
+roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[4],
                                      long *launches)
 {
     if (!ctx || !stage_ms) return roeam_fail(ctx, ROEAM_EINVAL, "bad argument");
@@ -599,16 +600,17 @@ roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pendi
     b->profiling = false;
     if (rc) return rc;
     BHIP(ctx, hipStreamSynchronize(ctx->stream));
-    double sum[3] = {0.0, 0.0, 0.0};
-    long cnt[3] = {0, 0, 0};
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    long cnt[4] = {0, 0, 0, 0};
     for (size_t k = 0; k < b->prof_stage.size(); ++k) {
         float ms = 0.f;
         BHIP(ctx, hipEventElapsedTime(&ms, b->prof_ev[2 * k], b->prof_ev[2 * k + 1]));
-        const int st = b->prof_stage[k] - 1;
+        const int code = b->prof_stage[k];
+        const int st = code >= 4 ? code - 4 : code - 1;  // position of the stage within its step
         sum[st] += ms;
         cnt[st] += 1;
     }
-    for (int k = 0; k < 3; ++k) stage_ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
+    for (int k = 0; k < 4; ++k) stage_ms[k] = cnt[k] ? sum[k] / (double)cnt[k] : 0.0;
     if (launches) *launches = (long)b->prof_stage.size();
     return ROEAM_OK;
 }

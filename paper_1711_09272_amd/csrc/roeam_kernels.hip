@@ -72,13 +72,23 @@ __device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
     atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
 }
 
+// Stage codes of the stage kernel: 0 residual only; 1 forward Euler or the
+// first SSP-RK3 stage; 2, 3 the second and third SSP-RK3 stages; 4-7 the four
+// stages of the four-stage scheme.  The buffers each stage reads (stencil) and
+// writes, and whether it also reads Q^n at its own cells:
+//   1: q -> qa     2: qa -> qb (+Q^n)   3: qb -> q (+Q^n)
+//   4: q -> qa     5: qa -> qb (+Q^n)   6: qb -> qa (+Q^n)   7: qa -> q (+Q^n)
+// (a stage that writes q reads its stencil from another buffer, and its
+// pointwise read of Q^n is the cell it writes).
+__host__ __device__ constexpr bool first_stage(int stage) { return stage == 1 || stage == 4; }
+
 // Time-step logic shared by all stage kernels of a step with parity p.
 // Returns whether the step is active and its dt.
 __device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, double &dt, double &t_next,
                                             double &rate)
 {
     const StepState &s = z.st[p];
-    if (stage >= 2) {
+    if (!first_stage(stage)) {
         // the first stage has already decided: the step ran iff it advanced the count
         const StepState &n = z.st[p ^ 1];
         dt = n.dt;
@@ -146,11 +156,10 @@ __device__ __forceinline__ void tile_face(const DevSolve &S, const double (&sW)[
     for (int k = 0; k < 4; ++k) F[k] *= len;
 }
 
-// The tile body.  stage: 0 residual only (r_out), 1 Q + dt R into qa (forward
-// Euler, or the first SSP-RK3 stage), 2 SSP-RK3 second stage into qb, 3 third
-// stage into q.  p: step parity.  last: this stage ends the step (reduce the
-// rate of the new state into parity p^1); for stage 0 the rate of the input is
-// reduced into parity 0.
+// The tile body.  stage: a stage code (above; 0 writes the residual to r_out).
+// p: step parity.  last: this stage ends the step (reduce the rate of the new
+// state into parity p^1); for stage 0 the rate of the input is reduced into
+// parity 0.
 // SPLIT = false: NT threads sweep the i-faces, then the j-faces through one
 // LDS buffer (about two faces per thread).  SPLIT = true: one face per thread,
 // i-faces on the first ceil(NFX/64) waves and j-faces on the rest, in one pass.
@@ -173,7 +182,8 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
 
     const int tid = threadIdx.x;
-    const double *__restrict__ qin = (stage <= 1) ? S.q : (stage == 2 ? S.qa : S.qb);
+    const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
+    const bool reads_qn = stage >= 2 && stage != 4;  // Q^n at the own cells, besides the stencil input
     const int i0 = tx * TX, j0 = ty * TY;
     const int nx = S.nx, ny = S.ny;
 
@@ -192,7 +202,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 #pragma unroll
             for (int k = 0; k < 4; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
         }
-        if (stage >= 2) {
+        if (reads_qn) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
         }
@@ -202,7 +212,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     double dt = 0.0, t_next = 0.0, rate = 0.0;
     if (stage > 0) {
         const bool active = step_active(z, p, stage, dt, t_next, rate);
-        if (stage == 1 && first_block) {
+        if (first_stage(stage) && first_block) {
             // block 0 publishes the next step state
             if (tid == 0) {
                 const StepState &s = z.st[p];
@@ -365,14 +375,18 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         double Qn[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (stage == 1) {
-                Qn[k] = Qs[m][k] + dt * Rv[k];
-            } else {
-                Qn[k] = (stage == 2) ? 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k])
-                                     : (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]);
+            switch (stage) {
+            case 1: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
+            case 2: Qn[k] = 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k]); break;
+            case 3: Qn[k] = (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]); break;
+            // four-stage scheme: Q^(k) = Q^n + alpha_k dt R(Q^(k-1)), alpha = 1/4, 1/3, 1/2, 1
+            case 4: Qn[k] = Qs[m][k] + (0.25 * dt) * Rv[k]; break;
+            case 5: Qn[k] = Q0[m][k] + ((1.0 / 3.0) * dt) * Rv[k]; break;
+            case 6: Qn[k] = Q0[m][k] + (0.5 * dt) * Rv[k]; break;
+            default: Qn[k] = Q0[m][k] + dt * Rv[k]; break;
             }
         }
-        double *__restrict__ qo = (stage == 1) ? S.qa : (stage == 2 ? S.qb : S.q);
+        double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
 #pragma unroll
         for (int k = 0; k < 4; ++k) qo[k * S.plane + idx] = Qn[k];
         double W[4];

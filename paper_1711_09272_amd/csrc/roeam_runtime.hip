@@ -45,7 +45,7 @@ roeam_status roeam_check_params(roeam_ctx *ctx, const roeam_params *p, bool need
     if (!(p->eps2 >= 0.0) || !std::isfinite(p->eps2)) return fail(ctx, ROEAM_EINVAL, "eps2 must be >= 0");
     if (p->s1_mode != 0 && p->s1_mode != 1) return fail(ctx, ROEAM_EINVAL, "s1_mode must be 0 or 1");
     if (p->order != 1 && p->order != 2) return fail(ctx, ROEAM_EINVAL, "order must be 1 or 2");
-    if (p->time_scheme != 0 && p->time_scheme != 1) return fail(ctx, ROEAM_EINVAL, "time_scheme must be 0 or 1");
+    if (p->time_scheme < 0 || p->time_scheme > 2) return fail(ctx, ROEAM_EINVAL, "time_scheme must be 0, 1 or 2");
     if (p->precision != 0 && p->precision != 1) return fail(ctx, ROEAM_EINVAL, "precision must be 0 or 1");
     if (p->variant & ~ROEAM_V_SUPPORTED) return fail(ctx, ROEAM_EINVAL, "unsupported variant bits");
     if (p->scheme != ROEAM_SCHEME_ROEAM && p->scheme != ROEAM_SCHEME_ROE && p->scheme != ROEAM_SCHEME_ROE_HARTEN)
@@ -380,9 +380,11 @@ static hipError_t enqueue_step(const roeam_grid *g, const DevSolve &S, int shape
         if (e == hipSuccess) e = roeam::launch_copy_back(S, p, st);
         return e;
     }
-    e = roeam::launch_stage_single(d, S, shape, 1, p, 0, nullptr, st);
-    if (e == hipSuccess) e = roeam::launch_stage_single(d, S, shape, 2, p, 0, nullptr, st);
-    if (e == hipSuccess) e = roeam::launch_stage_single(d, S, shape, 3, p, 1, nullptr, st);
+    // stage codes 1-3 (SSP-RK3) or 4-7 (four-stage scheme)
+    const int first = time_scheme == 1 ? 1 : 4, nst = time_scheme == 1 ? 3 : 4;
+    e = hipSuccess;
+    for (int k = 0; k < nst && e == hipSuccess; ++k)
+        e = roeam::launch_stage_single(d, S, shape, first + k, p, k == nst - 1 ? 1 : 0, nullptr, st);
     return e;
 }
 
@@ -471,7 +473,7 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
 }
 
 roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params *p, double *q, long nsteps,
-                                double t0, double stage_ms[3], long *launches)
+                                double t0, double stage_ms[4], long *launches)
 {
     if (!ctx || !gc || !q || !stage_ms || nsteps < 1) return fail(ctx, ROEAM_EINVAL, "bad argument");
     if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
@@ -486,7 +488,8 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     int shape = 0;
     st = choose_shape(ctx, g, p, S, &shape);
     if (st) return st;
-    const int nst = p->time_scheme == 0 ? 1 : 3;
+    const int nst = p->time_scheme == 0 ? 1 : (p->time_scheme == 1 ? 3 : 4);
+    const int first = p->time_scheme == 2 ? 4 : 1;
     std::vector<hipEvent_t> ev((size_t)(2 * nst * nsteps));
     for (auto &e : ev) HIP_OK(ctx, hipEventCreate(&e));
     roeam_status rc = ROEAM_OK;
@@ -497,7 +500,8 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
         for (int stg = 1; stg <= nst && e == hipSuccess; ++stg) {
             hipEvent_t *pair = &ev[(size_t)(2 * (k * nst + stg - 1))];
             e = hipEventRecord(pair[0], s);
-            if (e == hipSuccess) e = roeam::launch_stage_single(g->d_solve, S, shape, stg, par, stg == nst ? 1 : 0, nullptr, s);
+            if (e == hipSuccess)
+                e = roeam::launch_stage_single(g->d_solve, S, shape, first + stg - 1, par, stg == nst ? 1 : 0, nullptr, s);
             if (e == hipSuccess) e = hipEventRecord(pair[1], s);
         }
         if (e == hipSuccess && nst == 1) e = roeam::launch_copy_back(S, par, s);
@@ -505,7 +509,7 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     g->final_parity = (int)(nsteps & 1);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(ctx, e, "profile step");
-    double sum[3] = {0, 0, 0};
+    double sum[4] = {0, 0, 0, 0};
     for (long k = 0; k < nsteps && rc == ROEAM_OK; ++k)
         for (int stg = 0; stg < nst; ++stg) {
             float ms = 0.f;
@@ -513,7 +517,7 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
             if (hipEventElapsedTime(&ms, pair[0], pair[1]) == hipSuccess) sum[stg] += ms;
         }
     for (auto &x : ev) (void)hipEventDestroy(x);
-    for (int stg = 0; stg < 3; ++stg) stage_ms[stg] = stg < nst ? sum[stg] / (double)nsteps : 0.0;
+    for (int stg = 0; stg < 4; ++stg) stage_ms[stg] = stg < nst ? sum[stg] / (double)nsteps : 0.0;
     if (launches) *launches = nsteps * nst;
     return rc;
 }

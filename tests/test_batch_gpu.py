@@ -35,6 +35,9 @@ def family():
     c = workloads.bump_case(50, rng, 8)
     c.params["precision"] = 1
     cases.append(c)
+    c = workloads.bump_case(37, rng, 6)
+    c.params["time_scheme"] = 2  # the four-stage scheme in its own group
+    cases.append(c)
     return cases
 
 
@@ -196,6 +199,6 @@ def test_batch_profile_run_matches_batch_run(C):
     _, b = submit_all(C, cases)
     stage_ms, launches = P.batch_profile_run(C, -1)
     rb = collect(C, b)
-    assert launches == 3 * 6 and all(t > 0.0 for t in stage_ms), (stage_ms, launches)
+    assert launches == 3 * 6 and all(t > 0.0 for t in stage_ms[:3]) and stage_ms[3] == 0.0, (stage_ms, launches)
     for (qa, sa, ca), (qb, sb, cb) in zip(ra, rb):
         assert ca == cb == P.OK and sa == sb and np.array_equal(qa, qb)

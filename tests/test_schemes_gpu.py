@@ -105,3 +105,39 @@ def test_scheme_argument_errors(C):
         with pytest.raises(P.RoeamError) as e:
             P.residual(C, g, prm, q)
         assert e.value.code == P.EINVAL, bad
+
+
+# --- the paper's four-stage Runge-Kutta (time_scheme 2) -------------------------
+
+def test_four_stage_sod_full_run(C):
+    """Sec. 7.1's setting: first order in space, four-stage Runge-Kutta in time,
+    Sod 400 x 4 to t = 0.2."""
+    case = workloads.sod(time_scheme=2)
+    q_or, st_or = oracle.run(case)
+    q_gpu, st = gpu_run(C, case)
+    err = state_error(q_gpu, q_or)
+    say(f"[step] sod four-stage: steps {st['steps']} / {st_or['steps']} err {err:.3e}")
+    assert st["steps"] == st_or["steps"] and st["t"] == st_or["t"] == 0.2
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_four_stage_vortex_steps(C, precision):
+    case = workloads.vortex(80, 0.01, time_scheme=2, precision=precision)
+    q_or, st_or = oracle.run(case, nsteps=25, params=dict(case.params, precision=0))
+    q_gpu, st = gpu_run(C, case, nsteps=25)
+    err = state_error(q_gpu, q_or)
+    say(f"[step] vortex four-stage precision {precision}: err {err:.3e}")
+    assert st["steps"] == 25 and abs(st["t"] - st_or["t"]) <= (1e-13 if precision == 0 else 1e-6) * st_or["t"]
+    assert err <= (TOL64 if precision == 0 else 1e-7)
+
+
+def test_four_stage_profile_driver(C):
+    import paper_1711_09272_amd as P
+    case = workloads.vortex(64, 0.01, time_scheme=2)
+    g = P.Grid.from_case(C, case)
+    q = g.to_device(case.q0)
+    stage_ms, launches = P.profile_step(C, g, case.params, q, 5)
+    assert launches == 20 and all(t > 0 for t in stage_ms), stage_ms
+    q_or, _ = oracle.run(case, nsteps=5)
+    assert state_error(g.from_device(q), q_or) <= TOL64
