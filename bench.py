@@ -101,21 +101,35 @@ def make_cases(workload: str, precision: int):
 
 
 def cpu_baseline(cases, sample_steps: int):
+    """The oracle as it stands on this host: all its OpenMP threads (the reported
+    value; its row loops give the same bits for any thread count), and one
+    thread on a shorter sample."""
     import oracle
-    t0 = time.perf_counter()
-    updates = 0
-    for case in cases:
-        _, st = oracle.run(case, nsteps=sample_steps)
-        updates += case.nx * case.ny * 3 * st["steps"]
-    dt = time.perf_counter() - t0
+
+    def timed(steps):
+        t0 = time.perf_counter()
+        updates = 0
+        for case in cases:
+            _, st = oracle.run(case, nsteps=steps)
+            updates += case.nx * case.ny * 3 * st["steps"]
+        return updates, time.perf_counter() - t0
+
     names = " + ".join(f"{c.nx}x{c.ny} M={c.params['mach_ref']:g}" for c in cases)
+    threads = oracle.max_threads()
+    oracle.set_threads(1)
+    u1, dt1 = timed(max(sample_steps // 3, 1))
+    oracle.set_threads(threads)
+    un, dtn = timed(sample_steps)
     return {
-        "value": updates / dt / 1e9,
+        "value": un / dtn / 1e9,
         "unit": "Gcell-updates/s per RK stage",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": f"first {sample_steps} SSP-RK3 steps of each grid of the same workload ({names}; "
-                  f"{updates} cell-stage updates, {dt:.1f} s, single thread)",
+                  f"{un} cell-stage updates, {dtn:.1f} s, {threads} OpenMP threads over rows)",
+        "single_thread": {"value": u1 / dt1 / 1e9, "cores": 1,
+                          "sample": f"first {max(sample_steps // 3, 1)} steps of each grid, {u1} cell-stage updates, "
+                                    f"{dt1:.1f} s"},
     }
 
 
@@ -360,7 +374,7 @@ def main():
     ap.add_argument("--arena-gb", type=int, default=48)
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps timed kernel by kernel with HIP events for the roofline object")
-    ap.add_argument("--cpu-sample-steps", type=int, default=75)
+    ap.add_argument("--cpu-sample-steps", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counter-run", action="store_true",
                     help="for rocprofv3 --pmc: only --profile-steps steps of directly launched stage "

@@ -38,7 +38,7 @@ SCHEME_ROEAM, SCHEME_ROE, SCHEME_ROE_HARTEN = 0, 1, 2
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no fused multiply-add contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                "-Wall", "-o", _LIB, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
@@ -99,8 +99,21 @@ def lib():
                               ctypes.c_double, ctypes.POINTER(_Stats)]
         L.orc_cell_areas.restype = None
         L.orc_cell_areas.argtypes = [ctypes.POINTER(_Grid), dp]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def set_threads(n: int):
+    """Threads of the oracle's row loops (OpenMP); results are the same bits for any count."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _dptr(a: np.ndarray):

@@ -14,6 +14,7 @@
 #include "roeam_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -434,15 +435,18 @@ static int load_prims(const orc_params *prm, const orc_grid *g, const double *q,
 {
     const int nx = g->nx, ny = g->ny;
     const size_t plane = (size_t)nx * ny;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             double Q[4] = {q[c], q[plane + c], q[2 * plane + c], q[3 * plane + c]};
             double W[4];
             conserved_to_prim(prm->gamma, Q, W);
-            if (!physical(W)) return ORC_ENONPHYS;
+            if (!physical(W)) bad = 1;
             set_prim(pf, i, j, W);
         }
+    if (bad) return ORC_ENONPHYS;
     fill_ghosts(prm, g, pf);
     return 0;
 }
@@ -472,34 +476,44 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
     rc = load_prims(prm, g, q, &pf);
     if (rc) { free(pf.W); free(Fx); free(Fy); return rc; }
 
-    double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4], S[2], n[2], len;
-    orc_face_diag d;
+    /* Rows of faces are independent; with OpenMP they are shared out among
+     * threads (each face is computed by one thread with the same arithmetic,
+     * so the result does not depend on the thread count). */
+    long negc = 0;
     /* i-faces: between (i-1, j) and (i, j), i = 0..nx */
+#pragma omp parallel for schedule(static) reduction(+ : negc)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i <= nx; ++i) {
+            double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4], S[2], n[2], len;
+            orc_face_diag d;
             get_prim(&pf, i - 2, j, m2); get_prim(&pf, i - 1, j, m1);
             get_prim(&pf, i, j, p0); get_prim(&pf, i + 1, j, p1);
             reconstruct(prm->order, m2, m1, p0, p1, WL, WR);
             xface_vector(g, i, j, S);
             unit_normal(g, S, n, &len);
             orc_face_flux(prm, WL, WR, n[0], n[1], s1_xface(prm, &pf, i, j), F, &d);
-            if (neg_uprime && d.absUp < 0.0) ++*neg_uprime;
+            if (d.absUp < 0.0) ++negc;
             for (int k = 0; k < 4; ++k) Fx[((size_t)j * (nx + 1) + i) * 4 + k] = F[k] * len;
         }
     /* j-faces: between (i, j-1) and (i, j), j = 0..ny */
+#pragma omp parallel for schedule(static) reduction(+ : negc)
     for (int j = 0; j <= ny; ++j)
         for (int i = 0; i < nx; ++i) {
+            double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4], S[2], n[2], len;
+            orc_face_diag d;
             get_prim(&pf, i, j - 2, m2); get_prim(&pf, i, j - 1, m1);
             get_prim(&pf, i, j, p0); get_prim(&pf, i, j + 1, p1);
             reconstruct(prm->order, m2, m1, p0, p1, WL, WR);
             yface_vector(g, i, j, S);
             unit_normal(g, S, n, &len);
             orc_face_flux(prm, WL, WR, n[0], n[1], s1_yface(prm, &pf, i, j), F, &d);
-            if (neg_uprime && d.absUp < 0.0) ++*neg_uprime;
+            if (d.absUp < 0.0) ++negc;
             for (int k = 0; k < 4; ++k) Fy[((size_t)j * nx + i) * 4 + k] = F[k] * len;
         }
+    if (neg_uprime) *neg_uprime += negc;
     /* Conservative sum: R = -(1/Omega) [(F_e - F_w) + (G_n - G_s)]. */
     const size_t plane = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double omega = cell_area(g, i, j);
@@ -556,15 +570,19 @@ int orc_max_rate(const orc_params *prm, const orc_grid *g, const double *q, doub
     const int nx = g->nx, ny = g->ny;
     const size_t plane = (size_t)nx * ny;
     double mx = 0.0;
+    int bad = 0;
+    /* the maximum does not depend on the order it is taken in */
+#pragma omp parallel for schedule(static) reduction(max : mx) reduction(| : bad)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             double Q[4] = {q[c], q[plane + c], q[2 * plane + c], q[3 * plane + c]};
             double W[4];
             conserved_to_prim(prm->gamma, Q, W);
-            if (!physical(W)) return ORC_ENONPHYS;
+            if (!physical(W)) { bad = 1; continue; }
             mx = dmax(mx, cell_rate(prm, g, W, i, j));
         }
+    if (bad) return ORC_ENONPHYS;
     *max_rate = mx;
     return 0;
 }
@@ -595,6 +613,7 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
             /* forward Euler: Q^{n+1} = Q^n + dt R(Q^n) */
             rc = residual_impl(prm, g, q, r, NULL, &neg);
             if (rc) break;
+#pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q[m] = q[m] + dt * r[m];
         } else if (prm->time_scheme == 2) {
             /* Four-stage Runge-Kutta (the paper's time scheme, Sec. 7.1; reading:
@@ -606,6 +625,7 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
                 rc = residual_impl(prm, g, in, r, NULL, &neg);
                 if (rc) break;
                 double *out = (k == 3) ? q : (k == 1 ? q2 : q1);
+#pragma omp parallel for schedule(static)
                 for (size_t m = 0; m < n; ++m) out[m] = q[m] + alpha[k] * dt * r[m];
                 in = out;
             }
@@ -614,12 +634,15 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
             /* SSP-RK3 (Shu-Osher form) */
             rc = residual_impl(prm, g, q, r, NULL, &neg);
             if (rc) break;
+#pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q1[m] = q[m] + dt * r[m];
             rc = residual_impl(prm, g, q1, r, NULL, &neg);
             if (rc) break;
+#pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q2[m] = 0.75 * q[m] + 0.25 * (q1[m] + dt * r[m]);
             rc = residual_impl(prm, g, q2, r, NULL, &neg);
             if (rc) break;
+#pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m)
                 q[m] = (1.0 / 3.0) * q[m] + (2.0 / 3.0) * (q2[m] + dt * r[m]);
         }
@@ -638,3 +661,7 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
     free(r); free(q1); free(q2);
     return rc;
 }
+
+/* Threads of the row loops (OpenMP); results do not depend on them. */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -107,6 +107,11 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
 /* Cell areas [ny][nx] (shoelace); face vectors for tests. */
 void orc_cell_areas(const orc_grid *g, double *omega);
 
+/* Threads used by the row loops (OpenMP); the results are bitwise the same
+ * for any count. */
+void orc_set_threads(int n);
+int orc_max_threads(void);
+
 #ifdef __cplusplus
 }
 #endif
