@@ -1,0 +1,61 @@
+"""Parity at the full sizes the benchmark runs, in its launch configuration:
+the fourth configuration's 256 grids through the batch engine (group shape
+chosen as in the bench), and the 2048^2 vortex of the roofline sweep through
+roeam_step with the autotuned shape.  The oracle computes a sample of grids
+(always including the largest) or the whole 2048^2 grid for a few steps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import ctx, say, state_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    return ctx()
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (0, 1e-12)])
+def test_batch256_full_size_sampled(C, precision, tol):
+    import torch
+    import paper_1711_09272_amd as P
+    steps = 3
+    cases = workloads.batch_family(256, nsteps=steps, precision=precision)
+    grids = [P.Grid.from_case(C, c) for c in cases]
+    q0 = [g.to_device(c.q0) for g, c in zip(grids, cases)]
+    outs = [g.empty_state() for g in grids]
+    P.batch_reserve(C, sum(g.footprint() for g in grids) + (64 << 20))
+    solves = [P.Solve(g, c.params, q, steps, 0.0, o) for g, c, q, o in zip(grids, cases, q0, outs)]
+    P.batch_submit(C, solves)
+    assert P.batch_run(C, -1) == 0
+    for s in solves:
+        done, st, rc = P.batch_poll(C, s.ticket)
+        assert done and rc == P.OK and st["steps"] == steps
+    torch.cuda.synchronize()
+    sizes = np.array([c.nx * c.ny for c in cases])
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 60))
+    pick = sorted(set([int(sizes.argmax()), int(sizes.argmin())] + list(rng.choice(len(cases), 4, replace=False))))
+    for k in pick:
+        c = cases[k]
+        q_or, st_or = oracle.run(c, nsteps=steps, params=dict(c.params, precision=0))
+        err = state_error(grids[k].from_device(outs[k]), q_or)
+        say(f"[batch256 precision {precision}] grid {k} {c.nx}x{c.ny} M={c.params['u_ref']:.3g} err {err:.3e}")
+        assert err <= tol
+
+
+def test_vortex2048_full_size(C):
+    import paper_1711_09272_amd as P
+    import torch
+    case = workloads.vortex(2048, 0.01)
+    g = P.Grid.from_case(C, case)
+    q = g.to_device(case.q0)
+    st = P.step(C, g, case.params, q, 2)
+    torch.cuda.synchronize()
+    q_or, st_or = oracle.run(case, nsteps=2)
+    err = state_error(g.from_device(q), q_or)
+    say(f"[vortex 2048^2] shape {P.SHAPES[g.tile_shape(case.params)]} 2 steps err {err:.3e}")
+    assert st["steps"] == 2 and abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
+    assert err <= 1e-12
