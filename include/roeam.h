@@ -170,10 +170,10 @@ roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *p
 /* Tile shape of the stage kernel for this grid (cells per workgroup /
  * threads): 0 = 32x15/256, 1 = 16x15/128, 2 = 8x7/64, 6 = 16x15/256,
  * 7 = 32x7/256 (one or two faces per thread), 3 = 8x7/128, 4 = 16x15/512,
- * 5 = 32x7/512 (one face per thread), or -1 (default) = chosen by the
- * autotuner, which times every shape on the grid at its first roeam_step and
- * keeps the fastest per (order, precision).  Every shape computes bitwise the
- * same result.  EINVAL: shape outside -1..7. */
+ * 5 = 32x7/512, 8 = 16x7/256 (one face per thread), or -1 (default) =
+ * chosen by the autotuner, which times every shape on the grid at its first
+ * roeam_step and keeps the fastest per (order, precision).  Every shape
+ * computes bitwise the same result.  EINVAL: shape outside -1..8. */
 roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
 /* The shape in use for these parameters (-1 if not tuned yet). */
 roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *params, int *shape);

@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5,
 BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 # stage-kernel tile shapes: cells x cells / threads per workgroup
-SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512", "16x15/256", "32x7/256"]
+SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512", "16x15/256", "32x7/256", "16x7/256"]
 
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",

@@ -245,10 +245,10 @@ static roeam_status process_status(roeam_ctx *ctx, BatchEngine *b, int which, bo
 
 // Tile shape of a group that forms with no forced or tuned shape on its
 // first grid, from the cells the group is about to hold (every queued solve
-// of the group): one-face-per-thread 8x7 tiles for small totals, where the
+// of the group): one-face-per-thread 16x7 tiles for small totals, where the
 // launch is latency-bound and needs many short workgroups; 16x15 tiles with
-// one face per thread and direction pass above about 200k cells, where fewer
-// halo cells per tile cell pay off (measured crossover on MI355X).
+// one pass per face direction above about 200k cells, where fewer halo cells
+// per tile cell pay off (measured crossover on MI355X).
 static int untuned_shape(const BatchEngine *b, int group)
 {
     long long cells = 0;
@@ -257,7 +257,7 @@ static int untuned_shape(const BatchEngine *b, int group)
         if (it != b->reqs.end() && it->second.group == group)
             cells += (long long)it->second.d.grid->nx * it->second.d.grid->ny;
     }
-    return cells >= 200000 ? 6 : 3;
+    return cells >= 200000 ? 6 : 8;
 }
 
 // Admit queued solves that fit (first fit in submission order).

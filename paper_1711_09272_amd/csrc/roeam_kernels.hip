@@ -514,8 +514,9 @@ struct TileShape {
 };
 // Tile shapes: id, TX, TY, threads, split.  Non-split shapes sweep the faces
 // in one or two passes per direction; split shapes give every face a thread.
-// 6 and 7 cover each face direction in one pass of 256 threads, so that a
-// pair of 256x256 grids fits the chip in one round of workgroups.
+// 6 and 7 cover each face direction in one pass of 256 threads; 8 gives every
+// face of a 16x7 tile a thread (fewer halo cells per tile cell than 8x7 at the
+// same one-face-per-thread latency).
 #define ROEAM_SHAPES(X)               \
     X(0, 32, 15, 256, false)          \
     X(1, 16, 15, 128, false)          \
@@ -524,7 +525,8 @@ struct TileShape {
     X(4, 16, 15, 512, true)           \
     X(5, 32, 7, 512, true)            \
     X(6, 16, 15, 256, false)          \
-    X(7, 32, 7, 256, false)
+    X(7, 32, 7, 256, false)           \
+    X(8, 16, 7, 256, true)
 
 #define ROEAM_SHAPE_ENTRY(ID, TX, TY, NT, SPLIT) {TX, TY, NT},
 static const TileShape kShapes[] = {ROEAM_SHAPES(ROEAM_SHAPE_ENTRY)};

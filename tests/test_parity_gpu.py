@@ -184,7 +184,7 @@ def test_invalid_arguments(C):
         P.Grid(C, 5, 5, dx=0.1, dy=0.1, bc=(PERIODIC, TRANSMISSIVE, PERIODIC, PERIODIC))
 
 
-@pytest.mark.parametrize("shape", range(8))
+@pytest.mark.parametrize("shape", range(9))
 def test_each_tile_shape_matches_oracle(C, shape):
     """Every tile shape of the stage kernel against the oracle, on a ragged grid
     with walls and Dirichlet sides, for the residual and for SSP-RK3 steps."""
