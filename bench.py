@@ -116,8 +116,9 @@ def cpu_baseline(cases, sample_steps: int):
 
     names = " + ".join(f"{c.nx}x{c.ny} M={c.params['mach_ref']:g}" for c in cases)
     threads = oracle.max_threads()
+    single_steps = max(min(sample_steps, 50), 1)
     oracle.set_threads(1)
-    u1, dt1 = timed(max(sample_steps // 3, 1))
+    u1, dt1 = timed(single_steps)
     oracle.set_threads(threads)
     un, dtn = timed(sample_steps)
     return {
@@ -128,8 +129,7 @@ def cpu_baseline(cases, sample_steps: int):
         "sample": f"first {sample_steps} SSP-RK3 steps of each grid of the same workload ({names}; "
                   f"{un} cell-stage updates, {dtn:.1f} s, {threads} OpenMP threads over rows)",
         "single_thread": {"value": u1 / dt1 / 1e9, "cores": 1,
-                          "sample": f"first {max(sample_steps // 3, 1)} steps of each grid, {u1} cell-stage updates, "
-                                    f"{dt1:.1f} s"},
+                          "sample": f"first {single_steps} steps of each grid, {u1} cell-stage updates, {dt1:.1f} s"},
     }
 
 
@@ -374,7 +374,8 @@ def main():
     ap.add_argument("--arena-gb", type=int, default=48)
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps timed kernel by kernel with HIP events for the roofline object")
-    ap.add_argument("--cpu-sample-steps", type=int, default=150)
+    ap.add_argument("--cpu-sample-steps", type=int, default=1000,
+                    help="steps of each grid the oracle runs on all host threads (one thread runs at most 50)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counter-run", action="store_true",
                     help="for rocprofv3 --pmc: only --profile-steps steps of directly launched stage "
