@@ -260,7 +260,8 @@ roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pendi
 /* Non-blocking poll: *done = 1 once the solve's output is written; stats
  * (nullable) then holds its statistics.  A solve that produced a
  * non-physical state is done with return value ROEAM_ENONPHYS; the other
- * solves are not affected.  ENOTFOUND: unknown ticket. */
+ * solves are not affected.  The poll that reports a ticket done also
+ * forgets it; later polls of it return ENOTFOUND (unknown ticket). */
 roeam_status roeam_batch_poll(roeam_ctx *ctx, uint64_t ticket, int *done, roeam_step_stats *stats);
 
 #ifdef __cplusplus

@@ -629,9 +629,13 @@ roeam_status roeam_batch_poll(roeam_ctx *ctx, uint64_t ticket, int *done, roeam_
         else if (q != hipErrorNotReady) return hip_err(ctx, q, "hipEventQuery");
     }
     *done = r.state == DONE;
-    if (*done && stats) *stats = r.stats;
-    if (*done && r.rc == ROEAM_ENONPHYS)
-        return roeam_fail(ctx, ROEAM_ENONPHYS, "solve produced a non-physical state");
+    if (!*done) return ROEAM_OK;
+    // reported done: the ticket is forgotten (a server's request table does not grow)
+    if (stats) *stats = r.stats;
+    const roeam_status rc = r.rc;
+    if (r.out_ev) (void)hipEventDestroy(r.out_ev);
+    b->reqs.erase(it);
+    if (rc == ROEAM_ENONPHYS) return roeam_fail(ctx, ROEAM_ENONPHYS, "solve produced a non-physical state");
     return ROEAM_OK;
 }
 

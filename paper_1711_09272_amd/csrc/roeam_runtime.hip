@@ -1,12 +1,11 @@
 // roeam_runtime.hip -- host side of the C ABI in include/roeam.h: contexts,
-// immutable grids, the residual call, the graph-captured step loop and the
-// continuous-batching engine.
+// immutable grids, the tile-shape autotuner, the residual call and the
+// graph-captured step loop (the batch engine is in roeam_batch.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <cstdio>
 #include <cstring>
-#include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -285,21 +284,35 @@ roeam_status roeam_grid_layout(const roeam_grid *g, int *nx, int *ny, long *pitc
 // autotuner times the first-stage kernel of every shape on the grid (stage 1
 // only reads q and writes the grid's own stage buffer, so it leaves q
 // untouched) and keeps the fastest, per (order, precision), in the grid and in
-// a process-wide table keyed by the grid size.
+// a process-wide table keyed by device and grid size (guarded by a mutex:
+// contexts on different host threads may tune at the same time).
 struct TuneKey {
-    int nx, ny, order, precision, metric;
+    int device, nx, ny, order, precision, metric;
     bool operator==(const TuneKey &o) const
     {
-        return nx == o.nx && ny == o.ny && order == o.order && precision == o.precision && metric == o.metric;
+        return device == o.device && nx == o.nx && ny == o.ny && order == o.order && precision == o.precision &&
+               metric == o.metric;
     }
 };
 struct TuneKeyHash {
     size_t operator()(const TuneKey &k) const
     {
-        return ((size_t)k.nx * 1000003u) ^ ((size_t)k.ny * 7919u) ^ (size_t)(k.order * 31 + k.precision * 7 + k.metric);
+        return ((size_t)k.nx * 1000003u) ^ ((size_t)k.ny * 7919u) ^
+               (size_t)(k.device * 131 + k.order * 31 + k.precision * 7 + k.metric);
     }
 };
 static std::unordered_map<TuneKey, int, TuneKeyHash> g_tuned;
+static std::mutex g_tuned_mu;
+
+// Two timing events, destroyed on every return path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
 
 static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_params *p, const DevSolve &S, int *shape)
 {
@@ -312,17 +325,21 @@ static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_para
         *shape = cached;
         return ROEAM_OK;
     }
-    const TuneKey key{g->nx, g->ny, p->order, p->precision, g->metric};
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-        cached = it->second;
-        *shape = cached;
-        return ROEAM_OK;
+    const TuneKey key{ctx->device, g->nx, g->ny, p->order, p->precision, g->metric};
+    {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            cached = it->second;
+            *shape = cached;
+            return ROEAM_OK;
+        }
     }
     hipStream_t s = ctx->stream;
-    hipEvent_t e0, e1;
-    HIP_OK(ctx, hipEventCreate(&e0));
-    HIP_OK(ctx, hipEventCreate(&e1));
+    EventPair ev;
+    HIP_OK(ctx, hipEventCreate(&ev.a));
+    HIP_OK(ctx, hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 1, s));
     HIP_OK(ctx, roeam::launch_rate(S, 0, s));
     int best = 0;
@@ -341,10 +358,11 @@ static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_para
             best = sh;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     cached = best;
-    g_tuned[key] = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned[key] = best;
+    }
     *shape = best;
     return ROEAM_OK;
 }
