@@ -165,7 +165,8 @@ __device__ __forceinline__ double detector_P(double pA, double rA, double pB, do
 // ---------------------------------------------------------------------------
 // state access
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void to_prim(double gm1, double q0, double q1, double q2, double q3, double W[4])
+// Primitives (rho, u, v, p) of a conserved state; returns 1/rho.
+__device__ __forceinline__ double to_prim(double gm1, double q0, double q1, double q2, double q3, double W[4])
 {
     double rho = q0;
     const double ir = rcp_nr(rho);
@@ -174,6 +175,7 @@ __device__ __forceinline__ void to_prim(double gm1, double q0, double q1, double
     W[1] = u;
     W[2] = v;
     W[3] = gm1 * (q3 - 0.5 * rho * (u * u + v * v));
+    return ir;
 }
 
 __device__ __forceinline__ void load_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
@@ -477,15 +479,15 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
 }
 
 // Explicit rate of one cell for the time-step rule:
-// (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega, ce = c / sqrt(theta_cell).
+// (|V.Si| + ce |Si| + |V.Sj| + ce |Sj|) / Omega, ce = c / sqrt(theta_cell)
+// (evaluated as c^2 rsq(c^2 theta)); ir = 1 / rho.
 template <int METRIC>
-__device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4], int i, int j)
+__device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4], double ir, int i, int j)
 {
-    const double c2 = S.gamma * W[3] * rcp_nr(W[0]);
+    const double c2 = S.gamma * W[3] * ir;
     const double M2 = (W[1] * W[1] + W[2] * W[2]) * rcp_nr(c2);
     const double theta = rmin(rmax(S.mr2, M2), 1.0);
-    const double ce2 = c2 * rcp_nr(theta);
-    const double ce = ce2 * rsq_nr(ce2);
+    const double ce = c2 * rsq_nr(c2 * theta);
     double six, siy, sjx, sjy, li, lj;
     if (METRIC == 0) {
         six = S.dy; siy = 0.0; sjx = 0.0; sjy = S.dx; li = S.dy; lj = S.dx;

@@ -72,6 +72,20 @@ __device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
     atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
 }
 
+// Per-wave reduction of the rate of the new state: each wave's lane 0 takes
+// its own word (workgroup and wave id mod kRateSlots), so the end of the last
+// stage needs no barrier and no LDS round trip.
+template <int NT>
+__device__ __forceinline__ void reduce_rate_waves(Slot &z, int p, double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0 && v > 0.0) {
+        const unsigned word = (blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) & (kRateSlots - 1);
+        atomicMax(&z.rate_bits[p][word], (unsigned long long)__double_as_longlong(v));
+    }
+}
+
 // Stage codes of the stage kernel: 0 residual only; 1 forward Euler or the
 // first SSP-RK3 stage; 2, 3 the second and third SSP-RK3 stages; 4-7 the four
 // stages of the four-stage scheme.  The buffers each stage reads (stencil) and
@@ -179,7 +193,6 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     __shared__ double sPy[TY + 1][TX + 2];
     __shared__ double sF[4][NFB];
     __shared__ double sG[4][SPLIT ? NFY : 1];
-    __shared__ double sRed[NT / 64 > 0 ? NT / 64 : 1];
 
     const int tid = threadIdx.x;
     const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
@@ -368,7 +381,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             if (last) {
                 double W[4] = {sW[0][cj + HL][ci + HL], sW[1][cj + HL][ci + HL], sW[2][cj + HL][ci + HL],
                                sW[3][cj + HL][ci + HL]};
-                lmax = rmax(lmax, cell_rate<METRIC>(S, W, gi, gj));
+                lmax = rmax(lmax, cell_rate<METRIC>(S, W, rcp_nr(W[0]), gi, gj));
             }
             continue;
         }
@@ -390,16 +403,15 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 #pragma unroll
         for (int k = 0; k < 4; ++k) qo[k * S.plane + idx] = Qn[k];
         double W[4];
-        to_prim(S.gm1, Qn[0], Qn[1], Qn[2], Qn[3], W);
+        const double ir = to_prim(S.gm1, Qn[0], Qn[1], Qn[2], Qn[3], W);
         if (!physical(W)) {
             atomicOr(&z.nonphys, 1);
         } else if (last) {
-            lmax = rmax(lmax, cell_rate<METRIC>(S, W, gi, gj));
+            lmax = rmax(lmax, cell_rate<METRIC>(S, W, ir, gi, gj));
         }
     }
     if (last) {
-        const double mx = block_max<NT>(lmax, sRed);
-        if (tid == 0 && mx > 0.0) reduce_rate(z, stage == 0 ? 0 : (p ^ 1), mx);
+        reduce_rate_waves<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax);
     }
 }
 
@@ -457,7 +469,10 @@ __global__ __launch_bounds__(256) void k_rate(DevSolve S, int p)
         double W[4];
         load_prim(S, S.q, i, j, W);
         if (!physical(W)) atomicOr(&S.slot->nonphys, 1);
-        else lmax = rmax(lmax, S.metric == 0 ? cell_rate<0>(S, W, i, j) : cell_rate<1>(S, W, i, j));
+        else {
+            const double ir = rcp_nr(W[0]);
+            lmax = rmax(lmax, S.metric == 0 ? cell_rate<0>(S, W, ir, i, j) : cell_rate<1>(S, W, ir, i, j));
+        }
     }
     const double m = block_max<256>(lmax, sRed);
     if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, p, m);

@@ -342,19 +342,27 @@ static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_para
     hipEvent_t e0 = ev.a, e1 = ev.b;
     HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 1, s));
     HIP_OK(ctx, roeam::launch_rate(S, 0, s));
+    // each shape: a warm-up launch, then the best of three timed rounds of
+    // four launches (a single round misranks shapes within a few percent of
+    // each other often enough to matter)
     int best = 0;
     float best_ms = 1e30f;
-    const int reps = 4;
+    const int reps = 4, rounds = 3;
     for (int sh = 0; sh < roeam::tile_shape_count(); ++sh) {
         HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, sh, 1, 0, 0, nullptr, s));  // warm-up
-        HIP_OK(ctx, hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, sh, 1, 0, 0, nullptr, s));
-        HIP_OK(ctx, hipEventRecord(e1, s));
-        HIP_OK(ctx, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_OK(ctx, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
+        float shape_ms = 1e30f;
+        for (int round = 0; round < rounds; ++round) {
+            HIP_OK(ctx, hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r)
+                HIP_OK(ctx, roeam::launch_stage_single(g->d_solve, S, sh, 1, 0, 0, nullptr, s));
+            HIP_OK(ctx, hipEventRecord(e1, s));
+            HIP_OK(ctx, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(ctx, hipEventElapsedTime(&ms, e0, e1));
+            shape_ms = ms < shape_ms ? ms : shape_ms;
+        }
+        if (shape_ms < best_ms) {
+            best_ms = shape_ms;
             best = sh;
         }
     }
