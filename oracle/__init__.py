@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "roeam_oracle.c")
+_SRC3 = os.path.join(_HERE, "roeam_oracle3d.c")
 _LIB = os.path.join(_HERE, "libroeam_oracle.so")
 
 V_XI_UNGATED = 1 << 0
@@ -35,11 +36,18 @@ V_DUP_ZERO = 1 << 7
 SCHEME_ROEAM, SCHEME_ROE, SCHEME_ROE_HARTEN = 0, 1, 2
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(os.path.getmtime(f) > t for f in (_SRC, _SRC3, os.path.join(_HERE, "roeam_oracle.h")))
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no fused multiply-add contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-               "-Wall", "-o", _LIB, _SRC, "-lm"]
+               "-Wall", "-o", _LIB, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
 
@@ -77,7 +85,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -99,6 +107,17 @@ def lib():
                               ctypes.c_double, ctypes.POINTER(_Stats)]
         L.orc_cell_areas.restype = None
         L.orc_cell_areas.argtypes = [ctypes.POINTER(_Grid), dp]
+        L.orc3_physical_flux.restype = None
+        L.orc3_physical_flux.argtypes = [ctypes.c_double, dp, dp, dp]
+        L.orc3_face_flux.restype = None
+        L.orc3_face_flux.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp]
+        L.orc3_residual.restype = ctypes.c_int
+        L.orc3_residual.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid3), dp, dp, dp]
+        L.orc3_max_rate.restype = ctypes.c_int
+        L.orc3_max_rate.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid3), dp, dp]
+        L.orc3_run.restype = ctypes.c_int
+        L.orc3_run.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid3), dp, ctypes.c_long,
+                               ctypes.c_double, ctypes.POINTER(_Stats)]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
@@ -237,3 +256,77 @@ def cell_areas(case) -> np.ndarray:
     om = np.zeros((case.ny, case.nx))
     lib().orc_cell_areas(ctypes.byref(gs.g), _dptr(om))
     return om
+
+
+# --------------------------------------------------------------------------
+# 3-D (uniform Cartesian grids)
+# --------------------------------------------------------------------------
+
+class _Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("dz", ctypes.c_double), ("bc", ctypes.c_int * 6),
+                ("bc_state", (ctypes.c_double * 5) * 6)]
+
+
+def _grid3(case) -> _Grid3:
+    g = _Grid3()
+    g.nx, g.ny, g.nz = case.nx, case.ny, case.nz
+    g.dx, g.dy, g.dz = case.dx, case.dy, case.dz
+    for s in range(6):
+        g.bc[s] = int(case.bc[s])
+        for k in range(5):
+            g.bc_state[s][k] = float(case.bc_state[s][k])
+    return g
+
+
+def physical_flux3(W, n, gamma: float = 1.4) -> np.ndarray:
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    nv = np.ascontiguousarray(n, dtype=np.float64)
+    F = np.zeros(5)
+    lib().orc3_physical_flux(float(gamma), _dptr(W), _dptr(nv), _dptr(F))
+    return F
+
+
+def face_flux3(params: Dict, WL, WR, n, s1: float = 1.0) -> np.ndarray:
+    """3-D numerical flux per unit face area; W = (rho, u, v, w, p), n unit."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    nv = np.ascontiguousarray(n, dtype=np.float64)
+    F = np.zeros(5)
+    prm = make_params(params)
+    lib().orc3_face_flux(ctypes.byref(prm), _dptr(WL), _dptr(WR), _dptr(nv), float(s1), _dptr(F))
+    return F
+
+
+def residual3(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None, with_scale: bool = False):
+    q = np.ascontiguousarray(case.q0 if q is None else q, dtype=np.float64)
+    assert q.shape == (5, case.nz, case.ny, case.nx)
+    g = _grid3(case)
+    prm = make_params(params or case.params)
+    r = np.zeros_like(q)
+    sc = np.zeros_like(q) if with_scale else None
+    _check(lib().orc3_residual(ctypes.byref(prm), ctypes.byref(g), _dptr(q), _dptr(r),
+                               _dptr(sc) if with_scale else None))
+    return (r, sc) if with_scale else r
+
+
+def max_rate3(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None) -> float:
+    q = np.ascontiguousarray(case.q0 if q is None else q, dtype=np.float64)
+    g = _grid3(case)
+    prm = make_params(params or case.params)
+    out = ctypes.c_double(0.0)
+    _check(lib().orc3_max_rate(ctypes.byref(prm), ctypes.byref(g), _dptr(q), ctypes.byref(out)))
+    return out.value
+
+
+def run3(case, nsteps: Optional[int] = None, t_end: Optional[float] = None, q: Optional[np.ndarray] = None,
+         params: Optional[Dict] = None, t0: float = 0.0):
+    q = np.array(case.q0 if q is None else q, dtype=np.float64, order="C", copy=True)
+    g = _grid3(case)
+    prm = make_params(params or case.params)
+    st = _Stats()
+    st.t = t0
+    rc = lib().orc3_run(ctypes.byref(prm), ctypes.byref(g), _dptr(q), int(case.nsteps if nsteps is None else nsteps),
+                        float(case.t_end if t_end is None else t_end), ctypes.byref(st))
+    _check(rc)
+    return q, {k: getattr(st, k) for k, _ in _Stats._fields_}

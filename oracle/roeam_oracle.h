@@ -107,6 +107,29 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
 /* Cell areas [ny][nx] (shoelace); face vectors for tests. */
 void orc_cell_areas(const orc_grid *g, double *omega);
 
+/* ------------------------------------------------------------------------ */
+/* 3-D, uniform Cartesian grids (roeam_oracle3d.c)                          */
+/* ------------------------------------------------------------------------ */
+/* Sides in 3-D: west, east (x), south, north (y), bottom, top (z). */
+enum { ORC_BOTTOM = 4, ORC_TOP = 5 };
+
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    int bc[6];             /* west, east, south, north, bottom, top            */
+    double bc_state[6][5]; /* Dirichlet conserved state per side              */
+} orc3_grid;
+
+/* Layout: q is [5][nz][ny][nx], rows (rho, rho u, rho v, rho w, rho E). */
+void orc3_physical_flux(double gamma, const double W[5], const double n[3], double F[5]);
+/* Eqs. (85)-(109) (or the classical schemes) in 3-D, per unit face area;
+ * W = (rho, u, v, w, p), n a unit normal. */
+void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5], const double n[3], double s1,
+                    double F[5]);
+int orc3_residual(const orc_params *prm, const orc3_grid *g, const double *q, double *r, double *scale);
+int orc3_max_rate(const orc_params *prm, const orc3_grid *g, const double *q, double *max_rate);
+int orc3_run(const orc_params *prm, const orc3_grid *g, double *q, long nsteps, double t_end, orc_run_stats *stats);
+
 /* Threads used by the row loops (OpenMP); the results are bitwise the same
  * for any count. */
 void orc_set_threads(int n);

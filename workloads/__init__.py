@@ -514,3 +514,132 @@ def smooth_random_case(nx: int, ny: int, seed: int, bc=(PERIODIC,) * 4, mach: fl
         bc_state[s] = conserved(gamma, 1.0, mach, 0.0, 1.0 / gamma)
     return Case(name=f"smooth_{nx}x{ny}", q0=q0, params=prm, bc=tuple(bc), dx=dx, dy=dy,
                 xn=xn, yn=yn, bc_state=bc_state, nsteps=10, t_end=0.0)
+
+
+# --------------------------------------------------------------------------
+# 3-D uniform Cartesian grids
+# --------------------------------------------------------------------------
+BOTTOM, TOP = 4, 5
+
+
+@dataclasses.dataclass
+class Case3:
+    name: str
+    q0: np.ndarray               # [5][nz][ny][nx], rows rho, rho u, rho v, rho w, rho E
+    params: Dict
+    bc: Tuple[int, int, int, int, int, int]
+    dx: float = 1.0
+    dy: float = 1.0
+    dz: float = 1.0
+    bc_state: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((6, 5)))
+    nsteps: int = 1
+    t_end: float = 0.0
+
+    @property
+    def nz(self) -> int:
+        return self.q0.shape[1]
+
+    @property
+    def ny(self) -> int:
+        return self.q0.shape[2]
+
+    @property
+    def nx(self) -> int:
+        return self.q0.shape[3]
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def conserved3(gamma: float, rho, u, v, w, p) -> np.ndarray:
+    rho, u, v, w, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, u, v, w, p)))
+    return np.stack([rho, rho * u, rho * v, rho * w, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def smooth_random_case3(nx: int, ny: int, nz: int, seed: int, bc=(PERIODIC,) * 6, mach: float = 0.5,
+                        amp: float = 0.2, **params) -> Case3:
+    """Smooth periodic-consistent random field on [0,1]^3: a few Fourier modes
+    per variable, Mach about ``mach`` in a random direction."""
+    gamma = params.get("gamma", 1.4)
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 300 + seed))
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+
+    def field():
+        out = np.zeros_like(X)
+        for _ in range(3):
+            kx, ky, kz = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            out += (rng.uniform(-1, 1) * np.sin(2 * math.pi * kx * X + ph[0]) * np.cos(2 * math.pi * ky * Y + ph[1])
+                    * np.cos(2 * math.pi * kz * Z + ph[2]))
+        return out / 3.0
+
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    rho = 1.0 + amp * field()
+    p = 1.0 / gamma * (1.0 + amp * field())
+    u, v, w = (mach * d[k] + amp * mach * field() for k in range(3))
+    q0 = conserved3(gamma, rho, u, v, w, p)
+    prm = default_params(order=2, eps1=1.0, mach_ref=max(mach, 1e-3), u_ref=mach)
+    prm.update(params)
+    bc_state = np.zeros((6, 5))
+    for s in range(6):
+        bc_state[s] = conserved3(gamma, 1.0, mach * d[0], mach * d[1], mach * d[2], 1.0 / gamma)
+    return Case3(name=f"smooth3_{nx}x{ny}x{nz}", q0=q0, params=prm, bc=tuple(bc), dx=1.0 / nx, dy=1.0 / ny,
+                 dz=1.0 / nz, bc_state=bc_state, nsteps=1)
+
+
+def rough_case3(nx: int, ny: int, nz: int, seed: int, bc=(PERIODIC,) * 6, **params) -> Case3:
+    """Cell-by-cell random states: density and pressure over two decades, Mach up
+    to 3 in random 3-D directions (limiter, detector and supersonic branches)."""
+    c = smooth_random_case3(nx, ny, nz, seed, bc=bc, **params)
+    gamma = c.params.get("gamma", 1.4)
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 400 + seed))
+    shp = (nz, ny, nx)
+    rho = np.exp(rng.uniform(-2.3, 2.3, shp))
+    p = np.exp(rng.uniform(-2.3, 2.3, shp))
+    cs = np.sqrt(gamma * p / rho)
+    M = rng.uniform(0, 3, shp)
+    d = rng.normal(size=(3,) + shp)
+    d /= np.linalg.norm(d, axis=0)
+    c.q0 = conserved3(gamma, rho, M * cs * d[0], M * cs * d[1], M * cs * d[2], p)
+    c.name = f"rough3_{nx}x{ny}x{nz}"
+    return c
+
+
+def extrude(case2: "Case", nz: int, bc_z=(PERIODIC, PERIODIC)) -> Case3:
+    """A 2-D case repeated along z (w = 0, unit dz): its 3-D solution is the
+    2-D one in every z-slice."""
+    q = case2.q0
+    q3 = np.stack([q[0], q[1], q[2], np.zeros_like(q[0]), q[3]])
+    q3 = np.ascontiguousarray(np.broadcast_to(q3[:, None], (5, nz) + q.shape[1:]))
+    bcs = np.zeros((6, 5))
+    for s in range(4):
+        b = case2.bc_state[s]
+        bcs[s] = (b[0], b[1], b[2], 0.0, b[3])
+    return Case3(name=case2.name + f"_x{nz}", q0=q3, params=dict(case2.params),
+                 bc=tuple(case2.bc) + tuple(bc_z), dx=case2.dx, dy=case2.dy, dz=1.0, bc_state=bcs,
+                 nsteps=case2.nsteps, t_end=case2.t_end)
+
+
+def vortex3(n: int = 64, nz: int = 16, mach: float = 0.01, **params) -> Case3:
+    """The low-Mach vortex of the second configuration extruded along z, with a
+    seeded +-1e-6 checkerboard in all three directions and a small seeded w."""
+    c2 = vortex(n, mach, checker_amp=0.0)
+    c = extrude(c2, nz)
+    gamma = c.params.get("gamma", 1.4)
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 500))
+    rho = c.q0[0]
+    u, v = c.q0[1] / rho, c.q0[2] / rho
+    p = (gamma - 1.0) * (c.q0[4] - 0.5 * rho * (u * u + v * v))
+    K, J, I = np.meshgrid(np.arange(nz), np.arange(n), np.arange(n), indexing="ij")
+    p = p * (1.0 + 1e-6 * np.where((I + J + K) % 2 == 0, 1.0, -1.0) * rng.uniform(0.5, 1.5, p.shape))
+    w = 0.1 * mach * np.sin(2 * math.pi * K / nz) * rng.uniform(0.5, 1.5, p.shape)
+    c.q0 = conserved3(gamma, rho, u, v, w, p)
+    c.dz = c.dx
+    c.params.update(params)
+    c.name = f"vortex3_{n}x{n}x{nz}_M{mach:g}"
+    return c
