@@ -211,6 +211,64 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *grid, const ro
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step_stats *stats);
 
 /* ------------------------------------------------------------------------ */
+/* 3-D uniform Cartesian grids                                              */
+/* ------------------------------------------------------------------------ */
+
+/* The scheme in three dimensions (the paper states its equations in 3-D:
+ * Eqs. 1-4 with w and n_z, the nine-face detector of Eq. 96 and the cross
+ * products of Eq. 109): state Q = (rho, rho u, rho v, rho w, rho E), cell
+ * (i, j, l) = [i dx, (i+1) dx] x [j dy, (j+1) dy] x [l dz, (l+1) dz].
+ *   - State arrays are device memory, FP64, structure of arrays:
+ *     q[k][l][j][i] at q + ((k*nz + l)*ny + j)*pitch + i, k = 0..4; pad
+ *     elements i >= nx are never read or written.
+ *   - Boundary kinds as for 2-D grids, per side W, E, S, N, bottom (l < 0),
+ *     top (l >= nz); ghost cells apply the x rule, then the y rule, then the
+ *     z rule (edges and corners follow); a slip wall mirrors the cells and
+ *     negates the velocity component normal to it.
+ *   - The flux of a face normal to axis a is Eq. (85) with n = e_a; f_rr of
+ *     Eq. (103) takes n2 along (n1 x n) x n1 (zero when n1 = +-n).
+ *   - Time step: dt = cfl / max over cells of
+ *     ((|u| + ce) dy dz + (|v| + ce) dx dz + (|w| + ce) dx dy) / (dx dy dz),
+ *     ce as for 2-D grids.
+ * All roeam_params fields mean what they mean for 2-D grids. */
+enum { ROEAM_BOTTOM = 4, ROEAM_TOP = 5 };
+
+typedef struct roeam_grid3d roeam_grid3d;
+
+/* Create an nx x ny x nz grid (each >= 2, nx*ny*nz < 2^31) of spacing dx, dy,
+ * dz (> 0).  bc[6] = kinds for W, E, S, N, bottom, top; a periodic kind must
+ * be used on both sides of its direction.  dirichlet_state: HOST array
+ * [6 sides][5] of conserved states for DIRICHLET sides (NULL allowed if none).
+ * The grid owns two stage buffers of the state size from its first
+ * roeam_step3d on.  EINVAL: sizes, spacing, kinds or Dirichlet states invalid;
+ * ENOMEM; EDEVICE. */
+roeam_status roeam_grid3d_create(roeam_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,
+                                 const int bc[6], const double *dirichlet_state, roeam_grid3d **out);
+roeam_status roeam_grid3d_destroy(roeam_grid3d *grid);
+/* Layout of state arrays: q[k][l][j][i] at ((k*nz + l)*ny + j)*pitch + i. */
+roeam_status roeam_grid3d_layout(const roeam_grid3d *grid, int *nx, int *ny, int *nz, long *pitch);
+/* Brick shape of the 3-D stage kernel (cells per workgroup / threads):
+ * 0 = 8x8x4/256 (default), 1 = 8x4x4/128, 2 = 16x8x4/512, 3 = 16x4x4/256.
+ * Every shape computes bitwise the same result.  EINVAL: shape outside 0..3. */
+roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
+/* Residual R = dQ/dt = -(1/V) sum over the cell's six faces of F A (Eq. 85
+ * per unit area times the face area).  q: device, 3-D state layout, read
+ * only; r: device, same layout, written.  max_rate_out: nullable DEVICE
+ * pointer to one double receiving the largest explicit rate of q.
+ * Asynchronous.  EINVAL: NULL q/r, bad params; EDEVICE. */
+roeam_status roeam_residual3d(roeam_ctx *ctx, const roeam_grid3d *grid, const roeam_params *params,
+                              const double *q, double *r, double *max_rate_out);
+/* Advance q (device, 3-D state layout) in place, as roeam_step does for 2-D
+ * grids: up to nsteps steps of params->time_scheme from time t0, stopping at
+ * t_end (t_end <= 0: no stop), device-resident dt and t, captured HIP graphs;
+ * stats != NULL waits and fills them (ENONPHYS for a non-physical state).
+ * EINVAL: NULL q, nsteps < 0, bad params; EDEVICE. */
+roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *grid, const roeam_params *params, double *q,
+                          long nsteps, double t0, double t_end, roeam_step_stats *stats);
+/* Wait for the grid's last roeam_step3d and read its statistics. */
+roeam_status roeam_last_stats3d(roeam_ctx *ctx, const roeam_grid3d *grid, roeam_step_stats *stats);
+
+/* ------------------------------------------------------------------------ */
 /* Batched and served solves                                                */
 /* ------------------------------------------------------------------------ */
 

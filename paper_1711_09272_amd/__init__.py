@@ -28,7 +28,11 @@ EXPORTS = [
     "roeam_grid_tile_shape", "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll",
+    "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
+    "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
+# 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
+SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256"]
 
 
 class RoeamError(RuntimeError):
@@ -103,6 +107,14 @@ def lib():
         "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 4),
                                         ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
+        "roeam_grid3d_create": (i, [vp, i, i, i, d, d, d, ctypes.POINTER(ctypes.c_int * 6), vp, ctypes.POINTER(vp)]),
+        "roeam_grid3d_destroy": (i, [vp]),
+        "roeam_grid3d_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                    ctypes.POINTER(ctypes.c_long)]),
+        "roeam_grid3d_set_tile_shape": (i, [vp, i]),
+        "roeam_residual3d": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
+        "roeam_step3d": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
+        "roeam_last_stats3d": (i, [vp, vp, ctypes.POINTER(StepStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -408,3 +420,106 @@ def batch_poll(ctx: Context, ticket: int):
     if done.value:
         ctx.leave()  # outputs written by the library's stream are read after this
     return bool(done.value), (st.as_dict() if done.value else None), rc
+
+
+# ---------------------------------------------------------------------------
+# 3-D uniform Cartesian grids
+# ---------------------------------------------------------------------------
+
+class Grid3:
+    """An immutable 3-D uniform Cartesian grid of the library; state tensors are
+    [5, nz, ny, pitch] (rho, rho u, rho v, rho w, rho E)."""
+
+    def __init__(self, ctx: Context, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
+                 bc: Sequence[int] = (0,) * 6, bc_state: Optional[np.ndarray] = None):
+        self.ctx = ctx
+        bca = (ctypes.c_int * 6)(*[int(b) for b in bc])
+        st = None
+        self._keep = []
+        if bc_state is not None:
+            sa = np.ascontiguousarray(bc_state, dtype=np.float64).reshape(30)
+            self._keep.append(sa)
+            st = ctypes.c_void_p(sa.ctypes.data)
+        h = ctypes.c_void_p()
+        ctx.check(lib().roeam_grid3d_create(ctx.h, int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                                            ctypes.byref(bca), st, ctypes.byref(h)))
+        self.h = h
+        a, b, c, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+        lib().roeam_grid3d_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p))
+        self.nx, self.ny, self.nz, self.pitch = a.value, b.value, c.value, p.value
+
+    @classmethod
+    def from_case(cls, ctx: Context, case) -> "Grid3":
+        return cls(ctx, case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, bc=case.bc, bc_state=case.bc_state)
+
+    def empty_state(self):
+        import torch
+        return torch.zeros((5, self.nz, self.ny, self.pitch), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+
+    def to_device(self, q: np.ndarray):
+        import torch
+        t = self.empty_state()
+        t[..., : self.nx] = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64))
+        return t
+
+    def from_device(self, t) -> np.ndarray:
+        return t[..., : self.nx].detach().cpu().numpy().copy()
+
+    def set_tile_shape(self, shape: int):
+        """Brick shape (see SHAPES3)."""
+        self.ctx.check(lib().roeam_grid3d_set_tile_shape(self.h, int(shape)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().roeam_grid3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_ptr3(t, grid: Grid3) -> ctypes.c_void_p:
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    shape = (5, grid.nz, grid.ny, grid.pitch)
+    assert tuple(t.shape) == shape, (tuple(t.shape), shape)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def residual3(ctx: Context, grid: Grid3, prm: Dict, q, r=None, rate_out=None):
+    """R = dQ/dt of the 3-D state tensor q (device, [5, nz, ny, pitch]); returns r.
+    rate_out: optional 1-element float64 device tensor for the max explicit rate."""
+    if r is None:
+        r = grid.empty_state()
+    p = params(prm)
+    rp = ctypes.c_void_p(rate_out.data_ptr()) if rate_out is not None else None
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_residual3d(ctx.h, grid.h, ctypes.byref(p), _dev_ptr3(q, grid), _dev_ptr3(r, grid), rp))
+    finally:
+        ctx.leave()
+    return r
+
+
+def step3(ctx: Context, grid: Grid3, prm: Dict, q, nsteps: int, t0: float = 0.0, t_end: float = 0.0,
+          sync: bool = True) -> Optional[Dict]:
+    """Advance the 3-D state q in place; returns the step statistics when sync (else None)."""
+    p = params(prm)
+    st = StepStats()
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_step3d(ctx.h, grid.h, ctypes.byref(p), _dev_ptr3(q, grid), int(nsteps), float(t0),
+                                     float(t_end), ctypes.byref(st) if sync else None))
+    finally:
+        ctx.leave()
+    return st.as_dict() if sync else None
+
+
+def last_stats3(ctx: Context, grid: Grid3) -> Dict:
+    st = StepStats()
+    ctx.check(lib().roeam_last_stats3d(ctx.h, grid.h, ctypes.byref(st)))
+    ctx.leave()
+    return st.as_dict()

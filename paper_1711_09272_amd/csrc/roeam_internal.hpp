@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "roeam_device.hpp"
+#include "roeam_device3d.hpp"
 
 namespace roeam {
 
@@ -36,5 +37,12 @@ hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
 hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
+
+// 3-D uniform Cartesian grids (brick shapes 0..brick_shape_count()-1).
+int brick_shape_count();
+hipError_t launch_stage3(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last, double *r_out,
+                         hipStream_t st);
+hipError_t launch_rate3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);
+hipError_t launch_copy_back3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);
 
 } // namespace roeam

@@ -1,0 +1,140 @@
+// roeam_stage.hpp -- device helpers shared by the 2-D and 3-D stage kernels:
+// the MUSCL limiter, the explicit-rate words of a solve's slot, the step
+// state that the first stage of every step advances, and the XCD-aware
+// workgroup-to-tile map.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "roeam_device.hpp"
+
+namespace roeam {
+
+// minmod(a, b): 0 when the slopes differ in sign, else the one nearer zero,
+// written as max(0, min(a, b)) + min(0, max(a, b)) (four min/max and an add).
+__device__ __forceinline__ double minmod(double a, double b)
+{
+    return rmax(0.0, rmin(a, b)) + rmin(0.0, rmax(a, b));
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    if (NT == 64) return v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) m = rmax(m, red[w]);
+    return m;
+}
+
+// Max explicit rate of the state at parity p: lane k of every wave reads rate
+// word k, then a wave max.  Every lane of every wave ends with the same value.
+__device__ __forceinline__ double read_rate(const Slot &z, int p)
+{
+    static_assert(kRateSlots == 64, "one rate word per lane");
+    const int lane = threadIdx.x & 63;
+    double v = __longlong_as_double((long long)z.rate_bits[p][lane]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
+{
+    atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
+}
+
+// Per-wave reduction of the rate of the new state: each wave's lane 0 takes
+// its own word (workgroup and wave id mod kRateSlots), so the end of the last
+// stage needs no barrier and no LDS round trip.
+template <int NT>
+__device__ __forceinline__ void reduce_rate_waves(Slot &z, int p, double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0 && v > 0.0) {
+        const unsigned word = (blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) & (kRateSlots - 1);
+        atomicMax(&z.rate_bits[p][word], (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// Stage codes of the stage kernel: 0 residual only; 1 forward Euler or the
+// first SSP-RK3 stage; 2, 3 the second and third SSP-RK3 stages; 4-7 the four
+// stages of the four-stage scheme.  The buffers each stage reads (stencil) and
+// writes, and whether it also reads Q^n at its own cells:
+//   1: q -> qa     2: qa -> qb (+Q^n)   3: qb -> q (+Q^n)
+//   4: q -> qa     5: qa -> qb (+Q^n)   6: qb -> qa (+Q^n)   7: qa -> q (+Q^n)
+// (a stage that writes q reads its stencil from another buffer, and its
+// pointwise read of Q^n is the cell it writes).
+__host__ __device__ constexpr bool first_stage(int stage) { return stage == 1 || stage == 4; }
+
+// Time-step logic shared by all stage kernels of a step with parity p.
+// Returns whether the step is active and its dt.
+__device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, double &dt, double &t_next,
+                                            double &rate)
+{
+    const StepState &s = z.st[p];
+    if (!first_stage(stage)) {
+        // the first stage has already decided: the step ran iff it advanced the count
+        const StepState &n = z.st[p ^ 1];
+        dt = n.dt;
+        return n.steps != s.steps;
+    }
+    rate = read_rate(z, p);
+    if (z.nonphys || (z.t_end > 0.0 && s.t >= z.t_end) || s.steps >= z.max_steps || !(rate > 0.0)) return false;
+    dt = z.cfl / rate;
+    t_next = s.t + dt;
+    if (z.t_end > 0.0 && s.t + dt >= z.t_end) {
+        dt = z.t_end - s.t;
+        t_next = z.t_end;
+    }
+    return true;
+}
+
+// Start of a stage kernel's workgroup: decide whether the step is active and
+// its dt; on the first stage, workgroup 0 (first_block) publishes the next
+// step state and, unless this stage also ends the step, clears the rate words
+// that the step's last stage will reduce into.
+__device__ __forceinline__ bool begin_stage(Slot &z, int p, int stage, int last, int first_block, double &dt)
+{
+    double t_next = 0.0, rate = 0.0;
+    const bool active = step_active(z, p, stage, dt, t_next, rate);
+    if (first_stage(stage) && first_block) {
+        const int tid = threadIdx.x;
+        if (tid == 0) {
+            const StepState &s = z.st[p];
+            StepState &n = z.st[p ^ 1];
+            if (active) {
+                n.t = t_next;
+                n.dt = dt;
+                n.steps = s.steps + 1;
+                z.dt_last = dt;
+                z.rate_last = rate;
+            } else {
+                n.t = s.t;
+                n.dt = 0.0;
+                n.steps = s.steps;
+            }
+        }
+        // multi-stage schemes: the last stage reduces into parity p^1; forward
+        // Euler reduces in this kernel, so its words were cleared earlier.
+        if (!last && tid < kRateSlots) z.rate_bits[p ^ 1][tid] = 0ull;
+    }
+    return active;
+}
+
+// Map a linear workgroup id to a tile so that each of the 8 XCDs (which take
+// workgroups round-robin) gets a contiguous band of tiles and keeps the
+// shared halos in its own L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+{
+    const int chunk = (ntiles + 7) >> 3;
+    return (b & 7) * chunk + (b >> 3);
+}
+
+} // namespace roeam

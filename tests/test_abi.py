@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "roeam.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(roeam_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(roeam_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
@@ -37,6 +37,10 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.roeam_residual(None, None, None, None, None, None) == P.EINVAL
     assert L.roeam_step(None, None, None, None, 1, 0.0, 0.0, None) == P.EINVAL
     assert L.roeam_grid_layout(None, None, None, None) == P.EINVAL
+    assert L.roeam_grid3d_destroy(None) == P.EINVAL
+    assert L.roeam_residual3d(None, None, None, None, None, None) == P.EINVAL
+    assert L.roeam_step3d(None, None, None, None, 1, 0.0, 0.0, None) == P.EINVAL
+    assert L.roeam_grid3d_layout(None, None, None, None, None) == P.EINVAL
     assert L.roeam_last_error(None) == b"NULL context"
     h = ctypes.c_void_p()
     assert L.roeam_ctx_create(0, None, None) == P.EINVAL
