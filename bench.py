@@ -34,15 +34,25 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL_STAGE = {1: 64.0, 2: 96.0, 3: 96.0}
 
 
+# 3-D: five rows; stage 1 reads Q and writes Q1 (80 B), stages 2 and 3 read the
+# stage input and Q^n and write the result (120 B each).
+BYTES_PER_CELL_STAGE_3D = {1: 80.0, 2: 120.0, 3: 120.0}
+
+
 # The device code of the stage kernels: counter summaries taken on other
 # sources are stale.  (Host-side scheduling files are not part of the hash.)
-KERNEL_SOURCES = ("roeam_kernels.hip", "roeam_device.hpp")
+KERNEL_SOURCES = ("roeam_kernels.hip", "roeam_device.hpp", "roeam_stage.hpp")
+KERNEL_SOURCES_3D = ("roeam_kernels3d.hip", "roeam_device3d.hpp", "roeam_device.hpp", "roeam_stage.hpp")
 
 
-def kernel_source_hash() -> str:
+def is_3d(workload: str) -> bool:
+    return workload.startswith("vortex3d")
+
+
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1711_09272_amd", "csrc")
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -60,7 +70,7 @@ def counter_summary(workload: str, precision: int, kind: str, key: str):
         parts = line.split()
         if len(parts) >= 2 and not line.startswith("#"):
             vals[parts[0]] = parts[1]
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    if vals.get("kernel_source_hash") != kernel_source_hash(KERNEL_SOURCES_3D if is_3d(workload) else KERNEL_SOURCES):
         return None
     try:
         return float(vals[key])
@@ -355,6 +365,126 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def parse_3d(workload: str):
+    """vortex3dNxNZ -> (N, NZ)."""
+    dims = workload[len("vortex3d"):].split("x")
+    if len(dims) != 2:
+        raise SystemExit(f"unknown workload {workload} (3-D form: vortex3dNxNZ)")
+    return int(dims[0]), int(dims[1])
+
+
+def cpu_baseline_3d(case, sample_steps: int):
+    import oracle
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    _, st = oracle.run3(case, nsteps=sample_steps)
+    dt = time.perf_counter() - t0
+    updates = case.cells * 3 * st["steps"]
+    return {
+        "value": updates / dt / 1e9,
+        "unit": "Gcell-updates/s per RK stage",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {sample_steps} SSP-RK3 steps of the same {case.nx}x{case.ny}x{case.nz} grid "
+                  f"({updates} cell-stage updates, {dt:.1f} s, {threads} OpenMP threads over z-planes)",
+    }
+
+
+def bench_3d(args):
+    """One 3-D grid: the vortex extruded along a periodic z with a seeded w and
+    +-1e-6 checkerboard (all three face directions and the nine-face detector
+    active), through roeam_step3d."""
+    import torch
+    import paper_1711_09272_amd as P
+    import workloads
+    n, nz = parse_3d(args.workload)
+    case = workloads.vortex3(n, nz, 0.01, time_scheme=1, precision=args.precision)
+    cells = case.cells
+    ctx = P.Context(0)
+    grid = P.Grid3.from_case(ctx, case)
+    shape = args.tile_shape if args.tile_shape >= 0 else 6
+    grid.set_tile_shape(shape)
+    q = grid.to_device(case.q0)
+    prm = case.params
+    stream = torch.cuda.current_stream()
+    if args.counter_run:
+        P.step3(ctx, grid, prm, q, args.profile_steps, sync=True)
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": args.workload, "cells": cells, "profile_steps": args.profile_steps,
+                          "copy_bytes": src.numel() * 8, "tile_shape": P.SHAPES3[shape]}), flush=True)
+        return
+    P.step3(ctx, grid, prm, q, args.warmup, sync=True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    P.step3(ctx, grid, prm, q, args.steps, sync=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    st = P.last_stats3(ctx, grid)
+    if st["nonphys"] or st["steps"] != args.steps:
+        raise SystemExit(f"bench run failed: {st}")
+    value = cells * 3 * args.steps / (gpu_ms / 1e3) / 1e9
+    launch_ms = gpu_ms / (3 * args.steps)
+    bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE_3D.values()) / 3.0
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, args.precision)
+    valu = measured_valu(args.workload, args.precision)
+    alu = None
+    if valu is not None:
+        lane_rate = valu * cells / (launch_ms / 1e3)
+        alu = {"bound": "alu", "achieved": round(lane_rate / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 3),
+               "unit": "T VALU lane-instr/s", "frac": round(lane_rate / PEAK_VALU_LANE_INSTR, 4),
+               "valu_lane_instr_per_cell_stage": valu}
+    out = {
+        "metric": "Gcell-updates/s per RK stage",
+        "value": round(value, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32-flux/f64-state",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D low-Mach vortex {n}x{n}x{nz} (extruded along a periodic z, seeded w and "
+                        "+-1e-6 checkerboard), M=0.01, FP64 state, MUSCL-minmod + SSP-RK3, Roe-AM (nine-face "
+                        "detector, eps1=1, eps2=0.05), CFL 0.4",
+            "cells": cells,
+            "stages_per_step": 3,
+            "tile_shape": P.SHAPES3[shape],
+            "wall_s": round(wall, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5),
+            "traffic": traffic,
+            "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
+            "alu": alu,
+            "kernel": "k_stage3<order 2, FP%s, %s>" % ("64" if args.precision == 0 else "32-coef", P.SHAPES3[shape]),
+            "kernel_grid": f"{n}x{n}x{nz}",
+            "launch_ms": round(launch_ms, 6),
+            "timed_region_launches": 3 * args.steps,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_3d(case, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,7 +492,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="vortex256pair",
                     help="vortex256pair (both Mach numbers, batched; the default line), vortexN (one "
-                         "N x N grid), batch256 (fourth configuration), serve (fifth configuration)")
+                         "N x N grid), batch256 (fourth configuration), serve (fifth configuration), "
+                         "vortex3dNxNZ (one 3-D N x N x NZ grid)")
     ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
                     help="0 FP64, 1 FP32 coefficients (default: 0; batch256 defaults to 1)")
     ap.add_argument("--tile-shape", type=int, default=-1,
@@ -392,6 +523,10 @@ def main():
         return bench_serve(args)
     if args.precision is None:
         args.precision = 0
+    if is_3d(args.workload):
+        if args.cpu_sample_steps == 1000:
+            args.cpu_sample_steps = 5
+        return bench_3d(args)
 
     import torch
     import paper_1711_09272_amd as P

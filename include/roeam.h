@@ -248,8 +248,10 @@ roeam_status roeam_grid3d_destroy(roeam_grid3d *grid);
 /* Layout of state arrays: q[k][l][j][i] at ((k*nz + l)*ny + j)*pitch + i. */
 roeam_status roeam_grid3d_layout(const roeam_grid3d *grid, int *nx, int *ny, int *nz, long *pitch);
 /* Brick shape of the 3-D stage kernel (cells per workgroup / threads):
- * 0 = 8x8x4/256 (default), 1 = 8x4x4/128, 2 = 16x8x4/512, 3 = 16x4x4/256.
- * Every shape computes bitwise the same result.  EINVAL: shape outside 0..3. */
+ * 0 = 8x8x4/256, 1 = 8x4x4/128, 2 = 16x8x4/512, 3 = 16x4x4/256,
+ * 4 = 8x8x4/320, 5 = 8x4x4/192, 6 = 16x8x4/640 (default), 7 = 8x8x8/576
+ * (4-7: one thread per face of each direction).  Every shape computes bitwise the same
+ * result.  EINVAL: shape outside 0..7. */
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
 /* Residual R = dQ/dt = -(1/V) sum over the cell's six faces of F A (Eq. 85
  * per unit area times the face area).  q: device, 3-D state layout, read

@@ -32,7 +32,8 @@ EXPORTS = [
     "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
 # 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
-SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256"]
+SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256", "8x8x4/320", "8x4x4/192", "16x8x4/640",
+           "8x8x8/576"]
 
 
 class RoeamError(RuntimeError):

@@ -337,12 +337,18 @@ __global__ __launch_bounds__(256) void k_copy_back3(const DevSolve3 *__restrict_
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Brick shapes: id, TX, TY, TZ, threads.
+// Brick shapes: id, TX, TY, TZ, threads.  Shapes 4-7 give every face of a
+// sweep its own thread (threads >= the largest face count of one axis), so
+// each sweep is a single pass.
 #define ROEAM_SHAPES3(X)   \
     X(0, 8, 8, 4, 256)     \
     X(1, 8, 4, 4, 128)     \
     X(2, 16, 8, 4, 512)    \
-    X(3, 16, 4, 4, 256)
+    X(3, 16, 4, 4, 256)    \
+    X(4, 8, 8, 4, 320)     \
+    X(5, 8, 4, 4, 192)     \
+    X(6, 16, 8, 4, 640)    \
+    X(7, 8, 8, 8, 576)
 
 struct BrickShape {
     int tx, ty, tz, nt;

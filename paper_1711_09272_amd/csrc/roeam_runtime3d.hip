@@ -26,7 +26,7 @@ struct roeam_grid3d {
     DevSolve3 *h_solve = nullptr;     // pinned staging copy of the last descriptor sent
     bool solve_valid = false;
     GraphCache gc;
-    int shape = 0;
+    int shape = 6;                    // 16x8x4 bricks, one thread per face (fastest measured on 128^3)
     int final_parity = 0;
 };
 

@@ -106,7 +106,7 @@ def test_residual3_fp32_flux(C, name):
     assert np.all(err <= TOL32), err
 
 
-@pytest.mark.parametrize("shape", range(4))
+@pytest.mark.parametrize("shape", range(8))
 def test_every_brick_shape_is_bitwise_identical(C, shape):
     """All brick shapes evaluate the same faces with the same arithmetic."""
     case = workloads.rough_case3(37, 19, 13, 15, bc=ALL_WALLS, order=2, eps1=1.0, mach_ref=0.05)
@@ -188,7 +188,7 @@ def test_invalid_arguments_3d(C):
     case = workloads.smooth_random_case3(4, 4, 4, 19)
     g = P.Grid3.from_case(C, case)
     with pytest.raises(P.RoeamError):
-        g.set_tile_shape(4)
+        g.set_tile_shape(8)
     q = g.to_device(case.q0)
     with pytest.raises(P.RoeamError):
         P.residual3(C, g, dict(case.params, order=3), q)
