@@ -34,6 +34,7 @@ V_XI_EQ46 = 1 << 6
 V_DUP_ZERO = 1 << 7
 
 SCHEME_ROEAM, SCHEME_ROE, SCHEME_ROE_HARTEN = 0, 1, 2
+MAX_SCALARS = 2  # transported scalars (rho k rows of Eq. 85) a 2-D grid may carry
 
 
 def _stale() -> bool:
@@ -63,7 +64,8 @@ class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("metric", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("xn", ctypes.POINTER(ctypes.c_double)), ("yn", ctypes.POINTER(ctypes.c_double)),
-                ("bc", ctypes.c_int * 4), ("bc_state", (ctypes.c_double * 4) * 4)]
+                ("bc", ctypes.c_int * 4), ("bc_state", (ctypes.c_double * 4) * 4),
+                ("nscalars", ctypes.c_int), ("bc_scalar", (ctypes.c_double * MAX_SCALARS) * 4)]
 
 
 _DIAG_FIELDS = ["UL", "UR", "U", "dU", "dp", "rho", "u", "v", "H", "c", "M", "Mbar", "theta",
@@ -96,6 +98,9 @@ def lib():
         L.orc_face_flux.restype = None
         L.orc_face_flux.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, dp, ctypes.POINTER(_Diag)]
+        L.orc_face_flux_sc.restype = None
+        L.orc_face_flux_sc.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, dp]
         L.orc_physical_flux.restype = None
         L.orc_physical_flux.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_residual.restype = ctypes.c_int
@@ -166,6 +171,14 @@ class GridSpec:
             g.bc[s] = int(case.bc[s])
             for k in range(4):
                 g.bc_state[s][k] = float(case.bc_state[s][k])
+        ns = case.q0.shape[0] - 4
+        assert 0 <= ns <= MAX_SCALARS
+        g.nscalars = ns
+        bcs = getattr(case, "bc_scalar", None)
+        if ns and bcs is not None:
+            for s in range(4):
+                for m in range(ns):
+                    g.bc_scalar[s][m] = float(bcs[s][m])
         self.g = g
 
 
@@ -196,6 +209,17 @@ def face_flux(params: Dict, WL, WR, nx: float, ny: float, s1: float = 1.0) -> Tu
     return F, {k: getattr(d, k) for k in _DIAG_FIELDS}
 
 
+def face_flux_sc(params: Dict, WL, WR, nx: float, ny: float, s1: float = 1.0) -> np.ndarray:
+    """Flux per unit face length with transported scalars: W = (rho, u, v, p, k_1, ..)."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    ns = len(WL) - 4
+    F = np.zeros(4 + ns)
+    prm = make_params(params)
+    lib().orc_face_flux_sc(ctypes.byref(prm), _dptr(WL), _dptr(WR), float(nx), float(ny), float(s1), ns, _dptr(F))
+    return F
+
+
 class NonPhysical(RuntimeError):
     pass
 
@@ -212,7 +236,7 @@ def residual(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None
     """R = dQ/dt for the case's grid; q defaults to case.q0.  Returns r (and the
     per-cell flux scale sum_faces |F| |S| / Omega when ``with_scale``)."""
     q = np.ascontiguousarray(case.q0 if q is None else q, dtype=np.float64)
-    assert q.shape == (4, case.ny, case.nx)
+    assert q.shape == (case.q0.shape[0], case.ny, case.nx)
     gs = GridSpec(case)
     prm = make_params(params or case.params)
     r = np.zeros_like(q)

@@ -225,23 +225,53 @@ void orc_face_flux(const orc_params *prm, const double WL[4], const double WR[4]
     if (diag) *diag = d;
 }
 
+/* Eq. (85) with the transported-scalar rows (rho k, ...): the same xi,
+ * dU_p, dU_u of the face; rho^ k^ with the Roe average of k (sqrt(rho)
+ * weights, like u, v and H); no pressure term. */
+void orc_face_flux_sc(const orc_params *prm, const double *WL, const double *WR, double nx, double ny,
+                      double s1, int ns, double *F)
+{
+    orc_face_diag d;
+    orc_face_flux(prm, WL, WR, nx, ny, s1, F, &d);
+    const double rL = WL[0], rR = WR[0];
+    const double rr = sqrt(rR / rL);
+    const int classical = prm->scheme == ORC_SCHEME_ROE || prm->scheme == ORC_SCHEME_ROE_HARTEN;
+    for (int m = 0; m < ns; ++m) {
+        double kL = WL[4 + m], kR = WR[4 + m];
+        double PsiL = rL * kL, PsiR = rR * kR;
+        double khat = (kL + rr * kR) / (1.0 + rr);
+        double diss;
+        if (classical)
+            diss = d.xi * (PsiR - PsiL) + (d.dUuR + d.dUuL + d.dUp) * (d.rho * khat); /* Eq. (7) */
+        else
+            diss = d.xi * (PsiR - PsiL) + d.dUp * (d.rho * khat) + d.dUuR * PsiR + d.dUuL * PsiL;
+        F[4 + m] = 0.5 * (d.UL * PsiL + d.UR * PsiR) - 0.5 * diss;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid, ghosts and the residual                                             */
 /* ------------------------------------------------------------------------ */
 
+/* Largest number of components of a cell: (rho, u, v, p) and the scalars k_m. */
+#define ORC_MAXC (4 + ORC_MAX_SCALARS)
+
 typedef struct {
     int nx, ny, NX, NY;   /* NX = nx + 4, NY = ny + 4 (two ghost layers) */
-    double *W;            /* primitives [4][NY][NX] */
+    int nc;               /* components: 4 + scalars */
+    double *W;            /* primitives [nc][NY][NX]: rho, u, v, p, k_1 .. */
 } prim_field;
 
 #define PIDX(pf, k, i, j) ((size_t)(k) * (pf)->NX * (pf)->NY + (size_t)((j) + 2) * (pf)->NX + (size_t)((i) + 2))
 
-static void conserved_to_prim(double gamma, const double Q[4], double W[4])
+/* (rho, rho u, rho v, rho E, rho k_1 ..) -> (rho, u, v, p, k_1 ..); nc components. */
+static void conserved_to_prim(double gamma, const double *Q, double *W, int nc)
 {
     double rho = Q[0];
     double u = Q[1] / rho, v = Q[2] / rho;
     double p = (gamma - 1.0) * (Q[3] - 0.5 * rho * (u * u + v * v));
     W[0] = rho; W[1] = u; W[2] = v; W[3] = p;
+    for (int k = 4; k < nc; ++k) W[k] = Q[k] / rho;
 }
 
 static int physical(const double W[4])
@@ -310,13 +340,22 @@ static void reflect(double W[4], const double n[2])
     W[2] = W[2] - 2.0 * vn * n[1];
 }
 
-static void get_prim(const prim_field *pf, int i, int j, double W[4])
+static void get_prim(const prim_field *pf, int i, int j, double *W)
 {
-    for (int k = 0; k < 4; ++k) W[k] = pf->W[PIDX(pf, k, i, j)];
+    for (int k = 0; k < pf->nc; ++k) W[k] = pf->W[PIDX(pf, k, i, j)];
 }
-static void set_prim(prim_field *pf, int i, int j, const double W[4])
+static void set_prim(prim_field *pf, int i, int j, const double *W)
 {
-    for (int k = 0; k < 4; ++k) pf->W[PIDX(pf, k, i, j)] = W[k];
+    for (int k = 0; k < pf->nc; ++k) pf->W[PIDX(pf, k, i, j)] = W[k];
+}
+
+/* Dirichlet state of a side, primitive, scalars included. */
+static void dirichlet_prim(const orc_params *prm, const orc_grid *g, int side, int nc, double *W)
+{
+    double Q[ORC_MAXC];
+    for (int k = 0; k < 4; ++k) Q[k] = g->bc_state[side][k];
+    for (int k = 4; k < nc; ++k) Q[k] = g->bc_scalar[side][k - 4];
+    conserved_to_prim(prm->gamma, Q, W, nc);
 }
 
 /* Ghost cells, two layers.  Boundary conditions are not in the paper; the
@@ -325,8 +364,8 @@ static void set_prim(prim_field *pf, int i, int j, const double W[4])
  * defines the corners. */
 static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf)
 {
-    const int nx = g->nx, ny = g->ny;
-    double W[4], n[2], S[2], len;
+    const int nx = g->nx, ny = g->ny, nc = pf->nc;
+    double W[ORC_MAXC], n[2], S[2], len;
     for (int j = 0; j < ny; ++j) {
         for (int gi = 1; gi <= 2; ++gi) {
             /* west ghost i = -gi */
@@ -336,7 +375,7 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             case ORC_BC_SLIPWALL:
                 get_prim(pf, gi - 1, j, W);
                 xface_vector(g, 0, j, S); unit_normal(g, S, n, &len); reflect(W, n); break;
-            default: conserved_to_prim(prm->gamma, g->bc_state[ORC_WEST], W); break;
+            default: dirichlet_prim(prm, g, ORC_WEST, nc, W); break;
             }
             set_prim(pf, -gi, j, W);
             /* east ghost i = nx - 1 + gi */
@@ -346,7 +385,7 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             case ORC_BC_SLIPWALL:
                 get_prim(pf, nx - gi, j, W);
                 xface_vector(g, nx, j, S); unit_normal(g, S, n, &len); reflect(W, n); break;
-            default: conserved_to_prim(prm->gamma, g->bc_state[ORC_EAST], W); break;
+            default: dirichlet_prim(prm, g, ORC_EAST, nc, W); break;
             }
             set_prim(pf, nx - 1 + gi, j, W);
         }
@@ -360,7 +399,7 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             case ORC_BC_SLIPWALL:
                 get_prim(pf, i, gj - 1, W);
                 yface_vector(g, ic, 0, S); unit_normal(g, S, n, &len); reflect(W, n); break;
-            default: conserved_to_prim(prm->gamma, g->bc_state[ORC_SOUTH], W); break;
+            default: dirichlet_prim(prm, g, ORC_SOUTH, nc, W); break;
             }
             set_prim(pf, i, -gj, W);
             switch (g->bc[ORC_NORTH]) {
@@ -369,7 +408,7 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             case ORC_BC_SLIPWALL:
                 get_prim(pf, i, ny - gj, W);
                 yface_vector(g, ic, ny, S); unit_normal(g, S, n, &len); reflect(W, n); break;
-            default: conserved_to_prim(prm->gamma, g->bc_state[ORC_NORTH], W); break;
+            default: dirichlet_prim(prm, g, ORC_NORTH, nc, W); break;
             }
             set_prim(pf, i, ny - 1 + gj, W);
         }
@@ -386,10 +425,10 @@ static double minmod(double a, double b)
 /* Face states from four cells m2, m1 | p0, p1 along the face normal.
  * First order (Sec. 7.1): the two adjacent cells.  MUSCL-minmod on the
  * primitive variables (not in the paper; named by the test configurations). */
-static void reconstruct(int order, const double m2[4], const double m1[4], const double p0[4],
-                        const double p1[4], double WL[4], double WR[4])
+static void reconstruct(int order, int nc, const double *m2, const double *m1, const double *p0,
+                        const double *p1, double *WL, double *WR)
 {
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < nc; ++k) {
         if (order == 1) {
             WL[k] = m1[k];
             WR[k] = p0[k];
@@ -402,7 +441,7 @@ static void reconstruct(int order, const double m2[4], const double m1[4], const
 
 static double P_between(const prim_field *pf, int ia, int ja, int ib, int jb)
 {
-    double A[4], B[4];
+    double A[ORC_MAXC], B[ORC_MAXC];
     get_prim(pf, ia, ja, A);
     get_prim(pf, ib, jb, B);
     return orc_detector_P(A[3], A[0], B[3], B[0]);
@@ -433,16 +472,16 @@ static double s1_yface(const orc_params *prm, const prim_field *pf, int i, int j
 
 static int load_prims(const orc_params *prm, const orc_grid *g, const double *q, prim_field *pf)
 {
-    const int nx = g->nx, ny = g->ny;
+    const int nx = g->nx, ny = g->ny, nc = pf->nc;
     const size_t plane = (size_t)nx * ny;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
-            double Q[4] = {q[c], q[plane + c], q[2 * plane + c], q[3 * plane + c]};
-            double W[4];
-            conserved_to_prim(prm->gamma, Q, W);
+            double Q[ORC_MAXC], W[ORC_MAXC];
+            for (int k = 0; k < nc; ++k) Q[k] = q[k * plane + c];
+            conserved_to_prim(prm->gamma, Q, W, nc);
             if (!physical(W)) bad = 1;
             set_prim(pf, i, j, W);
         }
@@ -459,6 +498,7 @@ static int check_args(const orc_params *prm, const orc_grid *g)
     if (prm->scheme == ORC_SCHEME_ROEAM && !(prm->mach_ref > 0.0)) return ORC_EINVAL;
     if (g->metric == 1 && (!g->xn || !g->yn)) return ORC_EINVAL;
     if (prm->order != 1 && prm->order != 2) return ORC_EINVAL;
+    if (g->nscalars < 0 || g->nscalars > ORC_MAX_SCALARS) return ORC_EINVAL;
     return 0;
 }
 
@@ -467,11 +507,11 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
 {
     int rc = check_args(prm, g);
     if (rc) return rc;
-    const int nx = g->nx, ny = g->ny;
-    prim_field pf = {nx, ny, nx + 4, ny + 4, NULL};
-    pf.W = (double *)malloc(sizeof(double) * 4 * (size_t)pf.NX * pf.NY);
-    double *Fx = (double *)malloc(sizeof(double) * 4 * (size_t)ny * (nx + 1));
-    double *Fy = (double *)malloc(sizeof(double) * 4 * (size_t)(ny + 1) * nx);
+    const int nx = g->nx, ny = g->ny, nc = 4 + g->nscalars;
+    prim_field pf = {nx, ny, nx + 4, ny + 4, nc, NULL};
+    pf.W = (double *)malloc(sizeof(double) * nc * (size_t)pf.NX * pf.NY);
+    double *Fx = (double *)malloc(sizeof(double) * nc * (size_t)ny * (nx + 1));
+    double *Fy = (double *)malloc(sizeof(double) * nc * (size_t)(ny + 1) * nx);
     if (!pf.W || !Fx || !Fy) { free(pf.W); free(Fx); free(Fy); return ORC_ENOMEM; }
     rc = load_prims(prm, g, q, &pf);
     if (rc) { free(pf.W); free(Fx); free(Fy); return rc; }
@@ -484,31 +524,37 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
 #pragma omp parallel for schedule(static) reduction(+ : negc)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i <= nx; ++i) {
-            double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4], S[2], n[2], len;
+            double m2[ORC_MAXC], m1[ORC_MAXC], p0[ORC_MAXC], p1[ORC_MAXC], WL[ORC_MAXC], WR[ORC_MAXC];
+            double F[ORC_MAXC], S[2], n[2], len;
             orc_face_diag d;
             get_prim(&pf, i - 2, j, m2); get_prim(&pf, i - 1, j, m1);
             get_prim(&pf, i, j, p0); get_prim(&pf, i + 1, j, p1);
-            reconstruct(prm->order, m2, m1, p0, p1, WL, WR);
+            reconstruct(prm->order, nc, m2, m1, p0, p1, WL, WR);
             xface_vector(g, i, j, S);
             unit_normal(g, S, n, &len);
-            orc_face_flux(prm, WL, WR, n[0], n[1], s1_xface(prm, &pf, i, j), F, &d);
+            double s1 = s1_xface(prm, &pf, i, j);
+            orc_face_flux(prm, WL, WR, n[0], n[1], s1, F, &d);
+            if (nc > 4) orc_face_flux_sc(prm, WL, WR, n[0], n[1], s1, nc - 4, F);
             if (d.absUp < 0.0) ++negc;
-            for (int k = 0; k < 4; ++k) Fx[((size_t)j * (nx + 1) + i) * 4 + k] = F[k] * len;
+            for (int k = 0; k < nc; ++k) Fx[((size_t)j * (nx + 1) + i) * nc + k] = F[k] * len;
         }
     /* j-faces: between (i, j-1) and (i, j), j = 0..ny */
 #pragma omp parallel for schedule(static) reduction(+ : negc)
     for (int j = 0; j <= ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4], F[4], S[2], n[2], len;
+            double m2[ORC_MAXC], m1[ORC_MAXC], p0[ORC_MAXC], p1[ORC_MAXC], WL[ORC_MAXC], WR[ORC_MAXC];
+            double F[ORC_MAXC], S[2], n[2], len;
             orc_face_diag d;
             get_prim(&pf, i, j - 2, m2); get_prim(&pf, i, j - 1, m1);
             get_prim(&pf, i, j, p0); get_prim(&pf, i, j + 1, p1);
-            reconstruct(prm->order, m2, m1, p0, p1, WL, WR);
+            reconstruct(prm->order, nc, m2, m1, p0, p1, WL, WR);
             yface_vector(g, i, j, S);
             unit_normal(g, S, n, &len);
-            orc_face_flux(prm, WL, WR, n[0], n[1], s1_yface(prm, &pf, i, j), F, &d);
+            double s1 = s1_yface(prm, &pf, i, j);
+            orc_face_flux(prm, WL, WR, n[0], n[1], s1, F, &d);
+            if (nc > 4) orc_face_flux_sc(prm, WL, WR, n[0], n[1], s1, nc - 4, F);
             if (d.absUp < 0.0) ++negc;
-            for (int k = 0; k < 4; ++k) Fy[((size_t)j * nx + i) * 4 + k] = F[k] * len;
+            for (int k = 0; k < nc; ++k) Fy[((size_t)j * nx + i) * nc + k] = F[k] * len;
         }
     if (neg_uprime) *neg_uprime += negc;
     /* Conservative sum: R = -(1/Omega) [(F_e - F_w) + (G_n - G_s)]. */
@@ -517,11 +563,11 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double omega = cell_area(g, i, j);
-            for (int k = 0; k < 4; ++k) {
-                double fw = Fx[((size_t)j * (nx + 1) + i) * 4 + k];
-                double fe = Fx[((size_t)j * (nx + 1) + i + 1) * 4 + k];
-                double gs = Fy[((size_t)j * nx + i) * 4 + k];
-                double gn = Fy[((size_t)(j + 1) * nx + i) * 4 + k];
+            for (int k = 0; k < nc; ++k) {
+                double fw = Fx[((size_t)j * (nx + 1) + i) * nc + k];
+                double fe = Fx[((size_t)j * (nx + 1) + i + 1) * nc + k];
+                double gs = Fy[((size_t)j * nx + i) * nc + k];
+                double gn = Fy[((size_t)(j + 1) * nx + i) * nc + k];
                 r[k * plane + (size_t)j * nx + i] = -((fe - fw) + (gn - gs)) / omega;
                 if (scale)
                     scale[k * plane + (size_t)j * nx + i] =
@@ -578,7 +624,7 @@ int orc_max_rate(const orc_params *prm, const orc_grid *g, const double *q, doub
             size_t c = (size_t)j * nx + i;
             double Q[4] = {q[c], q[plane + c], q[2 * plane + c], q[3 * plane + c]};
             double W[4];
-            conserved_to_prim(prm->gamma, Q, W);
+            conserved_to_prim(prm->gamma, Q, W, 4);
             if (!physical(W)) { bad = 1; continue; }
             mx = dmax(mx, cell_rate(prm, g, W, i, j));
         }
@@ -593,7 +639,7 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
     int rc = check_args(prm, g);
     if (rc) return rc;
     if (!(prm->cfl > 0.0) || prm->time_scheme < 0 || prm->time_scheme > 2) return ORC_EINVAL;
-    const size_t n = 4 * (size_t)g->nx * g->ny;
+    const size_t n = (4 + (size_t)g->nscalars) * g->nx * g->ny;
     double *r = (double *)malloc(sizeof(double) * n);
     double *q1 = (double *)malloc(sizeof(double) * n);
     double *q2 = (double *)malloc(sizeof(double) * n);

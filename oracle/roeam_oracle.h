@@ -8,8 +8,10 @@
  * constant with the HIP library.  Only tests/, the smoke check and the CPU
  * baseline leg of the benchmark may load it.
  *
- * Layout: conserved state q is [4][ny][nx] row-major FP64, rows (rho, rho*u,
- * rho*v, rho*E).  Node coordinates are [ny+1][nx+1].
+ * Layout: conserved state q is [4 + ns][ny][nx] row-major FP64, rows (rho,
+ * rho*u, rho*v, rho*E) followed by the ns transported scalars rho*k_m of
+ * Eq. (85) (ns = orc_grid.nscalars, 0 .. ORC_MAX_SCALARS).  Node coordinates
+ * are [ny+1][nx+1].
  *
  * Parity unpinned (documented readings, checked only oracle == GPU): the
  * modified-entropy-fix / rotated-Riemann term of Eq. (86) (readings D6-D8),
@@ -57,6 +59,9 @@ typedef struct {
     unsigned variant; /* ORC_V_* bits                                             */
 } orc_params;
 
+/* Transported scalars (the rho k rows of Eq. 85) a 2-D grid may carry. */
+#define ORC_MAX_SCALARS 2
+
 typedef struct {
     int nx, ny;
     int metric;            /* 0: uniform dx, dy; 1: node coordinates            */
@@ -64,6 +69,8 @@ typedef struct {
     const double *xn, *yn; /* metric 1: [ny+1][nx+1]                            */
     int bc[4];             /* west, east, south, north                          */
     double bc_state[4][4]; /* Dirichlet conserved state per side                */
+    int nscalars;          /* transported scalars, 0 .. ORC_MAX_SCALARS          */
+    double bc_scalar[4][ORC_MAX_SCALARS]; /* Dirichlet rho k_m per side          */
 } orc_grid;
 
 /* Every intermediate of one face evaluation, for property tests. */
@@ -91,10 +98,17 @@ double orc_detector_P(double pA, double rhoA, double pB, double rhoB);
  * Writes the numerical flux per unit face length; diag may be NULL. */
 void orc_face_flux(const orc_params *prm, const double WL[4], const double WR[4],
                    double nx, double ny, double s1, double F[4], orc_face_diag *diag);
+/* One face with ns transported scalars: W = (rho, u, v, p, k_1 .. k_ns) on
+ * each side, F = 4 + ns rows.  The scalar rows are those of Eq. (85): central
+ * U rho k, minus half of xi Delta(rho k) + dU_p rho^ k^ + dU_uR (rho k)_R +
+ * dU_uL (rho k)_L (classical Roe: xi Delta(rho k) + (dU_u + dU_p) rho^ k^),
+ * with k^ the sqrt(rho)-weighted Roe average. */
+void orc_face_flux_sc(const orc_params *prm, const double *WL, const double *WR, double nx, double ny,
+                      double s1, int ns, double *F);
 /* Physical face flux of Eq. (4) for one state. */
 void orc_physical_flux(double gamma, const double W[4], double nx, double ny, double F[4]);
 
-/* R = dQ/dt.  q, r: [4][ny][nx].  scale (nullable): per-cell sum over the
+/* R = dQ/dt.  q, r: [4 + nscalars][ny][nx].  scale (nullable): per-cell sum over the
  * four faces of |F_k| |S| / Omega, used by the cancellation-aware error norm.
  * Returns 0, or -4 if a cell has rho <= 0, p <= 0 or a non-finite value. */
 int orc_residual(const orc_params *prm, const orc_grid *g, const double *q, double *r, double *scale);

@@ -7,7 +7,8 @@ which otherwise share no code.
 
 A :class:`Case` describes one structured 2-D grid:
 
-* ``q0``: conserved state, float64 array [4, ny, nx] (rho, rho u, rho v, rho E);
+* ``q0``: conserved state, float64 array [4 + ns, ny, nx] (rho, rho u, rho v, rho E,
+  then ``ns`` transported scalars rho k_m, usually none);
 * geometry: uniform ``dx``, ``dy`` or node coordinates ``xn``, ``yn`` [ny+1, nx+1];
 * ``bc``: boundary kinds for (west, east, south, north);
 * ``bc_state``: conserved Dirichlet state per side [4, 4];
@@ -50,6 +51,11 @@ class Case:
     bc_state: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((4, 4)))
     nsteps: int = 1
     t_end: float = 0.0
+    bc_scalar: Optional[np.ndarray] = None  # [4 sides, nscalars] Dirichlet rho k_m
+
+    @property
+    def nscalars(self) -> int:
+        return self.q0.shape[0] - 4
 
     @property
     def ny(self) -> int:
@@ -514,6 +520,42 @@ def smooth_random_case(nx: int, ny: int, seed: int, bc=(PERIODIC,) * 4, mach: fl
         bc_state[s] = conserved(gamma, 1.0, mach, 0.0, 1.0 / gamma)
     return Case(name=f"smooth_{nx}x{ny}", q0=q0, params=prm, bc=tuple(bc), dx=dx, dy=dy,
                 xn=xn, yn=yn, bc_state=bc_state, nsteps=10, t_end=0.0)
+
+
+def add_scalars(case: "Case", ns: int, seed: int = 0, mode: str = "rough", value: float = 1.0,
+                k_bc: Optional[np.ndarray] = None) -> "Case":
+    """The case with ``ns`` transported scalars appended (rows rho k_m):
+    mode "rough": k_m ~ U(0.1, 2) cell by cell; "smooth": a seeded Fourier field in
+    (0.2, 1.8); "const": k_m = value everywhere (also on Dirichlet sides); "double":
+    two scalars with k_2 = 2 k_1, k_1 rough.  Dirichlet sides carry k_bc[side, m]
+    (default: value) times their density."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 600 + seed))
+    rho = case.q0[0]
+    ks = []
+    for m in range(ns):
+        if mode == "const":
+            k = np.full_like(rho, value)
+        elif mode == "smooth":
+            j, i = np.meshgrid(np.arange(case.ny), np.arange(case.nx), indexing="ij")
+            ph = rng.uniform(0, 2 * math.pi, 2)
+            k = 1.0 + 0.8 * np.sin(2 * math.pi * i / case.nx + ph[0]) * np.cos(2 * math.pi * j / case.ny + ph[1])
+        elif mode == "double":
+            k = rng.uniform(0.1, 2.0, rho.shape) if m == 0 else 2.0 * ks[0]
+        else:
+            k = rng.uniform(0.1, 2.0, rho.shape)
+        ks.append(k)
+    c = dataclasses.replace(case)
+    c.q0 = np.concatenate([case.q0, np.stack([rho * k for k in ks])]) if ns else case.q0.copy()
+    bcs = np.zeros((4, max(ns, 1)))
+    for sd in range(4):
+        for m in range(ns):
+            kb = value if k_bc is None else k_bc[sd][m]
+            if mode == "double" and m == 1 and k_bc is None:
+                kb = 2.0 * value
+            bcs[sd, m] = case.bc_state[sd][0] * kb
+    c.bc_scalar = bcs[:, :ns] if ns else None
+    c.name = f"{case.name}_sc{ns}{mode}"
+    return c
 
 
 # --------------------------------------------------------------------------
