@@ -13,7 +13,8 @@
  * Conventions
  *   - State arrays are device memory, FP64, structure of arrays:
  *     q[k][j][i] at q + k*ny*pitch + j*pitch + i, k = 0..3 (rho, rho u,
- *     rho v, rho E), j = 0..ny-1, i = 0..nx-1.  The row pitch (in elements)
+ *     rho v, rho E) and k = 4..3+ns for a grid carrying ns transported
+ *     scalars (rho k_m, see roeam_grid_set_scalars), j = 0..ny-1, i = 0..nx-1.  The row pitch (in elements)
  *     is chosen by the library and read back with roeam_grid_layout(); pad
  *     elements i >= nx are never read or written.
  *   - Every function returns a roeam_status; no C++ exception crosses the
@@ -175,6 +176,24 @@ roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *p
  * roeam_step and keeps the fastest per (order, precision).  Every shape
  * computes bitwise the same result.  EINVAL: shape outside -1..8. */
 roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
+/* Transported scalars (Eq. 85: the rows rho k, ... of turbulence or species
+ * variables, "other scalar equations" in Sec. 6.2).  A grid may carry up to
+ * ROEAM_MAX_SCALARS of them as state rows 4 .. 3 + nscalars (rho k_m).  Their
+ * flux is Eq. (85)'s: central U rho k, minus half of xi Delta(rho k)
+ * + dU_p rho^ k^ + dU_u,R (rho k)_R + dU_u,L (rho k)_L (classical Roe:
+ * xi Delta(rho k) + (dU_u + dU_p) rho^ k^), with k^ the sqrt(rho)-weighted Roe
+ * average and no pressure term; MUSCL reconstructs k = (rho k)/rho.  The flow
+ * rows do not depend on the scalars.  Boundary kinds act on k as on rho
+ * (periodic, copy, mirror); a Dirichlet side takes dirichlet_scalars, a HOST
+ * array [4 sides][nscalars] of rho k_m (NULL allowed when no side is
+ * Dirichlet).  Call before the grid's residual or step calls; a change drops
+ * the grid's stage buffers, captured graphs and tuned tile shapes (waiting for
+ * the context stream first).  Grids with scalars run through roeam_residual,
+ * roeam_step and roeam_profile_step; roeam_batch_submit rejects them (EINVAL).
+ * EINVAL: nscalars outside 0..ROEAM_MAX_SCALARS, missing or non-finite
+ * Dirichlet scalars; EDEVICE. */
+#define ROEAM_MAX_SCALARS 2
+roeam_status roeam_grid_set_scalars(roeam_grid *grid, int nscalars, const double *dirichlet_scalars);
 /* The shape in use for these parameters (-1 if not tuned yet). */
 roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *params, int *shape);
 

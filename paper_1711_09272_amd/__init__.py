@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libroeam.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+MAX_SCALARS = 2  # transported scalars (rho k rows) a 2-D grid may carry
 BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 # stage-kernel tile shapes: cells x cells / threads per workgroup
@@ -25,7 +26,7 @@ SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512"
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
     "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_grid_set_tile_shape",
-    "roeam_grid_tile_shape", "roeam_residual", "roeam_step",
+    "roeam_grid_tile_shape", "roeam_grid_set_scalars", "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
@@ -96,6 +97,7 @@ def lib():
         "roeam_grid_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]),
         "roeam_grid_set_tile_shape": (i, [vp, i]),
         "roeam_grid_tile_shape": (i, [vp, ctypes.POINTER(Params), ctypes.POINTER(i)]),
+        "roeam_grid_set_scalars": (i, [vp, i, vp]),
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
@@ -225,15 +227,35 @@ class Grid:
         a, b, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
         lib().roeam_grid_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(p))
         self.nx, self.ny, self.pitch = a.value, b.value, p.value
+        self.nsc = 0
 
     @classmethod
     def from_case(cls, ctx: Context, case) -> "Grid":
-        return cls(ctx, case.nx, case.ny, dx=case.dx, dy=case.dy, xn=case.xn, yn=case.yn, bc=case.bc,
-                   bc_state=case.bc_state)
+        g = cls(ctx, case.nx, case.ny, dx=case.dx, dy=case.dy, xn=case.xn, yn=case.yn, bc=case.bc,
+                bc_state=case.bc_state)
+        ns = case.q0.shape[0] - 4
+        if ns:
+            g.set_scalars(ns, getattr(case, "bc_scalar", None))
+        return g
+
+    def set_scalars(self, nscalars: int, bc_scalar: Optional[np.ndarray] = None):
+        """Carry nscalars transported scalars (state rows 4..); bc_scalar: [4 sides, nscalars]
+        Dirichlet rho k_m."""
+        arg = None
+        if bc_scalar is not None and nscalars:
+            sa = np.ascontiguousarray(np.asarray(bc_scalar, dtype=np.float64)[:, :nscalars]).reshape(-1)
+            self._keep.append(sa)
+            arg = ctypes.c_void_p(sa.ctypes.data)
+        self.ctx.check(lib().roeam_grid_set_scalars(self.h, int(nscalars), arg))
+        self.nsc = int(nscalars)
+
+    @property
+    def rows(self) -> int:
+        return 4 + self.nsc
 
     def empty_state(self):
         import torch
-        return torch.zeros((4, self.ny, self.pitch), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        return torch.zeros((self.rows, self.ny, self.pitch), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
 
     def to_device(self, q: np.ndarray):
         import torch
@@ -272,7 +294,7 @@ class Grid:
 def _dev_ptr(t, grid: Grid) -> ctypes.c_void_p:
     import torch
     assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
-    assert tuple(t.shape) == (4, grid.ny, grid.pitch), (tuple(t.shape), (4, grid.ny, grid.pitch))
+    assert tuple(t.shape) == (grid.rows, grid.ny, grid.pitch), (tuple(t.shape), (grid.rows, grid.ny, grid.pitch))
     return ctypes.c_void_p(t.data_ptr())
 
 

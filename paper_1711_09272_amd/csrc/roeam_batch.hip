@@ -476,6 +476,8 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
     for (int i = 0; i < n; ++i) {
         const roeam_solve_desc &d = descs[i];
         if (!d.grid || d.grid->ctx != ctx) return roeam_fail(ctx, ROEAM_EINVAL, "descriptor grid invalid");
+        if (d.grid->nsc != 0)
+            return roeam_fail(ctx, ROEAM_EINVAL, "grids with transported scalars run through roeam_step only");
         roeam_status st = roeam_check_params(ctx, &d.params, true);
         if (st) return st;
         if (!d.q0 || !d.q_out) return roeam_fail(ctx, ROEAM_EINVAL, "q0 and q_out are required");

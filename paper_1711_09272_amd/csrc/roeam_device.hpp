@@ -17,6 +17,8 @@ enum : unsigned {
     V_XI_ROE = 16u, V_DUP_ROE = 32u, V_XI_EQ46 = 64u, V_DUP_ZERO = 128u
 };
 enum { SCHEME_ROEAM = 0, SCHEME_ROE = 1, SCHEME_ROE_HARTEN = 2 };
+// Transported scalars (the rho k rows of Eq. 85) a 2-D solve may carry.
+constexpr int kMaxScalars = 2;
 
 // Per-solve time-integration state, resident in device memory.  The step
 // state is double-buffered by step parity p: the first stage kernel of a step
@@ -58,6 +60,8 @@ struct DevSolve {
     const double *xn, *yn;      // nodes [(ny+1)][(nx+1)]
     int bc[4];
     double bcw[4][4];           // Dirichlet states, primitive (rho, u, v, p)
+    int nsc;                    // transported scalars: rows 4 .. 3 + nsc of the state (rho k_m)
+    double bck[4][kMaxScalars]; // Dirichlet scalars, primitive k_m
     // scheme
     double gamma, gm1, g_gm1, igm1, mr2, u_ref, dv_min2, eps1, eps2, eps_lambda, cfl, inv_area;
     int s1_mode, order, precision, scheme;
@@ -178,10 +182,15 @@ __device__ __forceinline__ double to_prim(double gm1, double q0, double q1, doub
     return ir;
 }
 
-__device__ __forceinline__ void load_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
+// Primitives of cell (i, j): (rho, u, v, p) and, for NSC transported
+// scalars, k_m = (rho k_m) / rho.
+template <int NSC = 0>
+__device__ __forceinline__ void load_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
 {
     long long idx = (long long)j * S.pitch + i;
-    to_prim(S.gm1, q[idx], q[S.plane + idx], q[2 * S.plane + idx], q[3 * S.plane + idx], W);
+    const double ir = to_prim(S.gm1, q[idx], q[S.plane + idx], q[2 * S.plane + idx], q[3 * S.plane + idx], W);
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) W[4 + m] = q[(4 + m) * S.plane + idx] * ir;
 }
 
 template <int METRIC>
@@ -243,23 +252,25 @@ __device__ __forceinline__ void reflect(double W[4], double nx, double ny)
 
 // Primitive state of cell (i, j) where j is inside the grid and i may lie in
 // the two ghost columns on either side.
-template <int METRIC>
-__device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
+template <int METRIC, int NSC = 0>
+__device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
 {
-    if (i >= 0 && i < S.nx) { load_prim(S, q, i, j, W); return; }
+    if (i >= 0 && i < S.nx) { load_prim<NSC>(S, q, i, j, W); return; }
     // constant-index selects keep the by-value kernel argument out of scratch
     const bool west = i < 0;
     const int kind = west ? S.bc[SIDE_W] : S.bc[SIDE_E];
     if (kind == BC_DIRICHLET) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) W[k] = west ? S.bcw[SIDE_W][k] : S.bcw[SIDE_E][k];
+#pragma unroll
+        for (int m = 0; m < NSC; ++m) W[4 + m] = west ? S.bck[SIDE_W][m] : S.bck[SIDE_E][m];
         return;
     }
     int is;
     if (kind == BC_PERIODIC) is = i < 0 ? i + S.nx : i - S.nx;
     else if (kind == BC_TRANSMISSIVE) is = i < 0 ? 0 : S.nx - 1;
     else is = i < 0 ? -i - 1 : 2 * S.nx - 1 - i;
-    load_prim(S, q, is, j, W);
+    load_prim<NSC>(S, q, is, j, W);
     if (kind == BC_SLIPWALL) {
         double sx, sy, nx, ny, len;
         xface_vec<METRIC>(S, i < 0 ? 0 : S.nx, j, sx, sy);
@@ -270,22 +281,24 @@ __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__
 
 // Primitive state of any cell within two layers of the grid: the x rule, then
 // the y rule (which also defines the corners).
-template <int METRIC>
-__device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double W[4])
+template <int METRIC, int NSC = 0>
+__device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
 {
-    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC>(S, q, i, j, W); return; }
+    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC, NSC>(S, q, i, j, W); return; }
     const bool south = j < 0;
     const int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
     if (kind == BC_DIRICHLET) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) W[k] = south ? S.bcw[SIDE_S][k] : S.bcw[SIDE_N][k];
+#pragma unroll
+        for (int m = 0; m < NSC; ++m) W[4 + m] = south ? S.bck[SIDE_S][m] : S.bck[SIDE_N][m];
         return;
     }
     int js;
     if (kind == BC_PERIODIC) js = j < 0 ? j + S.ny : j - S.ny;
     else if (kind == BC_TRANSMISSIVE) js = j < 0 ? 0 : S.ny - 1;
     else js = j < 0 ? -j - 1 : 2 * S.ny - 1 - j;
-    fetch_prim_x<METRIC>(S, q, i, js, W);
+    fetch_prim_x<METRIC, NSC>(S, q, i, js, W);
     if (kind == BC_SLIPWALL) {
         int ic = i < 0 ? 0 : (i > S.nx - 1 ? S.nx - 1 : i);
         double sx, sy, nx, ny, len;
@@ -303,9 +316,9 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
 // multiplied by xi is the conserved one (energy row rho E) and the pressure
 // vector is (0, n, U), as Eq. (7) has them.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void roe_classic(const DevSolve &S, const double WL[4], const double WR[4], double nx,
-                                            double ny, double F[4])
+template <typename R, int NSC = 0>
+__device__ __forceinline__ void roe_classic(const DevSolve &S, const double *WL, const double *WR, double nx,
+                                            double ny, double *F)
 {
     const double rL = WL[0], uL = WL[1], vL = WL[2], pL = WL[3];
     const double rR = WR[0], uR = WR[1], vR = WR[2], pR = WR[3];
@@ -353,6 +366,14 @@ __device__ __forceinline__ void roe_classic(const DevSolve &S, const double WL[4
     F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
          - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + Ud * (rhod * (double)v));
     F[3] = 0.5 * (UL * (rL * HL) + UR * (rR * HR)) - 0.5 * (xid * (rER - rEL) + pd * (double)U + Ud * (rhod * (double)H));
+    // transported scalars: xi Delta(rho k) + (dU_u + dU_p) rho^ k^, no pressure term
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) {
+        const double kL = WL[4 + m], kR = WR[4 + m];
+        const double PL = rL * kL, PR = rR * kR;
+        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
+        F[4 + m] = 0.5 * (UL * PL + UR * PR) - 0.5 * (xid * (PR - PL) + Ud * (rhod * khat));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,12 +381,12 @@ __device__ __forceinline__ void roe_classic(const DevSolve &S, const double WL[4
 // R is the precision of the dissipation coefficients; the side quantities,
 // the central term, the jumps of Eq. (85) and the final assembly stay FP64.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4], const double WR[4], double nx,
-                                           double ny, double s1d, double F[4])
+template <typename R, int NSC = 0>
+__device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, const double *WR, double nx,
+                                           double ny, double s1d, double *F)
 {
     if (__builtin_expect(S.scheme != SCHEME_ROEAM, 0)) {
-        roe_classic<R>(S, WL, WR, nx, ny, F);
+        roe_classic<R, NSC>(S, WL, WR, nx, ny, F);
         return;
     }
     const double rL = WL[0], uL = WL[1], vL = WL[2], pL = WL[3];
@@ -476,6 +497,15 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double WL[4]
          - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
     F[3] = 0.5 * (UL * PsiL3 + UR * PsiR3)
          - 0.5 * (xid * (PsiR3 - PsiL3) + dUpd * (rhod * (double)H) + dUud * (PsiR3 + PsiL3));
+    // transported scalars (rho k rows of Eq. 85): Psi = rho k, Psi^ = rho^ k^
+    // with the Roe average of k, no pressure term
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) {
+        const double kL = WL[4 + m], kR = WR[4 + m];
+        const double PL = rL * kL, PR = rR * kR;
+        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
+        F[4 + m] = 0.5 * (UL * PL + UR * PR) - 0.5 * (xid * (PR - PL) + dUpd * (rhod * khat) + dUud * (PR + PL));
+    }
 }
 
 // Explicit rate of one cell for the time-step rule:

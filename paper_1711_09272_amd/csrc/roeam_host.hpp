@@ -51,6 +51,8 @@ struct roeam_grid {
     double *d_xn = nullptr, *d_yn = nullptr;
     int bc[4] = {0, 0, 0, 0};
     double bcq[4][4] = {};
+    int nsc = 0;                                 // transported scalars (rows 4 .. 3 + nsc)
+    double bcs[4][roeam::kMaxScalars] = {};      // Dirichlet rho k_m per side
     double *d_qa = nullptr, *d_qb = nullptr;
     Slot *d_slot = nullptr;
     Slot *h_slot = nullptr;  // pinned readback

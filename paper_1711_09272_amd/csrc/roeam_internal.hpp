@@ -28,6 +28,9 @@ int tile_shape_count();
 // dS: the descriptor in device memory (read by the kernel); S: its host copy.
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                double *r_out, hipStream_t st);
+// The same with one or two transported scalars (S.nsc), roeam_kernels_sc.hip.
+hipError_t launch_stage_single_sc(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                                  double *r_out, hipStream_t st);
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
                               int metric, int shape, int stage, int p, int last, hipStream_t st);
 hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st);

@@ -1,4 +1,6 @@
-// roeam_kernels.hip -- gfx950 kernels of the Roe-AM finite-volume step.
+// roeam_kernels.hip -- gfx950 kernels of the Roe-AM finite-volume step: the
+// stage kernel (templates in roeam_stage2d.hpp) without transported scalars,
+// for single grids and batches, and the small kernels around it.
 //
 // One fused stage kernel per Runge-Kutta stage.  A workgroup owns a tile of
 // TX x TY cells: it stages the tile plus its halo as primitives in LDS, builds
@@ -14,330 +16,9 @@
 #include "roeam_device.hpp"
 #include "roeam_internal.hpp"
 #include "roeam_stage.hpp"
+#include "roeam_stage2d.hpp"
 
 namespace roeam {
-
-template <int ORDER>
-__device__ __forceinline__ void reconstruct(const double m2[4], const double m1[4], const double p0[4],
-                                            const double p1[4], double WL[4], double WR[4])
-{
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (ORDER == 1) {
-            WL[k] = m1[k];
-            WR[k] = p0[k];
-        } else {
-            const double d1 = p0[k] - m1[k];
-            WL[k] = m1[k] + 0.5 * minmod(m1[k] - m2[k], d1);
-            WR[k] = p0[k] - 0.5 * minmod(d1, p1[k] - p0[k]);
-        }
-    }
-}
-
-// One i-face (between local cells (fi-1, fj) and (fi, fj)) or j-face (between
-// (fi, fr-1) and (fi, fr)) of a tile: stencil from the LDS primitives, the
-// detector minimum over the face and its four transverse neighbours, and the
-// flux times the face length.
-template <int ORDER, int PREC, int METRIC, int TX, int TY, bool XDIR>
-__device__ __forceinline__ void tile_face(const DevSolve &S, const double (&sW)[4][TY + 2 * ORDER][TX + 2 * ORDER],
-                                          const double (&sPx)[TY + 2][TX + 1], const double (&sPy)[TY + 1][TX + 2],
-                                          int fi, int fj, int gi, int gj, double F[4])
-{
-    using R = typename std::conditional<PREC == 0, double, float>::type;
-    constexpr int HL = ORDER;
-    double m2[4], m1[4], p0[4], p1[4], WL[4], WR[4];
-    const int ly = fj + HL, lx = fi + HL;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (XDIR) {
-            m1[k] = sW[k][ly][lx - 1];
-            p0[k] = sW[k][ly][lx];
-            if (ORDER == 2) {
-                m2[k] = sW[k][ly][lx - 2];
-                p1[k] = sW[k][ly][lx + 1];
-            }
-        } else {
-            m1[k] = sW[k][ly - 1][lx];
-            p0[k] = sW[k][ly][lx];
-            if (ORDER == 2) {
-                m2[k] = sW[k][ly - 2][lx];
-                p1[k] = sW[k][ly + 1][lx];
-            }
-        }
-    }
-    double s1 = 1.0;
-    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
-        double a;
-        if (XDIR) {
-            a = rmin(rmin(sPx[fj + 1][fi], sPy[fj][fi]), rmin(sPy[fj + 1][fi], rmin(sPy[fj][fi + 1], sPy[fj + 1][fi + 1])));
-        } else {
-            a = rmin(rmin(sPy[fj][fi + 1], sPx[fj][fi]), rmin(sPx[fj][fi + 1], rmin(sPx[fj + 1][fi], sPx[fj + 1][fi + 1])));
-        }
-        s1 = pow8(fswitch(a));
-    }
-    reconstruct<ORDER>(m2, m1, p0, p1, WL, WR);
-    double sx, sy, nxv, nyv, len;
-    if (XDIR) xface_vec<METRIC>(S, gi, gj, sx, sy);
-    else yface_vec<METRIC>(S, gi, gj, sx, sy);
-    unit_normal<METRIC>(S, sx, sy, nxv, nyv, len);
-    roeam_flux<R>(S, WL, WR, nxv, nyv, s1, F);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) F[k] *= len;
-}
-
-// The tile body.  stage: a stage code (above; 0 writes the residual to r_out).
-// p: step parity.  last: this stage ends the step (reduce the rate of the new
-// state into parity p^1); for stage 0 the rate of the input is reduced into
-// parity 0.
-// SPLIT = false: NT threads sweep the i-faces, then the j-faces through one
-// LDS buffer (about two faces per thread).  SPLIT = true: one face per thread,
-// i-faces on the first ceil(NFX/64) waves and j-faces on the rest, in one pass.
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
-__device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, int stage, int p, int last,
-                                           int first_block, double *__restrict__ r_out)
-{
-    constexpr int HL = ORDER;
-    constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL;
-    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
-    constexpr int NFXR = (NFX + 63) / 64 * 64;  // i-face threads in SPLIT mode
-    static_assert(!SPLIT || NFXR + NFY <= NT, "split shape must give every face a thread");
-    constexpr int NFB = SPLIT ? NFX : (NFX > NFY ? NFX : NFY);
-    constexpr int CPT = (TX * TY + NT - 1) / NT;  // cells per thread
-    __shared__ double sW[4][LY][LX];
-    __shared__ double sPx[TY + 2][TX + 1];
-    __shared__ double sPy[TY + 1][TX + 2];
-    __shared__ double sF[4][NFB];
-    __shared__ double sG[4][SPLIT ? NFY : 1];
-
-    const int tid = threadIdx.x;
-    const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
-    const bool reads_qn = stage >= 2 && stage != 4;  // Q^n at the own cells, besides the stencil input
-    const int i0 = tx * TX, j0 = ty * TY;
-    const int nx = S.nx, ny = S.ny;
-
-    // Own cells' stage input (and Q^n for stages 2-3) are loaded first so their
-    // latency is hidden behind the face work; cells outside the grid load cell
-    // (0, 0) and are never stored.
-    double Qs[CPT][4], Q0[CPT][4];
-    long long cidx[CPT];
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-        const int c = tid + m * NT;
-        const int cj = c / TX, ci = c - cj * TX;
-        const bool ok = c < TX * TY && i0 + ci < nx && j0 + cj < ny;
-        cidx[m] = ok ? (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
-        if (stage > 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
-        }
-        if (reads_qn) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
-        }
-    }
-
-    Slot &z = *S.slot;
-    double dt = 0.0;
-    if (stage > 0 && !begin_stage(z, p, stage, last, first_block, dt)) return;
-
-    // 1. tile + halo -> primitives in LDS (fully unrolled: all loads in flight)
-    const bool interior = (i0 - HL >= 0) && (i0 + TX + HL <= nx) && (j0 - HL >= 0) && (j0 + TY + HL <= ny);
-    constexpr int NLOAD = (LX * LY + NT - 1) / NT;
-#pragma unroll
-    for (int it = 0; it < NLOAD; ++it) {
-        const int e = tid + it * NT;
-        if (e >= LX * LY) break;
-        const int ly = e / LX, lx = e - ly * LX;
-        int gi = i0 - HL + lx, gj = j0 - HL + ly;
-        double W[4];
-        if (interior) {
-            load_prim(S, qin, gi, gj, W);
-        } else {
-            // cells past the ghost layers of a ragged tile feed no valid face
-            gi = gi > nx + 1 ? nx + 1 : gi;
-            gj = gj > ny + 1 ? ny + 1 : gj;
-            fetch_prim<METRIC>(S, qin, gi, gj, W);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sW[k][ly][lx] = W[k];
-    }
-    __syncthreads();
-
-    // 2. detector ratios, Eq. (97), from cell-centre values
-    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
-        // one sweep over the i-face ratios then the j-face ratios, so that
-        // the threads stay busy across the two arrays
-        constexpr int NPX = (TY + 2) * (TX + 1), NPY = (TY + 1) * (TX + 2);
-        for (int e = tid; e < NPX + NPY; e += NT) {
-            int a, b;  // LDS cell offsets (within one plane of sW) of the two cells
-            double *dst;
-            if (e < NPX) {
-                const int r = e / (TX + 1), fi = e - r * (TX + 1);
-                a = (r - 1 + HL) * LX + fi - 1 + HL;
-                b = a + 1;
-                dst = &sPx[r][fi];
-            } else {
-                const int f = e - NPX;
-                const int fr = f / (TX + 2), cc = f - fr * (TX + 2);
-                a = (fr - 1 + HL) * LX + cc - 1 + HL;
-                b = a + LX;
-                dst = &sPy[fr][cc];
-            }
-            const double *p3 = &sW[3][0][0], *p0 = &sW[0][0][0];
-            *dst = detector_P(p3[a], p0[a], p3[b], p0[b]);
-        }
-        __syncthreads();
-    }
-
-    // 3. every face of the tile exactly once
-    double dfx[CPT][4];
-    if (SPLIT) {
-        if (tid < NFXR) {
-            const int f = tid;
-            const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
-            if (f < NFX && i0 + fi <= nx && j0 + fj < ny) {
-                double F[4];
-                tile_face<ORDER, PREC, METRIC, TX, TY, true>(S, sW, sPx, sPy, fi, fj, i0 + fi, j0 + fj, F);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
-            }
-        } else {
-            const int f = tid - NFXR;
-            const int fr = f / TX, fi = f - fr * TX;
-            if (f < NFY && i0 + fi < nx && j0 + fr <= ny) {
-                double F[4];
-                tile_face<ORDER, PREC, METRIC, TX, TY, false>(S, sW, sPx, sPy, fi, fr, i0 + fi, j0 + fr, F);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) sG[k][f] = F[k];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const int c = tid + m * NT;
-            const int cj = c / TX, ci = c - cj * TX;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
-        }
-    } else {
-        for (int f = tid; f < NFX; f += NT) {
-            const int fj = f / (TX + 1), fi = f - fj * (TX + 1);
-            if (i0 + fi > nx || j0 + fj >= ny) continue;
-            double F[4];
-            tile_face<ORDER, PREC, METRIC, TX, TY, true>(S, sW, sPx, sPy, fi, fj, i0 + fi, j0 + fj, F);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
-        }
-        __syncthreads();
-        // i-direction part of the residual, kept in registers
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const int c = tid + m * NT;
-            const int cj = c / TX, ci = c - cj * TX;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                dfx[m][k] = (c < TX * TY) ? sF[k][cj * (TX + 1) + ci + 1] - sF[k][cj * (TX + 1) + ci] : 0.0;
-        }
-        __syncthreads();
-        // j-faces through the same LDS buffer
-        for (int f = tid; f < NFY; f += NT) {
-            const int fr = f / TX, fi = f - fr * TX;
-            if (i0 + fi >= nx || j0 + fr > ny) continue;
-            double F[4];
-            tile_face<ORDER, PREC, METRIC, TX, TY, false>(S, sW, sPx, sPy, fi, fr, i0 + fi, j0 + fr, F);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) sF[k][f] = F[k];
-        }
-        __syncthreads();
-    }
-    const double(&sJ)[4][SPLIT ? NFY : NFB] = *reinterpret_cast<const double(*)[4][SPLIT ? NFY : NFB]>(SPLIT ? &sG[0][0] : &sF[0][0]);
-
-    // 4. conservative residual R = -((F_e - F_w) + (G_n - G_s)) / Omega and the stage update
-    double lmax = 0.0;
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-        const int c = tid + m * NT;
-        const int cj = c / TX, ci = c - cj * TX;
-        const int gi = i0 + ci, gj = j0 + cj;
-        if (c >= TX * TY || gi >= nx || gj >= ny) continue;
-        const double iom = METRIC == 0 ? S.inv_area : rcp_nr(cell_area<METRIC>(S, gi, gj));
-        double Rv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Rv[k] = -(dfx[m][k] + (sJ[k][(cj + 1) * TX + ci] - sJ[k][cj * TX + ci])) * iom;
-        const long long idx = cidx[m];
-        if (stage == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) r_out[k * S.plane + idx] = Rv[k];
-            if (last) {
-                double W[4] = {sW[0][cj + HL][ci + HL], sW[1][cj + HL][ci + HL], sW[2][cj + HL][ci + HL],
-                               sW[3][cj + HL][ci + HL]};
-                lmax = rmax(lmax, cell_rate<METRIC>(S, W, rcp_nr(W[0]), gi, gj));
-            }
-            continue;
-        }
-        double Qn[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            switch (stage) {
-            case 1: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
-            case 2: Qn[k] = 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k]); break;
-            case 3: Qn[k] = (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]); break;
-            // four-stage scheme: Q^(k) = Q^n + alpha_k dt R(Q^(k-1)), alpha = 1/4, 1/3, 1/2, 1
-            case 4: Qn[k] = Qs[m][k] + (0.25 * dt) * Rv[k]; break;
-            case 5: Qn[k] = Q0[m][k] + ((1.0 / 3.0) * dt) * Rv[k]; break;
-            case 6: Qn[k] = Q0[m][k] + (0.5 * dt) * Rv[k]; break;
-            default: Qn[k] = Q0[m][k] + dt * Rv[k]; break;
-            }
-        }
-        double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) qo[k * S.plane + idx] = Qn[k];
-        double W[4];
-        const double ir = to_prim(S.gm1, Qn[0], Qn[1], Qn[2], Qn[3], W);
-        if (!physical(W)) {
-            atomicOr(&z.nonphys, 1);
-        } else if (last) {
-            lmax = rmax(lmax, cell_rate<METRIC>(S, W, ir, gi, gj));
-        }
-    }
-    if (last) {
-        reduce_rate_waves<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax);
-    }
-}
-
-// Minimum waves per SIMD asked of the register allocator: the uniform-grid
-// FP32-coefficient kernels of the one-pass 256-thread shapes fit five waves
-// without spills (measured 4% faster at 2048^2); the FP64 and node-grid ones
-// would spill, so they keep the default.
-constexpr int stage_min_waves(int prec, int metric, int nt, bool split)
-{
-    return (prec == 1 && metric == 0 && nt == 256 && !split) ? 5 : 1;
-}
-
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT)) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
-                                                     double *r_out)
-{
-    const DevSolve &S = *Sp;
-    const int txs = (S.nx + TX - 1) / TX, tys = (S.ny + TY - 1) / TY;
-    const int nt = txs * tys;
-    const int t = xcd_tile(blockIdx.x, nt);
-    if (t >= nt) return;
-    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
-}
-
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT)) void k_stage_batch(const DevSolve *__restrict__ solves,
-                                                    const TileEntry *__restrict__ tiles, int ntiles, int stage,
-                                                    int p, int last)
-{
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    if (t >= ntiles) return;
-    const TileEntry te = tiles[t];
-    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
-                                        nullptr);
-}
 
 // Explicit rate of a state (sets dt of the first step of a run) into the
 // rate words of parity p.
@@ -392,8 +73,7 @@ __global__ void k_copy_back(DevSolve S, int p)
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(c / S.nx), i = (int)(c - (long long)j * S.nx);
         const long long idx = (long long)j * S.pitch + i;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
+        for (int k = 0; k < 4 + S.nsc; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
     }
 }
 
@@ -409,22 +89,6 @@ __global__ void k_rate_out(const Slot *s, double *out)
 struct TileShape {
     int tx, ty, nt;
 };
-// Tile shapes: id, TX, TY, threads, split.  Non-split shapes sweep the faces
-// in one or two passes per direction; split shapes give every face a thread.
-// 6 and 7 cover each face direction in one pass of 256 threads; 8 gives every
-// face of a 16x7 tile a thread (fewer halo cells per tile cell than 8x7 at the
-// same one-face-per-thread latency).
-#define ROEAM_SHAPES(X)               \
-    X(0, 32, 15, 256, false)          \
-    X(1, 16, 15, 128, false)          \
-    X(2, 8, 7, 64, false)             \
-    X(3, 8, 7, 128, true)             \
-    X(4, 16, 15, 512, true)           \
-    X(5, 32, 7, 512, true)            \
-    X(6, 16, 15, 256, false)          \
-    X(7, 32, 7, 256, false)           \
-    X(8, 16, 7, 256, true)
-
 #define ROEAM_SHAPE_ENTRY(ID, TX, TY, NT, SPLIT) {TX, TY, NT},
 static const TileShape kShapes[] = {ROEAM_SHAPES(ROEAM_SHAPE_ENTRY)};
 #undef ROEAM_SHAPE_ENTRY
@@ -443,39 +107,12 @@ int tile_shape_count() { return kNumShapes; }
     case ID: hipLaunchKernelGGL((ROEAM_KERNEL<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>), dim3(blocks), dim3(NT), 0, st, \
                                 ROEAM_ARGS); break;
 
-template <int ORDER, int PREC, int METRIC>
-static void launch_single_shape(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
-                                double *r_out, hipStream_t st)
-{
-    const TileShape &sh = kShapes[shape];
-    const int nt = ((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty);
-    const int blocks = ((nt + 7) >> 3) << 3;
-#define ROEAM_KERNEL k_stage_single
-#define ROEAM_ARGS dS, stage, p, last, r_out
-    switch (shape) { ROEAM_SHAPES(ROEAM_SHAPE_CASE) }
-#undef ROEAM_KERNEL
-#undef ROEAM_ARGS
-}
-
-template <int ORDER, int PREC>
-static void launch_single_metric(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
-                                 double *r_out, hipStream_t st)
-{
-    if (S.metric == 0) launch_single_shape<ORDER, PREC, 0>(dS, S, shape, stage, p, last, r_out, st);
-    else launch_single_shape<ORDER, PREC, 1>(dS, S, shape, stage, p, last, r_out, st);
-}
-
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                double *r_out, hipStream_t st)
 {
     if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
-    if (S.order == 1) {
-        if (S.precision == 0) launch_single_metric<1, 0>(dS, S, shape, stage, p, last, r_out, st);
-        else launch_single_metric<1, 1>(dS, S, shape, stage, p, last, r_out, st);
-    } else {
-        if (S.precision == 0) launch_single_metric<2, 0>(dS, S, shape, stage, p, last, r_out, st);
-        else launch_single_metric<2, 1>(dS, S, shape, stage, p, last, r_out, st);
-    }
+    if (S.nsc != 0) return launch_stage_single_sc(dS, S, shape, stage, p, last, r_out, st);
+    launch_single_nsc<0>(dS, S, shape, stage, p, last, r_out, st);
     return hipGetLastError();
 }
 

@@ -1,0 +1,18 @@
+// roeam_kernels_sc.hip -- the 2-D stage kernel with one or two transported
+// scalars (the rho k rows of Eq. 85), single-grid launches.  A translation unit
+// of its own so that these instantiations compile beside the scalar-free ones.
+#include "roeam_stage2d.hpp"
+
+namespace roeam {
+
+hipError_t launch_stage_single_sc(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
+                                  double *r_out, hipStream_t st)
+{
+    if (shape < 0 || shape >= tile_shape_count()) return hipErrorInvalidValue;
+    if (S.nsc == 1) launch_single_nsc<1>(dS, S, shape, stage, p, last, r_out, st);
+    else if (S.nsc == 2) launch_single_nsc<2>(dS, S, shape, stage, p, last, r_out, st);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+} // namespace roeam

@@ -81,6 +81,10 @@ DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q,
         S.bc[s] = g->bc[s];
         prim_of(p->gamma, g->bcq[s], S.bcw[s]);
     }
+    S.nsc = g->nsc;
+    for (int s = 0; s < 4; ++s)
+        for (int m = 0; m < g->nsc; ++m)
+            S.bck[s][m] = g->bc[s] == ROEAM_BC_DIRICHLET ? g->bcs[s][m] / g->bcq[s][0] : 0.0;
     S.gamma = p->gamma;
     S.gm1 = p->gamma - 1.0;
     S.g_gm1 = p->gamma / (p->gamma - 1.0);
@@ -120,7 +124,7 @@ static DevSolve make_solve(const roeam_grid *g, const roeam_params *p, double *q
 static roeam_status ensure_stage_buffers(roeam_ctx *ctx, roeam_grid *g)
 {
     if (g->d_qa && g->d_qb) return ROEAM_OK;
-    const size_t bytes = sizeof(double) * 4 * (size_t)g->ny * (size_t)g->pitch;
+    const size_t bytes = sizeof(double) * (4 + (size_t)g->nsc) * (size_t)g->ny * (size_t)g->pitch;
     hipError_t e = g->d_qa ? hipSuccess : hipMalloc(&g->d_qa, bytes);
     if (e == hipSuccess && !g->d_qb) e = hipMalloc(&g->d_qb, bytes);
     if (e != hipSuccess)
@@ -287,18 +291,18 @@ roeam_status roeam_grid_layout(const roeam_grid *g, int *nx, int *ny, long *pitc
 // a process-wide table keyed by device and grid size (guarded by a mutex:
 // contexts on different host threads may tune at the same time).
 struct TuneKey {
-    int device, nx, ny, order, precision, metric;
+    int device, nx, ny, order, precision, metric, nsc;
     bool operator==(const TuneKey &o) const
     {
         return device == o.device && nx == o.nx && ny == o.ny && order == o.order && precision == o.precision &&
-               metric == o.metric;
+               metric == o.metric && nsc == o.nsc;
     }
 };
 struct TuneKeyHash {
     size_t operator()(const TuneKey &k) const
     {
         return ((size_t)k.nx * 1000003u) ^ ((size_t)k.ny * 7919u) ^
-               (size_t)(k.device * 131 + k.order * 31 + k.precision * 7 + k.metric);
+               (size_t)(k.device * 131 + k.order * 31 + k.precision * 7 + k.metric + k.nsc * 1009);
     }
 };
 static std::unordered_map<TuneKey, int, TuneKeyHash> g_tuned;
@@ -325,7 +329,7 @@ static roeam_status choose_shape(roeam_ctx *ctx, roeam_grid *g, const roeam_para
         *shape = cached;
         return ROEAM_OK;
     }
-    const TuneKey key{ctx->device, g->nx, g->ny, p->order, p->precision, g->metric};
+    const TuneKey key{ctx->device, g->nx, g->ny, p->order, p->precision, g->metric, g->nsc};
     {
         std::lock_guard<std::mutex> lk(g_tuned_mu);
         auto it = g_tuned.find(key);
@@ -546,6 +550,37 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
     for (int stg = 0; stg < 4; ++stg) stage_ms[stg] = stg < nst ? sum[stg] / (double)nsteps : 0.0;
     if (launches) *launches = nsteps * nst;
     return rc;
+}
+
+roeam_status roeam_grid_set_scalars(roeam_grid *g, int nscalars, const double *dirichlet_scalars)
+{
+    if (!g) return ROEAM_EINVAL;
+    roeam_ctx *ctx = g->ctx;
+    if (nscalars < 0 || nscalars > ROEAM_MAX_SCALARS)
+        return fail(ctx, ROEAM_EINVAL, "nscalars must be 0 .. ROEAM_MAX_SCALARS");
+    bool need = false;
+    for (int s = 0; s < 4; ++s) need |= g->bc[s] == ROEAM_BC_DIRICHLET;
+    if (need && nscalars > 0 && !dirichlet_scalars) return fail(ctx, ROEAM_EINVAL, "Dirichlet side without scalars");
+    for (int s = 0; s < 4 && need; ++s)
+        for (int m = 0; m < nscalars; ++m)
+            if (g->bc[s] == ROEAM_BC_DIRICHLET && !std::isfinite(dirichlet_scalars[s * nscalars + m]))
+                return fail(ctx, ROEAM_EINVAL, "non-finite Dirichlet scalar");
+    // work queued on the stage buffers may still run: wait before replacing them
+    if (g->nsc != nscalars && (g->d_qa || g->d_qb)) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+        if (g->d_qa) (void)hipFree(g->d_qa);
+        if (g->d_qb) (void)hipFree(g->d_qb);
+        g->d_qa = g->d_qb = nullptr;
+    }
+    g->nsc = nscalars;
+    for (int s = 0; s < 4; ++s)
+        for (int m = 0; m < roeam::kMaxScalars; ++m)
+            g->bcs[s][m] = (m < nscalars && g->bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_scalars[s * nscalars + m] : 0.0;
+    g->gc.release();
+    g->solve_valid = false;
+    for (auto &row : g->shape_tuned) row[0] = row[1] = -1;
+    return ROEAM_OK;
 }
 
 roeam_status roeam_grid_set_tile_shape(roeam_grid *g, int shape)
