@@ -349,13 +349,34 @@ static void set_prim(prim_field *pf, int i, int j, const double *W)
     for (int k = 0; k < pf->nc; ++k) pf->W[PIDX(pf, k, i, j)] = W[k];
 }
 
-/* Dirichlet state of a side, primitive, scalars included. */
-static void dirichlet_prim(const orc_params *prm, const orc_grid *g, int side, int nc, double *W)
+/* Dirichlet state of a side (or, hi != 0, its state above a moving split),
+ * primitive, scalars included. */
+static void dirichlet_prim_of(const orc_params *prm, const orc_grid *g, int side, int hi, int nc, double *W)
 {
     double Q[ORC_MAXC];
-    for (int k = 0; k < 4; ++k) Q[k] = g->bc_state[side][k];
+    for (int k = 0; k < 4; ++k) Q[k] = hi ? g->bc_state_hi[side][k] : g->bc_state[side][k];
     for (int k = 4; k < nc; ++k) Q[k] = g->bc_scalar[side][k - 4];
     conserved_to_prim(prm->gamma, Q, W, nc);
+}
+static void dirichlet_prim(const orc_params *prm, const orc_grid *g, int side, int nc, double *W)
+{
+    dirichlet_prim_of(prm, g, side, 0, nc, W);
+}
+
+/* A moving-split side at coordinate xc (cell centre) along it: below the
+ * split point a + b t_bc its Dirichlet state (W filled, returns -1), above it
+ * the hi kind: a Dirichlet state (W filled, -1) or a slip wall (returned). */
+static int moving_side(const orc_params *prm, const orc_grid *g, int side, double xc, int nc, double *W)
+{
+    if (xc < g->split_a[side] + g->split_b[side] * g->t_bc) {
+        dirichlet_prim(prm, g, side, nc, W);
+        return -1;
+    }
+    if (g->split_hi[side] == ORC_BC_DIRICHLET) {
+        dirichlet_prim_of(prm, g, side, 1, nc, W);
+        return -1;
+    }
+    return ORC_BC_SLIPWALL;
 }
 
 /* Ghost cells, two layers.  Boundary conditions are not in the paper; the
@@ -369,7 +390,10 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
     for (int j = 0; j < ny; ++j) {
         for (int gi = 1; gi <= 2; ++gi) {
             /* west ghost i = -gi */
-            switch (g->bc[ORC_WEST]) {
+            int kind = g->bc[ORC_WEST];
+            if (kind == ORC_BC_MOVING) kind = moving_side(prm, g, ORC_WEST, (j + 0.5) * g->dy, nc, W);
+            switch (kind) {
+            case -1: break;
             case ORC_BC_PERIODIC: get_prim(pf, nx - gi, j, W); break;
             case ORC_BC_TRANSMISSIVE: get_prim(pf, 0, j, W); break;
             case ORC_BC_SLIPWALL:
@@ -379,7 +403,10 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             }
             set_prim(pf, -gi, j, W);
             /* east ghost i = nx - 1 + gi */
-            switch (g->bc[ORC_EAST]) {
+            kind = g->bc[ORC_EAST];
+            if (kind == ORC_BC_MOVING) kind = moving_side(prm, g, ORC_EAST, (j + 0.5) * g->dy, nc, W);
+            switch (kind) {
+            case -1: break;
             case ORC_BC_PERIODIC: get_prim(pf, gi - 1, j, W); break;
             case ORC_BC_TRANSMISSIVE: get_prim(pf, nx - 1, j, W); break;
             case ORC_BC_SLIPWALL:
@@ -393,7 +420,10 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
     for (int i = -2; i < nx + 2; ++i) {
         int ic = i < 0 ? 0 : (i > nx - 1 ? nx - 1 : i); /* wall normal of the nearest column */
         for (int gj = 1; gj <= 2; ++gj) {
-            switch (g->bc[ORC_SOUTH]) {
+            int kind = g->bc[ORC_SOUTH];
+            if (kind == ORC_BC_MOVING) kind = moving_side(prm, g, ORC_SOUTH, (i + 0.5) * g->dx, nc, W);
+            switch (kind) {
+            case -1: break;
             case ORC_BC_PERIODIC: get_prim(pf, i, ny - gj, W); break;
             case ORC_BC_TRANSMISSIVE: get_prim(pf, i, 0, W); break;
             case ORC_BC_SLIPWALL:
@@ -402,7 +432,10 @@ static void fill_ghosts(const orc_params *prm, const orc_grid *g, prim_field *pf
             default: dirichlet_prim(prm, g, ORC_SOUTH, nc, W); break;
             }
             set_prim(pf, i, -gj, W);
-            switch (g->bc[ORC_NORTH]) {
+            kind = g->bc[ORC_NORTH];
+            if (kind == ORC_BC_MOVING) kind = moving_side(prm, g, ORC_NORTH, (i + 0.5) * g->dx, nc, W);
+            switch (kind) {
+            case -1: break;
             case ORC_BC_PERIODIC: get_prim(pf, i, gj - 1, W); break;
             case ORC_BC_TRANSMISSIVE: get_prim(pf, i, ny - 1, W); break;
             case ORC_BC_SLIPWALL:
@@ -499,6 +532,12 @@ static int check_args(const orc_params *prm, const orc_grid *g)
     if (g->metric == 1 && (!g->xn || !g->yn)) return ORC_EINVAL;
     if (prm->order != 1 && prm->order != 2) return ORC_EINVAL;
     if (g->nscalars < 0 || g->nscalars > ORC_MAX_SCALARS) return ORC_EINVAL;
+    for (int s = 0; s < 4; ++s) {
+        if (g->bc[s] < ORC_BC_PERIODIC || g->bc[s] > ORC_BC_MOVING) return ORC_EINVAL;
+        if (g->bc[s] != ORC_BC_MOVING) continue;
+        if (g->metric != 0 || g->bc[s ^ 1] == ORC_BC_PERIODIC) return ORC_EINVAL;
+        if (g->split_hi[s] != ORC_BC_DIRICHLET && g->split_hi[s] != ORC_BC_SLIPWALL) return ORC_EINVAL;
+    }
     return 0;
 }
 
@@ -645,6 +684,8 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
     double *q2 = (double *)malloc(sizeof(double) * n);
     if (!r || !q1 || !q2) { free(r); free(q1); free(q2); return ORC_ENOMEM; }
     double t = stats ? stats->t : 0.0;
+    /* moving boundaries are evaluated at the time of each stage's input state */
+    orc_grid gs = *g;
     long steps = 0, neg = 0;
     double dt = 0.0, rate = 0.0;
     rc = 0;
@@ -657,7 +698,8 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
         if (t_end > 0.0 && t + dt >= t_end) { dt = t_end - t; last = 1; }
         if (prm->time_scheme == 0) {
             /* forward Euler: Q^{n+1} = Q^n + dt R(Q^n) */
-            rc = residual_impl(prm, g, q, r, NULL, &neg);
+            gs.t_bc = t;
+            rc = residual_impl(prm, &gs, q, r, NULL, &neg);
             if (rc) break;
 #pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q[m] = q[m] + dt * r[m];
@@ -668,7 +710,8 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
             const double alpha[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
             const double *in = q;
             for (int k = 0; k < 4 && !rc; ++k) {
-                rc = residual_impl(prm, g, in, r, NULL, &neg);
+                gs.t_bc = t + (k == 0 ? 0.0 : alpha[k - 1] * dt);
+                rc = residual_impl(prm, &gs, in, r, NULL, &neg);
                 if (rc) break;
                 double *out = (k == 3) ? q : (k == 1 ? q2 : q1);
 #pragma omp parallel for schedule(static)
@@ -677,16 +720,19 @@ int orc_run(const orc_params *prm, const orc_grid *g, double *q, long nsteps, do
             }
             if (rc) break;
         } else {
-            /* SSP-RK3 (Shu-Osher form) */
-            rc = residual_impl(prm, g, q, r, NULL, &neg);
+            /* SSP-RK3 (Shu-Osher form); stage inputs at t, t + dt, t + dt/2 */
+            gs.t_bc = t;
+            rc = residual_impl(prm, &gs, q, r, NULL, &neg);
             if (rc) break;
 #pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q1[m] = q[m] + dt * r[m];
-            rc = residual_impl(prm, g, q1, r, NULL, &neg);
+            gs.t_bc = t + dt;
+            rc = residual_impl(prm, &gs, q1, r, NULL, &neg);
             if (rc) break;
 #pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m) q2[m] = 0.75 * q[m] + 0.25 * (q1[m] + dt * r[m]);
-            rc = residual_impl(prm, g, q2, r, NULL, &neg);
+            gs.t_bc = t + 0.5 * dt;
+            rc = residual_impl(prm, &gs, q2, r, NULL, &neg);
             if (rc) break;
 #pragma omp parallel for schedule(static)
             for (size_t m = 0; m < n; ++m)

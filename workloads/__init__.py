@@ -27,7 +27,7 @@ import numpy as np
 
 SEED_BASE = 171109272
 
-PERIODIC, TRANSMISSIVE, SLIPWALL, DIRICHLET = 0, 1, 2, 3
+PERIODIC, TRANSMISSIVE, SLIPWALL, DIRICHLET, MOVING = 0, 1, 2, 3, 4
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 
 
@@ -52,6 +52,10 @@ class Case:
     nsteps: int = 1
     t_end: float = 0.0
     bc_scalar: Optional[np.ndarray] = None  # [4 sides, nscalars] Dirichlet rho k_m
+    # moving-split sides (kind MOVING): {side: (a, b, hi_kind, conserved state above the split)};
+    # below the split point a + b t (cell-centre coordinate along the side) the side's bc_state
+    moving: Optional[Dict] = None
+    t_bc: float = 0.0  # time at which a residual evaluates moving sides
 
     @property
     def nscalars(self) -> int:
@@ -520,6 +524,41 @@ def smooth_random_case(nx: int, ny: int, seed: int, bc=(PERIODIC,) * 4, mach: fl
         bc_state[s] = conserved(gamma, 1.0, mach, 0.0, 1.0 / gamma)
     return Case(name=f"smooth_{nx}x{ny}", q0=q0, params=prm, bc=tuple(bc), dx=dx, dy=dy,
                 xn=xn, yn=yn, bc_state=bc_state, nsteps=10, t_end=0.0)
+
+
+def dmr_states(gamma: float = 1.4):
+    """Pre- and post-shock primitive states (rho, u, v, p) of the Mach-10 shock of
+    the double-Mach reflection: pre (1.4, 0, 0, 1); post from the normal-shock
+    relations at gamma = 1.4 (exact: rho = 8, p = 233/2, speed 33/4 along the
+    shock normal (cos 30, -sin 30))."""
+    w2 = 8.25
+    return (1.4, 0.0, 0.0, 1.0), (8.0, w2 * math.cos(math.pi / 6), -w2 * 0.5, 116.5)
+
+
+def dmr(nx: int = 800, ny: int = 200, t_end: float = 0.2, **params) -> Case:
+    """Double-Mach reflection (Sec. 7.4): [0, 4] x [0, 1], a Mach-10 shock at 60
+    degrees to the wall through (1/6, 0) moving into (1.4, 0, 0, 1); post-shock
+    inflow on the left, transmissive right; the bottom is post-shock for
+    x < 1/6 and a slip wall beyond; the top follows the exact shock,
+    x_s(t) = 1/6 + (1 + 20 t) / sqrt(3) (post-shock left of it).  200 x 800 cells
+    by default (the paper's grid, read as 800 in x and 200 in y, dx = dy = 1/200)."""
+    gamma = params.get("gamma", 1.4)
+    pre, post = dmr_states(gamma)
+    dx, dy = 4.0 / nx, 1.0 / ny
+    X, Y = cell_centres(nx, ny, 0.0, 0.0, dx, dy)
+    behind = X < 1.0 / 6.0 + Y / math.sqrt(3.0)
+    q0 = np.where(behind[None], conserved(gamma, *post)[:, None, None], conserved(gamma, *pre)[:, None, None])
+    bc_state = np.zeros((4, 4))
+    qpost, qpre = conserved(gamma, *post), conserved(gamma, *pre)
+    for sd in range(4):
+        bc_state[sd] = qpost
+    prm = default_params(order=2, time_scheme=1, cfl=0.4, mach_ref=1.0, u_ref=8.25, eps1=1.0, eps2=0.05)
+    prm.update(params)
+    moving = {SOUTH: (1.0 / 6.0, 0.0, SLIPWALL, qpost), NORTH: (1.0 / 6.0 + 1.0 / math.sqrt(3.0),
+                                                                20.0 / math.sqrt(3.0), DIRICHLET, qpre)}
+    return Case(name=f"dmr_{nx}x{ny}", q0=np.ascontiguousarray(q0), params=prm,
+                bc=(DIRICHLET, TRANSMISSIVE, MOVING, MOVING), dx=dx, dy=dy, bc_state=bc_state, nsteps=10 ** 6,
+                t_end=t_end, moving=moving)
 
 
 def add_scalars(case: "Case", ns: int, seed: int = 0, mode: str = "rough", value: float = 1.0,
