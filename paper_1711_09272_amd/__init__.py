@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libroeam.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 MAX_SCALARS = 2  # transported scalars (rho k rows) a 2-D grid may carry
-BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET = 0, 1, 2, 3
+BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET, BC_MOVING = 0, 1, 2, 3, 4
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 # stage-kernel tile shapes: cells x cells / threads per workgroup
 SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512", "16x15/256", "32x7/256", "16x7/256"]
@@ -26,7 +26,8 @@ SHAPES = ["32x15/256", "16x15/128", "8x7/64", "8x7/128", "16x15/512", "32x7/512"
 EXPORTS = [
     "roeam_ctx_create", "roeam_ctx_destroy", "roeam_ctx_set_stream", "roeam_last_error",
     "roeam_grid_create", "roeam_grid_destroy", "roeam_grid_layout", "roeam_grid_set_tile_shape",
-    "roeam_grid_tile_shape", "roeam_grid_set_scalars", "roeam_residual", "roeam_step",
+    "roeam_grid_tile_shape", "roeam_grid_set_scalars", "roeam_grid_set_moving_side", "roeam_grid_set_boundary_time",
+    "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
@@ -98,6 +99,8 @@ def lib():
         "roeam_grid_set_tile_shape": (i, [vp, i]),
         "roeam_grid_tile_shape": (i, [vp, ctypes.POINTER(Params), ctypes.POINTER(i)]),
         "roeam_grid_set_scalars": (i, [vp, i, vp]),
+        "roeam_grid_set_moving_side": (i, [vp, i, d, d, i, vp]),
+        "roeam_grid_set_boundary_time": (i, [vp, d]),
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
@@ -236,7 +239,23 @@ class Grid:
         ns = case.q0.shape[0] - 4
         if ns:
             g.set_scalars(ns, getattr(case, "bc_scalar", None))
+        for side, (a, b, hi, state_hi) in (getattr(case, "moving", None) or {}).items():
+            g.set_moving_side(side, a, b, hi, state_hi)
+        g.set_boundary_time(getattr(case, "t_bc", 0.0))
         return g
+
+    def set_moving_side(self, side: int, a: float, b: float, hi_kind: int, state_hi=None):
+        """Split a + b t of a BC_MOVING side; above it a slip wall or the conserved state_hi."""
+        arg = None
+        if state_hi is not None:
+            sa = np.ascontiguousarray(state_hi, dtype=np.float64).reshape(4)
+            self._keep.append(sa)
+            arg = ctypes.c_void_p(sa.ctypes.data)
+        self.ctx.check(lib().roeam_grid_set_moving_side(self.h, int(side), float(a), float(b), int(hi_kind), arg))
+
+    def set_boundary_time(self, t: float):
+        """Time at which residual() evaluates moving sides."""
+        self.ctx.check(lib().roeam_grid_set_boundary_time(self.h, float(t)))
 
     def set_scalars(self, nscalars: int, bc_scalar: Optional[np.ndarray] = None):
         """Carry nscalars transported scalars (state rows 4..); bc_scalar: [4 sides, nscalars]

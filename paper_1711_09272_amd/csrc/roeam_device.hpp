@@ -10,7 +10,10 @@
 
 namespace roeam {
 
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_SLIPWALL = 2, BC_DIRICHLET = 3 };
+// BC_MOVING (uniform grids): the side's Dirichlet state where the cell-centre
+// coordinate along the side is below spl_a + spl_b t, else its spl_hi kind
+// (another Dirichlet state or a slip wall); t is the time of the stage input.
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_SLIPWALL = 2, BC_DIRICHLET = 3, BC_MOVING = 4 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum : unsigned {
     V_XI_UNGATED = 1u, V_EXPFIX_F8 = 2u, V_CLAMP_UPRIME = 4u, V_NO_EQ92 = 8u,
@@ -62,6 +65,10 @@ struct DevSolve {
     double bcw[4][4];           // Dirichlet states, primitive (rho, u, v, p)
     int nsc;                    // transported scalars: rows 4 .. 3 + nsc of the state (rho k_m)
     double bck[4][kMaxScalars]; // Dirichlet scalars, primitive k_m
+    double spl_a[4], spl_b[4];  // BC_MOVING sides: split at a + b t
+    int spl_hi[4];              // BC_MOVING sides: kind above the split
+    double bcw_hi[4][4];        // BC_MOVING sides: Dirichlet state above the split, primitive
+    double t_res;               // time of moving sides in a residual-only launch
     // scheme
     double gamma, gm1, g_gm1, igm1, mr2, u_ref, dv_min2, eps1, eps2, eps_lambda, cfl, inv_area;
     int s1_mode, order, precision, scheme;
@@ -252,13 +259,32 @@ __device__ __forceinline__ void reflect(double W[4], double nx, double ny)
 
 // Primitive state of cell (i, j) where j is inside the grid and i may lie in
 // the two ghost columns on either side.
+// A BC_MOVING side at cell-centre coordinate xc along it and time tb: fills W
+// with a Dirichlet state and returns -1, or returns the kind to apply.
+template <int NSC>
+__device__ __forceinline__ int moving_side(const DevSolve &S, int sd, double xc, double tb, double *W)
+{
+    const bool lo = xc < S.spl_a[sd] + S.spl_b[sd] * tb;
+    if (!lo && S.spl_hi[sd] != BC_DIRICHLET) return BC_SLIPWALL;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) W[k] = lo ? S.bcw[sd][k] : S.bcw_hi[sd][k];
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) W[4 + m] = S.bck[sd][m];
+    return -1;
+}
+
 template <int METRIC, int NSC = 0>
-__device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
+__device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W,
+                                             double tb)
 {
     if (i >= 0 && i < S.nx) { load_prim<NSC>(S, q, i, j, W); return; }
     // constant-index selects keep the by-value kernel argument out of scratch
     const bool west = i < 0;
-    const int kind = west ? S.bc[SIDE_W] : S.bc[SIDE_E];
+    int kind = west ? S.bc[SIDE_W] : S.bc[SIDE_E];
+    if (kind == BC_MOVING) {
+        kind = moving_side<NSC>(S, west ? SIDE_W : SIDE_E, (j + 0.5) * S.dy, tb, W);
+        if (kind < 0) return;
+    }
     if (kind == BC_DIRICHLET) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) W[k] = west ? S.bcw[SIDE_W][k] : S.bcw[SIDE_E][k];
@@ -282,11 +308,16 @@ __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__
 // Primitive state of any cell within two layers of the grid: the x rule, then
 // the y rule (which also defines the corners).
 template <int METRIC, int NSC = 0>
-__device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
+__device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W,
+                                           double tb)
 {
-    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC, NSC>(S, q, i, j, W); return; }
+    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC, NSC>(S, q, i, j, W, tb); return; }
     const bool south = j < 0;
-    const int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
+    int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
+    if (kind == BC_MOVING) {
+        kind = moving_side<NSC>(S, south ? SIDE_S : SIDE_N, (i + 0.5) * S.dx, tb, W);
+        if (kind < 0) return;
+    }
     if (kind == BC_DIRICHLET) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) W[k] = south ? S.bcw[SIDE_S][k] : S.bcw[SIDE_N][k];
@@ -298,7 +329,7 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
     if (kind == BC_PERIODIC) js = j < 0 ? j + S.ny : j - S.ny;
     else if (kind == BC_TRANSMISSIVE) js = j < 0 ? 0 : S.ny - 1;
     else js = j < 0 ? -j - 1 : 2 * S.ny - 1 - j;
-    fetch_prim_x<METRIC, NSC>(S, q, i, js, W);
+    fetch_prim_x<METRIC, NSC>(S, q, i, js, W, tb);
     if (kind == BC_SLIPWALL) {
         int ic = i < 0 ? 0 : (i > S.nx - 1 ? S.nx - 1 : i);
         double sx, sy, nx, ny, len;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "../../include/roeam.h"
@@ -51,6 +52,11 @@ struct roeam_grid {
     double *d_xn = nullptr, *d_yn = nullptr;
     int bc[4] = {0, 0, 0, 0};
     double bcq[4][4] = {};
+    double spl_a[4] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, HUGE_VAL};  // moving sides: split at a + b t
+    double spl_b[4] = {0, 0, 0, 0};
+    int spl_hi[4] = {ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL};
+    double bcq_hi[4][4] = {};                    // moving sides: conserved state above the split
+    double t_res = 0.0;                          // time of moving sides in roeam_residual
     int nsc = 0;                                 // transported scalars (rows 4 .. 3 + nsc)
     double bcs[4][roeam::kMaxScalars] = {};      // Dirichlet rho k_m per side
     double *d_qa = nullptr, *d_qb = nullptr;

@@ -81,10 +81,17 @@ DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q,
         S.bc[s] = g->bc[s];
         prim_of(p->gamma, g->bcq[s], S.bcw[s]);
     }
+    for (int s = 0; s < 4; ++s) {
+        S.spl_a[s] = g->spl_a[s];
+        S.spl_b[s] = g->spl_b[s];
+        S.spl_hi[s] = g->spl_hi[s];
+        if (g->bc[s] == ROEAM_BC_MOVING && g->spl_hi[s] == ROEAM_BC_DIRICHLET) prim_of(p->gamma, g->bcq_hi[s], S.bcw_hi[s]);
+    }
+    S.t_res = g->t_res;
     S.nsc = g->nsc;
     for (int s = 0; s < 4; ++s)
         for (int m = 0; m < g->nsc; ++m)
-            S.bck[s][m] = g->bc[s] == ROEAM_BC_DIRICHLET ? g->bcs[s][m] / g->bcq[s][0] : 0.0;
+            S.bck[s][m] = (g->bc[s] == ROEAM_BC_DIRICHLET || g->bc[s] == ROEAM_BC_MOVING) ? g->bcs[s][m] / g->bcq[s][0] : 0.0;
     S.gamma = p->gamma;
     S.gm1 = p->gamma - 1.0;
     S.g_gm1 = p->gamma / (p->gamma - 1.0);
@@ -208,12 +215,15 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
     if (nx < 2 || ny < 2) return fail(ctx, ROEAM_EINVAL, "nx and ny must be >= 2");
     if ((long long)nx * ny > (1ll << 31) - 1) return fail(ctx, ROEAM_EINVAL, "grid too large");
     for (int s = 0; s < 4; ++s)
-        if (bc[s] < ROEAM_BC_PERIODIC || bc[s] > ROEAM_BC_DIRICHLET) return fail(ctx, ROEAM_EINVAL, "bad boundary kind");
+        if (bc[s] < ROEAM_BC_PERIODIC || bc[s] > ROEAM_BC_MOVING) return fail(ctx, ROEAM_EINVAL, "bad boundary kind");
+    for (int s = 0; s < 4; ++s)
+        if (bc[s] == ROEAM_BC_MOVING && (m->kind != 0 || bc[s ^ 1] == ROEAM_BC_PERIODIC))
+            return fail(ctx, ROEAM_EINVAL, "a moving side needs a uniform grid and a non-periodic opposite side");
     if ((bc[0] == ROEAM_BC_PERIODIC) != (bc[1] == ROEAM_BC_PERIODIC) ||
         (bc[2] == ROEAM_BC_PERIODIC) != (bc[3] == ROEAM_BC_PERIODIC))
         return fail(ctx, ROEAM_EINVAL, "a periodic direction needs periodic kinds on both sides");
     bool need_dir = false;
-    for (int s = 0; s < 4; ++s) need_dir |= bc[s] == ROEAM_BC_DIRICHLET;
+    for (int s = 0; s < 4; ++s) need_dir |= bc[s] == ROEAM_BC_DIRICHLET || bc[s] == ROEAM_BC_MOVING;
     if (need_dir && !dirichlet_state) return fail(ctx, ROEAM_EINVAL, "Dirichlet side without a state");
     if (m->kind == 0) {
         if (!(m->dx > 0.0) || !(m->dy > 0.0)) return fail(ctx, ROEAM_EINVAL, "dx, dy must be > 0");
@@ -233,7 +243,7 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
     }
     if (need_dir) {
         for (int s = 0; s < 4; ++s) {
-            if (bc[s] != ROEAM_BC_DIRICHLET) continue;
+            if (bc[s] != ROEAM_BC_DIRICHLET && bc[s] != ROEAM_BC_MOVING) continue;
             const double *Q = dirichlet_state + 4 * s;
             if (!(Q[0] > 0.0)) return fail(ctx, ROEAM_EINVAL, "Dirichlet density must be > 0");
             for (int k = 0; k < 4; ++k)
@@ -252,7 +262,8 @@ roeam_status roeam_grid_create(roeam_ctx *ctx, int nx, int ny, const roeam_metri
     g->dy = m->kind == 0 ? m->dy : 0.0;
     for (int s = 0; s < 4; ++s) {
         g->bc[s] = bc[s];
-        for (int k = 0; k < 4; ++k) g->bcq[s][k] = (bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_state[4 * s + k] : 0.0;
+        for (int k = 0; k < 4; ++k)
+            g->bcq[s][k] = (bc[s] == ROEAM_BC_DIRICHLET || bc[s] == ROEAM_BC_MOVING) ? dirichlet_state[4 * s + k] : 0.0;
     }
     hipError_t e = hipMalloc(&g->d_slot, sizeof(Slot));
     if (e == hipSuccess) e = hipHostMalloc(&g->h_slot, sizeof(Slot), hipHostMallocDefault);
@@ -559,11 +570,12 @@ roeam_status roeam_grid_set_scalars(roeam_grid *g, int nscalars, const double *d
     if (nscalars < 0 || nscalars > ROEAM_MAX_SCALARS)
         return fail(ctx, ROEAM_EINVAL, "nscalars must be 0 .. ROEAM_MAX_SCALARS");
     bool need = false;
-    for (int s = 0; s < 4; ++s) need |= g->bc[s] == ROEAM_BC_DIRICHLET;
+    for (int s = 0; s < 4; ++s) need |= g->bc[s] == ROEAM_BC_DIRICHLET || g->bc[s] == ROEAM_BC_MOVING;
     if (need && nscalars > 0 && !dirichlet_scalars) return fail(ctx, ROEAM_EINVAL, "Dirichlet side without scalars");
     for (int s = 0; s < 4 && need; ++s)
         for (int m = 0; m < nscalars; ++m)
-            if (g->bc[s] == ROEAM_BC_DIRICHLET && !std::isfinite(dirichlet_scalars[s * nscalars + m]))
+            if ((g->bc[s] == ROEAM_BC_DIRICHLET || g->bc[s] == ROEAM_BC_MOVING) &&
+                !std::isfinite(dirichlet_scalars[s * nscalars + m]))
                 return fail(ctx, ROEAM_EINVAL, "non-finite Dirichlet scalar");
     // work queued on the stage buffers may still run: wait before replacing them
     if (g->nsc != nscalars && (g->d_qa || g->d_qb)) {
@@ -576,10 +588,41 @@ roeam_status roeam_grid_set_scalars(roeam_grid *g, int nscalars, const double *d
     g->nsc = nscalars;
     for (int s = 0; s < 4; ++s)
         for (int m = 0; m < roeam::kMaxScalars; ++m)
-            g->bcs[s][m] = (m < nscalars && g->bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_scalars[s * nscalars + m] : 0.0;
+            g->bcs[s][m] = (m < nscalars && (g->bc[s] == ROEAM_BC_DIRICHLET || g->bc[s] == ROEAM_BC_MOVING))
+                               ? dirichlet_scalars[s * nscalars + m]
+                               : 0.0;
     g->gc.release();
     g->solve_valid = false;
     for (auto &row : g->shape_tuned) row[0] = row[1] = -1;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid_set_moving_side(roeam_grid *g, int side, double a, double b, int hi_kind, const double *state_hi)
+{
+    if (!g) return ROEAM_EINVAL;
+    roeam_ctx *ctx = g->ctx;
+    if (side < 0 || side > 3 || g->bc[side] != ROEAM_BC_MOVING)
+        return fail(ctx, ROEAM_EINVAL, "side is not a ROEAM_BC_MOVING side of this grid");
+    if (std::isnan(a) || !std::isfinite(b)) return fail(ctx, ROEAM_EINVAL, "split a must not be NaN, b must be finite");
+    if (hi_kind != ROEAM_BC_SLIPWALL && hi_kind != ROEAM_BC_DIRICHLET)
+        return fail(ctx, ROEAM_EINVAL, "hi_kind must be ROEAM_BC_SLIPWALL or ROEAM_BC_DIRICHLET");
+    if (hi_kind == ROEAM_BC_DIRICHLET) {
+        if (!state_hi) return fail(ctx, ROEAM_EINVAL, "Dirichlet hi side without a state");
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(state_hi[k])) return fail(ctx, ROEAM_EINVAL, "non-finite state");
+        if (!(state_hi[0] > 0.0)) return fail(ctx, ROEAM_EINVAL, "Dirichlet density must be > 0");
+    }
+    g->spl_a[side] = a;
+    g->spl_b[side] = b;
+    g->spl_hi[side] = hi_kind;
+    for (int k = 0; k < 4; ++k) g->bcq_hi[side][k] = hi_kind == ROEAM_BC_DIRICHLET ? state_hi[k] : 0.0;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid_set_boundary_time(roeam_grid *g, double t)
+{
+    if (!g || !std::isfinite(t)) return ROEAM_EINVAL;
+    g->t_res = t;
     return ROEAM_OK;
 }
 

@@ -73,6 +73,14 @@ __device__ __forceinline__ void reduce_rate_waves(Slot &z, int p, double v)
 // pointwise read of Q^n is the cell it writes).
 __host__ __device__ constexpr bool first_stage(int stage) { return stage == 1 || stage == 4; }
 
+// Fraction of dt at which a stage's input state lies (the abscissae c of the
+// schemes): stage codes 1-3 are SSP-RK3 (0, 1, 1/2), 4-7 the four-stage scheme
+// (0, 1/4, 1/3, 1/2).
+__host__ __device__ constexpr double stage_abscissa(int stage)
+{
+    return stage == 2 ? 1.0 : stage == 3 ? 0.5 : stage == 5 ? 0.25 : stage == 6 ? 1.0 / 3.0 : stage == 7 ? 0.5 : 0.0;
+}
+
 // Time-step logic shared by all stage kernels of a step with parity p.
 // Returns whether the step is active and its dt.
 __device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, double &dt, double &t_next,
