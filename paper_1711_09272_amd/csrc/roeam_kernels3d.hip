@@ -151,6 +151,7 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
     __shared__ double sW[5 * PL];
     __shared__ double sP[B::NPX + B::NPY + B::NPZ];
     __shared__ double sF[5][B::NFB];
+    __shared__ double sRed[NT / 64];
 
     const int tid = threadIdx.x;
     const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
@@ -281,7 +282,7 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
         if (!physical3(W)) atomicOr(&z.nonphys, 1);
         else if (last) lmax = rmax(lmax, cell_rate3(S, W, ir));
     }
-    if (last) reduce_rate_waves<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax);
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, sRed);
 }
 
 template <int ORDER, int PREC, int TX, int TY, int TZ, int NT>

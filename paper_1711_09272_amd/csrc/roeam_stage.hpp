@@ -49,18 +49,15 @@ __device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
     atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
 }
 
-// Per-wave reduction of the rate of the new state: each wave's lane 0 takes
-// its own word (workgroup and wave id mod kRateSlots), so the end of the last
-// stage needs no barrier and no LDS round trip.
+// Workgroup reduction of the rate of the new state, then one device-scope
+// atomic per workgroup (word = workgroup id mod kRateSlots).  One atomic per
+// wave instead (no barrier) measured 25% slower on the last stage of a 2048^2
+// grid: the atomics on the 64 words contend.  red: NT/64 doubles of LDS.
 template <int NT>
-__device__ __forceinline__ void reduce_rate_waves(Slot &z, int p, double v)
+__device__ __forceinline__ void reduce_rate_block(Slot &z, int p, double v, double *red)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0 && v > 0.0) {
-        const unsigned word = (blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) & (kRateSlots - 1);
-        atomicMax(&z.rate_bits[p][word], (unsigned long long)__double_as_longlong(v));
-    }
+    const double m = block_max<NT>(v, red);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(z, p, m);
 }
 
 // Stage codes of the stage kernel: 0 residual only; 1 forward Euler or the

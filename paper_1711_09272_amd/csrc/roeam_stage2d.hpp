@@ -123,6 +123,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     __shared__ double sPy[TY + 1][TX + 2];
     __shared__ double sF[NC][NFB];
     __shared__ double sG[NC][SPLIT ? NFY : 1];
+    __shared__ double sRed[NT / 64];
 
     const int tid = threadIdx.x;
     const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
@@ -320,7 +321,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
     }
     if (last) {
-        reduce_rate_waves<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax);
+        reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, sRed);
     }
 }
 
