@@ -41,7 +41,7 @@ BYTES_PER_CELL_STAGE_3D = {1: 80.0, 2: 120.0, 3: 120.0}
 
 # The device code of the stage kernels: counter summaries taken on other
 # sources are stale.  (Host-side scheduling files are not part of the hash.)
-KERNEL_SOURCES = ("roeam_kernels.hip", "roeam_device.hpp", "roeam_stage.hpp")
+KERNEL_SOURCES = ("roeam_kernels.hip", "roeam_stage2d.hpp", "roeam_device.hpp", "roeam_stage.hpp")
 KERNEL_SOURCES_3D = ("roeam_kernels3d.hip", "roeam_device3d.hpp", "roeam_device.hpp", "roeam_stage.hpp")
 
 

@@ -259,12 +259,23 @@ __device__ __forceinline__ void reflect(double W[4], double nx, double ny)
 
 // Primitive state of cell (i, j) where j is inside the grid and i may lie in
 // the two ghost columns on either side.
-// A BC_MOVING side at cell-centre coordinate xc along it and time tb: fills W
-// with a Dirichlet state and returns -1, or returns the kind to apply.
+// Time of the state a stage reads, for moving boundary sides: the step start
+// t of parity p plus c dt (c the stage abscissa), or t_res for a residual-only
+// launch (slot == nullptr).  Read only where a moving side needs it.
+struct BoundaryClock {
+    const Slot *slot;
+    int p;
+    double c_dt;
+    double t_res;
+    __device__ __forceinline__ double time() const { return slot ? slot->st[p].t + c_dt : t_res; }
+};
+
+// A BC_MOVING side at cell-centre coordinate xc along it: fills W with a
+// Dirichlet state and returns -1, or returns the kind to apply.
 template <int NSC>
-__device__ __forceinline__ int moving_side(const DevSolve &S, int sd, double xc, double tb, double *W)
+__device__ __forceinline__ int moving_side(const DevSolve &S, int sd, double xc, const BoundaryClock &clk, double *W)
 {
-    const bool lo = xc < S.spl_a[sd] + S.spl_b[sd] * tb;
+    const bool lo = xc < S.spl_a[sd] + S.spl_b[sd] * clk.time();
     if (!lo && S.spl_hi[sd] != BC_DIRICHLET) return BC_SLIPWALL;
 #pragma unroll
     for (int k = 0; k < 4; ++k) W[k] = lo ? S.bcw[sd][k] : S.bcw_hi[sd][k];
@@ -275,14 +286,14 @@ __device__ __forceinline__ int moving_side(const DevSolve &S, int sd, double xc,
 
 template <int METRIC, int NSC = 0>
 __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W,
-                                             double tb)
+                                             const BoundaryClock &clk)
 {
     if (i >= 0 && i < S.nx) { load_prim<NSC>(S, q, i, j, W); return; }
     // constant-index selects keep the by-value kernel argument out of scratch
     const bool west = i < 0;
     int kind = west ? S.bc[SIDE_W] : S.bc[SIDE_E];
     if (kind == BC_MOVING) {
-        kind = moving_side<NSC>(S, west ? SIDE_W : SIDE_E, (j + 0.5) * S.dy, tb, W);
+        kind = moving_side<NSC>(S, west ? SIDE_W : SIDE_E, (j + 0.5) * S.dy, clk, W);
         if (kind < 0) return;
     }
     if (kind == BC_DIRICHLET) {
@@ -309,13 +320,13 @@ __device__ __forceinline__ void fetch_prim_x(const DevSolve &S, const double *__
 // the y rule (which also defines the corners).
 template <int METRIC, int NSC = 0>
 __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W,
-                                           double tb)
+                                           const BoundaryClock &clk)
 {
-    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC, NSC>(S, q, i, j, W, tb); return; }
+    if (j >= 0 && j < S.ny) { fetch_prim_x<METRIC, NSC>(S, q, i, j, W, clk); return; }
     const bool south = j < 0;
     int kind = south ? S.bc[SIDE_S] : S.bc[SIDE_N];
     if (kind == BC_MOVING) {
-        kind = moving_side<NSC>(S, south ? SIDE_S : SIDE_N, (i + 0.5) * S.dx, tb, W);
+        kind = moving_side<NSC>(S, south ? SIDE_S : SIDE_N, (i + 0.5) * S.dx, clk, W);
         if (kind < 0) return;
     }
     if (kind == BC_DIRICHLET) {
@@ -329,7 +340,7 @@ __device__ __forceinline__ void fetch_prim(const DevSolve &S, const double *__re
     if (kind == BC_PERIODIC) js = j < 0 ? j + S.ny : j - S.ny;
     else if (kind == BC_TRANSMISSIVE) js = j < 0 ? 0 : S.ny - 1;
     else js = j < 0 ? -j - 1 : 2 * S.ny - 1 - j;
-    fetch_prim_x<METRIC, NSC>(S, q, i, js, W, tb);
+    fetch_prim_x<METRIC, NSC>(S, q, i, js, W, clk);
     if (kind == BC_SLIPWALL) {
         int ic = i < 0 ? 0 : (i > S.nx - 1 ? S.nx - 1 : i);
         double sx, sy, nx, ny, len;

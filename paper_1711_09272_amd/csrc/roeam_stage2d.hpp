@@ -157,7 +157,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     if (stage > 0 && !begin_stage(z, p, stage, last, first_block, dt)) return;
     // time of this stage's input state (moving boundary sides): the step start
     // plus the stage abscissa, 0, 1, 1/2 (SSP-RK3) or 0, 1/4, 1/3, 1/2 (four-stage)
-    const double tb = stage == 0 ? S.t_res : z.st[p].t + stage_abscissa(stage) * dt;
+    const BoundaryClock clk{stage == 0 ? nullptr : &z, p, stage_abscissa(stage) * dt, S.t_res};
 
     // 1. tile + halo -> primitives in LDS (fully unrolled: all loads in flight)
     const bool interior = (i0 - HL >= 0) && (i0 + TX + HL <= nx) && (j0 - HL >= 0) && (j0 + TY + HL <= ny);
@@ -175,7 +175,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             // cells past the ghost layers of a ragged tile feed no valid face
             gi = gi > nx + 1 ? nx + 1 : gi;
             gj = gj > ny + 1 ? ny + 1 : gj;
-            fetch_prim<METRIC, NSC>(S, qin, gi, gj, W, tb);
+            fetch_prim<METRIC, NSC>(S, qin, gi, gj, W, clk);
         }
 #pragma unroll
         for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
