@@ -94,8 +94,9 @@ def measured_valu(workload: str, precision: int):
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 
 
-def make_cases(workload: str, precision: int):
-    """The grids of a workload (list) and whether they run as one batch."""
+def make_cases(workload: str, precision: int, order=None, eps1=None):
+    """The grids of a workload (list) and whether they run as one batch
+    (order / eps1: overrides of the workload's MUSCL order and eps1)."""
     import workloads
     if workload == "vortex256pair":
         cases = [workloads.vortex(256, 0.01), workloads.vortex(256, 0.001)]
@@ -107,6 +108,10 @@ def make_cases(workload: str, precision: int):
         raise SystemExit(f"unknown workload {workload}")
     for c in cases:
         c.params["precision"] = precision
+        if order is not None:
+            c.params["order"] = order
+        if eps1 is not None:
+            c.params["eps1"] = eps1
     return cases, batched
 
 
@@ -496,6 +501,10 @@ def main():
                          "vortex3dNxNZ (one 3-D N x N x NZ grid)")
     ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
                     help="0 FP64, 1 FP32 coefficients (default: 0; batch256 defaults to 1)")
+    ap.add_argument("--order", type=int, default=None, choices=[1, 2],
+                    help="override the reconstruction order of the vortex workloads (roofline sweep)")
+    ap.add_argument("--eps1", type=float, default=None, choices=[0.0, 1.0],
+                    help="override eps1 of the vortex workloads (roofline sweep)")
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="stage-kernel tile shape index for the vortex workloads (-1: autotune)")
     ap.add_argument("--batch-grids", type=int, default=256)
@@ -531,7 +540,7 @@ def main():
     import torch
     import paper_1711_09272_amd as P
 
-    cases, batched = make_cases(args.workload, args.precision)
+    cases, batched = make_cases(args.workload, args.precision, args.order, args.eps1)
     cells = sum(c.nx * c.ny for c in cases)
     ctx = P.Context(0)
     grids = [P.Grid.from_case(ctx, c) for c in cases]
@@ -598,8 +607,10 @@ def main():
     launch_ms = gpu_ms / (3 * args.steps)
     bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, args.precision)
-    valu = measured_valu(args.workload, args.precision)
+    # counter summaries are taken on the workload as configured; not for overridden variants
+    overridden = args.order is not None or args.eps1 is not None
+    traffic = None if overridden else measured_traffic(args.workload, args.precision)
+    valu = None if overridden else measured_valu(args.workload, args.precision)
     alu = None
     if valu is not None:
         lane_rate = valu * cells / (launch_ms / 1e3)
@@ -615,7 +626,7 @@ def main():
         "traffic": traffic,
         "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
         "alu": alu,
-        "kernel": "%s<order 2, FP%s, uniform, %s>" % (kname, "64" if args.precision == 0 else "32-coef",
+        "kernel": "%s<order %d, FP%s, uniform, %s>" % (kname, prm["order"], "64" if args.precision == 0 else "32-coef",
                                                       P.SHAPES[shape] if shape >= 0 else "?"),
         "kernel_grid": kgrid,
         "launch_ms": round(launch_ms, 6),
@@ -642,7 +653,8 @@ def main():
             "workload": ("low-Mach isentropic vortex, two 256x256 periodic grids (M=0.01 and M=0.001) "
                          "advanced together as one batch" if batched else
                          f"low-Mach isentropic vortex {case.nx}x{case.ny} periodic, M=0.01")
-                        + ", FP64 state, MUSCL-minmod + SSP-RK3, Roe-AM (detector, eps1=1, eps2=0.05), CFL 0.4",
+                        + ", FP64 state, %s + SSP-RK3, Roe-AM (detector, eps1=%g, eps2=0.05), CFL 0.4"
+                        % ("MUSCL-minmod" if prm["order"] == 2 else "first order", prm["eps1"]),
             "cells": cells,
             "grids": len(cases),
             "stages_per_step": 3,
