@@ -250,6 +250,14 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *grid, const ro
                                 long nsteps, double t0, double stage_ms[4], long *launches);
 /* Wait for the grid's last roeam_step and read its statistics. */
 roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step_stats *stats);
+/* Norms of a residual array r (device, the grid's state layout, e.g. from
+ * roeam_residual) for convergence monitoring: norms_out (DEVICE, 2 * rows
+ * doubles, rows = 4 + nscalars) receives sqrt(mean over cells of r_k^2) in
+ * [0, rows) and max |r_k| in [rows, 2 rows).  A fixed-order two-pass
+ * reduction: the same bits on every call.  The grid keeps a small scratch
+ * buffer, allocated at the first call.  Asynchronous.  EINVAL: NULL argument;
+ * EDEVICE. */
+roeam_status roeam_residual_norms(roeam_ctx *ctx, const roeam_grid *grid, const double *r, double *norms_out);
 
 /* ------------------------------------------------------------------------ */
 /* 3-D uniform Cartesian grids                                              */
@@ -310,6 +318,8 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *grid, const roeam_
                           long nsteps, double t0, double t_end, roeam_step_stats *stats);
 /* Wait for the grid's last roeam_step3d and read its statistics. */
 roeam_status roeam_last_stats3d(roeam_ctx *ctx, const roeam_grid3d *grid, roeam_step_stats *stats);
+/* roeam_residual_norms for a 3-D residual array (rows = 5, norms_out 10 doubles). */
+roeam_status roeam_residual_norms3d(roeam_ctx *ctx, const roeam_grid3d *grid, const double *r, double *norms_out);
 
 /* ------------------------------------------------------------------------ */
 /* Batched and served solves                                                */
@@ -335,6 +345,13 @@ typedef struct {
  * state copies per solve plus per-solve slots); must be called before the
  * first submit.  ENOMEM if the allocation fails. */
 roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes);
+/* The same over caller-owned DEVICE memory (for example a torch tensor's
+ * storage) of arena_bytes at `arena`, 256-byte aligned: the engine places the
+ * resident solves' state there and never frees it.  The memory must stay
+ * valid, and must not be used otherwise, until the context is destroyed or
+ * another reserve/attach replaces the engine.  EINVAL: NULL or unaligned
+ * arena, too small; EBUSY: the current engine has work. */
+roeam_status roeam_batch_attach(roeam_ctx *ctx, void *arena, size_t arena_bytes);
 /* Bytes of arena a solve on this grid occupies while resident. */
 size_t roeam_batch_footprint(const roeam_grid *grid);
 /* Queue n solves; tickets_out[n] receives their tickets.  Solves are

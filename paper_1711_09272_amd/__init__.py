@@ -29,7 +29,8 @@ EXPORTS = [
     "roeam_grid_tile_shape", "roeam_grid_set_scalars", "roeam_grid_set_moving_side", "roeam_grid_set_boundary_time",
     "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
-    "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll",
+    "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll", "roeam_batch_attach", "roeam_residual_norms",
+    "roeam_residual_norms3d",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
     "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
@@ -104,9 +105,12 @@ def lib():
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
+        "roeam_residual_norms": (i, [vp, vp, vp, vp]),
+        "roeam_residual_norms3d": (i, [vp, vp, vp, vp]),
         "roeam_profile_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d,
                                    ctypes.POINTER(ctypes.c_double * 4), ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_reserve": (i, [vp, ctypes.c_size_t]),
+        "roeam_batch_attach": (i, [vp, vp, ctypes.c_size_t]),
         "roeam_batch_footprint": (ctypes.c_size_t, [vp]),
         "roeam_batch_submit": (i, [vp, i, ctypes.POINTER(SolveDesc), ctypes.POINTER(ctypes.c_uint64)]),
         "roeam_batch_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i)]),
@@ -346,6 +350,23 @@ def step(ctx: Context, grid: Grid, prm: Dict, q, nsteps: int, t0: float = 0.0, t
     return st.as_dict() if sync else None
 
 
+def residual_norms(ctx: Context, grid, r):
+    """RMS and max |.| per row of a residual tensor (2-D or 3-D grid); returns a
+    float64 device tensor [2, rows] (row 0: RMS, row 1: max)."""
+    import torch
+    three_d = isinstance(grid, Grid3)
+    rows = 5 if three_d else grid.rows
+    out = torch.zeros(2 * rows, dtype=torch.float64, device=f"cuda:{ctx.device}")
+    rp = _dev_ptr3(r, grid) if three_d else _dev_ptr(r, grid)
+    fn = lib().roeam_residual_norms3d if three_d else lib().roeam_residual_norms
+    ctx.enter()
+    try:
+        ctx.check(fn(ctx.h, grid.h, rp, ctypes.c_void_p(out.data_ptr())))
+    finally:
+        ctx.leave()
+    return out.view(2, rows)
+
+
 def last_stats(ctx: Context, grid: Grid) -> Dict:
     st = StepStats()
     ctx.check(lib().roeam_last_stats(ctx.h, grid.h, ctypes.byref(st)))
@@ -413,6 +434,14 @@ def padded(grid: Grid, q: np.ndarray) -> np.ndarray:
 
 def batch_reserve(ctx: Context, nbytes: int):
     ctx.check(lib().roeam_batch_reserve(ctx.h, int(nbytes)))
+
+
+def batch_attach(ctx: Context, arena):
+    """Run the batch engine over caller-owned device memory: a contiguous torch
+    tensor (its storage must outlive the engine; keep a reference)."""
+    nbytes = arena.numel() * arena.element_size()
+    ctx.check(lib().roeam_batch_attach(ctx.h, ctypes.c_void_p(arena.data_ptr()), int(nbytes)))
+    ctx._arena = arena
 
 
 def batch_submit(ctx: Context, solves) -> list:

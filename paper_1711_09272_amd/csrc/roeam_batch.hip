@@ -116,6 +116,7 @@ struct BatchEngine {
     int device = 0;
     char *d_arena = nullptr;
     size_t arena_bytes = 0;
+    bool owns_arena = true;  // false: the caller's memory (roeam_batch_attach), never freed here
     Arena alloc;
     DevSolve *d_solves = nullptr;
     DevSolve *h_solves = nullptr;   // pinned host mirror
@@ -172,7 +173,7 @@ static void release_engine(BatchEngine *b)
     if (b->d_slots) (void)hipFree(b->d_slots);
     if (b->h_solves) (void)hipHostFree(b->h_solves);
     if (b->d_solves) (void)hipFree(b->d_solves);
-    if (b->d_arena) (void)hipFree(b->d_arena);
+    if (b->d_arena && b->owns_arena) (void)hipFree(b->d_arena);
     delete b;
 }
 
@@ -424,10 +425,13 @@ size_t roeam_batch_footprint(const roeam_grid *g)
     return 3 * align_up(state_bytes(g));
 }
 
-roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes)
+// A new engine over `arena` (the caller's device memory) or, arena == nullptr,
+// over arena_bytes the engine allocates itself.
+static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes)
 {
     if (!ctx) return ROEAM_EINVAL;
     if (arena_bytes < kAlign) return roeam_fail(ctx, ROEAM_EINVAL, "arena too small");
+    if (arena && ((uintptr_t)arena % kAlign) != 0) return roeam_fail(ctx, ROEAM_EINVAL, "arena not 256-byte aligned");
     BHIP(ctx, hipSetDevice(ctx->device));
     if (ctx->batch) {
         BatchEngine *b = ctx->batch;
@@ -439,7 +443,13 @@ roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes)
     BatchEngine *b = new (std::nothrow) BatchEngine;
     if (!b) return roeam_fail(ctx, ROEAM_ENOMEM, "host allocation");
     b->device = ctx->device;
-    hipError_t e = hipMalloc(&b->d_arena, arena_bytes);
+    hipError_t e = hipSuccess;
+    if (arena) {
+        b->d_arena = (char *)arena;
+        b->owns_arena = false;
+    } else {
+        e = hipMalloc(&b->d_arena, arena_bytes);
+    }
     if (e == hipSuccess) e = hipMalloc(&b->d_solves, sizeof(DevSolve) * kMaxSolves);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_solves, sizeof(DevSolve) * kMaxSolves, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&b->d_slots, sizeof(Slot) * kMaxSolves);
@@ -466,6 +476,14 @@ roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes)
     }
     ctx->batch = b;
     return ROEAM_OK;
+}
+
+roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes) { return setup_engine(ctx, nullptr, arena_bytes); }
+
+roeam_status roeam_batch_attach(roeam_ctx *ctx, void *arena, size_t arena_bytes)
+{
+    if (!arena) return roeam_fail(ctx, ROEAM_EINVAL, "arena is NULL");
+    return setup_engine(ctx, arena, arena_bytes);
 }
 
 roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *descs, uint64_t *tickets_out)

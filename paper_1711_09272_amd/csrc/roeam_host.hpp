@@ -66,6 +66,7 @@ struct roeam_grid {
     int shape_forced = -1;   // tile shape set by the caller, or -1
     int shape_tuned[2][2] = {{-1, -1}, {-1, -1}};  // autotuned shape per [order-1][precision]
     int final_parity = 0;    // parity of the step state after the last roeam_step
+    double *d_norm_part = nullptr;  // scratch of roeam_residual_norms (allocated at its first call)
     DevSolve *d_solve = nullptr;  // descriptor read by the single-grid kernels
     DevSolve *h_solve = nullptr;  // pinned staging copy of the last descriptor sent
     bool solve_valid = false;

@@ -40,6 +40,11 @@ hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
 hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
+// RMS and max |.| per row of r[k][line][pitch] (rows 4..6, nx valid per line)
+// into out[2 rows]; part: scratch of 2 rows doubles per block, max_blocks blocks.
+constexpr int kNormMaxBlocks = 1024;
+hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int nlines, long long pitch, double *part,
+                        int max_blocks, double *out, hipStream_t st);
 
 // 3-D uniform Cartesian grids (brick shapes 0..brick_shape_count()-1).
 int brick_shape_count();

@@ -203,6 +203,7 @@ roeam_status roeam_grid_destroy(roeam_grid *g)
     if (g->h_slot) (void)hipHostFree(g->h_slot);
     if (g->d_solve) (void)hipFree(g->d_solve);
     if (g->h_solve) (void)hipHostFree(g->h_solve);
+    if (g->d_norm_part) (void)hipFree(g->d_norm_part);
     delete g;
     return ROEAM_OK;
 }
@@ -638,6 +639,19 @@ roeam_status roeam_grid_tile_shape(const roeam_grid *g, const roeam_params *p, i
     if (!g || !p || !shape || (p->order != 1 && p->order != 2) || (p->precision != 0 && p->precision != 1))
         return ROEAM_EINVAL;
     *shape = g->shape_forced >= 0 ? g->shape_forced : g->shape_tuned[p->order - 1][p->precision];
+    return ROEAM_OK;
+}
+
+roeam_status roeam_residual_norms(roeam_ctx *ctx, const roeam_grid *gc, const double *r, double *norms_out)
+{
+    if (!ctx || !gc || !r || !norms_out) return fail(ctx, ROEAM_EINVAL, "NULL argument");
+    if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    roeam_grid *g = const_cast<roeam_grid *>(gc);
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    if (!g->d_norm_part)
+        HIP_OK(ctx, hipMalloc(&g->d_norm_part, sizeof(double) * 2 * (4 + roeam::kMaxScalars) * roeam::kNormMaxBlocks));
+    HIP_OK(ctx, roeam::launch_norms(r, 4 + g->nsc, (long long)g->ny * g->pitch, g->nx, g->ny, g->pitch, g->d_norm_part,
+                                    roeam::kNormMaxBlocks, norms_out, ctx->stream));
     return ROEAM_OK;
 }
 

@@ -27,6 +27,7 @@ struct roeam_grid3d {
     bool solve_valid = false;
     GraphCache gc;
     int shape = 6;                    // 16x8x4 bricks, one thread per face (fastest measured on 128^3)
+    double *d_norm_part = nullptr;    // scratch of roeam_residual_norms3d
     int final_parity = 0;
 };
 
@@ -160,6 +161,7 @@ roeam_status roeam_grid3d_destroy(roeam_grid3d *g)
     if (g->h_slot) (void)hipHostFree(g->h_slot);
     if (g->d_solve) (void)hipFree(g->d_solve);
     if (g->h_solve) (void)hipHostFree(g->h_solve);
+    if (g->d_norm_part) (void)hipFree(g->d_norm_part);
     delete g;
     return ROEAM_OK;
 }
@@ -313,6 +315,18 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *gc, const roeam_pa
     }
     g->final_parity = (int)(launched & 1);
     if (stats) return fill_stats3(ctx, g, stats);
+    return ROEAM_OK;
+}
+
+roeam_status roeam_residual_norms3d(roeam_ctx *ctx, const roeam_grid3d *gc, const double *r, double *norms_out)
+{
+    if (!ctx || !gc || !r || !norms_out) return fail(ctx, ROEAM_EINVAL, "NULL argument");
+    if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    roeam_grid3d *g = const_cast<roeam_grid3d *>(gc);
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    if (!g->d_norm_part) HIP_OK(ctx, hipMalloc(&g->d_norm_part, sizeof(double) * 2 * 5 * roeam::kNormMaxBlocks));
+    HIP_OK(ctx, roeam::launch_norms(r, 5, (long long)g->nz * g->ny * g->pitch, g->nx, g->ny * g->nz, g->pitch,
+                                    g->d_norm_part, roeam::kNormMaxBlocks, norms_out, ctx->stream));
     return ROEAM_OK;
 }
 
