@@ -108,6 +108,8 @@ def lib():
         L.orc_physical_flux.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_residual.restype = ctypes.c_int
         L.orc_residual.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid), dp, dp, dp]
+        L.orc_rotated_mach.restype = ctypes.c_int
+        L.orc_rotated_mach.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid), dp, dp, dp]
         L.orc_max_rate.restype = ctypes.c_int
         L.orc_max_rate.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid), dp, dp]
         L.orc_run.restype = ctypes.c_int
@@ -254,6 +256,17 @@ def residual(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None
                             _dptr(sc) if with_scale else None)
     _check(rc)
     return (r, sc) if with_scale else r
+
+
+def rotated_mach(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None):
+    """f_rr / c on the i-faces [ny, nx+1] and the j-faces [ny+1, nx] (Fig. 7's diagnostic)."""
+    q = np.ascontiguousarray(case.q0 if q is None else q, dtype=np.float64)
+    gs = GridSpec(case)
+    prm = make_params(params or case.params)
+    fx = np.zeros((case.ny, case.nx + 1))
+    fy = np.zeros((case.ny + 1, case.nx))
+    _check(lib().orc_rotated_mach(ctypes.byref(prm), ctypes.byref(gs.g), _dptr(q), _dptr(fx), _dptr(fy)))
+    return fx, fy
 
 
 def max_rate(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None) -> float:

@@ -541,8 +541,19 @@ static int check_args(const orc_params *prm, const orc_grid *g)
     return 0;
 }
 
+/* frr_x, frr_y (nullable): f_rr / c of every i-face [ny][nx+1] and j-face
+ * [ny+1][nx] (the rotated Mach number of Eqs. 103-109; 0 where eps1 = 0). */
+static int residual_impl_diag(const orc_params *prm, const orc_grid *g, const double *q, double *r,
+                              double *scale, long *neg_uprime, double *frr_x, double *frr_y);
+
 static int residual_impl(const orc_params *prm, const orc_grid *g, const double *q, double *r,
                          double *scale, long *neg_uprime)
+{
+    return residual_impl_diag(prm, g, q, r, scale, neg_uprime, NULL, NULL);
+}
+
+static int residual_impl_diag(const orc_params *prm, const orc_grid *g, const double *q, double *r,
+                              double *scale, long *neg_uprime, double *frr_x, double *frr_y)
 {
     int rc = check_args(prm, g);
     if (rc) return rc;
@@ -575,6 +586,7 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
             orc_face_flux(prm, WL, WR, n[0], n[1], s1, F, &d);
             if (nc > 4) orc_face_flux_sc(prm, WL, WR, n[0], n[1], s1, nc - 4, F);
             if (d.absUp < 0.0) ++negc;
+            if (frr_x) frr_x[(size_t)j * (nx + 1) + i] = d.frr / d.c;
             for (int k = 0; k < nc; ++k) Fx[((size_t)j * (nx + 1) + i) * nc + k] = F[k] * len;
         }
     /* j-faces: between (i, j-1) and (i, j), j = 0..ny */
@@ -593,6 +605,7 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
             orc_face_flux(prm, WL, WR, n[0], n[1], s1, F, &d);
             if (nc > 4) orc_face_flux_sc(prm, WL, WR, n[0], n[1], s1, nc - 4, F);
             if (d.absUp < 0.0) ++negc;
+            if (frr_y) frr_y[(size_t)j * nx + i] = d.frr / d.c;
             for (int k = 0; k < nc; ++k) Fy[((size_t)j * nx + i) * nc + k] = F[k] * len;
         }
     if (neg_uprime) *neg_uprime += negc;
@@ -620,6 +633,16 @@ static int residual_impl(const orc_params *prm, const orc_grid *g, const double 
 int orc_residual(const orc_params *prm, const orc_grid *g, const double *q, double *r, double *scale)
 {
     return residual_impl(prm, g, q, r, scale, NULL);
+}
+
+int orc_rotated_mach(const orc_params *prm, const orc_grid *g, const double *q, double *frr_x, double *frr_y)
+{
+    const size_t n = (4 + (size_t)g->nscalars) * g->nx * g->ny;
+    double *r = (double *)malloc(sizeof(double) * n);
+    if (!r) return ORC_ENOMEM;
+    int rc = residual_impl_diag(prm, g, q, r, NULL, NULL, frr_x, frr_y);
+    free(r);
+    return rc;
 }
 
 /* Explicit rate of one cell (time-step rule; the paper prints none):

@@ -123,6 +123,10 @@ void orc_physical_flux(double gamma, const double W[4], double nx, double ny, do
  * four faces of |F_k| |S| / Omega, used by the cancellation-aware error norm.
  * Returns 0, or -4 if a cell has rho <= 0, p <= 0 or a non-finite value. */
 int orc_residual(const orc_params *prm, const orc_grid *g, const double *q, double *r, double *scale);
+/* Diagnostic of Sec. 7.2 (Fig. 7): the rotated Mach number f_rr / c of
+ * Eqs. (103)-(109) on every i-face [ny][nx+1] and j-face [ny+1][nx] (either
+ * pointer nullable), from the same face states as orc_residual. */
+int orc_rotated_mach(const orc_params *prm, const orc_grid *g, const double *q, double *frr_x, double *frr_y);
 /* Largest explicit rate lambda over cells (time-step rule). */
 int orc_max_rate(const orc_params *prm, const orc_grid *g, const double *q, double *max_rate);
 /* Advance q in place: nsteps steps or until t reaches t_end (t_end <= 0: no

@@ -427,3 +427,21 @@ def test_time_scheme_order_on_small_acoustics(time_scheme, lo, hi):
     e = [np.abs(sol[c] - sol[0.0125]).max() for c in (0.8, 0.4, 0.2)]
     for k in range(2):
         assert lo <= e[k] / e[k + 1] <= hi, e
+
+
+def test_rotated_mach_diagnostic_fig7():
+    """Sec. 7.2, Fig. 7 (a soft pin: the paper states neither the boundaries nor
+    the shock start): on the odd-even case of Fig. 6(i) -- Mach 6, 800 x 20
+    cells, centreline displaced by +-0.1 alternately (Eq. 113), eps1 = 1,
+    eps2 = 0.05, t = 100 -- the rotated Mach number f_rr / c on the faces
+    parallel to x peaks on the perturbed centreline near the shock at about
+    1.73, and is nearly zero on the smooth flow."""
+    c = workloads.odd_even(nx=800, ny=20, mach=6.0, eps_y=0.1, seeded=False, shock_x=20.0, t_end=100.0)
+    q, st = oracle.run(c)
+    assert st["t"] == 100.0 and st["nonphys"] == 0
+    _, fy = oracle.rotated_mach(c, q=q)
+    j, i = np.unravel_index(np.argmax(fy), fy.shape)
+    shock = int(np.argmax(np.abs(np.diff(q[0, 5]))))
+    assert 1.5 <= fy.max() <= 2.0, fy.max()
+    assert j == 10 and abs(i - shock) <= 20, (j, i, shock)
+    assert np.median(fy) < 1e-6

@@ -239,3 +239,15 @@ def test_autotuner_picks_a_shape(C):
     q = g.to_device(case.q0)
     P.step(C, g, case.params, q, 2)
     assert g.tile_shape(case.params) in range(len(P.SHAPES))
+
+
+def test_odd_even_fig6i_to_t100(C):
+    """The odd-even case of Fig. 6(i) (Mach 6, 800 x 20, eps_y = 0.1, Eq. 113,
+    eps1 = 1) for its whole duration, t = 100 (2763 steps), against the oracle."""
+    case = workloads.odd_even(nx=800, ny=20, mach=6.0, eps_y=0.1, seeded=False, shock_x=20.0, t_end=100.0)
+    q_or, st_or = oracle.run(case)
+    q_gpu, st = gpu_run(C, case)
+    err = state_error(q_gpu, q_or)
+    say(f"[step] odd-even Fig. 6(i) to t=100: {st['steps']} steps (oracle {st_or['steps']}), err {err:.3e}")
+    assert st["t"] == 100.0 and st["steps"] == st_or["steps"]
+    assert err <= TOL64
