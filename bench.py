@@ -293,6 +293,80 @@ def bench_batch(args):
                      "p50_s": percentile(alone64, 50), "p99_s": percentile(alone64, 99)},
         },
     }
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: the first 16 grids, all their steps
+        import oracle
+        sample = cases[:16]
+        t0 = time.perf_counter()
+        upd = 0
+        for c in sample:
+            _, st = oracle.run(c, nsteps=args.steps)
+            upd += c.nx * c.ny * 3 * st["steps"]
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": upd / dt / 1e9, "unit": "Gcell-updates/s per RK stage",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"the first {len(sample)} of the {len(cases)} grids, {args.steps} steps each, "
+                                         f"FP64 ({upd} cell-stage updates, {dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_to_t_end(args):
+    """The first and third configurations, each run to its end time through
+    roeam_step: Sod 400 x 4 (first order, forward Euler, to t = 0.2) and the
+    Mach-20 odd-even channel 800 x 80 (MUSCL, SSP-RK3, node grid, to t = 30).
+    The oracle runs the same case in full for the CPU baseline."""
+    import torch
+    import paper_1711_09272_amd as P
+    import workloads
+    case = workloads.sod() if args.workload == "sod" else workloads.odd_even()
+    if args.precision:
+        case.params["precision"] = args.precision
+    stages = {0: 1, 1: 3, 2: 4}[case.params["time_scheme"]]
+    ctx = P.Context(0)
+    g = P.Grid.from_case(ctx, case)
+    stream = torch.cuda.current_stream()
+    times = []
+    for rep in range(2):  # the first run tunes the tile shape and captures graphs
+        q = g.to_device(case.q0)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        P.step(ctx, g, case.params, q, case.nsteps, 0.0, case.t_end, sync=False)
+        ev1.record(stream)
+        st = P.last_stats(ctx, g)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1) / 1e3)
+        if st["nonphys"] or st["t"] != case.t_end:
+            raise SystemExit(f"run failed: {st}")
+    gpu_s = times[-1]
+    updates = case.nx * case.ny * stages * st["steps"]
+    shape = g.tile_shape(case.params)
+    out = {
+        "metric": "Gcell-updates/s per RK stage",
+        "value": round(updates / gpu_s / 1e9, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": st["steps"],
+        "ms_per_step": round(gpu_s * 1e3 / st["steps"], 5),
+        "higher_is_better": True,
+        "dtype": "f64" if not args.precision else "f32-flux/f64-state",
+        "data": "synthetic",
+        "config": {"workload": ("Sod shock tube 400x4, first order, forward Euler, CFL 0.4, to t = 0.2"
+                                if args.workload == "sod" else
+                                "Mach-20 odd-even channel 800x80 (node grid, centreline +-1e-6), MUSCL + "
+                                "SSP-RK3, CFL 0.4, to t = 30"),
+                   "cells": case.nx * case.ny, "stages_per_step": stages, "t_end": case.t_end,
+                   "tile_shape": P.SHAPES[shape] if shape >= 0 else None, "run_s": round(gpu_s, 5)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        _, st_or = oracle.run(case)
+        dt = time.perf_counter() - t0
+        upd = case.nx * case.ny * stages * st_or["steps"]
+        out["cpu_baseline"] = {"value": upd / dt / 1e9, "unit": "Gcell-updates/s per RK stage",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"the whole run ({st_or['steps']} steps, {upd} cell-stage updates, {dt:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 
@@ -498,7 +572,8 @@ def main():
     ap.add_argument("--workload", default="vortex256pair",
                     help="vortex256pair (both Mach numbers, batched; the default line), vortexN (one "
                          "N x N grid), batch256 (fourth configuration), serve (fifth configuration), "
-                         "vortex3dNxNZ (one 3-D N x N x NZ grid)")
+                         "vortex3dNxNZ (one 3-D N x N x NZ grid), sod and oddeven (first and third "
+                         "configurations, each run to its end time)")
     ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
                     help="0 FP64, 1 FP32 coefficients (default: 0; batch256 defaults to 1)")
     ap.add_argument("--order", type=int, default=None, choices=[1, 2],
@@ -530,6 +605,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload in ("sod", "oddeven"):
+        return bench_to_t_end(args)
     if args.precision is None:
         args.precision = 0
     if is_3d(args.workload):
