@@ -35,7 +35,7 @@ V_DUP_ZERO = 1 << 7
 
 SCHEME_ROEAM, SCHEME_ROE, SCHEME_ROE_HARTEN = 0, 1, 2
 BC_MOVING = 4  # a side split at a + b t: Dirichlet below, its hi kind above
-MAX_SCALARS = 2  # transported scalars (rho k rows of Eq. 85) a 2-D grid may carry
+MAX_SCALARS = 2  # transported scalars (rho k rows of Eq. 85) a grid may carry
 
 
 def _stale() -> bool:
@@ -121,6 +121,8 @@ def lib():
         L.orc3_physical_flux.argtypes = [ctypes.c_double, dp, dp, dp]
         L.orc3_face_flux.restype = None
         L.orc3_face_flux.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp]
+        L.orc3_face_flux_sc.restype = None
+        L.orc3_face_flux_sc.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
         L.orc3_residual.restype = ctypes.c_int
         L.orc3_residual.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid3), dp, dp, dp]
         L.orc3_max_rate.restype = ctypes.c_int
@@ -311,7 +313,8 @@ def cell_areas(case) -> np.ndarray:
 class _Grid3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dy", ctypes.c_double), ("dz", ctypes.c_double), ("bc", ctypes.c_int * 6),
-                ("bc_state", (ctypes.c_double * 5) * 6)]
+                ("bc_state", (ctypes.c_double * 5) * 6), ("nscalars", ctypes.c_int),
+                ("bc_scalar", (ctypes.c_double * MAX_SCALARS) * 6)]
 
 
 def _grid3(case) -> _Grid3:
@@ -322,6 +325,14 @@ def _grid3(case) -> _Grid3:
         g.bc[s] = int(case.bc[s])
         for k in range(5):
             g.bc_state[s][k] = float(case.bc_state[s][k])
+    ns = case.q0.shape[0] - 5
+    assert 0 <= ns <= MAX_SCALARS
+    g.nscalars = ns
+    bcs = getattr(case, "bc_scalar", None)
+    if ns and bcs is not None:
+        for s in range(6):
+            for m in range(ns):
+                g.bc_scalar[s][m] = float(bcs[s][m])
     return g
 
 
@@ -344,9 +355,22 @@ def face_flux3(params: Dict, WL, WR, n, s1: float = 1.0) -> np.ndarray:
     return F
 
 
+def face_flux3_sc(params: Dict, WL, WR, n, s1: float = 1.0) -> np.ndarray:
+    """3-D flux with transported scalars: W = (rho, u, v, w, p, k_1, ..), F has len(W) rows."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    ns = WL.shape[0] - 5
+    assert WR.shape == WL.shape and 0 <= ns <= MAX_SCALARS
+    nv = np.ascontiguousarray(n, dtype=np.float64)
+    F = np.zeros(5 + ns)
+    prm = make_params(params)
+    lib().orc3_face_flux_sc(ctypes.byref(prm), _dptr(WL), _dptr(WR), _dptr(nv), float(s1), ns, _dptr(F))
+    return F
+
+
 def residual3(case, q: Optional[np.ndarray] = None, params: Optional[Dict] = None, with_scale: bool = False):
     q = np.ascontiguousarray(case.q0 if q is None else q, dtype=np.float64)
-    assert q.shape == (5, case.nz, case.ny, case.nx)
+    assert q.shape == (case.q0.shape[0], case.nz, case.ny, case.nx)
     g = _grid3(case)
     prm = make_params(params or case.params)
     r = np.zeros_like(q)

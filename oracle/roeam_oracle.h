@@ -147,14 +147,21 @@ typedef struct {
     double dx, dy, dz;
     int bc[6];             /* west, east, south, north, bottom, top            */
     double bc_state[6][5]; /* Dirichlet conserved state per side              */
+    int nscalars;          /* transported scalars, 0 .. ORC_MAX_SCALARS          */
+    double bc_scalar[6][ORC_MAX_SCALARS]; /* Dirichlet rho k_m per side          */
 } orc3_grid;
 
-/* Layout: q is [5][nz][ny][nx], rows (rho, rho u, rho v, rho w, rho E). */
+/* Layout: q is [5 + ns][nz][ny][nx], rows (rho, rho u, rho v, rho w, rho E)
+ * and the ns transported scalars rho k_m. */
 void orc3_physical_flux(double gamma, const double W[5], const double n[3], double F[5]);
 /* Eqs. (85)-(109) (or the classical schemes) in 3-D, per unit face area;
  * W = (rho, u, v, w, p), n a unit normal. */
 void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5], const double n[3], double s1,
                     double F[5]);
+/* The same with ns transported scalars: W = (rho, u, v, w, p, k_1 ..), F = 5 + ns rows
+ * (the rho k rows of Eq. 85 as printed, in three dimensions). */
+void orc3_face_flux_sc(const orc_params *prm, const double *WL, const double *WR, const double n[3], double s1,
+                       int ns, double *F);
 int orc3_residual(const orc_params *prm, const orc3_grid *g, const double *q, double *r, double *scale);
 int orc3_max_rate(const orc_params *prm, const orc3_grid *g, const double *q, double *max_rate);
 int orc3_run(const orc_params *prm, const orc3_grid *g, double *q, long nsteps, double t_end, orc_run_stats *stats);

@@ -9,7 +9,8 @@
  * orders, rows of cells shared out by OpenMP without changing any value's
  * arithmetic.  It shares nothing with the HIP library.
  *
- * Layout: q is [5][nz][ny][nx], rows (rho, rho u, rho v, rho w, rho E).
+ * Layout: q is [5 + ns][nz][ny][nx], rows (rho, rho u, rho v, rho w, rho E)
+ * and ns transported scalars rho k_m.
  */
 #include "roeam_oracle.h"
 
@@ -83,19 +84,30 @@ static double rotated_speed3(const double n[3], const double dV[3], const double
     return fabs(alpha1 * U1) + fabs(a2U2); /* Eq. (103) */
 }
 
-void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5], const double n[3], double s1,
-                    double F[5])
+/* Eq. (85) in 3-D with ns transported scalars after the five flow rows: each
+ * scalar row has Psi = rho k, Psi^ = rho^ k^ (k^ the sqrt(rho)-weighted Roe
+ * average), no pressure term, and the face's xi, dU_p, dU_u (classical Roe:
+ * xi Delta(rho k) + (dU_u + dU_p) rho^ k^). */
+void orc3_face_flux_sc(const orc_params *prm, const double *WL, const double *WR, const double n[3], double s1,
+                       int ns, double *F)
 {
     const double g = prm->gamma;
     const double rL = WL[0], rR = WR[0], pL = WL[4], pR = WR[4];
     const double VL[3] = {WL[1], WL[2], WL[3]}, VR[3] = {WR[1], WR[2], WR[3]};
     double UL = dot3(n, VL), UR = dot3(n, VR);
     double HL = enthalpy3(g, WL), HR = enthalpy3(g, WR);
-    double PsiL[5] = {rL, rL * VL[0], rL * VL[1], rL * VL[2], rL * HL};
-    double PsiR[5] = {rR, rR * VR[0], rR * VR[1], rR * VR[2], rR * HR};
-    double FbL[5], FbR[5];
+    const int nc = 5 + ns;
+    double PsiL[5 + ORC_MAX_SCALARS] = {rL, rL * VL[0], rL * VL[1], rL * VL[2], rL * HL};
+    double PsiR[5 + ORC_MAX_SCALARS] = {rR, rR * VR[0], rR * VR[1], rR * VR[2], rR * HR};
+    double FbL[5 + ORC_MAX_SCALARS], FbR[5 + ORC_MAX_SCALARS];
     orc3_physical_flux(g, WL, n, FbL);
     orc3_physical_flux(g, WR, n, FbR);
+    for (int m = 0; m < ns; ++m) {
+        PsiL[5 + m] = rL * WL[5 + m];
+        PsiR[5 + m] = rR * WR[5 + m];
+        FbL[5 + m] = dot3(n, VL) * PsiL[5 + m];
+        FbR[5 + m] = dot3(n, VR) * PsiR[5 + m];
+    }
 
     /* Roe averages (sqrt(rho) weights) */
     double rr = sqrt(rR / rL);
@@ -105,10 +117,11 @@ void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5
     double H = (HL + rr * HR) / (1.0 + rr);
     double c = sqrt((g - 1.0) * (H - 0.5 * dot3(V, V)));
     double U = dot3(n, V);
-    double PsiHat[5] = {rho, rho * V[0], rho * V[1], rho * V[2], rho * H};
+    double PsiHat[5 + ORC_MAX_SCALARS] = {rho, rho * V[0], rho * V[1], rho * V[2], rho * H};
+    for (int m = 0; m < ns; ++m) PsiHat[5 + m] = rho * ((WL[5 + m] + rr * WR[5 + m]) / (1.0 + rr));
     double dU = UR - UL, dp = pR - pL;
-    double pvec[5] = {0.0, n[0], n[1], n[2], 0.0};
-    double diss[5];
+    double pvec[5 + ORC_MAX_SCALARS] = {0.0, n[0], n[1], n[2], 0.0};
+    double diss[5 + ORC_MAX_SCALARS];
 
     if (prm->scheme == ORC_SCHEME_ROE || prm->scheme == ORC_SCHEME_ROE_HARTEN) {
         /* classical Roe, Eq. (7) with Eqs. (8)-(12); Harten's fix, Eqs. (114)-(115) */
@@ -124,10 +137,11 @@ void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5
         double dpp = 0.5 * (l5 - l4) * dp / c;
         double dUu = 0.5 * (l5 - l4) * dU / c;
         double dUp = (0.5 * (l5 + l4) - l1) * dp / (rho * c * c);
-        double dQ[5] = {rR - rL, PsiR[1] - PsiL[1], PsiR[2] - PsiL[2], PsiR[3] - PsiL[3],
-                        rhoE3(g, WR) - rhoE3(g, WL)};
-        double pv7[5] = {0.0, n[0], n[1], n[2], U};
-        for (int k = 0; k < 5; ++k) diss[k] = xi * dQ[k] + (dpu + dpp) * pv7[k] + (dUu + dUp) * PsiHat[k];
+        double dQ[5 + ORC_MAX_SCALARS] = {rR - rL, PsiR[1] - PsiL[1], PsiR[2] - PsiL[2], PsiR[3] - PsiL[3],
+                                          rhoE3(g, WR) - rhoE3(g, WL)};
+        double pv7[5 + ORC_MAX_SCALARS] = {0.0, n[0], n[1], n[2], U};
+        for (int m = 0; m < ns; ++m) dQ[5 + m] = PsiR[5 + m] - PsiL[5 + m];
+        for (int k = 0; k < nc; ++k) diss[k] = xi * dQ[k] + (dpu + dpp) * pv7[k] + (dUu + dUp) * PsiHat[k];
     } else {
         const unsigned var = prm->variant;
         double cL = sqrt(g * pL / rL), cR = sqrt(g * pR / rR);
@@ -160,40 +174,51 @@ void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5
         if (var & ORC_V_DUP_ROE) dUp = dmax(0.0, c - absU) * dp / (rho * c * c);
         if (var & ORC_V_DUP_ZERO) dUp = 0.0;
         double dUu = 0.5 * sgn(U) * dmin(absUp, c) * dU / c;                             /* Eqs. (90)-(91) */
-        for (int k = 0; k < 5; ++k)
+        for (int k = 0; k < nc; ++k)
             diss[k] = xi * (PsiR[k] - PsiL[k]) + (dpp + dpu) * pvec[k] + dUp * PsiHat[k] + dUu * PsiR[k]
                     + dUu * PsiL[k];
     }
-    for (int k = 0; k < 5; ++k) F[k] = 0.5 * (FbL[k] + FbR[k]) - 0.5 * diss[k]; /* Eq. (85) */
+    for (int k = 0; k < nc; ++k) F[k] = 0.5 * (FbL[k] + FbR[k]) - 0.5 * diss[k]; /* Eq. (85) */
+}
+
+void orc3_face_flux(const orc_params *prm, const double WL[5], const double WR[5], const double n[3], double s1,
+                    double F[5])
+{
+    orc3_face_flux_sc(prm, WL, WR, n, s1, 0, F);
 }
 
 /* ------------------------------------------------------------------------ */
 /* grid, ghosts, residual                                                   */
 /* ------------------------------------------------------------------------ */
 
+#define ORC3_MAXC (5 + ORC_MAX_SCALARS)
+
 typedef struct {
     int nx, ny, nz, NX, NY, NZ; /* N* = n* + 4 (two ghost layers) */
-    double *W;                  /* primitives [5][NZ][NY][NX] */
+    int nc;                     /* components: 5 + scalars */
+    double *W;                  /* primitives [nc][NZ][NY][NX]: rho, u, v, w, p, k_1 .. */
 } prim3;
 
 static size_t P3(const prim3 *f, int k, int i, int j, int l)
 {
     return (((size_t)k * f->NZ + (size_t)(l + 2)) * f->NY + (size_t)(j + 2)) * f->NX + (size_t)(i + 2);
 }
-static void get3(const prim3 *f, int i, int j, int l, double W[5])
+static void get3(const prim3 *f, int i, int j, int l, double *W)
 {
-    for (int k = 0; k < 5; ++k) W[k] = f->W[P3(f, k, i, j, l)];
+    for (int k = 0; k < f->nc; ++k) W[k] = f->W[P3(f, k, i, j, l)];
 }
-static void set3(prim3 *f, int i, int j, int l, const double W[5])
+static void set3(prim3 *f, int i, int j, int l, const double *W)
 {
-    for (int k = 0; k < 5; ++k) f->W[P3(f, k, i, j, l)] = W[k];
+    for (int k = 0; k < f->nc; ++k) f->W[P3(f, k, i, j, l)] = W[k];
 }
-static void prim_of3(double gamma, const double Q[5], double W[5])
+/* nc components: the five flow primitives and k_m = (rho k_m) / rho */
+static void prim_of3(double gamma, const double *Q, double *W, int nc)
 {
     double rho = Q[0];
     double u = Q[1] / rho, v = Q[2] / rho, w = Q[3] / rho;
     W[0] = rho; W[1] = u; W[2] = v; W[3] = w;
     W[4] = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u + v * v + w * w));
+    for (int k = 5; k < nc; ++k) W[k] = Q[k] / rho;
 }
 static int physical3(const double W[5])
 {
@@ -206,7 +231,7 @@ static int physical3(const double W[5])
  * boundary, given the line of cells along the side's axis: a[] is the index
  * of interior cell m (0 .. n-1) along that axis. */
 static void ghost3(const orc_params *prm, const orc3_grid *g, const prim3 *f, int side, int gd, int i, int j, int l,
-                   double W[5])
+                   double *W)
 {
     const int axis = side / 2, hi = side & 1;
     const int n = axis == 0 ? g->nx : (axis == 1 ? g->ny : g->nz);
@@ -215,7 +240,13 @@ static void ghost3(const orc_params *prm, const orc3_grid *g, const prim3 *f, in
     case ORC_BC_PERIODIC: m = hi ? gd - 1 : n - gd; break;
     case ORC_BC_TRANSMISSIVE: m = hi ? n - 1 : 0; break;
     case ORC_BC_SLIPWALL: m = hi ? n - gd : gd - 1; break;
-    default: prim_of3(prm->gamma, g->bc_state[side], W); return;
+    default: {
+        double Q[ORC3_MAXC];
+        for (int k = 0; k < 5; ++k) Q[k] = g->bc_state[side][k];
+        for (int k = 5; k < f->nc; ++k) Q[k] = g->bc_scalar[side][k - 5];
+        prim_of3(prm->gamma, Q, W, f->nc);
+        return;
+    }
     }
     int ii = i, jj = j, ll = l;
     if (axis == 0) ii = m;
@@ -229,7 +260,7 @@ static void ghost3(const orc_params *prm, const orc3_grid *g, const prim3 *f, in
  * and interior l, then z-ghosts for every (i, j): edges and corners follow. */
 static void fill_ghosts3(const orc_params *prm, const orc3_grid *g, prim3 *f)
 {
-    double W[5];
+    double W[ORC3_MAXC];
     const int nx = g->nx, ny = g->ny, nz = g->nz;
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
@@ -260,9 +291,9 @@ static int load_prims3(const orc_params *prm, const orc3_grid *g, const double *
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t c = ((size_t)l * g->ny + j) * g->nx + i;
-                double Q[5], W[5];
-                for (int k = 0; k < 5; ++k) Q[k] = q[k * vol + c];
-                prim_of3(prm->gamma, Q, W);
+                double Q[ORC3_MAXC], W[ORC3_MAXC];
+                for (int k = 0; k < f->nc; ++k) Q[k] = q[k * vol + c];
+                prim_of3(prm->gamma, Q, W, f->nc);
                 if (!physical3(W)) bad = 1;
                 set3(f, i, j, l, W);
             }
@@ -279,7 +310,7 @@ static double minmod(double a, double b)
 
 static double P3between(const prim3 *f, int ia, int ja, int la, int ib, int jb, int lb)
 {
-    double A[5], B[5];
+    double A[ORC3_MAXC], B[ORC3_MAXC];
     get3(f, ia, ja, la, A);
     get3(f, ib, jb, lb, B);
     return orc_detector_P(A[4], A[0], B[4], B[0]);
@@ -314,26 +345,28 @@ static int check3(const orc_params *prm, const orc3_grid *g)
     if (!(prm->gamma > 1.0)) return ORC_EINVAL;
     if (prm->scheme == ORC_SCHEME_ROEAM && !(prm->mach_ref > 0.0)) return ORC_EINVAL;
     if (prm->order != 1 && prm->order != 2) return ORC_EINVAL;
+    if (g->nscalars < 0 || g->nscalars > ORC_MAX_SCALARS) return ORC_EINVAL;
     return 0;
 }
 
 /* Faces normal to `axis`: face (i, j, l) lies between cell (i, j, l) - e_axis
- * and (i, j, l).  Flux per unit area into F[(face index) * 5 + k]. */
+ * and (i, j, l).  Flux per unit area into F[(face index) * nc + k]. */
 static void face_fluxes3(const orc_params *prm, const orc3_grid *g, const prim3 *f, int axis, double *F)
 {
     const int fx = g->nx + (axis == 0), fy = g->ny + (axis == 1), fz = g->nz + (axis == 2);
     const int e[3] = {axis == 0, axis == 1, axis == 2};
     const double n[3] = {(double)e[0], (double)e[1], (double)e[2]};
+    const int nc = f->nc;
 #pragma omp parallel for schedule(static)
     for (int l = 0; l < fz; ++l)
         for (int j = 0; j < fy; ++j)
             for (int i = 0; i < fx; ++i) {
-                double m2[5], m1[5], p0[5], p1[5], WL[5], WR[5];
+                double m2[ORC3_MAXC], m1[ORC3_MAXC], p0[ORC3_MAXC], p1[ORC3_MAXC], WL[ORC3_MAXC], WR[ORC3_MAXC];
                 get3(f, i - 2 * e[0], j - 2 * e[1], l - 2 * e[2], m2);
                 get3(f, i - e[0], j - e[1], l - e[2], m1);
                 get3(f, i, j, l, p0);
                 get3(f, i + e[0], j + e[1], l + e[2], p1);
-                for (int k = 0; k < 5; ++k) {
+                for (int k = 0; k < nc; ++k) {
                     if (prm->order == 1) {
                         WL[k] = m1[k];
                         WR[k] = p0[k];
@@ -342,10 +375,10 @@ static void face_fluxes3(const orc_params *prm, const orc3_grid *g, const prim3 
                         WR[k] = p0[k] - 0.5 * minmod(p0[k] - m1[k], p1[k] - p0[k]);
                     }
                 }
-                double Fc[5];
-                orc3_face_flux(prm, WL, WR, n, s1_face3(prm, f, axis, i, j, l), Fc);
+                double Fc[ORC3_MAXC];
+                orc3_face_flux_sc(prm, WL, WR, n, s1_face3(prm, f, axis, i, j, l), nc - 5, Fc);
                 size_t idx = ((size_t)l * fy + j) * fx + i;
-                for (int k = 0; k < 5; ++k) F[idx * 5 + k] = Fc[k];
+                for (int k = 0; k < nc; ++k) F[idx * nc + k] = Fc[k];
             }
 }
 
@@ -353,12 +386,12 @@ static int residual3_impl(const orc_params *prm, const orc3_grid *g, const doubl
 {
     int rc = check3(prm, g);
     if (rc) return rc;
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    prim3 f = {nx, ny, nz, nx + 4, ny + 4, nz + 4, NULL};
-    f.W = (double *)malloc(sizeof(double) * 5 * (size_t)f.NX * f.NY * f.NZ);
-    double *Fx = (double *)malloc(sizeof(double) * 5 * (size_t)(nx + 1) * ny * nz);
-    double *Fy = (double *)malloc(sizeof(double) * 5 * (size_t)nx * (ny + 1) * nz);
-    double *Fz = (double *)malloc(sizeof(double) * 5 * (size_t)nx * ny * (nz + 1));
+    const int nx = g->nx, ny = g->ny, nz = g->nz, nc = 5 + g->nscalars;
+    prim3 f = {nx, ny, nz, nx + 4, ny + 4, nz + 4, nc, NULL};
+    f.W = (double *)malloc(sizeof(double) * nc * (size_t)f.NX * f.NY * f.NZ);
+    double *Fx = (double *)malloc(sizeof(double) * nc * (size_t)(nx + 1) * ny * nz);
+    double *Fy = (double *)malloc(sizeof(double) * nc * (size_t)nx * (ny + 1) * nz);
+    double *Fz = (double *)malloc(sizeof(double) * nc * (size_t)nx * ny * (nz + 1));
     if (!f.W || !Fx || !Fy || !Fz) { free(f.W); free(Fx); free(Fy); free(Fz); return ORC_ENOMEM; }
     rc = load_prims3(prm, g, q, &f);
     if (rc) { free(f.W); free(Fx); free(Fy); free(Fz); return rc; }
@@ -373,13 +406,13 @@ static int residual3_impl(const orc_params *prm, const orc3_grid *g, const doubl
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = ((size_t)l * ny + j) * nx + i;
-                for (int k = 0; k < 5; ++k) {
-                    double fw = Fx[(((size_t)l * ny + j) * (nx + 1) + i) * 5 + k] * Ax;
-                    double fe = Fx[(((size_t)l * ny + j) * (nx + 1) + i + 1) * 5 + k] * Ax;
-                    double gs = Fy[(((size_t)l * (ny + 1) + j) * nx + i) * 5 + k] * Ay;
-                    double gn = Fy[(((size_t)l * (ny + 1) + j + 1) * nx + i) * 5 + k] * Ay;
-                    double hb = Fz[(((size_t)l * ny + j) * nx + i) * 5 + k] * Az;
-                    double ht = Fz[(((size_t)(l + 1) * ny + j) * nx + i) * 5 + k] * Az;
+                for (int k = 0; k < nc; ++k) {
+                    double fw = Fx[(((size_t)l * ny + j) * (nx + 1) + i) * nc + k] * Ax;
+                    double fe = Fx[(((size_t)l * ny + j) * (nx + 1) + i + 1) * nc + k] * Ax;
+                    double gs = Fy[(((size_t)l * (ny + 1) + j) * nx + i) * nc + k] * Ay;
+                    double gn = Fy[(((size_t)l * (ny + 1) + j + 1) * nx + i) * nc + k] * Ay;
+                    double hb = Fz[(((size_t)l * ny + j) * nx + i) * nc + k] * Az;
+                    double ht = Fz[(((size_t)(l + 1) * ny + j) * nx + i) * nc + k] * Az;
                     r[k * plane + c] = -(((fe - fw) + (gn - gs)) + (ht - hb)) / vol;
                     if (scale)
                         scale[k * plane + c] =
@@ -413,7 +446,7 @@ int orc3_max_rate(const orc_params *prm, const orc3_grid *g, const double *q, do
                 size_t c = ((size_t)l * g->ny + j) * g->nx + i;
                 double Q[5], W[5];
                 for (int k = 0; k < 5; ++k) Q[k] = q[k * vol + c];
-                prim_of3(prm->gamma, Q, W);
+                prim_of3(prm->gamma, Q, W, 5);
                 if (!physical3(W)) { bad = 1; continue; }
                 double cs = sqrt(prm->gamma * W[4] / W[0]);
                 double M = sqrt(W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / cs;
@@ -432,7 +465,7 @@ int orc3_run(const orc_params *prm, const orc3_grid *g, double *q, long nsteps, 
     int rc = check3(prm, g);
     if (rc) return rc;
     if (!(prm->cfl > 0.0) || prm->time_scheme < 0 || prm->time_scheme > 2) return ORC_EINVAL;
-    const size_t n = 5 * (size_t)g->nx * g->ny * g->nz;
+    const size_t n = (5 + (size_t)g->nscalars) * g->nx * g->ny * g->nz;
     double *r = (double *)malloc(sizeof(double) * n);
     double *q1 = (double *)malloc(sizeof(double) * n);
     double *q2 = (double *)malloc(sizeof(double) * n);

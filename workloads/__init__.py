@@ -570,14 +570,19 @@ def add_scalars(case: "Case", ns: int, seed: int = 0, mode: str = "rough", value
     (default: value) times their density."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 600 + seed))
     rho = case.q0[0]
+    nsides = len(case.bc)  # 4 in 2-D, 6 in 3-D (a Case3 works as well)
     ks = []
     for m in range(ns):
         if mode == "const":
             k = np.full_like(rho, value)
         elif mode == "smooth":
-            j, i = np.meshgrid(np.arange(case.ny), np.arange(case.nx), indexing="ij")
-            ph = rng.uniform(0, 2 * math.pi, 2)
-            k = 1.0 + 0.8 * np.sin(2 * math.pi * i / case.nx + ph[0]) * np.cos(2 * math.pi * j / case.ny + ph[1])
+            idx = np.meshgrid(*(np.arange(n) for n in rho.shape), indexing="ij")
+            ph = rng.uniform(0, 2 * math.pi, rho.ndim)
+            nd = rho.ndim  # axis nd-1 is x; phases go x, y, z
+            k = 0.8 * np.sin(2 * math.pi * idx[nd - 1] / rho.shape[nd - 1] + ph[0])
+            for d in range(nd - 2, -1, -1):
+                k = k * np.cos(2 * math.pi * idx[d] / rho.shape[d] + ph[nd - 1 - d])
+            k = 1.0 + k
         elif mode == "double":
             k = rng.uniform(0.1, 2.0, rho.shape) if m == 0 else 2.0 * ks[0]
         else:
@@ -585,8 +590,8 @@ def add_scalars(case: "Case", ns: int, seed: int = 0, mode: str = "rough", value
         ks.append(k)
     c = dataclasses.replace(case)
     c.q0 = np.concatenate([case.q0, np.stack([rho * k for k in ks])]) if ns else case.q0.copy()
-    bcs = np.zeros((4, max(ns, 1)))
-    for sd in range(4):
+    bcs = np.zeros((nsides, max(ns, 1)))
+    for sd in range(nsides):
         for m in range(ns):
             kb = value if k_bc is None else k_bc[sd][m]
             if mode == "double" and m == 1 and k_bc is None:
@@ -615,6 +620,7 @@ class Case3:
     bc_state: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((6, 5)))
     nsteps: int = 1
     t_end: float = 0.0
+    bc_scalar: Optional[np.ndarray] = None  # [6 sides, nscalars] Dirichlet rho k_m
 
     @property
     def nz(self) -> int:
@@ -693,17 +699,25 @@ def rough_case3(nx: int, ny: int, nz: int, seed: int, bc=(PERIODIC,) * 6, **para
 
 def extrude(case2: "Case", nz: int, bc_z=(PERIODIC, PERIODIC)) -> Case3:
     """A 2-D case repeated along z (w = 0, unit dz): its 3-D solution is the
-    2-D one in every z-slice."""
+    2-D one in every z-slice.  Transported scalars ride along; Dirichlet z sides
+    take the (rho, rho u, rho v, 0, rho E) of the west side and its scalars."""
     q = case2.q0
-    q3 = np.stack([q[0], q[1], q[2], np.zeros_like(q[0]), q[3]])
-    q3 = np.ascontiguousarray(np.broadcast_to(q3[:, None], (5, nz) + q.shape[1:]))
+    ns = q.shape[0] - 4
+    q3 = np.stack([q[0], q[1], q[2], np.zeros_like(q[0]), q[3]] + [q[4 + m] for m in range(ns)])
+    q3 = np.ascontiguousarray(np.broadcast_to(q3[:, None], (5 + ns, nz) + q.shape[1:]))
     bcs = np.zeros((6, 5))
-    for s in range(4):
-        b = case2.bc_state[s]
+    for s in range(6):
+        b = case2.bc_state[s if s < 4 else 0]
         bcs[s] = (b[0], b[1], b[2], 0.0, b[3])
+    bsc = None
+    if ns:
+        bsc = np.zeros((6, ns))
+        if case2.bc_scalar is not None:
+            for s in range(6):
+                bsc[s] = case2.bc_scalar[s if s < 4 else 0][:ns]
     return Case3(name=case2.name + f"_x{nz}", q0=q3, params=dict(case2.params),
                  bc=tuple(case2.bc) + tuple(bc_z), dx=case2.dx, dy=case2.dy, dz=1.0, bc_state=bcs,
-                 nsteps=case2.nsteps, t_end=case2.t_end)
+                 nsteps=case2.nsteps, t_end=case2.t_end, bc_scalar=bsc)
 
 
 def vortex3(n: int = 64, nz: int = 16, mach: float = 0.01, **params) -> Case3:
