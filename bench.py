@@ -42,7 +42,8 @@ BYTES_PER_CELL_STAGE_3D = {1: 80.0, 2: 120.0, 3: 120.0}
 # The device code of the stage kernels: counter summaries taken on other
 # sources are stale.  (Host-side scheduling files are not part of the hash.)
 KERNEL_SOURCES = ("roeam_kernels.hip", "roeam_stage2d.hpp", "roeam_device.hpp", "roeam_stage.hpp")
-KERNEL_SOURCES_3D = ("roeam_kernels3d.hip", "roeam_device3d.hpp", "roeam_device.hpp", "roeam_stage.hpp")
+KERNEL_SOURCES_3D = ("roeam_kernels3d.hip", "roeam_stage3d.hpp", "roeam_device3d.hpp", "roeam_device.hpp",
+                     "roeam_stage.hpp")
 
 
 def is_3d(workload: str) -> bool:

@@ -268,8 +268,10 @@ roeam_status roeam_residual_norms(roeam_ctx *ctx, const roeam_grid *grid, const 
  * products of Eq. 109): state Q = (rho, rho u, rho v, rho w, rho E), cell
  * (i, j, l) = [i dx, (i+1) dx] x [j dy, (j+1) dy] x [l dz, (l+1) dz].
  *   - State arrays are device memory, FP64, structure of arrays:
- *     q[k][l][j][i] at q + ((k*nz + l)*ny + j)*pitch + i, k = 0..4; pad
- *     elements i >= nx are never read or written.
+ *     q[k][l][j][i] at q + ((k*nz + l)*ny + j)*pitch + i, k = 0..4 + nscalars
+ *     (rows rho, rho u, rho v, rho w, rho E, then the transported scalars rho k_m
+ *     of roeam_grid3d_set_scalars); pad elements i >= nx are never read or
+ *     written.
  *   - Boundary kinds as for 2-D grids, per side W, E, S, N, bottom (l < 0),
  *     top (l >= nz); ghost cells apply the x rule, then the y rule, then the
  *     z rule (edges and corners follow); a slip wall mirrors the cells and
@@ -296,11 +298,21 @@ roeam_status roeam_grid3d_create(roeam_ctx *ctx, int nx, int ny, int nz, double 
 roeam_status roeam_grid3d_destroy(roeam_grid3d *grid);
 /* Layout of state arrays: q[k][l][j][i] at ((k*nz + l)*ny + j)*pitch + i. */
 roeam_status roeam_grid3d_layout(const roeam_grid3d *grid, int *nx, int *ny, int *nz, long *pitch);
+/* Transported scalars on a 3-D grid: as roeam_grid_set_scalars (Eq. 85 with its
+ * rho k rows, here in three dimensions), state rows 5 .. 4 + nscalars;
+ * dirichlet_scalars: HOST array [6 sides][nscalars] of rho k_m (NULL allowed
+ * when no side is Dirichlet).  A change drops the grid's stage buffers and
+ * captured graphs (waiting for the context stream first).  EINVAL: nscalars
+ * outside 0..ROEAM_MAX_SCALARS, missing or non-finite Dirichlet scalars;
+ * EDEVICE. */
+roeam_status roeam_grid3d_set_scalars(roeam_grid3d *grid, int nscalars, const double *dirichlet_scalars);
 /* Brick shape of the 3-D stage kernel (cells per workgroup / threads):
  * 0 = 8x8x4/256, 1 = 8x4x4/128, 2 = 16x8x4/512, 3 = 16x4x4/256,
  * 4 = 8x8x4/320, 5 = 8x4x4/192, 6 = 16x8x4/640 (default), 7 = 8x8x8/576
  * (4-7: one thread per face of each direction).  Every shape computes bitwise the same
- * result.  EINVAL: shape outside 0..7. */
+ * result.  With two transported scalars the 16x8x4 bricks (2 and 6) exceed the
+ * LDS of a workgroup; such a grid runs shape 4 instead.  EINVAL: shape outside
+ * 0..7. */
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
 /* Residual R = dQ/dt = -(1/V) sum over the cell's six faces of F A (Eq. 85
  * per unit area times the face area).  q: device, 3-D state layout, read
@@ -318,7 +330,8 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *grid, const roeam_
                           long nsteps, double t0, double t_end, roeam_step_stats *stats);
 /* Wait for the grid's last roeam_step3d and read its statistics. */
 roeam_status roeam_last_stats3d(roeam_ctx *ctx, const roeam_grid3d *grid, roeam_step_stats *stats);
-/* roeam_residual_norms for a 3-D residual array (rows = 5, norms_out 10 doubles). */
+/* roeam_residual_norms for a 3-D residual array (rows = 5 + nscalars,
+ * norms_out 2 * rows doubles). */
 roeam_status roeam_residual_norms3d(roeam_ctx *ctx, const roeam_grid3d *grid, const double *r, double *norms_out);
 
 /* ------------------------------------------------------------------------ */

@@ -32,7 +32,7 @@ EXPORTS = [
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll", "roeam_batch_attach", "roeam_residual_norms",
     "roeam_residual_norms3d",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
-    "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
+    "roeam_grid3d_set_scalars", "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
 # 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
 SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256", "8x8x4/320", "8x4x4/192", "16x8x4/640",
@@ -122,6 +122,7 @@ def lib():
         "roeam_grid3d_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                     ctypes.POINTER(ctypes.c_long)]),
         "roeam_grid3d_set_tile_shape": (i, [vp, i]),
+        "roeam_grid3d_set_scalars": (i, [vp, i, vp]),
         "roeam_residual3d": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step3d": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
         "roeam_last_stats3d": (i, [vp, vp, ctypes.POINTER(StepStats)]),
@@ -355,7 +356,7 @@ def residual_norms(ctx: Context, grid, r):
     float64 device tensor [2, rows] (row 0: RMS, row 1: max)."""
     import torch
     three_d = isinstance(grid, Grid3)
-    rows = 5 if three_d else grid.rows
+    rows = grid.rows
     out = torch.zeros(2 * rows, dtype=torch.float64, device=f"cuda:{ctx.device}")
     rp = _dev_ptr3(r, grid) if three_d else _dev_ptr(r, grid)
     fn = lib().roeam_residual_norms3d if three_d else lib().roeam_residual_norms
@@ -498,8 +499,8 @@ def batch_poll(ctx: Context, ticket: int):
 # ---------------------------------------------------------------------------
 
 class Grid3:
-    """An immutable 3-D uniform Cartesian grid of the library; state tensors are
-    [5, nz, ny, pitch] (rho, rho u, rho v, rho w, rho E)."""
+    """A 3-D uniform Cartesian grid of the library; state tensors are
+    [5 + nsc, nz, ny, pitch] (rho, rho u, rho v, rho w, rho E, rho k_m)."""
 
     def __init__(self, ctx: Context, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
                  bc: Sequence[int] = (0,) * 6, bc_state: Optional[np.ndarray] = None):
@@ -518,14 +519,35 @@ class Grid3:
         a, b, c, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
         lib().roeam_grid3d_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p))
         self.nx, self.ny, self.nz, self.pitch = a.value, b.value, c.value, p.value
+        self.nsc = 0
 
     @classmethod
     def from_case(cls, ctx: Context, case) -> "Grid3":
-        return cls(ctx, case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, bc=case.bc, bc_state=case.bc_state)
+        g = cls(ctx, case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, bc=case.bc, bc_state=case.bc_state)
+        ns = case.q0.shape[0] - 5
+        if ns:
+            g.set_scalars(ns, getattr(case, "bc_scalar", None))
+        return g
+
+    def set_scalars(self, nscalars: int, bc_scalar: Optional[np.ndarray] = None):
+        """Carry nscalars transported scalars (state rows 5..); bc_scalar: [6 sides, nscalars]
+        Dirichlet rho k_m."""
+        arg = None
+        if bc_scalar is not None and nscalars:
+            sa = np.ascontiguousarray(np.asarray(bc_scalar, dtype=np.float64)[:, :nscalars]).reshape(-1)
+            self._keep.append(sa)
+            arg = ctypes.c_void_p(sa.ctypes.data)
+        self.ctx.check(lib().roeam_grid3d_set_scalars(self.h, int(nscalars), arg))
+        self.nsc = int(nscalars)
+
+    @property
+    def rows(self) -> int:
+        return 5 + self.nsc
 
     def empty_state(self):
         import torch
-        return torch.zeros((5, self.nz, self.ny, self.pitch), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        return torch.zeros((self.rows, self.nz, self.ny, self.pitch), dtype=torch.float64,
+                           device=f"cuda:{self.ctx.device}")
 
     def to_device(self, q: np.ndarray):
         import torch
@@ -555,13 +577,13 @@ class Grid3:
 def _dev_ptr3(t, grid: Grid3) -> ctypes.c_void_p:
     import torch
     assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
-    shape = (5, grid.nz, grid.ny, grid.pitch)
+    shape = (grid.rows, grid.nz, grid.ny, grid.pitch)
     assert tuple(t.shape) == shape, (tuple(t.shape), shape)
     return ctypes.c_void_p(t.data_ptr())
 
 
 def residual3(ctx: Context, grid: Grid3, prm: Dict, q, r=None, rate_out=None):
-    """R = dQ/dt of the 3-D state tensor q (device, [5, nz, ny, pitch]); returns r.
+    """R = dQ/dt of the 3-D state tensor q (device, [rows, nz, ny, pitch]); returns r.
     rate_out: optional 1-element float64 device tensor for the max explicit rate."""
     if r is None:
         r = grid.empty_state()

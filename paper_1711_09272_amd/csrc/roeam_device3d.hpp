@@ -1,7 +1,7 @@
 // roeam_device3d.hpp -- device-side building blocks of the 3-D Roe-AM path on
 // uniform Cartesian grids: solve descriptor, boundary-mapped cell fetch, the
 // Roe-AM flux of Eqs. (85)-(109) with five conserved rows and the 3-D time-step
-// rule.
+// rule, and the transported scalars (rows rho k_m) of Eq. (85).
 //
 // The flux is evaluated in the frame of its face: a face normal to axis a
 // takes the velocity components in the cyclic order (normal, next, next but
@@ -30,6 +30,8 @@ struct DevSolve3 {
     unsigned variant;
     double *q, *qa, *qb;
     Slot *slot;
+    int nsc;                         // transported scalars, rows 5 .. 4 + nsc
+    double bck[6][kMaxScalars];      // Dirichlet scalars, primitive k_m
 };
 
 // Primitives (rho, u, v, w, p) of a conserved state; returns 1/rho.
@@ -46,14 +48,27 @@ __device__ __forceinline__ double to_prim3(double gm1, const double Q[5], double
     return ir;
 }
 
+// Primitives of cell (i, j, l) and, for NSC transported scalars, k_m = (rho k_m) / rho.
+template <int NSC = 0>
 __device__ __forceinline__ void load_prim3(const DevSolve3 &S, const double *__restrict__ q, int i, int j, int l,
-                                           double W[5])
+                                           double *W)
 {
     const long long idx = (long long)l * S.slab + (long long)j * S.pitch + i;
     double Q[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) Q[k] = q[k * S.plane + idx];
-    to_prim3(S.gm1, Q, W);
+    const double ir = to_prim3(S.gm1, Q, W);
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) W[5 + m] = q[(5 + m) * S.plane + idx] * ir;
+}
+
+template <int NSC>
+__device__ __forceinline__ void dirichlet3(const DevSolve3 &S, int side, double *W)
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) W[k] = S.bcw[side][k];
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) W[5 + m] = S.bck[side][m];
 }
 
 // Interior index of a ghost cell at position i (< 0 or >= n) of a side of kind
@@ -68,48 +83,48 @@ __device__ __forceinline__ int ghost_source(int kind, int i, int n)
 // Primitive state of any cell within two layers of the grid.  The x rule, then
 // the y rule, then the z rule (which also define edges and corners); a slip
 // wall mirrors the cell and negates the velocity component normal to it.
+template <int NSC = 0>
 __device__ __forceinline__ void fetch_prim3_x(const DevSolve3 &S, const double *__restrict__ q, int i, int j, int l,
-                                              double W[5])
+                                              double *W)
 {
-    if (i >= 0 && i < S.nx) { load_prim3(S, q, i, j, l, W); return; }
+    if (i >= 0 && i < S.nx) { load_prim3<NSC>(S, q, i, j, l, W); return; }
     const bool lo = i < 0;
     const int kind = lo ? S.bc[SIDE3_W] : S.bc[SIDE3_E];
     if (kind == BC_DIRICHLET) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) W[k] = lo ? S.bcw[SIDE3_W][k] : S.bcw[SIDE3_E][k];
+        dirichlet3<NSC>(S, lo ? SIDE3_W : SIDE3_E, W);
         return;
     }
-    load_prim3(S, q, ghost_source(kind, i, S.nx), j, l, W);
+    load_prim3<NSC>(S, q, ghost_source(kind, i, S.nx), j, l, W);
     if (kind == BC_SLIPWALL) W[1] = -W[1];
 }
 
+template <int NSC = 0>
 __device__ __forceinline__ void fetch_prim3_y(const DevSolve3 &S, const double *__restrict__ q, int i, int j, int l,
-                                              double W[5])
+                                              double *W)
 {
-    if (j >= 0 && j < S.ny) { fetch_prim3_x(S, q, i, j, l, W); return; }
+    if (j >= 0 && j < S.ny) { fetch_prim3_x<NSC>(S, q, i, j, l, W); return; }
     const bool lo = j < 0;
     const int kind = lo ? S.bc[SIDE3_S] : S.bc[SIDE3_N];
     if (kind == BC_DIRICHLET) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) W[k] = lo ? S.bcw[SIDE3_S][k] : S.bcw[SIDE3_N][k];
+        dirichlet3<NSC>(S, lo ? SIDE3_S : SIDE3_N, W);
         return;
     }
-    fetch_prim3_x(S, q, i, ghost_source(kind, j, S.ny), l, W);
+    fetch_prim3_x<NSC>(S, q, i, ghost_source(kind, j, S.ny), l, W);
     if (kind == BC_SLIPWALL) W[2] = -W[2];
 }
 
+template <int NSC = 0>
 __device__ __forceinline__ void fetch_prim3(const DevSolve3 &S, const double *__restrict__ q, int i, int j, int l,
-                                            double W[5])
+                                            double *W)
 {
-    if (l >= 0 && l < S.nz) { fetch_prim3_y(S, q, i, j, l, W); return; }
+    if (l >= 0 && l < S.nz) { fetch_prim3_y<NSC>(S, q, i, j, l, W); return; }
     const bool lo = l < 0;
     const int kind = lo ? S.bc[SIDE3_B] : S.bc[SIDE3_T];
     if (kind == BC_DIRICHLET) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) W[k] = lo ? S.bcw[SIDE3_B][k] : S.bcw[SIDE3_T][k];
+        dirichlet3<NSC>(S, lo ? SIDE3_B : SIDE3_T, W);
         return;
     }
-    fetch_prim3_y(S, q, i, j, ghost_source(kind, l, S.nz), W);
+    fetch_prim3_y<NSC>(S, q, i, j, ghost_source(kind, l, S.nz), W);
     if (kind == BC_SLIPWALL) W[3] = -W[3];
 }
 
@@ -117,8 +132,8 @@ __device__ __forceinline__ void fetch_prim3(const DevSolve3 &S, const double *__
 // Classical Roe flux, Eq. (7) with Eqs. (8)-(12) and Harten's fix of
 // Eqs. (114)-(115), in the face frame (n = e_1; W = rho, u_n, u_t1, u_t2, p).
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void roe_classic3(const DevSolve3 &S, const double WL[5], const double WR[5], double F[5])
+template <typename R, int NSC = 0>
+__device__ __forceinline__ void roe_classic3(const DevSolve3 &S, const double *WL, const double *WR, double *F)
 {
     const double rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
     const double rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
@@ -163,6 +178,14 @@ __device__ __forceinline__ void roe_classic3(const DevSolve3 &S, const double WL
     F[2] = 0.5 * (uL * PL2 + uR * PR2) - 0.5 * (xid * (PR2 - PL2) + Ud * (rhod * (double)v));
     F[3] = 0.5 * (uL * PL3 + uR * PR3) - 0.5 * (xid * (PR3 - PL3) + Ud * (rhod * (double)w));
     F[4] = 0.5 * (uL * (rL * HL) + uR * (rR * HR)) - 0.5 * (xid * (rER - rEL) + pd * (double)U + Ud * (rhod * (double)H));
+    // transported scalars: xi Delta(rho k) + (dU_u + dU_p) rho^ k^, no pressure term
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) {
+        const double kL = WL[5 + m], kR = WR[5 + m];
+        const double PL = rL * kL, PR = rR * kR;
+        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
+        F[5 + m] = 0.5 * (uL * PL + uR * PR) - 0.5 * (xid * (PR - PL) + Ud * (rhod * khat));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -170,12 +193,12 @@ __device__ __forceinline__ void roe_classic3(const DevSolve3 &S, const double WL
 // the precision of the dissipation coefficients; the side quantities, the
 // central term, the jumps of Eq. (85) and the assembly stay FP64.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double WL[5], const double WR[5], double s1d,
-                                            double F[5])
+template <typename R, int NSC = 0>
+__device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL, const double *WR, double s1d,
+                                            double *F)
 {
     if (__builtin_expect(S.scheme != SCHEME_ROEAM, 0)) {
-        roe_classic3<R>(S, WL, WR, F);
+        roe_classic3<R, NSC>(S, WL, WR, F);
         return;
     }
     const double rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
@@ -280,6 +303,14 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double WL[
     F[2] = 0.5 * (uL * PL2 + uR * PR2) - 0.5 * (xid * (PR2 - PL2) + dUpd * (rhod * (double)v) + dUud * (PR2 + PL2));
     F[3] = 0.5 * (uL * PL3 + uR * PR3) - 0.5 * (xid * (PR3 - PL3) + dUpd * (rhod * (double)w) + dUud * (PR3 + PL3));
     F[4] = 0.5 * (uL * PL4 + uR * PR4) - 0.5 * (xid * (PR4 - PL4) + dUpd * (rhod * (double)H) + dUud * (PR4 + PL4));
+    // transported scalars: Psi = rho k, Psi^ = rho^ k^ (Roe average of k), no pressure term
+#pragma unroll
+    for (int m = 0; m < NSC; ++m) {
+        const double kL = WL[5 + m], kR = WR[5 + m];
+        const double PL = rL * kL, PR = rR * kR;
+        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
+        F[5 + m] = 0.5 * (uL * PL + uR * PR) - 0.5 * (xid * (PR - PL) + dUpd * (rhod * khat) + dUud * (PR + PL));
+    }
 }
 
 // Explicit rate of one cell: ((|u| + ce) A_x + (|v| + ce) A_y + (|w| + ce) A_z) / V,

@@ -40,7 +40,7 @@ hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
 hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
-// RMS and max |.| per row of r[k][line][pitch] (rows 4..6, nx valid per line)
+// RMS and max |.| per row of r[k][line][pitch] (rows 4..7, nx valid per line)
 // into out[2 rows]; part: scratch of 2 rows doubles per block, max_blocks blocks.
 constexpr int kNormMaxBlocks = 1024;
 hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int nlines, long long pitch, double *part,
@@ -48,6 +48,11 @@ hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int 
 
 // 3-D uniform Cartesian grids (brick shapes 0..brick_shape_count()-1).
 int brick_shape_count();
+// Whether a brick shape's stage kernel fits the LDS of a workgroup for the given
+// MUSCL order and scalar count (16x8x4 bricks do not with two scalars).
+bool brick_shape_fits(int shape, int order, int nsc);
+hipError_t launch_stage3_sc(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last,
+                            double *r_out, hipStream_t st);
 hipError_t launch_stage3(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last, double *r_out,
                          hipStream_t st);
 hipError_t launch_rate3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);

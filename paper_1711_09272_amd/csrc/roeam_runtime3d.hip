@@ -29,7 +29,17 @@ struct roeam_grid3d {
     int shape = 6;                    // 16x8x4 bricks, one thread per face (fastest measured on 128^3)
     double *d_norm_part = nullptr;    // scratch of roeam_residual_norms3d
     int final_parity = 0;
+    int nsc = 0;                      // transported scalars (rows 5 .. 4 + nsc of q)
+    double bcs[6][roeam::kMaxScalars] = {}; // Dirichlet rho k_m per side
 };
+
+// Brick shape the stage kernel runs with: the grid's, or 8x8x4 bricks with 320
+// threads where the grid's does not fit the LDS with its scalars.
+constexpr int kFallbackShape3 = 4;
+static int stage_shape3(const roeam_grid3d *g, int order)
+{
+    return roeam::brick_shape_fits(g->shape, order, g->nsc) ? g->shape : kFallbackShape3;
+}
 
 static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg) { return roeam_fail(ctx, st, msg); }
 
@@ -88,6 +98,10 @@ static DevSolve3 make_solve3(const roeam_grid3d *g, const roeam_params *p, doubl
     S.qa = g->d_qa;
     S.qb = g->d_qb;
     S.slot = g->d_slot;
+    S.nsc = g->nsc;
+    for (int s = 0; s < 6; ++s)
+        if (g->bc[s] == ROEAM_BC_DIRICHLET)
+            for (int m = 0; m < g->nsc; ++m) S.bck[s][m] = g->bcs[s][m] / g->bcq[s][0];
     return S;
 }
 
@@ -108,7 +122,7 @@ static hipError_t upload_solve3(roeam_grid3d *g, const DevSolve3 &S, hipStream_t
 static roeam_status ensure_stage_buffers3(roeam_ctx *ctx, roeam_grid3d *g)
 {
     if (g->d_qa && g->d_qb) return ROEAM_OK;
-    const size_t bytes = sizeof(double) * 5 * (size_t)g->nz * (size_t)g->ny * (size_t)g->pitch;
+    const size_t bytes = sizeof(double) * (5 + (size_t)g->nsc) * (size_t)g->nz * (size_t)g->ny * (size_t)g->pitch;
     hipError_t e = g->d_qa ? hipSuccess : hipMalloc(&g->d_qa, bytes);
     if (e == hipSuccess && !g->d_qb) e = hipMalloc(&g->d_qb, bytes);
     if (e != hipSuccess)
@@ -123,15 +137,16 @@ static roeam_status ensure_stage_buffers3(roeam_ctx *ctx, roeam_grid3d *g)
 static hipError_t enqueue_step3(const roeam_grid3d *g, const DevSolve3 &S, int time_scheme, int p, hipStream_t st)
 {
     const DevSolve3 *d = g->d_solve;
+    const int shape = stage_shape3(g, S.order);
     if (time_scheme == 0) {
-        hipError_t e = roeam::launch_stage3(d, S, g->shape, 1, p, 1, nullptr, st);
+        hipError_t e = roeam::launch_stage3(d, S, shape, 1, p, 1, nullptr, st);
         if (e == hipSuccess) e = roeam::launch_copy_back3(d, S, p, st);
         return e;
     }
     const int first = time_scheme == 1 ? 1 : 4, nst = time_scheme == 1 ? 3 : 4;
     hipError_t e = hipSuccess;
     for (int k = 0; k < nst && e == hipSuccess; ++k)
-        e = roeam::launch_stage3(d, S, g->shape, first + k, p, k == nst - 1 ? 1 : 0, nullptr, st);
+        e = roeam::launch_stage3(d, S, shape, first + k, p, k == nst - 1 ? 1 : 0, nullptr, st);
     return e;
 }
 
@@ -227,6 +242,36 @@ roeam_status roeam_grid3d_layout(const roeam_grid3d *g, int *nx, int *ny, int *n
     return ROEAM_OK;
 }
 
+roeam_status roeam_grid3d_set_scalars(roeam_grid3d *g, int nscalars, const double *dirichlet_scalars)
+{
+    if (!g) return ROEAM_EINVAL;
+    roeam_ctx *ctx = g->ctx;
+    if (nscalars < 0 || nscalars > ROEAM_MAX_SCALARS)
+        return fail(ctx, ROEAM_EINVAL, "nscalars must be 0 .. ROEAM_MAX_SCALARS");
+    bool need = false;
+    for (int s = 0; s < 6; ++s) need |= g->bc[s] == ROEAM_BC_DIRICHLET;
+    if (need && nscalars > 0 && !dirichlet_scalars) return fail(ctx, ROEAM_EINVAL, "Dirichlet side without scalars");
+    for (int s = 0; s < 6 && need; ++s)
+        for (int m = 0; m < nscalars; ++m)
+            if (g->bc[s] == ROEAM_BC_DIRICHLET && !std::isfinite(dirichlet_scalars[s * nscalars + m]))
+                return fail(ctx, ROEAM_EINVAL, "non-finite Dirichlet scalar");
+    // work queued on the stage buffers may still run: wait before replacing them
+    if (g->nsc != nscalars && (g->d_qa || g->d_qb)) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+        if (g->d_qa) (void)hipFree(g->d_qa);
+        if (g->d_qb) (void)hipFree(g->d_qb);
+        g->d_qa = g->d_qb = nullptr;
+    }
+    g->nsc = nscalars;
+    for (int s = 0; s < 6; ++s)
+        for (int m = 0; m < roeam::kMaxScalars; ++m)
+            g->bcs[s][m] = (m < nscalars && g->bc[s] == ROEAM_BC_DIRICHLET) ? dirichlet_scalars[s * nscalars + m] : 0.0;
+    g->gc.release();
+    g->solve_valid = false;
+    return ROEAM_OK;
+}
+
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *g, int shape)
 {
     if (!g || shape < 0 || shape >= roeam::brick_shape_count()) return ROEAM_EINVAL;
@@ -248,7 +293,7 @@ roeam_status roeam_residual3d(roeam_ctx *ctx, const roeam_grid3d *gc, const roea
     hipStream_t s = ctx->stream;
     HIP_OK(ctx, upload_solve3(g, S, s));
     if (max_rate_out) HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 0, s));
-    HIP_OK(ctx, roeam::launch_stage3(g->d_solve, S, g->shape, 0, 0, max_rate_out ? 1 : 0, r, s));
+    HIP_OK(ctx, roeam::launch_stage3(g->d_solve, S, stage_shape3(g, p->order), 0, 0, max_rate_out ? 1 : 0, r, s));
     if (max_rate_out) HIP_OK(ctx, roeam::launch_rate_out(g->d_slot, max_rate_out, s));
     return ROEAM_OK;
 }
@@ -282,7 +327,7 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *gc, const roeam_pa
         int chunk = (int)(nsteps < kStepsPerGraph ? nsteps : kStepsPerGraph);
         chunk += chunk & 1;
         GraphCache &G = g->gc;
-        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || G.shape != g->shape ||
+        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || G.shape != stage_shape3(g, p->order) ||
             std::memcmp(&G.params, p, sizeof *p) != 0) {
             G.release();
             HIP_OK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
@@ -298,7 +343,7 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *gc, const roeam_pa
             G.q = q;
             G.stream = s;
             G.chunk = chunk;
-            G.shape = g->shape;
+            G.shape = stage_shape3(g, p->order);
             G.params = *p;
         }
         const long launches = (nsteps + chunk - 1) / chunk;
@@ -324,8 +369,9 @@ roeam_status roeam_residual_norms3d(roeam_ctx *ctx, const roeam_grid3d *gc, cons
     if (gc->ctx != ctx) return fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
     roeam_grid3d *g = const_cast<roeam_grid3d *>(gc);
     HIP_OK(ctx, hipSetDevice(ctx->device));
-    if (!g->d_norm_part) HIP_OK(ctx, hipMalloc(&g->d_norm_part, sizeof(double) * 2 * 5 * roeam::kNormMaxBlocks));
-    HIP_OK(ctx, roeam::launch_norms(r, 5, (long long)g->nz * g->ny * g->pitch, g->nx, g->ny * g->nz, g->pitch,
+    if (!g->d_norm_part)
+        HIP_OK(ctx, hipMalloc(&g->d_norm_part, sizeof(double) * 2 * (5 + roeam::kMaxScalars) * roeam::kNormMaxBlocks));
+    HIP_OK(ctx, roeam::launch_norms(r, 5 + g->nsc, (long long)g->nz * g->ny * g->pitch, g->nx, g->ny * g->nz, g->pitch,
                                     g->d_norm_part, roeam::kNormMaxBlocks, norms_out, ctx->stream));
     return ROEAM_OK;
 }

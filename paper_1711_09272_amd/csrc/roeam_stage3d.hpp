@@ -1,0 +1,385 @@
+// roeam_stage3d.hpp -- the 3-D stage kernel as templates over the MUSCL order,
+// the coefficient precision, the number of transported scalars and the brick
+// shape; roeam_kernels3d.hip instantiates the scalar-free kernels,
+// roeam_kernels3d_sc.hip those with one or two scalars.
+//
+// A workgroup owns a brick of TX x TY x TZ cells.  It stages the brick and its
+// halo (two layers for MUSCL, one for piecewise-constant states) as primitives
+// in LDS, builds the detector ratio of Eq. (97) of every face within one layer
+// of the brick, then sweeps the x-, y- and z-faces in turn through one LDS flux
+// buffer, each face evaluated exactly once (Eq. 85, nine-face detector of
+// Eq. 96), accumulates the conservative residual of its cells in registers and
+// applies the stage update, the positivity check and the explicit-rate
+// reduction exactly as the 2-D stage kernel does (same stage codes, same step
+// state).  One kernel per Runge-Kutta stage.
+#pragma once
+
+#include <type_traits>
+
+#include "roeam_device3d.hpp"
+#include "roeam_internal.hpp"
+#include "roeam_stage.hpp"
+
+namespace roeam {
+
+template <int TX, int TY, int TZ, int HL>
+struct Brick {
+    static constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL, LZ = TZ + 2 * HL;
+    // detector ratios: x-faces (TX+1) x (TY+2) x (TZ+2), y-faces (TX+2) x (TY+1) x (TZ+2),
+    // z-faces (TX+2) x (TY+2) x (TZ+1), i.e. every face within one cell layer of the brick
+    static constexpr int NPX = (TZ + 2) * (TY + 2) * (TX + 1);
+    static constexpr int NPY = (TZ + 2) * (TY + 1) * (TX + 2);
+    static constexpr int NPZ = (TZ + 1) * (TY + 2) * (TX + 2);
+    static constexpr int NFX = TZ * TY * (TX + 1), NFY = TZ * (TY + 1) * TX, NFZ = (TZ + 1) * TY * TX;
+    static constexpr int NFB = NFX > NFY ? (NFX > NFZ ? NFX : NFZ) : (NFY > NFZ ? NFY : NFZ);
+    static constexpr int PL = LX * LY * LZ;  // one row of the LDS primitives
+    // LDS offset of brick cell (i, j, l), -HL <= i < TX + HL etc.
+    static __device__ __forceinline__ int cell(int i, int j, int l) { return ((l + HL) * LY + (j + HL)) * LX + i + HL; }
+    // ratio of the x-face at fi (0..TX) in row (j, l), j, l in -1..TY / -1..TZ
+    static __device__ __forceinline__ int px(int fi, int j, int l) { return ((l + 1) * (TY + 2) + j + 1) * (TX + 1) + fi; }
+    static __device__ __forceinline__ int py(int i, int fj, int l) { return NPX + ((l + 1) * (TY + 1) + fj) * (TX + 2) + i + 1; }
+    static __device__ __forceinline__ int pz(int i, int j, int fl) { return NPX + NPY + (fl * (TY + 2) + j + 1) * (TX + 2) + i + 1; }
+};
+
+// Detector minimum of Eq. (96) for the face of axis AXIS whose upper cell is
+// brick cell (i, j, l): the face itself and, in each transverse direction, the
+// two faces of each of its two cells.
+template <int AXIS, class B>
+__device__ __forceinline__ double face_detector(const double *__restrict__ sP, int i, int j, int l)
+{
+    if (AXIS == 0) {
+        return rmin(rmin(rmin(sP[B::px(i, j, l)], sP[B::py(i - 1, j, l)]),
+                         rmin(sP[B::py(i - 1, j + 1, l)], sP[B::py(i, j, l)])),
+                    rmin(rmin(sP[B::py(i, j + 1, l)], sP[B::pz(i - 1, j, l)]),
+                         rmin(sP[B::pz(i - 1, j, l + 1)], rmin(sP[B::pz(i, j, l)], sP[B::pz(i, j, l + 1)]))));
+    } else if (AXIS == 1) {
+        return rmin(rmin(rmin(sP[B::py(i, j, l)], sP[B::px(i, j - 1, l)]),
+                         rmin(sP[B::px(i + 1, j - 1, l)], sP[B::px(i, j, l)])),
+                    rmin(rmin(sP[B::px(i + 1, j, l)], sP[B::pz(i, j - 1, l)]),
+                         rmin(sP[B::pz(i, j - 1, l + 1)], rmin(sP[B::pz(i, j, l)], sP[B::pz(i, j, l + 1)]))));
+    } else {
+        return rmin(rmin(rmin(sP[B::pz(i, j, l)], sP[B::px(i, j, l - 1)]),
+                         rmin(sP[B::px(i + 1, j, l - 1)], sP[B::px(i, j, l)])),
+                    rmin(rmin(sP[B::px(i + 1, j, l)], sP[B::py(i, j, l - 1)]),
+                         rmin(sP[B::py(i, j + 1, l - 1)], rmin(sP[B::py(i, j, l)], sP[B::py(i, j + 1, l)]))));
+    }
+}
+
+// Flux times area of the face of axis AXIS whose upper cell is brick cell
+// (i, j, l), rows in global order (rho, rho u, rho v, rho w, rho E, rho k_m).
+template <int ORDER, int PREC, int AXIS, int NSC, class B>
+__device__ __forceinline__ void brick_face(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
+                                           int i, int j, int l, double *F)
+{
+    constexpr int NR = 5 + NSC;
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    constexpr int PL = B::LX * B::LY * B::LZ;                     // one row of sW
+    constexpr int ST = AXIS == 0 ? 1 : (AXIS == 1 ? B::LX : B::LX * B::LY);
+    // face frame: rho, normal velocity, the two others in cyclic order, p
+    constexpr int RN = 1 + AXIS, RT1 = 1 + (AXIS + 1) % 3, RT2 = 1 + (AXIS + 2) % 3;
+    const int c = B::cell(i, j, l);
+    double WL[NR], WR[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int row = k == 1 ? RN : (k == 2 ? RT1 : (k == 3 ? RT2 : k));
+        const double *r = sW + row * PL;
+        const double m1 = r[c - ST], p0 = r[c];
+        if (ORDER == 1) {
+            WL[k] = m1;
+            WR[k] = p0;
+        } else {
+            const double m2 = r[c - 2 * ST], p1 = r[c + ST];
+            const double d1 = p0 - m1;
+            WL[k] = m1 + 0.5 * minmod(m1 - m2, d1);
+            WR[k] = p0 - 0.5 * minmod(d1, p1 - p0);
+        }
+    }
+    double s1 = 1.0;
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) s1 = pow8(fswitch(face_detector<AXIS, B>(sP, i, j, l)));
+    double Ff[NR];
+    roeam_flux3<R, NSC>(S, WL, WR, s1, Ff);
+    const double area = AXIS == 0 ? S.ax : (AXIS == 1 ? S.ay : S.az);
+    F[0] = Ff[0] * area;
+    F[RN] = Ff[1] * area;
+    F[RT1] = Ff[2] * area;
+    F[RT2] = Ff[3] * area;
+#pragma unroll
+    for (int k = 4; k < NR; ++k) F[k] = Ff[k] * area;
+}
+
+// All faces of one axis into sF, then add their differences to the cells'
+// residual sums d (in registers).  The caller separates the sweeps by barriers.
+template <int ORDER, int PREC, int AXIS, int NSC, int TX, int TY, int TZ, int NT, class B>
+__device__ __forceinline__ void sweep_axis(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
+                                           double (&sF)[5 + NSC][B::NFB], int i0, int j0, int l0, double (*d)[5 + NSC])
+{
+    constexpr int NR = 5 + NSC;
+    constexpr int FX = TX + (AXIS == 0), FY = TY + (AXIS == 1), FZ = TZ + (AXIS == 2);
+    constexpr int NF = FX * FY * FZ;
+    constexpr int CPT = (TX * TY * TZ + NT - 1) / NT;
+    for (int f = threadIdx.x; f < NF; f += NT) {
+        const int i = f % FX, r = f / FX, j = r % FY, l = r / FY;
+        // the face lies on the grid (a face at index n of its axis is the upper boundary)
+        if (i0 + i > S.nx - (AXIS != 0) || j0 + j > S.ny - (AXIS != 1) || l0 + l > S.nz - (AXIS != 2)) continue;
+        double F[NR];
+        brick_face<ORDER, PREC, AXIS, NSC, B>(S, sW, sP, i, j, l, F);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sF[k][f] = F[k];
+    }
+    __syncthreads();
+    constexpr int up = AXIS == 0 ? 1 : (AXIS == 1 ? FX : FX * FY);
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = threadIdx.x + m * NT;
+        if (c >= TX * TY * TZ) continue;
+        const int ci = c % TX, r = c / TX, cj = r % TY, cl = r / TY;
+        const int lo = (cl * FY + cj) * FX + ci;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double df = sF[k][lo + up] - sF[k][lo];
+            d[m][k] = AXIS == 0 ? df : d[m][k] + df;
+        }
+    }
+    __syncthreads();
+}
+
+// Stage codes, buffers and step logic as in the 2-D stage kernel:
+//   0 residual only; 1 forward Euler / first SSP-RK3 stage (q -> qa);
+//   2 (qa -> qb, + Q^n), 3 (qb -> q, + Q^n); 4-7 the four-stage scheme
+//   (q -> qa, qa -> qb, qb -> qa, qa -> q; + Q^n from the second on).
+// Transported scalars (NSC rows after rho E) ride along every step; the
+// positivity check and the rate read the flow rows only.
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, int bz, int stage, int p, int last,
+                                            int first_block, double *__restrict__ r_out)
+{
+    constexpr int HL = ORDER;
+    using B = Brick<TX, TY, TZ, HL>;
+    constexpr int NC = TX * TY * TZ;
+    constexpr int CPT = (NC + NT - 1) / NT;
+    constexpr int PL = B::PL;
+    constexpr int NR = 5 + NSC;
+    __shared__ double sW[NR * PL];
+    __shared__ double sP[B::NPX + B::NPY + B::NPZ];
+    __shared__ double sF[NR][B::NFB];
+    __shared__ double sRed[NT / 64];
+
+    const int tid = threadIdx.x;
+    const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
+    const bool reads_qn = stage >= 2 && stage != 4;
+    const int i0 = bx * TX, j0 = by * TY, l0 = bz * TZ;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+
+    // own cells' stage input (and Q^n) first, so their latency hides behind the face work
+    double Qs[CPT][NR], Q0[CPT][NR];
+    long long cidx[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * NT;
+        const int ci = c % TX, r = c / TX, cj = r % TY, cl = r / TY;
+        const bool ok = c < NC && i0 + ci < nx && j0 + cj < ny && l0 + cl < nz;
+        cidx[m] = ok ? (long long)(l0 + cl) * S.slab + (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
+        if (stage > 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
+        }
+        if (reads_qn) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
+        }
+    }
+
+    Slot &z = *S.slot;
+    double dt = 0.0;
+    if (stage > 0 && !begin_stage(z, p, stage, last, first_block, dt)) return;
+
+    // 1. brick + halo -> primitives in LDS
+    const bool interior = i0 - HL >= 0 && i0 + TX + HL <= nx && j0 - HL >= 0 && j0 + TY + HL <= ny && l0 - HL >= 0 &&
+                          l0 + TZ + HL <= nz;
+    constexpr int NLOAD = (PL + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < NLOAD; ++it) {
+        const int e = tid + it * NT;
+        if (e >= PL) break;
+        const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
+        int gi = i0 - HL + lx, gj = j0 - HL + ly, gl = l0 - HL + lz;
+        double W[NR];
+        if (interior) {
+            load_prim3<NSC>(S, qin, gi, gj, gl, W);
+        } else {
+            // cells past the ghost layers of a ragged brick feed no face on the grid
+            gi = gi > nx + 1 ? nx + 1 : gi;
+            gj = gj > ny + 1 ? ny + 1 : gj;
+            gl = gl > nz + 1 ? nz + 1 : gl;
+            fetch_prim3<NSC>(S, qin, gi, gj, gl, W);
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sW[k * PL + e] = W[k];
+    }
+    __syncthreads();
+
+    // 2. detector ratios, Eq. (97), of every face within one layer of the brick
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
+        for (int e = tid; e < B::NPX + B::NPY + B::NPZ; e += NT) {
+            int a, st;  // LDS offset of the lower cell, stride to the upper one
+            if (e < B::NPX) {
+                const int fi = e % (TX + 1), r = e / (TX + 1), j = r % (TY + 2) - 1, l = r / (TY + 2) - 1;
+                a = B::cell(fi - 1, j, l);
+                st = 1;
+            } else if (e < B::NPX + B::NPY) {
+                const int f = e - B::NPX;
+                const int i = f % (TX + 2) - 1, r = f / (TX + 2), fj = r % (TY + 1), l = r / (TY + 1) - 1;
+                a = B::cell(i, fj - 1, l);
+                st = B::LX;
+            } else {
+                const int f = e - B::NPX - B::NPY;
+                const int i = f % (TX + 2) - 1, r = f / (TX + 2), j = r % (TY + 2) - 1, fl = r / (TY + 2);
+                a = B::cell(i, j, fl - 1);
+                st = B::LX * B::LY;
+            }
+            const double *p4 = sW + 4 * PL;
+            sP[e] = detector_P(p4[a], sW[a], p4[a + st], sW[a + st]);
+        }
+        __syncthreads();
+    }
+
+    // 3. x-, y- and z-faces, each exactly once; residual sums ((x) + (y)) + (z)
+    double d[CPT][NR];
+    sweep_axis<ORDER, PREC, 0, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
+    sweep_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
+    sweep_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
+
+    // 4. R = -(sum of face fluxes times areas) / V and the stage update
+    double lmax = 0.0;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int c = tid + m * NT;
+        const int ci = c % TX, r = c / TX, cj = r % TY, cl = r / TY;
+        if (c >= NC || i0 + ci >= nx || j0 + cj >= ny || l0 + cl >= nz) continue;
+        double Rv[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) Rv[k] = -d[m][k] * S.inv_vol;
+        const long long idx = cidx[m];
+        if (stage == 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) r_out[k * S.plane + idx] = Rv[k];
+            if (last) {
+                const int o = B::cell(ci, cj, cl);
+                double W[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) W[k] = sW[k * PL + o];
+                lmax = rmax(lmax, cell_rate3(S, W, rcp_nr(W[0])));
+            }
+            continue;
+        }
+        double Qn[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            switch (stage) {
+            case 1: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
+            case 2: Qn[k] = 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k]); break;
+            case 3: Qn[k] = (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]); break;
+            case 4: Qn[k] = Qs[m][k] + (0.25 * dt) * Rv[k]; break;
+            case 5: Qn[k] = Q0[m][k] + ((1.0 / 3.0) * dt) * Rv[k]; break;
+            case 6: Qn[k] = Q0[m][k] + (0.5 * dt) * Rv[k]; break;
+            default: Qn[k] = Q0[m][k] + dt * Rv[k]; break;
+            }
+        }
+        double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) qo[k * S.plane + idx] = Qn[k];
+        double W[5];
+        const double ir = to_prim3(S.gm1, Qn, W);
+        if (!physical3(W)) atomicOr(&z.nonphys, 1);
+        else if (last) lmax = rmax(lmax, cell_rate3(S, W, ir));
+    }
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, sRed);
+}
+
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void k_stage3(const DevSolve3 *__restrict__ Sp, int stage, int p, int last, double *r_out)
+{
+    const DevSolve3 &S = *Sp;
+    const int bxs = (S.nx + TX - 1) / TX, bys = (S.ny + TY - 1) / TY, bzs = (S.nz + TZ - 1) / TZ;
+    const int nb = bxs * bys * bzs;
+    const int t = xcd_tile(blockIdx.x, nb);
+    if (t >= nb) return;
+    const int r = t / bxs;
+    stage_brick<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, t % bxs, r % bys, r / bys, stage, p, last, t == 0, r_out);
+}
+
+// Brick shapes: id, TX, TY, TZ, threads.  Shapes 4-7 give every face of a
+// sweep its own thread (threads >= the largest face count of one axis), so
+// each sweep is a single pass.
+#define ROEAM_SHAPES3(X)   \
+    X(0, 8, 8, 4, 256)     \
+    X(1, 8, 4, 4, 128)     \
+    X(2, 16, 8, 4, 512)    \
+    X(3, 16, 4, 4, 256)    \
+    X(4, 8, 8, 4, 320)     \
+    X(5, 8, 4, 4, 192)     \
+    X(6, 16, 8, 4, 640)    \
+    X(7, 8, 8, 8, 576)
+
+struct BrickShape {
+    int tx, ty, tz, nt;
+};
+#define ROEAM_SHAPE3_ENTRY(ID, TX, TY, TZ, NT) {TX, TY, TZ, NT},
+static const BrickShape kShapes3[] = {ROEAM_SHAPES3(ROEAM_SHAPE3_ENTRY)};
+#undef ROEAM_SHAPE3_ENTRY
+constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
+
+// Static LDS of the stage kernel: primitives of brick + halo, detector ratios,
+// the flux buffer and the reduction words.  Shapes over the 160 KiB of a
+// gfx950 workgroup are not built (16x8x4 with two scalars).
+constexpr long long kLdsBytes3 = 160 * 1024;
+constexpr long long stage3_lds_bytes(int order, int nsc, int tx, int ty, int tz, int nt)
+{
+    const long long lx = tx + 2 * order, ly = ty + 2 * order, lz = tz + 2 * order;
+    const long long npx = (long long)(tz + 2) * (ty + 2) * (tx + 1), npy = (long long)(tz + 2) * (ty + 1) * (tx + 2),
+                    npz = (long long)(tz + 1) * (ty + 2) * (tx + 2);
+    const long long nfx = (long long)tz * ty * (tx + 1), nfy = (long long)tz * (ty + 1) * tx, nfz = (long long)(tz + 1) * ty * tx;
+    const long long nfb = nfx > nfy ? (nfx > nfz ? nfx : nfz) : (nfy > nfz ? nfy : nfz);
+    return 8 * ((5 + nsc) * lx * ly * lz + npx + npy + npz + (5 + nsc) * nfb + nt / 64);
+}
+
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
+static hipError_t launch3_one(const DevSolve3 *dS, int blocks, int stage, int p, int last, double *r_out, hipStream_t st)
+{
+    if constexpr (stage3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT) > kLdsBytes3) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_stage3<ORDER, PREC, NSC, TX, TY, TZ, NT>), dim3(blocks), dim3(NT), 0, st, dS, stage, p, last,
+                           r_out);
+        return hipSuccess;
+    }
+}
+
+template <int ORDER, int PREC, int NSC>
+static hipError_t launch3_shape(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last,
+                                double *r_out, hipStream_t st)
+{
+    const BrickShape &sh = kShapes3[shape];
+    const long long nb = (long long)((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty) * ((S.nz + sh.tz - 1) / sh.tz);
+    const int blocks = (int)(((nb + 7) >> 3) << 3);
+#define ROEAM_SHAPE3_CASE(ID, TX, TY, TZ, NT) \
+    case ID: return launch3_one<ORDER, PREC, NSC, TX, TY, TZ, NT>(dS, blocks, stage, p, last, r_out, st);
+    switch (shape) { ROEAM_SHAPES3(ROEAM_SHAPE3_CASE) }
+#undef ROEAM_SHAPE3_CASE
+    return hipErrorInvalidValue;
+}
+
+// All orders and precisions of one scalar count.
+template <int NSC>
+static hipError_t launch3_nsc(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last,
+                              double *r_out, hipStream_t st)
+{
+    if (S.order == 1) {
+        return S.precision == 0 ? launch3_shape<1, 0, NSC>(dS, S, shape, stage, p, last, r_out, st)
+                                : launch3_shape<1, 1, NSC>(dS, S, shape, stage, p, last, r_out, st);
+    }
+    return S.precision == 0 ? launch3_shape<2, 0, NSC>(dS, S, shape, stage, p, last, r_out, st)
+                            : launch3_shape<2, 1, NSC>(dS, S, shape, stage, p, last, r_out, st);
+}
+
+} // namespace roeam
