@@ -58,15 +58,16 @@ typedef struct roeam_grid roeam_grid; /* immutable grid: sizes, metrics, boundar
  *   DIRICHLET     a fixed state supplied at grid creation;
  *   MOVING        (uniform grids) a side split at a + b t along it: below the
  *                 split (cell-centre coordinate x for south/north, y for
- *                 west/east) the side's Dirichlet state from grid creation,
- *                 above it a slip wall or a second Dirichlet state (see
- *                 roeam_grid_set_moving_side; until then the whole side is
- *                 Dirichlet).  t is the time of the state the stage reads: the
- *                 step's start plus 0, dt, dt/2 for the SSP-RK3 stages and
- *                 0, dt/4, dt/3, dt/2 for the four-stage scheme.  The
- *                 double-Mach reflection of Sec. 7.4 needs it (a wall from
- *                 x = 1/6 on, a top side that follows the exact incident
- *                 shock).
+ *                 west/east) the side's Dirichlet state from grid creation or
+ *                 a slip wall, above it a slip wall or a second Dirichlet
+ *                 state (see roeam_grid_set_moving_side; until then the whole
+ *                 side is Dirichlet).  t is the time of the state the stage
+ *                 reads: the step's start plus 0, dt, dt/2 for the SSP-RK3
+ *                 stages and 0, dt/4, dt/3, dt/2 for the four-stage scheme.
+ *                 The double-Mach reflection of Sec. 7.4 needs it (a wall
+ *                 from x = 1/6 on, a top side that follows the exact incident
+ *                 shock), and so does the supersonic corner of Sec. 7.3 (the
+ *                 step's wall below the corner, the inflow above it; b = 0).
  * Two ghost layers are used.  Corner ghosts apply the x rule first and then
  * the y rule. */
 typedef enum {
@@ -188,11 +189,13 @@ roeam_status roeam_grid_layout(const roeam_grid *grid, int *nx, int *ny, long *p
  * roeam_step and keeps the fastest per (order, precision).  Every shape
  * computes bitwise the same result.  EINVAL: shape outside -1..8. */
 roeam_status roeam_grid_set_tile_shape(roeam_grid *grid, int shape);
-/* Split of a ROEAM_BC_MOVING side: a + b t (a may be +-infinity), hi_kind
- * ROEAM_BC_SLIPWALL or ROEAM_BC_DIRICHLET above the split, state_hi a HOST
- * conserved state [4] for the latter (NULL otherwise).  Later calls see it.
- * EINVAL: not a moving side, NaN a, non-finite b, bad hi_kind or state. */
-roeam_status roeam_grid_set_moving_side(roeam_grid *grid, int side, double a, double b, int hi_kind,
+/* Split of a ROEAM_BC_MOVING side: a + b t (a may be +-infinity); lo_kind
+ * below the split: ROEAM_BC_DIRICHLET (the side's state from grid creation)
+ * or ROEAM_BC_SLIPWALL; hi_kind above it: ROEAM_BC_SLIPWALL or
+ * ROEAM_BC_DIRICHLET, state_hi a HOST conserved state [4] for the latter (NULL
+ * otherwise).  Later calls see it.  EINVAL: not a moving side, NaN a,
+ * non-finite b, bad lo_kind, hi_kind or state. */
+roeam_status roeam_grid_set_moving_side(roeam_grid *grid, int side, double a, double b, int lo_kind, int hi_kind,
                                         const double *state_hi);
 /* Time at which roeam_residual evaluates moving sides (default 0; steps use
  * their own stage times).  EINVAL: NULL grid, non-finite t. */

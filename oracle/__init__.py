@@ -34,7 +34,9 @@ V_XI_EQ46 = 1 << 6
 V_DUP_ZERO = 1 << 7
 
 SCHEME_ROEAM, SCHEME_ROE, SCHEME_ROE_HARTEN = 0, 1, 2
-BC_MOVING = 4  # a side split at a + b t: Dirichlet below, its hi kind above
+BC_DIRICHLET = 3
+BC_SLIPWALL = 2
+BC_MOVING = 4  # a side split at a + b t: its lo kind below, its hi kind above
 MAX_SCALARS = 2  # transported scalars (rho k rows of Eq. 85) a grid may carry
 
 
@@ -68,7 +70,8 @@ class _Grid(ctypes.Structure):
                 ("bc", ctypes.c_int * 4), ("bc_state", (ctypes.c_double * 4) * 4),
                 ("nscalars", ctypes.c_int), ("bc_scalar", (ctypes.c_double * MAX_SCALARS) * 4),
                 ("split_a", ctypes.c_double * 4), ("split_b", ctypes.c_double * 4), ("split_hi", ctypes.c_int * 4),
-                ("bc_state_hi", (ctypes.c_double * 4) * 4), ("t_bc", ctypes.c_double)]
+                ("bc_state_hi", (ctypes.c_double * 4) * 4), ("t_bc", ctypes.c_double),
+                ("split_lo", ctypes.c_int * 4)]
 
 
 _DIAG_FIELDS = ["UL", "UR", "U", "dU", "dp", "rho", "u", "v", "H", "c", "M", "Mbar", "theta",
@@ -186,11 +189,14 @@ class GridSpec:
             for s in range(4):
                 for m in range(ns):
                     g.bc_scalar[s][m] = float(bcs[s][m])
-        # moving-split sides: {side: (a, b, hi_kind, state_hi)}; below the split the side's bc_state
-        for side, (sa, sb, hi, st_hi) in (getattr(case, "moving", None) or {}).items():
-            g.split_a[side], g.split_b[side], g.split_hi[side] = float(sa), float(sb), int(hi)
+        # moving-split sides: {side: (a, b, hi_kind, state_hi[, lo_kind])}; below the split the
+        # lo kind (default Dirichlet: the side's bc_state), above it the hi kind
+        for side, spec in (getattr(case, "moving", None) or {}).items():
+            sa, sb, hi, st_hi = spec[:4]
+            lo = spec[4] if len(spec) > 4 else BC_DIRICHLET
+            g.split_a[side], g.split_b[side], g.split_hi[side], g.split_lo[side] = float(sa), float(sb), int(hi), int(lo)
             for k in range(4):
-                g.bc_state_hi[side][k] = float(st_hi[k])
+                g.bc_state_hi[side][k] = float(st_hi[k]) if st_hi is not None else 0.0
         g.t_bc = float(getattr(case, "t_bc", 0.0))
         self.g = g
 

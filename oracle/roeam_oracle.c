@@ -364,16 +364,14 @@ static void dirichlet_prim(const orc_params *prm, const orc_grid *g, int side, i
 }
 
 /* A moving-split side at coordinate xc (cell centre) along it: below the
- * split point a + b t_bc its Dirichlet state (W filled, returns -1), above it
- * the hi kind: a Dirichlet state (W filled, -1) or a slip wall (returned). */
+ * split point a + b t_bc the lo kind, above it the hi kind; a Dirichlet kind
+ * fills W (the side's state below, bc_state_hi above) and returns -1, a slip
+ * wall is returned. */
 static int moving_side(const orc_params *prm, const orc_grid *g, int side, double xc, int nc, double *W)
 {
-    if (xc < g->split_a[side] + g->split_b[side] * g->t_bc) {
-        dirichlet_prim(prm, g, side, nc, W);
-        return -1;
-    }
-    if (g->split_hi[side] == ORC_BC_DIRICHLET) {
-        dirichlet_prim_of(prm, g, side, 1, nc, W);
+    const int lo = xc < g->split_a[side] + g->split_b[side] * g->t_bc;
+    if ((lo ? g->split_lo[side] : g->split_hi[side]) == ORC_BC_DIRICHLET) {
+        dirichlet_prim_of(prm, g, side, !lo, nc, W);
         return -1;
     }
     return ORC_BC_SLIPWALL;
@@ -537,6 +535,7 @@ static int check_args(const orc_params *prm, const orc_grid *g)
         if (g->bc[s] != ORC_BC_MOVING) continue;
         if (g->metric != 0 || g->bc[s ^ 1] == ORC_BC_PERIODIC) return ORC_EINVAL;
         if (g->split_hi[s] != ORC_BC_DIRICHLET && g->split_hi[s] != ORC_BC_SLIPWALL) return ORC_EINVAL;
+        if (g->split_lo[s] != ORC_BC_DIRICHLET && g->split_lo[s] != ORC_BC_SLIPWALL) return ORC_EINVAL;
     }
     return 0;
 }

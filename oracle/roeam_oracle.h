@@ -28,10 +28,12 @@ extern "C" {
 /* Boundary kinds (the paper names none; the test configurations do).
  * ORC_BC_MOVING (uniform grids): a side split at a + b t along it (cell-centre
  * coordinate, x for south/north, y for west/east, t = orc_grid.t_bc): below the
- * split the side's Dirichlet state bc_state, above it its split_hi kind, either
- * a Dirichlet state bc_state_hi or a slip wall.  The double-Mach reflection
- * (Sec. 7.4) needs it: a wall that starts at x = 1/6 and a top boundary that
- * follows the exact incident shock. */
+ * split its split_lo kind, either the side's Dirichlet state bc_state or a slip
+ * wall; above it its split_hi kind, either a Dirichlet state bc_state_hi or a
+ * slip wall.  The double-Mach reflection (Sec. 7.4) needs it (a wall that starts
+ * at x = 1/6 and a top boundary that follows the exact incident shock), and so
+ * does the supersonic corner (Sec. 7.3: the step's face below the corner, the
+ * inflow channel above it). */
 enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_SLIPWALL = 2, ORC_BC_DIRICHLET = 3, ORC_BC_MOVING = 4 };
 /* Sides. */
 enum { ORC_WEST = 0, ORC_EAST = 1, ORC_SOUTH = 2, ORC_NORTH = 3 };
@@ -82,6 +84,7 @@ typedef struct {
     double bc_state_hi[4][4];      /* ORC_BC_MOVING: Dirichlet state above it   */
     double t_bc;           /* time of moving boundaries for orc_residual; orc_run
                               uses the time of each stage's input state          */
+    int split_lo[4];       /* ORC_BC_MOVING: kind below the split               */
 } orc_grid;
 
 /* Every intermediate of one face evaluation, for property tests. */

@@ -100,7 +100,7 @@ def lib():
         "roeam_grid_set_tile_shape": (i, [vp, i]),
         "roeam_grid_tile_shape": (i, [vp, ctypes.POINTER(Params), ctypes.POINTER(i)]),
         "roeam_grid_set_scalars": (i, [vp, i, vp]),
-        "roeam_grid_set_moving_side": (i, [vp, i, d, d, i, vp]),
+        "roeam_grid_set_moving_side": (i, [vp, i, d, d, i, i, vp]),
         "roeam_grid_set_boundary_time": (i, [vp, d]),
         "roeam_residual": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
@@ -244,19 +244,22 @@ class Grid:
         ns = case.q0.shape[0] - 4
         if ns:
             g.set_scalars(ns, getattr(case, "bc_scalar", None))
-        for side, (a, b, hi, state_hi) in (getattr(case, "moving", None) or {}).items():
-            g.set_moving_side(side, a, b, hi, state_hi)
+        for side, spec in (getattr(case, "moving", None) or {}).items():
+            a, b, hi, state_hi = spec[:4]
+            g.set_moving_side(side, a, b, hi, state_hi, lo_kind=spec[4] if len(spec) > 4 else BC_DIRICHLET)
         g.set_boundary_time(getattr(case, "t_bc", 0.0))
         return g
 
-    def set_moving_side(self, side: int, a: float, b: float, hi_kind: int, state_hi=None):
-        """Split a + b t of a BC_MOVING side; above it a slip wall or the conserved state_hi."""
+    def set_moving_side(self, side: int, a: float, b: float, hi_kind: int, state_hi=None, lo_kind: int = BC_DIRICHLET):
+        """Split a + b t of a BC_MOVING side; below it the side's Dirichlet state or a slip wall
+        (lo_kind), above it a slip wall or the conserved state_hi (hi_kind)."""
         arg = None
         if state_hi is not None:
             sa = np.ascontiguousarray(state_hi, dtype=np.float64).reshape(4)
             self._keep.append(sa)
             arg = ctypes.c_void_p(sa.ctypes.data)
-        self.ctx.check(lib().roeam_grid_set_moving_side(self.h, int(side), float(a), float(b), int(hi_kind), arg))
+        self.ctx.check(lib().roeam_grid_set_moving_side(self.h, int(side), float(a), float(b), int(lo_kind),
+                                                        int(hi_kind), arg))
 
     def set_boundary_time(self, t: float):
         """Time at which residual() evaluates moving sides."""

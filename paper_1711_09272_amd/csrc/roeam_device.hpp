@@ -67,6 +67,7 @@ struct DevSolve {
     double bck[4][kMaxScalars]; // Dirichlet scalars, primitive k_m
     double spl_a[4], spl_b[4];  // BC_MOVING sides: split at a + b t
     int spl_hi[4];              // BC_MOVING sides: kind above the split
+    int spl_lo[4];              // BC_MOVING sides: kind below the split
     double bcw_hi[4][4];        // BC_MOVING sides: Dirichlet state above the split, primitive
     double t_res;               // time of moving sides in a residual-only launch
     // scheme
@@ -276,7 +277,7 @@ template <int NSC>
 __device__ __forceinline__ int moving_side(const DevSolve &S, int sd, double xc, const BoundaryClock &clk, double *W)
 {
     const bool lo = xc < S.spl_a[sd] + S.spl_b[sd] * clk.time();
-    if (!lo && S.spl_hi[sd] != BC_DIRICHLET) return BC_SLIPWALL;
+    if ((lo ? S.spl_lo[sd] : S.spl_hi[sd]) != BC_DIRICHLET) return BC_SLIPWALL;
 #pragma unroll
     for (int k = 0; k < 4; ++k) W[k] = lo ? S.bcw[sd][k] : S.bcw_hi[sd][k];
 #pragma unroll

@@ -55,6 +55,7 @@ struct roeam_grid {
     double spl_a[4] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, HUGE_VAL};  // moving sides: split at a + b t
     double spl_b[4] = {0, 0, 0, 0};
     int spl_hi[4] = {ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL, ROEAM_BC_SLIPWALL};
+    int spl_lo[4] = {ROEAM_BC_DIRICHLET, ROEAM_BC_DIRICHLET, ROEAM_BC_DIRICHLET, ROEAM_BC_DIRICHLET};
     double bcq_hi[4][4] = {};                    // moving sides: conserved state above the split
     double t_res = 0.0;                          // time of moving sides in roeam_residual
     int nsc = 0;                                 // transported scalars (rows 4 .. 3 + nsc)

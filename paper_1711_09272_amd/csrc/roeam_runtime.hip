@@ -85,6 +85,7 @@ DevSolve roeam_make_solve(const roeam_grid *g, const roeam_params *p, double *q,
         S.spl_a[s] = g->spl_a[s];
         S.spl_b[s] = g->spl_b[s];
         S.spl_hi[s] = g->spl_hi[s];
+        S.spl_lo[s] = g->spl_lo[s];
         if (g->bc[s] == ROEAM_BC_MOVING && g->spl_hi[s] == ROEAM_BC_DIRICHLET) prim_of(p->gamma, g->bcq_hi[s], S.bcw_hi[s]);
     }
     S.t_res = g->t_res;
@@ -598,7 +599,8 @@ roeam_status roeam_grid_set_scalars(roeam_grid *g, int nscalars, const double *d
     return ROEAM_OK;
 }
 
-roeam_status roeam_grid_set_moving_side(roeam_grid *g, int side, double a, double b, int hi_kind, const double *state_hi)
+roeam_status roeam_grid_set_moving_side(roeam_grid *g, int side, double a, double b, int lo_kind, int hi_kind,
+                                        const double *state_hi)
 {
     if (!g) return ROEAM_EINVAL;
     roeam_ctx *ctx = g->ctx;
@@ -607,6 +609,8 @@ roeam_status roeam_grid_set_moving_side(roeam_grid *g, int side, double a, doubl
     if (std::isnan(a) || !std::isfinite(b)) return fail(ctx, ROEAM_EINVAL, "split a must not be NaN, b must be finite");
     if (hi_kind != ROEAM_BC_SLIPWALL && hi_kind != ROEAM_BC_DIRICHLET)
         return fail(ctx, ROEAM_EINVAL, "hi_kind must be ROEAM_BC_SLIPWALL or ROEAM_BC_DIRICHLET");
+    if (lo_kind != ROEAM_BC_SLIPWALL && lo_kind != ROEAM_BC_DIRICHLET)
+        return fail(ctx, ROEAM_EINVAL, "lo_kind must be ROEAM_BC_SLIPWALL or ROEAM_BC_DIRICHLET");
     if (hi_kind == ROEAM_BC_DIRICHLET) {
         if (!state_hi) return fail(ctx, ROEAM_EINVAL, "Dirichlet hi side without a state");
         for (int k = 0; k < 4; ++k)
@@ -616,6 +620,7 @@ roeam_status roeam_grid_set_moving_side(roeam_grid *g, int side, double a, doubl
     g->spl_a[side] = a;
     g->spl_b[side] = b;
     g->spl_hi[side] = hi_kind;
+    g->spl_lo[side] = lo_kind;
     for (int k = 0; k < 4; ++k) g->bcq_hi[side][k] = hi_kind == ROEAM_BC_DIRICHLET ? state_hi[k] : 0.0;
     return ROEAM_OK;
 }

@@ -561,6 +561,40 @@ def dmr(nx: int = 800, ny: int = 200, t_end: float = 0.2, **params) -> Case:
                 t_end=t_end, moving=moving)
 
 
+def corner_states():
+    """Pre- and post-shock primitive states (rho, u, v, p) of the supersonic corner
+    (Sec. 7.3, as printed): the shock moves at rho_L u_L / (rho_L - rho_R) = 5.09
+    into gas at rest."""
+    return (1.4, 0.0, 0.0, 1.0), (7.04108, 4.07794, 0.0, 30.05942)
+
+
+def corner(n: int = 400, t_end: float = 0.155, **params) -> Case:
+    """Supersonic corner (Sec. 7.3) on the paper's n x n grid of [0, 1]^2 with the
+    90-degree corner at (0.05, 0.5) and the shock at x = 0.05.  The inflow channel
+    x < 0.05, y > 0.5 holds the post-shock state, which is supersonic (u = 4.08 >
+    c = 2.44), so nothing travels upstream into it and it stays uniform; the case
+    is therefore the block x > 0.05 (0.95 n x n cells) whose west side is the
+    step's slip wall below y = 0.5 and post-shock inflow above it.  East, south
+    and north sides are transmissive.  Gas at rest (1.4, 0, 0, 1) fills the block
+    at t = 0.  The paper's setting of its Sec. 7 tests: first order in space, the
+    four-stage Runge-Kutta scheme, eps1 = 0 unless stated (Fig. 8f: eps1 = 1,
+    eps2 = 0.05)."""
+    assert n % 20 == 0, "the corner must fall on a cell face"
+    gamma = params.get("gamma", 1.4)
+    pre, post = corner_states()
+    nx, ny = (19 * n) // 20, n
+    dx = dy = 1.0 / n
+    qpre, qpost = conserved(gamma, *pre), conserved(gamma, *post)
+    q0 = np.ascontiguousarray(np.broadcast_to(qpre[:, None, None], (4, ny, nx)))
+    bc_state = np.zeros((4, 4))
+    bc_state[WEST] = qpost
+    prm = default_params(order=1, time_scheme=2, cfl=0.4, mach_ref=1.0, u_ref=post[1], eps1=0.0, eps2=0.05)
+    prm.update(params)
+    moving = {WEST: (0.5, 0.0, DIRICHLET, qpost, SLIPWALL)}
+    return Case(name=f"corner_{nx}x{ny}", q0=q0, params=prm, bc=(MOVING, TRANSMISSIVE, TRANSMISSIVE, TRANSMISSIVE),
+                dx=dx, dy=dy, bc_state=bc_state, nsteps=10 ** 6, t_end=t_end, moving=moving)
+
+
 def add_scalars(case: "Case", ns: int, seed: int = 0, mode: str = "rough", value: float = 1.0,
                 k_bc: Optional[np.ndarray] = None) -> "Case":
     """The case with ``ns`` transported scalars appended (rows rho k_m):
