@@ -482,7 +482,7 @@ def bench_3d(args):
     cells = case.cells
     ctx = P.Context(0)
     grid = P.Grid3.from_case(ctx, case)
-    shape = args.tile_shape if args.tile_shape >= 0 else 6
+    shape = args.tile_shape if args.tile_shape >= 0 else 8
     grid.set_tile_shape(shape)
     q = grid.to_device(case.q0)
     prm = case.params
@@ -553,7 +553,8 @@ def bench_3d(args):
             "traffic": traffic,
             "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
             "alu": alu,
-            "kernel": "k_stage3<order 2, FP%s, %s>" % ("64" if args.precision == 0 else "32-coef", P.SHAPES3[shape]),
+            "kernel": "k_stage3%s<order 2, FP%s, %s>" % ("p" if P.SHAPES3[shape].endswith("p") else "",
+                                                         "64" if args.precision == 0 else "32-coef", P.SHAPES3[shape]),
             "kernel_grid": f"{n}x{n}x{nz}",
             "launch_ms": round(launch_ms, 6),
             "timed_region_launches": 3 * args.steps,

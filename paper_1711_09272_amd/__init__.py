@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libroeam.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-MAX_SCALARS = 2  # transported scalars (rho k rows) a 2-D grid may carry
+MAX_SCALARS = 2  # transported scalars (rho k rows) a grid may carry
 BC_PERIODIC, BC_TRANSMISSIVE, BC_SLIPWALL, BC_DIRICHLET, BC_MOVING = 0, 1, 2, 3, 4
 V_XI_UNGATED, V_EXPFIX_F8, V_CLAMP_UPRIME = 1, 2, 4
 # stage-kernel tile shapes: cells x cells / threads per workgroup
@@ -36,7 +36,7 @@ EXPORTS = [
 ]
 # 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
 SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256", "8x8x4/320", "8x4x4/192", "16x8x4/640",
-           "8x8x8/576"]
+           "8x8x8/576", "16x8x4/512p", "8x8x8/512p"]  # p: persistent, prefetching the next brick's halo
 
 
 class RoeamError(RuntimeError):

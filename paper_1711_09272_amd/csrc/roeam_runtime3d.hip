@@ -26,16 +26,18 @@ struct roeam_grid3d {
     DevSolve3 *h_solve = nullptr;     // pinned staging copy of the last descriptor sent
     bool solve_valid = false;
     GraphCache gc;
-    int shape = 6;                    // 16x8x4 bricks, one thread per face (fastest measured on 128^3)
+    int shape = 8;                    // persistent 16x8x4/512 bricks (fastest measured on 128^3)
     double *d_norm_part = nullptr;    // scratch of roeam_residual_norms3d
     int final_parity = 0;
     int nsc = 0;                      // transported scalars (rows 5 .. 4 + nsc of q)
     double bcs[6][roeam::kMaxScalars] = {}; // Dirichlet rho k_m per side
 };
 
-// Brick shape the stage kernel runs with: the grid's, or 8x8x4 bricks with 320
-// threads where the grid's does not fit the LDS with its scalars.
-constexpr int kFallbackShape3 = 4;
+// Brick shape the stage kernel runs with: the grid's, or persistent 8x8x8
+// bricks with 512 threads where the grid's does not fit the LDS with its
+// scalars (fastest measured with two scalars on 128^3: 350 us per stage, the
+// 8x8x4/320 brick 561).
+constexpr int kFallbackShape3 = 9;
 static int stage_shape3(const roeam_grid3d *g, int order)
 {
     return roeam::brick_shape_fits(g->shape, order, g->nsc) ? g->shape : kFallbackShape3;

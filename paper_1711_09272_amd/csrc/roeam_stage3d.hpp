@@ -6,8 +6,8 @@
 // A workgroup owns a brick of TX x TY x TZ cells.  It stages the brick and its
 // halo (two layers for MUSCL, one for piecewise-constant states) as primitives
 // in LDS, builds the detector ratio of Eq. (97) of every face within one layer
-// of the brick, then sweeps the x-, y- and z-faces in turn through one LDS flux
-// buffer, each face evaluated exactly once (Eq. 85, nine-face detector of
+// of the brick, then sweeps the x-, y- and z-faces in turn through one or two
+// LDS flux buffers, each face evaluated exactly once (Eq. 85, nine-face detector of
 // Eq. 96), accumulates the conservative residual of its cells in registers and
 // applies the stage update, the positivity check and the explicit-rate
 // reduction exactly as the 2-D stage kernel does (same stage codes, same step
@@ -40,6 +40,29 @@ struct Brick {
     static __device__ __forceinline__ int py(int i, int fj, int l) { return NPX + ((l + 1) * (TY + 1) + fj) * (TX + 2) + i + 1; }
     static __device__ __forceinline__ int pz(int i, int j, int fl) { return NPX + NPY + (fl * (TY + 2) + j + 1) * (TX + 2) + i + 1; }
 };
+
+// Static LDS of the stage kernel: primitives of brick + halo, detector ratios,
+// the flux buffer (two with db) and the reduction words.  Shapes over the 160 KiB
+// of a gfx950 workgroup are not built (16x8x4 with two scalars).
+constexpr long long kLdsBytes3 = 160 * 1024;
+constexpr long long stage3_lds_bytes(int order, int nsc, int tx, int ty, int tz, int nt, bool db = false)
+{
+    const long long lx = tx + 2 * order, ly = ty + 2 * order, lz = tz + 2 * order;
+    const long long npx = (long long)(tz + 2) * (ty + 2) * (tx + 1), npy = (long long)(tz + 2) * (ty + 1) * (tx + 2),
+                    npz = (long long)(tz + 1) * (ty + 2) * (tx + 2);
+    const long long nfx = (long long)tz * ty * (tx + 1), nfy = (long long)tz * (ty + 1) * tx, nfz = (long long)(tz + 1) * ty * tx;
+    const long long nfb = nfx > nfy ? (nfx > nfz ? nfx : nfz) : (nfy > nfz ? nfy : nfz);
+    return 8 * ((5 + nsc) * lx * ly * lz + npx + npy + npz + (db ? 2 : 1) * (5 + nsc) * nfb + nt / 64);
+}
+// A second flux buffer lets a sweep's accumulation overlap the next sweep's
+// faces (three barriers instead of six); taken where it keeps the number of
+// workgroups a CU can hold.
+constexpr bool stage3_double_buffer(int order, int nsc, int tx, int ty, int tz, int nt)
+{
+    const long long one = stage3_lds_bytes(order, nsc, tx, ty, tz, nt, false);
+    const long long two = stage3_lds_bytes(order, nsc, tx, ty, tz, nt, true);
+    return two <= kLdsBytes3 && kLdsBytes3 / two == kLdsBytes3 / one;
+}
 
 // Detector minimum of Eq. (96) for the face of axis AXIS whose upper cell is
 // brick cell (i, j, l): the face itself and, in each transverse direction, the
@@ -107,16 +130,14 @@ __device__ __forceinline__ void brick_face(const DevSolve3 &S, const double *__r
     for (int k = 4; k < NR; ++k) F[k] = Ff[k] * area;
 }
 
-// All faces of one axis into sF, then add their differences to the cells'
-// residual sums d (in registers).  The caller separates the sweeps by barriers.
+// All faces of one axis into sF.
 template <int ORDER, int PREC, int AXIS, int NSC, int TX, int TY, int TZ, int NT, class B>
-__device__ __forceinline__ void sweep_axis(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
-                                           double (&sF)[5 + NSC][B::NFB], int i0, int j0, int l0, double (*d)[5 + NSC])
+__device__ __forceinline__ void faces_axis(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
+                                           double (&sF)[5 + NSC][B::NFB], int i0, int j0, int l0)
 {
     constexpr int NR = 5 + NSC;
     constexpr int FX = TX + (AXIS == 0), FY = TY + (AXIS == 1), FZ = TZ + (AXIS == 2);
     constexpr int NF = FX * FY * FZ;
-    constexpr int CPT = (TX * TY * TZ + NT - 1) / NT;
     for (int f = threadIdx.x; f < NF; f += NT) {
         const int i = f % FX, r = f / FX, j = r % FY, l = r / FY;
         // the face lies on the grid (a face at index n of its axis is the upper boundary)
@@ -126,7 +147,16 @@ __device__ __forceinline__ void sweep_axis(const DevSolve3 &S, const double *__r
 #pragma unroll
         for (int k = 0; k < NR; ++k) sF[k][f] = F[k];
     }
-    __syncthreads();
+}
+
+// Add the face differences of one axis (from sF) to the cells' residual sums d
+// (in registers), in the order x, y, z.
+template <int AXIS, int NSC, int TX, int TY, int TZ, int NT, class B>
+__device__ __forceinline__ void acc_axis(const double (&sF)[5 + NSC][B::NFB], double (*d)[5 + NSC])
+{
+    constexpr int NR = 5 + NSC;
+    constexpr int FX = TX + (AXIS == 0), FY = TY + (AXIS == 1);
+    constexpr int CPT = (TX * TY * TZ + NT - 1) / NT;
     constexpr int up = AXIS == 0 ? 1 : (AXIS == 1 ? FX : FX * FY);
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -140,8 +170,21 @@ __device__ __forceinline__ void sweep_axis(const DevSolve3 &S, const double *__r
             d[m][k] = AXIS == 0 ? df : d[m][k] + df;
         }
     }
-    __syncthreads();
 }
+
+// Shared memory of the stage kernel: primitives of brick + halo, detector
+// ratios, one or two flux buffers and the reduction words.
+template <int ORDER, int NSC, int TX, int TY, int TZ, int NT>
+struct StageLds {
+    using B = Brick<TX, TY, TZ, ORDER>;
+    static constexpr int NR = 5 + NSC;
+    static constexpr bool DB = stage3_double_buffer(ORDER, NSC, TX, TY, TZ, NT);
+    double sW[NR * B::PL];
+    double sP[B::NPX + B::NPY + B::NPZ];
+    double sF[NR][B::NFB];
+    double sF2[DB ? NR : 1][DB ? B::NFB : 1];
+    double sRed[NT / 64];
+};
 
 // Stage codes, buffers and step logic as in the 2-D stage kernel:
 //   0 residual only; 1 forward Euler / first SSP-RK3 stage (q -> qa);
@@ -149,35 +192,34 @@ __device__ __forceinline__ void sweep_axis(const DevSolve3 &S, const double *__r
 //   (q -> qa, qa -> qb, qb -> qa, qa -> q; + Q^n from the second on).
 // Transported scalars (NSC rows after rho E) ride along every step; the
 // positivity check and the rate read the flow rows only.
-template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
-__device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, int bz, int stage, int p, int last,
-                                            int first_block, double *__restrict__ r_out)
+__device__ __forceinline__ const double *stage_input3(const DevSolve3 &S, int stage)
 {
-    constexpr int HL = ORDER;
-    using B = Brick<TX, TY, TZ, HL>;
-    constexpr int NC = TX * TY * TZ;
-    constexpr int CPT = (NC + NT - 1) / NT;
-    constexpr int PL = B::PL;
-    constexpr int NR = 5 + NSC;
-    __shared__ double sW[NR * PL];
-    __shared__ double sP[B::NPX + B::NPY + B::NPZ];
-    __shared__ double sF[NR][B::NFB];
-    __shared__ double sRed[NT / 64];
+    return (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
+}
 
-    const int tid = threadIdx.x;
-    const double *__restrict__ qin = (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
+// Origin of brick t (bricks numbered x fastest).
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void brick_origin(const DevSolve3 &S, int t, int &i0, int &j0, int &l0)
+{
+    const int bxs = (S.nx + TX - 1) / TX, bys = (S.ny + TY - 1) / TY;
+    const int r = t / bxs;
+    i0 = (t % bxs) * TX;
+    j0 = (r % bys) * TY;
+    l0 = (r / bys) * TZ;
+}
+
+// The own cells' stage input (and Q^n), into registers.
+template <int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void own_cells(const DevSolve3 &S, int stage, const double *__restrict__ qin, int i0, int j0,
+                                          int l0, double (*Qs)[5 + NSC], double (*Q0)[5 + NSC], long long *cidx)
+{
+    constexpr int NC = TX * TY * TZ, CPT = (NC + NT - 1) / NT, NR = 5 + NSC;
     const bool reads_qn = stage >= 2 && stage != 4;
-    const int i0 = bx * TX, j0 = by * TY, l0 = bz * TZ;
-    const int nx = S.nx, ny = S.ny, nz = S.nz;
-
-    // own cells' stage input (and Q^n) first, so their latency hides behind the face work
-    double Qs[CPT][NR], Q0[CPT][NR];
-    long long cidx[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int c = tid + m * NT;
+        const int c = threadIdx.x + m * NT;
         const int ci = c % TX, r = c / TX, cj = r % TY, cl = r / TY;
-        const bool ok = c < NC && i0 + ci < nx && j0 + cj < ny && l0 + cl < nz;
+        const bool ok = c < NC && i0 + ci < S.nx && j0 + cj < S.ny && l0 + cl < S.nz;
         cidx[m] = ok ? (long long)(l0 + cl) * S.slab + (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
         if (stage > 0) {
 #pragma unroll
@@ -188,18 +230,21 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
             for (int k = 0; k < NR; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
         }
     }
+}
 
-    Slot &z = *S.slot;
-    double dt = 0.0;
-    if (stage > 0 && !begin_stage(z, p, stage, last, first_block, dt)) return;
-
-    // 1. brick + halo -> primitives in LDS
+// Brick + halo -> primitives in LDS, read directly.
+template <int ORDER, int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void halo_direct(const DevSolve3 &S, const double *__restrict__ qin, int i0, int j0, int l0,
+                                            double *__restrict__ sW)
+{
+    using B = Brick<TX, TY, TZ, ORDER>;
+    constexpr int HL = ORDER, PL = B::PL, NR = 5 + NSC, NLOAD = (PL + NT - 1) / NT;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
     const bool interior = i0 - HL >= 0 && i0 + TX + HL <= nx && j0 - HL >= 0 && j0 + TY + HL <= ny && l0 - HL >= 0 &&
                           l0 + TZ + HL <= nz;
-    constexpr int NLOAD = (PL + NT - 1) / NT;
 #pragma unroll
     for (int it = 0; it < NLOAD; ++it) {
-        const int e = tid + it * NT;
+        const int e = threadIdx.x + it * NT;
         if (e >= PL) break;
         const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
         int gi = i0 - HL + lx, gj = j0 - HL + ly, gl = l0 - HL + lz;
@@ -216,7 +261,122 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
 #pragma unroll
         for (int k = 0; k < NR; ++k) sW[k * PL + e] = W[k];
     }
-    __syncthreads();
+}
+
+// Where the state of a cell within two layers of the grid comes from, by the
+// rules of fetch_prim3 (z rule, then y, then x): returns 1 + side for a
+// Dirichlet side, else 0 with idx the grid cell; bits 3, 4, 5 negate u, v, w
+// (slip walls on the way).
+__device__ __forceinline__ int map_cell3(const DevSolve3 &S, int i, int j, int l, long long &idx)
+{
+    int flip = 0;
+    if (l < 0 || l >= S.nz) {
+        const int sd = l < 0 ? SIDE3_B : SIDE3_T;
+        const int kind = S.bc[sd];
+        if (kind == BC_DIRICHLET) return 1 + sd;
+        l = ghost_source(kind, l, S.nz);
+        if (kind == BC_SLIPWALL) flip |= 32;
+    }
+    if (j < 0 || j >= S.ny) {
+        const int sd = j < 0 ? SIDE3_S : SIDE3_N;
+        const int kind = S.bc[sd];
+        if (kind == BC_DIRICHLET) return (1 + sd) | flip;
+        j = ghost_source(kind, j, S.ny);
+        if (kind == BC_SLIPWALL) flip |= 16;
+    }
+    if (i < 0 || i >= S.nx) {
+        const int sd = i < 0 ? SIDE3_W : SIDE3_E;
+        const int kind = S.bc[sd];
+        if (kind == BC_DIRICHLET) return (1 + sd) | flip;
+        i = ghost_source(kind, i, S.nx);
+        if (kind == BC_SLIPWALL) flip |= 8;
+    }
+    idx = (long long)l * S.slab + (long long)j * S.pitch + i;
+    return flip;
+}
+
+// Issue the loads of a brick's halo into registers (Hq), with the source code
+// of each staged cell (Hc; -1 past the staged box).
+template <int ORDER, int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void halo_prefetch(const DevSolve3 &S, const double *__restrict__ qin, int i0, int j0, int l0,
+                                              double (*Hq)[5 + NSC], int *Hc)
+{
+    using B = Brick<TX, TY, TZ, ORDER>;
+    constexpr int HL = ORDER, PL = B::PL, NR = 5 + NSC, NLOAD = (PL + NT - 1) / NT;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const bool interior = i0 - HL >= 0 && i0 + TX + HL <= nx && j0 - HL >= 0 && j0 + TY + HL <= ny && l0 - HL >= 0 &&
+                          l0 + TZ + HL <= nz;
+#pragma unroll
+    for (int it = 0; it < NLOAD; ++it) {
+        const int e = threadIdx.x + it * NT;
+        Hc[it] = -1;
+        if (e >= PL) continue;
+        const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
+        int gi = i0 - HL + lx, gj = j0 - HL + ly, gl = l0 - HL + lz;
+        long long idx = 0;
+        int code = 0;
+        if (interior) {
+            idx = (long long)gl * S.slab + (long long)gj * S.pitch + gi;
+        } else {
+            gi = gi > nx + 1 ? nx + 1 : gi;
+            gj = gj > ny + 1 ? ny + 1 : gj;
+            gl = gl > nz + 1 ? nz + 1 : gl;
+            code = map_cell3(S, gi, gj, gl, idx);
+        }
+        Hc[it] = code;
+        if ((code & 7) == 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Hq[it][k] = qin[k * S.plane + idx];
+        }
+    }
+}
+
+// Prefetched halo -> primitives in LDS (bitwise what halo_direct stages).
+template <int ORDER, int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void halo_commit(const DevSolve3 &S, const double (*Hq)[5 + NSC], const int *Hc,
+                                            double *__restrict__ sW)
+{
+    using B = Brick<TX, TY, TZ, ORDER>;
+    constexpr int PL = B::PL, NR = 5 + NSC, NLOAD = (PL + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < NLOAD; ++it) {
+        const int e = threadIdx.x + it * NT;
+        const int code = Hc[it];
+        if (code < 0) continue;
+        double W[NR];
+        if ((code & 7) == 0) {
+            const double ir = to_prim3(S.gm1, Hq[it], W);
+#pragma unroll
+            for (int m = 0; m < NSC; ++m) W[5 + m] = Hq[it][5 + m] * ir;
+        } else {
+            dirichlet3<NSC>(S, (code & 7) - 1, W);
+        }
+        if (code & 8) W[1] = -W[1];
+        if (code & 16) W[2] = -W[2];
+        if (code & 32) W[3] = -W[3];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sW[k * PL + e] = W[k];
+    }
+}
+
+// Detector ratios, faces, residual and stage update of one brick whose
+// primitives are in LDS (the caller has synchronised after staging them);
+// the rate of the new state goes into lmax.
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, NSC, TX, TY, TZ, NT> &L, int stage,
+                                           int last, double dt, int i0, int j0, int l0, const double (*Qs)[5 + NSC],
+                                           const double (*Q0)[5 + NSC], const long long *cidx, double *r_out,
+                                           double &lmax)
+{
+    using B = Brick<TX, TY, TZ, ORDER>;
+    constexpr int NC = TX * TY * TZ;
+    constexpr int CPT = (NC + NT - 1) / NT;
+    constexpr int PL = B::PL;
+    constexpr int NR = 5 + NSC;
+    const int tid = threadIdx.x;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    double *__restrict__ sW = L.sW;
+    double *__restrict__ sP = L.sP;
 
     // 2. detector ratios, Eq. (97), of every face within one layer of the brick
     if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
@@ -245,12 +405,32 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
 
     // 3. x-, y- and z-faces, each exactly once; residual sums ((x) + (y)) + (z)
     double d[CPT][NR];
-    sweep_axis<ORDER, PREC, 0, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
-    sweep_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
-    sweep_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, sF, i0, j0, l0, d);
+    faces_axis<ORDER, PREC, 0, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
+    __syncthreads();
+    if constexpr (StageLds<ORDER, NSC, TX, TY, TZ, NT>::DB) {
+        // x sums while the y-faces go to the second buffer, y sums while the
+        // z-faces go to the first (whose readers passed the barrier between)
+        acc_axis<0, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        faces_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF2, i0, j0, l0);
+        __syncthreads();
+        acc_axis<1, NSC, TX, TY, TZ, NT, B>(L.sF2, d);
+        faces_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
+        __syncthreads();
+        acc_axis<2, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+    } else {
+        acc_axis<0, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        __syncthreads();
+        faces_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
+        __syncthreads();
+        acc_axis<1, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        __syncthreads();
+        faces_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
+        __syncthreads();
+        acc_axis<2, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+    }
 
     // 4. R = -(sum of face fluxes times areas) / V and the stage update
-    double lmax = 0.0;
+    Slot &z = *S.slot;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = tid + m * NT;
@@ -293,62 +473,145 @@ __device__ __forceinline__ void stage_brick(const DevSolve3 &S, int bx, int by, 
         if (!physical3(W)) atomicOr(&z.nonphys, 1);
         else if (last) lmax = rmax(lmax, cell_rate3(S, W, ir));
     }
-    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, sRed);
 }
 
+// One workgroup per brick.
 template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
 __global__ __launch_bounds__(NT) void k_stage3(const DevSolve3 *__restrict__ Sp, int stage, int p, int last, double *r_out)
 {
+    constexpr int NC = TX * TY * TZ, CPT = (NC + NT - 1) / NT, NR = 5 + NSC;
     const DevSolve3 &S = *Sp;
+    __shared__ StageLds<ORDER, NSC, TX, TY, TZ, NT> L;
     const int bxs = (S.nx + TX - 1) / TX, bys = (S.ny + TY - 1) / TY, bzs = (S.nz + TZ - 1) / TZ;
     const int nb = bxs * bys * bzs;
     const int t = xcd_tile(blockIdx.x, nb);
     if (t >= nb) return;
-    const int r = t / bxs;
-    stage_brick<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, t % bxs, r % bys, r / bys, stage, p, last, t == 0, r_out);
+    int i0, j0, l0;
+    brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
+    const double *__restrict__ qin = stage_input3(S, stage);
+    // own cells' stage input (and Q^n) first, so their latency hides behind the face work
+    double Qs[CPT][NR], Q0[CPT][NR];
+    long long cidx[CPT];
+    own_cells<NSC, TX, TY, TZ, NT>(S, stage, qin, i0, j0, l0, Qs, Q0, cidx);
+    Slot &z = *S.slot;
+    double dt = 0.0;
+    if (stage > 0 && !begin_stage(z, p, stage, last, t == 0, dt)) return;
+    // 1. brick + halo -> primitives in LDS
+    halo_direct<ORDER, NSC, TX, TY, TZ, NT>(S, qin, i0, j0, l0, L.sW);
+    __syncthreads();
+    double lmax = 0.0;
+    brick_body<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, L, stage, last, dt, i0, j0, l0, Qs, Q0, cidx, r_out, lmax);
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, L.sRed);
 }
 
-// Brick shapes: id, TX, TY, TZ, threads.  Shapes 4-7 give every face of a
-// sweep its own thread (threads >= the largest face count of one axis), so
-// each sweep is a single pass.
-#define ROEAM_SHAPES3(X)   \
-    X(0, 8, 8, 4, 256)     \
-    X(1, 8, 4, 4, 128)     \
-    X(2, 16, 8, 4, 512)    \
-    X(3, 16, 4, 4, 256)    \
-    X(4, 8, 8, 4, 320)     \
-    X(5, 8, 4, 4, 192)     \
-    X(6, 16, 8, 4, 640)    \
-    X(7, 8, 8, 8, 576)
+// Persistent form: gridDim.x (a multiple of 8) resident workgroups; those of
+// XCD x (ids x mod 8) take the band of bricks [x c, (x + 1) c), c = ceil(n / 8),
+// in turn, and each loads the next brick's halo into registers while it works
+// on the current one.  Same arithmetic, bitwise the same result.
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp, int stage, int p, int last,
+                                                double *r_out)
+{
+    using B = Brick<TX, TY, TZ, ORDER>;
+    constexpr int NC = TX * TY * TZ, CPT = (NC + NT - 1) / NT, NR = 5 + NSC, NLOAD = (B::PL + NT - 1) / NT;
+    const DevSolve3 &S = *Sp;
+    __shared__ StageLds<ORDER, NSC, TX, TY, TZ, NT> L;
+    const int bxs = (S.nx + TX - 1) / TX, bys = (S.ny + TY - 1) / TY, bzs = (S.nz + TZ - 1) / TZ;
+    const int nb = bxs * bys * bzs;
+    const int chunk = (nb + 7) >> 3, xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;
+    const int t_end = min(nb, (xcd + 1) * chunk);
+    int t = xcd * chunk + (blockIdx.x >> 3);
+    const double *__restrict__ qin = stage_input3(S, stage);
+    double Hq[NLOAD][NR];
+    int Hc[NLOAD];
+    int i0, j0, l0;
+    if (t < t_end) {
+        brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
+        halo_prefetch<ORDER, NSC, TX, TY, TZ, NT>(S, qin, i0, j0, l0, Hq, Hc);
+    }
+    Slot &z = *S.slot;
+    double dt = 0.0;
+    if (stage > 0 && !begin_stage(z, p, stage, last, blockIdx.x == 0, dt)) return;
+    double lmax = 0.0;
+    for (; t < t_end; t += per_xcd) {
+        brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
+        double Qs[CPT][NR], Q0[CPT][NR];
+        long long cidx[CPT];
+        own_cells<NSC, TX, TY, TZ, NT>(S, stage, qin, i0, j0, l0, Qs, Q0, cidx);
+        __syncthreads();  // the previous brick's readers of the LDS arrays are done
+        halo_commit<ORDER, NSC, TX, TY, TZ, NT>(S, Hq, Hc, L.sW);
+        __syncthreads();
+        if (t + per_xcd < t_end) {
+            int i1, j1, l1;
+            brick_origin<TX, TY, TZ>(S, t + per_xcd, i1, j1, l1);
+            halo_prefetch<ORDER, NSC, TX, TY, TZ, NT>(S, qin, i1, j1, l1, Hq, Hc);
+        }
+        brick_body<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, L, stage, last, dt, i0, j0, l0, Qs, Q0, cidx, r_out, lmax);
+    }
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, L.sRed);
+}
+
+// Brick shapes: id, TX, TY, TZ, threads, persistent.  Shapes 4-9 give every
+// face of a sweep its own thread (threads >= the largest face count of one
+// axis), so each sweep is a single pass; 8 and 9 are persistent (resident
+// workgroups that prefetch the next brick's halo into registers; 512 threads
+// leave room for them).
+#define ROEAM_SHAPES3(X)      \
+    X(0, 8, 8, 4, 256, 0)     \
+    X(1, 8, 4, 4, 128, 0)     \
+    X(2, 16, 8, 4, 512, 0)    \
+    X(3, 16, 4, 4, 256, 0)    \
+    X(4, 8, 8, 4, 320, 0)     \
+    X(5, 8, 4, 4, 192, 0)     \
+    X(6, 16, 8, 4, 640, 0)    \
+    X(7, 8, 8, 8, 576, 0)     \
+    X(8, 16, 8, 4, 512, 1)    \
+    X(9, 8, 8, 8, 512, 1)
 
 struct BrickShape {
-    int tx, ty, tz, nt;
+    int tx, ty, tz, nt, persistent;
 };
-#define ROEAM_SHAPE3_ENTRY(ID, TX, TY, TZ, NT) {TX, TY, TZ, NT},
+#define ROEAM_SHAPE3_ENTRY(ID, TX, TY, TZ, NT, PE) {TX, TY, TZ, NT, PE},
 static const BrickShape kShapes3[] = {ROEAM_SHAPES3(ROEAM_SHAPE3_ENTRY)};
 #undef ROEAM_SHAPE3_ENTRY
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
-// Static LDS of the stage kernel: primitives of brick + halo, detector ratios,
-// the flux buffer and the reduction words.  Shapes over the 160 KiB of a
-// gfx950 workgroup are not built (16x8x4 with two scalars).
-constexpr long long kLdsBytes3 = 160 * 1024;
-constexpr long long stage3_lds_bytes(int order, int nsc, int tx, int ty, int tz, int nt)
+// Workgroups of a persistent kernel: as many as the GPU holds at once (CUs
+// times workgroups per CU from the occupancy query, cached per device), a
+// multiple of 8, and no more than the bricks need.
+template <class K>
+static int persistent_blocks(K kernel, int nt, long long nb)
 {
-    const long long lx = tx + 2 * order, ly = ty + 2 * order, lz = tz + 2 * order;
-    const long long npx = (long long)(tz + 2) * (ty + 2) * (tx + 1), npy = (long long)(tz + 2) * (ty + 1) * (tx + 2),
-                    npz = (long long)(tz + 1) * (ty + 2) * (tx + 2);
-    const long long nfx = (long long)tz * ty * (tx + 1), nfy = (long long)tz * (ty + 1) * tx, nfz = (long long)(tz + 1) * ty * tx;
-    const long long nfb = nfx > nfy ? (nfx > nfz ? nfx : nfz) : (nfy > nfz ? nfy : nfz);
-    return 8 * ((5 + nsc) * lx * ly * lz + npx + npy + npz + (5 + nsc) * nfb + nt / 64);
+    constexpr int kMaxDevices = 64;
+    static int cached[kMaxDevices];  // 0: not queried yet
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    if (cached[dev] == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), nt, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cached[dev] = cus * per_cu;
+    }
+    const long long want = nb < cached[dev] ? nb : cached[dev];
+    return (int)(((want + 7) >> 3) << 3);
 }
 
-template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT>
-static hipError_t launch3_one(const DevSolve3 *dS, int blocks, int stage, int p, int last, double *r_out, hipStream_t st)
+template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT, int PE>
+static hipError_t launch3_one(const DevSolve3 *dS, long long nb, int stage, int p, int last, double *r_out,
+                              hipStream_t st)
 {
-    if constexpr (stage3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT) > kLdsBytes3) {
+    if constexpr (stage3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT, StageLds<ORDER, NSC, TX, TY, TZ, NT>::DB) > kLdsBytes3) {
         return hipErrorInvalidValue;
+    } else if constexpr (PE) {
+        auto kernel = k_stage3p<ORDER, PREC, NSC, TX, TY, TZ, NT>;
+        const int blocks = persistent_blocks(kernel, NT, nb);
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(NT), 0, st, dS, stage, p, last, r_out);
+        return hipSuccess;
     } else {
+        const int blocks = (int)(((nb + 7) >> 3) << 3);
         hipLaunchKernelGGL((k_stage3<ORDER, PREC, NSC, TX, TY, TZ, NT>), dim3(blocks), dim3(NT), 0, st, dS, stage, p, last,
                            r_out);
         return hipSuccess;
@@ -361,9 +624,8 @@ static hipError_t launch3_shape(const DevSolve3 *dS, const DevSolve3 &S, int sha
 {
     const BrickShape &sh = kShapes3[shape];
     const long long nb = (long long)((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty) * ((S.nz + sh.tz - 1) / sh.tz);
-    const int blocks = (int)(((nb + 7) >> 3) << 3);
-#define ROEAM_SHAPE3_CASE(ID, TX, TY, TZ, NT) \
-    case ID: return launch3_one<ORDER, PREC, NSC, TX, TY, TZ, NT>(dS, blocks, stage, p, last, r_out, st);
+#define ROEAM_SHAPE3_CASE(ID, TX, TY, TZ, NT, PE) \
+    case ID: return launch3_one<ORDER, PREC, NSC, TX, TY, TZ, NT, PE>(dS, nb, stage, p, last, r_out, st);
     switch (shape) { ROEAM_SHAPES3(ROEAM_SHAPE3_CASE) }
 #undef ROEAM_SHAPE3_CASE
     return hipErrorInvalidValue;

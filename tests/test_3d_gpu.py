@@ -106,7 +106,7 @@ def test_residual3_fp32_flux(C, name):
     assert np.all(err <= TOL32), err
 
 
-@pytest.mark.parametrize("shape", range(8))
+@pytest.mark.parametrize("shape", range(10))
 def test_every_brick_shape_is_bitwise_identical(C, shape):
     """All brick shapes evaluate the same faces with the same arithmetic."""
     case = workloads.rough_case3(37, 19, 13, 15, bc=ALL_WALLS, order=2, eps1=1.0, mach_ref=0.05)
@@ -116,6 +116,28 @@ def test_every_brick_shape_is_bitwise_identical(C, shape):
     assert np.array_equal(r, r0)
     r_or, scale = oracle.residual3(case, with_scale=True)
     assert np.all(rerr(r, r_or, scale) <= TOL64)
+
+
+@pytest.mark.parametrize("shape", [8, 9])
+@pytest.mark.parametrize("ts,steps", [(0, 3), (1, 2), (2, 2)])
+def test_persistent_bricks_steps(C, shape, ts, steps):
+    """The persistent shapes on a grid with more bricks than resident workgroups
+    (64^3: 512 bricks, each workgroup takes several and prefetches the next):
+    every stage code, the step state and the rate reduction, bitwise equal to
+    the one-brick-per-workgroup kernel and within 1e-12 of the oracle."""
+    case = workloads.smooth_random_case3(64, 64, 64, 30, bc=ALL_WALLS, order=2, eps1=1.0, mach_ref=0.05,
+                                         time_scheme=ts, cfl=0.4)
+    say(f"[persistent shape {shape}] time scheme {ts}, {steps} steps, 64^3")
+    q6, st6 = gpu_run3(C, case, steps, shape=6)
+    q, st = gpu_run3(C, case, steps, shape=shape)
+    assert st["steps"] == steps and st["t"] == st6["t"]
+    assert np.array_equal(q, q6)
+    q_or, st_or = oracle.run3(case, nsteps=steps)
+    say(f"    err {serr(q, q_or):.3e}")
+    assert serr(q, q_or) <= TOL64 and abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
+    r6, rate6 = gpu_residual3(C, case, shape=6)
+    r, rate = gpu_residual3(C, case, shape=shape)
+    assert np.array_equal(r, r6) and rate == rate6
 
 
 def test_extruded_2d_case_matches_the_2d_oracle(C):
@@ -188,7 +210,7 @@ def test_invalid_arguments_3d(C):
     case = workloads.smooth_random_case3(4, 4, 4, 19)
     g = P.Grid3.from_case(C, case)
     with pytest.raises(P.RoeamError):
-        g.set_tile_shape(8)
+        g.set_tile_shape(10)
     q = g.to_device(case.q0)
     with pytest.raises(P.RoeamError):
         P.residual3(C, g, dict(case.params, order=3), q)

@@ -119,10 +119,11 @@ def test_unit_scalar_follows_the_mass_row_3d(C):
 
 
 @pytest.mark.parametrize("ns", [1, 2])
-@pytest.mark.parametrize("shape", range(8))
+@pytest.mark.parametrize("shape", range(10))
 def test_every_brick_shape_with_scalars(C, shape, ns):
     """Every shape computes the same bits; with two scalars the 16x8x4 bricks do
-    not fit the LDS and run the fallback shape, again the same bits."""
+    not fit the LDS and run the fallback shape (persistent 8x8x8), again the
+    same bits."""
     case = workloads.add_scalars(workloads.rough_case3(37, 19, 13, 15, bc=ALL_WALLS, order=2, eps1=1.0,
                                                        mach_ref=0.05), ns, seed=22)
     say(f"[brick shape {shape}, {ns} scalars] 37x19x13")
