@@ -164,6 +164,16 @@ template <typename R> __device__ __forceinline__ R pow8(R x)
     return x4 * x4;
 }
 
+// Global-memory views of the state and metric arrays.  The descriptor holds
+// generic pointers; accesses through these views are global_* instructions
+// instead of flat ones, which count against the LDS wait counter and which
+// the compiler may not move past LDS accesses (a flat address could be LDS):
+// with them the tile's halo loads issue together and the early loads of the
+// own cells stay in flight behind the LDS work.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ const gdouble *gptr(const double *p) { return (const gdouble *)p; }
+__device__ __forceinline__ gdouble *gptr(double *p) { return (gdouble *)p; }
+
 // Eq. (97): detector ratio of two neighbouring cells, min of the pressure and
 // density ratios, each taken below one.
 __device__ __forceinline__ double detector_P(double pA, double rA, double pB, double rB)
@@ -196,9 +206,10 @@ template <int NSC = 0>
 __device__ __forceinline__ void load_prim(const DevSolve &S, const double *__restrict__ q, int i, int j, double *W)
 {
     long long idx = (long long)j * S.pitch + i;
-    const double ir = to_prim(S.gm1, q[idx], q[S.plane + idx], q[2 * S.plane + idx], q[3 * S.plane + idx], W);
+    const gdouble *g = gptr(q);
+    const double ir = to_prim(S.gm1, g[idx], g[S.plane + idx], g[2 * S.plane + idx], g[3 * S.plane + idx], W);
 #pragma unroll
-    for (int m = 0; m < NSC; ++m) W[4 + m] = q[(4 + m) * S.plane + idx] * ir;
+    for (int m = 0; m < NSC; ++m) W[4 + m] = g[(4 + m) * S.plane + idx] * ir;
 }
 
 template <int METRIC>
@@ -206,8 +217,9 @@ __device__ __forceinline__ void xface_vec(const DevSolve &S, int i, int j, doubl
 {
     if (METRIC == 0) { sx = S.dy; sy = 0.0; return; }
     long long nxn = S.nx + 1;
-    double ddx = S.xn[(long long)(j + 1) * nxn + i] - S.xn[(long long)j * nxn + i];
-    double ddy = S.yn[(long long)(j + 1) * nxn + i] - S.yn[(long long)j * nxn + i];
+    const gdouble *xn = gptr(S.xn), *yn = gptr(S.yn);
+    double ddx = xn[(long long)(j + 1) * nxn + i] - xn[(long long)j * nxn + i];
+    double ddy = yn[(long long)(j + 1) * nxn + i] - yn[(long long)j * nxn + i];
     sx = ddy;
     sy = -ddx;
 }
@@ -216,8 +228,9 @@ __device__ __forceinline__ void yface_vec(const DevSolve &S, int i, int j, doubl
 {
     if (METRIC == 0) { sx = 0.0; sy = S.dx; return; }
     long long nxn = S.nx + 1;
-    double ddx = S.xn[(long long)j * nxn + i + 1] - S.xn[(long long)j * nxn + i];
-    double ddy = S.yn[(long long)j * nxn + i + 1] - S.yn[(long long)j * nxn + i];
+    const gdouble *xn = gptr(S.xn), *yn = gptr(S.yn);
+    double ddx = xn[(long long)j * nxn + i + 1] - xn[(long long)j * nxn + i];
+    double ddy = yn[(long long)j * nxn + i + 1] - yn[(long long)j * nxn + i];
     sx = -ddy;
     sy = ddx;
 }
@@ -242,7 +255,7 @@ __device__ __forceinline__ double cell_area(const DevSolve &S, int i, int j)
 {
     if (METRIC == 0) return S.area;
     long long nxn = S.nx + 1;
-    const double *x = S.xn, *y = S.yn;
+    const gdouble *x = gptr(S.xn), *y = gptr(S.yn);
     long long r0 = (long long)j * nxn, r1 = (long long)(j + 1) * nxn;
     double x00 = x[r0 + i], y00 = y[r0 + i];
     double x10 = x[r0 + i + 1], y10 = y[r0 + i + 1];

@@ -56,10 +56,10 @@ __device__ __forceinline__ void load_prim3(const DevSolve3 &S, const double *__r
     const long long idx = (long long)l * S.slab + (long long)j * S.pitch + i;
     double Q[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Q[k] = q[k * S.plane + idx];
+    for (int k = 0; k < 5; ++k) Q[k] = gptr(q)[k * S.plane + idx];
     const double ir = to_prim3(S.gm1, Q, W);
 #pragma unroll
-    for (int m = 0; m < NSC; ++m) W[5 + m] = q[(5 + m) * S.plane + idx] * ir;
+    for (int m = 0; m < NSC; ++m) W[5 + m] = gptr(q)[(5 + m) * S.plane + idx] * ir;
 }
 
 template <int NSC>

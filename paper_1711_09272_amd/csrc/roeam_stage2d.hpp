@@ -144,11 +144,11 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         cidx[m] = ok ? (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
         if (stage > 0) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
+            for (int k = 0; k < NC; ++k) Qs[m][k] = gptr(qin)[k * S.plane + cidx[m]];
         }
         if (reads_qn) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
+            for (int k = 0; k < NC; ++k) Q0[m][k] = gptr(S.q)[k * S.plane + cidx[m]];
         }
     }
 
@@ -159,26 +159,47 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     // plus the stage abscissa, 0, 1, 1/2 (SSP-RK3) or 0, 1/4, 1/3, 1/2 (four-stage)
     const BoundaryClock clk{stage == 0 ? nullptr : &z, p, stage_abscissa(stage) * dt, S.t_res};
 
-    // 1. tile + halo -> primitives in LDS (fully unrolled: all loads in flight)
+    // 1. tile + halo -> primitives in LDS.  Interior tiles issue every load of
+    // the thread first (lanes past the staged box load the box's first cell,
+    // which is on the grid) and convert afterwards, so that all loads are in
+    // flight together; tiles at the boundary map each cell in turn.
     const bool interior = (i0 - HL >= 0) && (i0 + TX + HL <= nx) && (j0 - HL >= 0) && (j0 + TY + HL <= ny);
     constexpr int NLOAD = (LX * LY + NT - 1) / NT;
+    if (interior) {
+        double Qh[NLOAD][NC];
 #pragma unroll
-    for (int it = 0; it < NLOAD; ++it) {
-        const int e = tid + it * NT;
-        if (e >= LX * LY) break;
-        const int ly = e / LX, lx = e - ly * LX;
-        int gi = i0 - HL + lx, gj = j0 - HL + ly;
-        double W[NC];
-        if (interior) {
-            load_prim<NSC>(S, qin, gi, gj, W);
-        } else {
-            // cells past the ghost layers of a ragged tile feed no valid face
-            gi = gi > nx + 1 ? nx + 1 : gi;
-            gj = gj > ny + 1 ? ny + 1 : gj;
-            fetch_prim<METRIC, NSC>(S, qin, gi, gj, W, clk);
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = tid + it * NT < LX * LY ? tid + it * NT : 0;
+            const int ly = e / LX, lx = e - ly * LX;
+            const long long idx = (long long)(j0 - HL + ly) * S.pitch + (i0 - HL + lx);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Qh[it][k] = gptr(qin)[k * S.plane + idx];
         }
 #pragma unroll
-        for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = tid + it * NT;
+            if (e >= LX * LY) break;
+            const int ly = e / LX, lx = e - ly * LX;
+            double W[NC];
+            const double ir = to_prim(S.gm1, Qh[it][0], Qh[it][1], Qh[it][2], Qh[it][3], W);
+#pragma unroll
+            for (int m = 0; m < NSC; ++m) W[4 + m] = Qh[it][4 + m] * ir;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = tid + it * NT;
+            if (e >= LX * LY) break;
+            const int ly = e / LX, lx = e - ly * LX;
+            // cells past the ghost layers of a ragged tile feed no valid face
+            const int gi = min(i0 - HL + lx, nx + 1), gj = min(j0 - HL + ly, ny + 1);
+            double W[NC];
+            fetch_prim<METRIC, NSC>(S, qin, gi, gj, W, clk);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
+        }
     }
     __syncthreads();
 
@@ -287,7 +308,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         const long long idx = cidx[m];
         if (stage == 0) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) r_out[k * S.plane + idx] = Rv[k];
+            for (int k = 0; k < NC; ++k) gptr(r_out)[k * S.plane + idx] = Rv[k];
             if (last) {
                 double W[4] = {sW[0][cj + HL][ci + HL], sW[1][cj + HL][ci + HL], sW[2][cj + HL][ci + HL],
                                sW[3][cj + HL][ci + HL]};
@@ -311,7 +332,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
         double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) qo[k * S.plane + idx] = Qn[k];
+        for (int k = 0; k < NC; ++k) gptr(qo)[k * S.plane + idx] = Qn[k];
         double W[4];
         const double ir = to_prim(S.gm1, Qn[0], Qn[1], Qn[2], Qn[3], W);
         if (!physical(W)) {

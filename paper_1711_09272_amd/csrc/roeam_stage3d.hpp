@@ -223,11 +223,11 @@ __device__ __forceinline__ void own_cells(const DevSolve3 &S, int stage, const d
         cidx[m] = ok ? (long long)(l0 + cl) * S.slab + (long long)(j0 + cj) * S.pitch + (i0 + ci) : 0;
         if (stage > 0) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) Qs[m][k] = qin[k * S.plane + cidx[m]];
+            for (int k = 0; k < NR; ++k) Qs[m][k] = gptr(qin)[k * S.plane + cidx[m]];
         }
         if (reads_qn) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) Q0[m][k] = S.q[k * S.plane + cidx[m]];
+            for (int k = 0; k < NR; ++k) Q0[m][k] = gptr(S.q)[k * S.plane + cidx[m]];
         }
     }
 }
@@ -242,22 +242,40 @@ __device__ __forceinline__ void halo_direct(const DevSolve3 &S, const double *__
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const bool interior = i0 - HL >= 0 && i0 + TX + HL <= nx && j0 - HL >= 0 && j0 + TY + HL <= ny && l0 - HL >= 0 &&
                           l0 + TZ + HL <= nz;
+    if (interior) {
+        // every load of the thread first (lanes past the box load its first
+        // cell, which is on the grid), then the conversions
+        double Qh[NLOAD][NR];
+#pragma unroll
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = threadIdx.x + it * NT < PL ? threadIdx.x + it * NT : 0;
+            const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
+            const long long idx = (long long)(l0 - HL + lz) * S.slab + (long long)(j0 - HL + ly) * S.pitch + (i0 - HL + lx);
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Qh[it][k] = gptr(qin)[k * S.plane + idx];
+        }
+#pragma unroll
+        for (int it = 0; it < NLOAD; ++it) {
+            const int e = threadIdx.x + it * NT;
+            if (e >= PL) break;
+            double W[NR];
+            const double ir = to_prim3(S.gm1, Qh[it], W);
+#pragma unroll
+            for (int m = 0; m < NSC; ++m) W[5 + m] = Qh[it][5 + m] * ir;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) sW[k * PL + e] = W[k];
+        }
+        return;
+    }
 #pragma unroll
     for (int it = 0; it < NLOAD; ++it) {
         const int e = threadIdx.x + it * NT;
         if (e >= PL) break;
         const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
-        int gi = i0 - HL + lx, gj = j0 - HL + ly, gl = l0 - HL + lz;
+        // cells past the ghost layers of a ragged brick feed no face on the grid
+        const int gi = min(i0 - HL + lx, nx + 1), gj = min(j0 - HL + ly, ny + 1), gl = min(l0 - HL + lz, nz + 1);
         double W[NR];
-        if (interior) {
-            load_prim3<NSC>(S, qin, gi, gj, gl, W);
-        } else {
-            // cells past the ghost layers of a ragged brick feed no face on the grid
-            gi = gi > nx + 1 ? nx + 1 : gi;
-            gj = gj > ny + 1 ? ny + 1 : gj;
-            gl = gl > nz + 1 ? nz + 1 : gl;
-            fetch_prim3<NSC>(S, qin, gi, gj, gl, W);
-        }
+        fetch_prim3<NSC>(S, qin, gi, gj, gl, W);
 #pragma unroll
         for (int k = 0; k < NR; ++k) sW[k * PL + e] = W[k];
     }
@@ -306,27 +324,25 @@ __device__ __forceinline__ void halo_prefetch(const DevSolve3 &S, const double *
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const bool interior = i0 - HL >= 0 && i0 + TX + HL <= nx && j0 - HL >= 0 && j0 + TY + HL <= ny && l0 - HL >= 0 &&
                           l0 + TZ + HL <= nz;
+    // (the loads are consumed one brick later, so they need not be grouped)
 #pragma unroll
     for (int it = 0; it < NLOAD; ++it) {
         const int e = threadIdx.x + it * NT;
         Hc[it] = -1;
         if (e >= PL) continue;
         const int lx = e % B::LX, r = e / B::LX, ly = r % B::LY, lz = r / B::LY;
-        int gi = i0 - HL + lx, gj = j0 - HL + ly, gl = l0 - HL + lz;
         long long idx = 0;
         int code = 0;
         if (interior) {
-            idx = (long long)gl * S.slab + (long long)gj * S.pitch + gi;
+            idx = (long long)(l0 - HL + lz) * S.slab + (long long)(j0 - HL + ly) * S.pitch + (i0 - HL + lx);
         } else {
-            gi = gi > nx + 1 ? nx + 1 : gi;
-            gj = gj > ny + 1 ? ny + 1 : gj;
-            gl = gl > nz + 1 ? nz + 1 : gl;
+            const int gi = min(i0 - HL + lx, nx + 1), gj = min(j0 - HL + ly, ny + 1), gl = min(l0 - HL + lz, nz + 1);
             code = map_cell3(S, gi, gj, gl, idx);
         }
         Hc[it] = code;
         if ((code & 7) == 0) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) Hq[it][k] = qin[k * S.plane + idx];
+            for (int k = 0; k < NR; ++k) Hq[it][k] = gptr(qin)[k * S.plane + idx];
         }
     }
 }
@@ -442,7 +458,7 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
         const long long idx = cidx[m];
         if (stage == 0) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) r_out[k * S.plane + idx] = Rv[k];
+            for (int k = 0; k < NR; ++k) gptr(r_out)[k * S.plane + idx] = Rv[k];
             if (last) {
                 const int o = B::cell(ci, cj, cl);
                 double W[5];
@@ -467,7 +483,7 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
         }
         double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
 #pragma unroll
-        for (int k = 0; k < NR; ++k) qo[k * S.plane + idx] = Qn[k];
+        for (int k = 0; k < NR; ++k) gptr(qo)[k * S.plane + idx] = Qn[k];
         double W[5];
         const double ir = to_prim3(S.gm1, Qn, W);
         if (!physical3(W)) atomicOr(&z.nonphys, 1);
