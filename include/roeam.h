@@ -213,8 +213,10 @@ roeam_status roeam_grid_set_boundary_time(roeam_grid *grid, double t);
  * array [4 sides][nscalars] of rho k_m (NULL allowed when no side is
  * Dirichlet).  Call before the grid's residual or step calls; a change drops
  * the grid's stage buffers, captured graphs and tuned tile shapes (waiting for
- * the context stream first).  Grids with scalars run through roeam_residual,
- * roeam_step and roeam_profile_step; roeam_batch_submit rejects them (EINVAL).
+ * the context stream first).  Grids with scalars run through every call,
+ * roeam_batch_submit included (the batch engine groups solves by scalar
+ * count); a grid's scalar count must not change while a solve of it is
+ * submitted and not yet done.
  * EINVAL: nscalars outside 0..ROEAM_MAX_SCALARS, missing or non-finite
  * Dirichlet scalars; EDEVICE. */
 #define ROEAM_MAX_SCALARS 2

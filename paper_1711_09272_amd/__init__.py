@@ -401,20 +401,20 @@ class Solve:
     """One batched solve: grid, parameters, initial state, run length and output.
 
     q0 / q_out: numpy arrays (host) or torch tensors (device) of shape
-    [4, ny, pitch]; they must stay alive until the ticket reports done."""
+    [grid.rows, ny, pitch]; they must stay alive until the ticket reports done."""
 
     def __init__(self, grid: Grid, prm: Dict, q0, nsteps: int, t_end: float = 0.0, q_out=None):
         self.grid, self.prm, self.nsteps, self.t_end = grid, prm, int(nsteps), float(t_end)
         self.q0 = q0
         if q_out is None:
-            q_out = np.zeros((4, grid.ny, grid.pitch))
+            q_out = np.zeros((grid.rows, grid.ny, grid.pitch))
         self.q_out = q_out
         self.ticket = None
 
     @staticmethod
     def _ptr(a, grid):
         if isinstance(a, np.ndarray):
-            assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (4, grid.ny, grid.pitch)
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (grid.rows, grid.ny, grid.pitch)
             return ctypes.c_void_p(a.ctypes.data), 0
         return _dev_ptr(a, grid), 1
 
@@ -430,8 +430,8 @@ class Solve:
 
 
 def padded(grid: Grid, q: np.ndarray) -> np.ndarray:
-    """Host state [4, ny, nx] -> the grid's padded layout [4, ny, pitch]."""
-    out = np.zeros((4, grid.ny, grid.pitch))
+    """Host state [rows, ny, nx] -> the grid's padded layout [rows, ny, pitch]."""
+    out = np.zeros((grid.rows, grid.ny, grid.pitch))
     out[:, :, : grid.nx] = q
     return out
 

@@ -32,12 +32,12 @@ namespace {
 constexpr int kMaxSolves = 4096;
 constexpr size_t kAlign = 256;
 constexpr int kGraphIters = 16;  // even
-constexpr int kGroups = 24;      // order (2) x precision (2) x time scheme (3) x metric (2)
+constexpr int kGroups = 72;      // order (2) x precision (2) x time scheme (3) x metric (2) x scalars (3)
 constexpr int kStatusEvery = 8;  // iterations between status snapshots without a graph
 
 size_t align_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
 
-size_t state_bytes(const roeam_grid *g) { return sizeof(double) * 4 * (size_t)g->ny * (size_t)g->pitch; }
+size_t state_bytes(const roeam_grid *g) { return sizeof(double) * (4 + (size_t)g->nsc) * (size_t)g->ny * (size_t)g->pitch; }
 
 // First-fit allocator over [0, cap) with coalescing.
 struct Arena {
@@ -101,7 +101,7 @@ struct Request {
 };
 
 struct Group {
-    int order = 2, precision = 0, time_scheme = 1, metric = 0, shape = 0;
+    int order = 2, precision = 0, time_scheme = 1, metric = 0, nsc = 0, shape = 0;
     std::vector<TileEntry> tiles;
     TileEntry *d_tiles = nullptr;
     TileEntry *h_tiles = nullptr;  // pinned staging of the last upload
@@ -135,7 +135,7 @@ struct BatchEngine {
     uint64_t next_ticket = 1;
     long iter = 0;
     long since_status = 0;          // iterations since the last status snapshot
-    Group groups[kGroups];          // (order-1, precision, time_scheme, metric)
+    Group groups[kGroups];          // (order-1, precision, time_scheme, metric, nsc)
     bool set_changed = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -147,9 +147,9 @@ struct BatchEngine {
     size_t prof_used = 0;
 };
 
-static int group_id(const roeam_params &p, int metric)
+static int group_id(const roeam_params &p, int metric, int nsc)
 {
-    return ((p.order - 1) * 2 + p.precision) * 6 + p.time_scheme * 2 + metric;
+    return (((p.order - 1) * 2 + p.precision) * 6 + p.time_scheme * 2 + metric) * 3 + nsc;
 }
 
 static void release_engine(BatchEngine *b)
@@ -349,7 +349,7 @@ static roeam_status upload_tiles(roeam_ctx *ctx, BatchEngine *b)
 static hipError_t stage_launch(BatchEngine *b, const Group &G, int n, int stage, int p, int last, hipStream_t s)
 {
     if (!b->profiling)
-        return roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, stage,
+        return roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.nsc, G.shape, stage,
                                          p, last, s);
     hipError_t e = hipSuccess;
     while (e == hipSuccess && b->prof_ev.size() < b->prof_used + 2) {
@@ -359,7 +359,7 @@ static hipError_t stage_launch(BatchEngine *b, const Group &G, int n, int stage,
     }
     if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used], s);
     if (e == hipSuccess)
-        e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.shape, stage, p,
+        e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.nsc, G.shape, stage, p,
                                       last, s);
     if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used + 1], s);
     if (e == hipSuccess) {
@@ -468,10 +468,12 @@ static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes
     for (int i = kMaxSolves - 1; i >= 0; --i) b->free_idx.push_back(i);
     for (int gidx = 0; gidx < kGroups; ++gidx) {
         Group &G = b->groups[gidx];
-        G.order = gidx / 12 + 1;
-        G.precision = (gidx / 6) & 1;
-        G.time_scheme = (gidx / 2) % 3;
-        G.metric = gidx & 1;
+        const int g = gidx / 3;
+        G.order = g / 12 + 1;
+        G.precision = (g / 6) & 1;
+        G.time_scheme = (g / 2) % 3;
+        G.metric = g & 1;
+        G.nsc = gidx % 3;
         G.shape = 0;
     }
     ctx->batch = b;
@@ -494,8 +496,6 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
     for (int i = 0; i < n; ++i) {
         const roeam_solve_desc &d = descs[i];
         if (!d.grid || d.grid->ctx != ctx) return roeam_fail(ctx, ROEAM_EINVAL, "descriptor grid invalid");
-        if (d.grid->nsc != 0)
-            return roeam_fail(ctx, ROEAM_EINVAL, "grids with transported scalars run through roeam_step only");
         roeam_status st = roeam_check_params(ctx, &d.params, true);
         if (st) return st;
         if (!d.q0 || !d.q_out) return roeam_fail(ctx, ROEAM_EINVAL, "q0 and q_out are required");
@@ -508,7 +508,7 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
         Request r;
         r.d = descs[i];
         r.bytes = roeam_batch_footprint(descs[i].grid);
-        r.group = group_id(descs[i].params, descs[i].grid->metric);
+        r.group = group_id(descs[i].params, descs[i].grid->metric, descs[i].grid->nsc);
         b->reqs.emplace(tk, r);
         b->queue.push_back(tk);
         tickets_out[i] = tk;

@@ -31,8 +31,12 @@ hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape,
 // The same with one or two transported scalars (S.nsc), roeam_kernels_sc.hip.
 hipError_t launch_stage_single_sc(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                   double *r_out, hipStream_t st);
+// Batched stage kernel over the tiles of one group (solves that share order,
+// precision, metric and scalar count nsc); nsc > 0 in roeam_kernels_sc.hip.
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int metric, int shape, int stage, int p, int last, hipStream_t st);
+                              int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st);
+hipError_t launch_stage_batch_sc(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
+                                 int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st);
 hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipStream_t st);
 hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,

@@ -103,10 +103,6 @@ void tile_shape(int shape, int *tx, int *ty)
 
 int tile_shape_count() { return kNumShapes; }
 
-#define ROEAM_SHAPE_CASE(ID, TX, TY, NT, SPLIT)                                                              \
-    case ID: hipLaunchKernelGGL((ROEAM_KERNEL<ORDER, PREC, METRIC, TX, TY, NT, SPLIT>), dim3(blocks), dim3(NT), 0, st, \
-                                ROEAM_ARGS); break;
-
 hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape, int stage, int p, int last,
                                double *r_out, hipStream_t st)
 {
@@ -116,38 +112,14 @@ hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape,
     return hipGetLastError();
 }
 
-template <int ORDER, int PREC, int METRIC>
-static void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int stage, int p,
-                               int last, hipStream_t st)
-{
-    const int blocks = ((ntiles + 7) >> 3) << 3;
-#define ROEAM_KERNEL k_stage_batch
-#define ROEAM_ARGS solves, tiles, ntiles, stage, p, last
-    switch (shape) { ROEAM_SHAPES(ROEAM_SHAPE_CASE) }
-#undef ROEAM_KERNEL
-#undef ROEAM_ARGS
-}
-
-template <int ORDER, int PREC>
-static void launch_batch_metric(const DevSolve *solves, const TileEntry *tiles, int ntiles, int metric, int shape,
-                                int stage, int p, int last, hipStream_t st)
-{
-    if (metric == 0) launch_batch_shape<ORDER, PREC, 0>(solves, tiles, ntiles, shape, stage, p, last, st);
-    else launch_batch_shape<ORDER, PREC, 1>(solves, tiles, ntiles, shape, stage, p, last, st);
-}
-
 hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int metric, int shape, int stage, int p, int last, hipStream_t st)
+                              int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
-    if (order == 1) {
-        if (precision == 0) launch_batch_metric<1, 0>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
-        else launch_batch_metric<1, 1>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
-    } else {
-        if (precision == 0) launch_batch_metric<2, 0>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
-        else launch_batch_metric<2, 1>(solves, tiles, ntiles, metric, shape, stage, p, last, st);
-    }
+    if (nsc != 0)
+        return launch_stage_batch_sc(solves, tiles, ntiles, order, precision, metric, nsc, shape, stage, p, last, st);
+    launch_batch_nsc<0>(solves, tiles, ntiles, order, precision, metric, shape, stage, p, last, st);
     return hipGetLastError();
 }
 
@@ -207,8 +179,7 @@ __global__ __launch_bounds__(NT) void k_copy_back_batch(const DevSolve *__restri
         const int gi = te.tx * TX + ci, gj = te.ty * TY + cj;
         if (gi >= S.nx || gj >= S.ny) continue;
         const long long idx = (long long)gj * S.pitch + gi;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
+        for (int k = 0; k < 4 + S.nsc; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
     }
 }
 

@@ -367,16 +367,45 @@ __global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) 
     stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT, NSC>(S, t % txs, t / txs, stage, p, last, t == 0, r_out);
 }
 
-template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, 0)) void k_stage_batch(const DevSolve *__restrict__ solves,
+template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
+__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) void k_stage_batch(const DevSolve *__restrict__ solves,
                                                     const TileEntry *__restrict__ tiles, int ntiles, int stage,
                                                     int p, int last)
 {
     const int t = xcd_tile(blockIdx.x, ntiles);
     if (t >= ntiles) return;
     const TileEntry te = tiles[t];
-    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT, 0>(solves[te.solve], te.tx, te.ty, stage, p, last, te.tx == 0 && te.ty == 0,
-                                        nullptr);
+    stage_tile<ORDER, PREC, METRIC, TX, TY, NT, SPLIT, NSC>(solves[te.solve], te.tx, te.ty, stage, p, last,
+                                                            te.tx == 0 && te.ty == 0, nullptr);
+}
+
+// Batched launch of the stage kernel (solves of one group, all with NSC
+// scalars) on tile shape `shape`.
+#define ROEAM_SHAPE_CASE_BATCH(ID, TX, TY, NT, SPLIT)                                                          \
+    case ID: hipLaunchKernelGGL((k_stage_batch<ORDER, PREC, METRIC, TX, TY, NT, SPLIT, NSC>), dim3(blocks), dim3(NT), \
+                                0, st, solves, tiles, ntiles, stage, p, last); break;
+
+template <int ORDER, int PREC, int METRIC, int NSC>
+inline void launch_batch_shape(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int stage, int p,
+                               int last, hipStream_t st)
+{
+    const int blocks = ((ntiles + 7) >> 3) << 3;
+    switch (shape) { ROEAM_SHAPES(ROEAM_SHAPE_CASE_BATCH) }
+}
+
+template <int NSC>
+inline void launch_batch_nsc(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
+                             int metric, int shape, int stage, int p, int last, hipStream_t st)
+{
+#define ROEAM_BATCH_METRIC(O, P)                                                                              \
+    if (metric == 0) launch_batch_shape<O, P, 0, NSC>(solves, tiles, ntiles, shape, stage, p, last, st);     \
+    else launch_batch_shape<O, P, 1, NSC>(solves, tiles, ntiles, shape, stage, p, last, st);
+    if (order == 1) {
+        if (precision == 0) { ROEAM_BATCH_METRIC(1, 0) } else { ROEAM_BATCH_METRIC(1, 1) }
+    } else {
+        if (precision == 0) { ROEAM_BATCH_METRIC(2, 0) } else { ROEAM_BATCH_METRIC(2, 1) }
+    }
+#undef ROEAM_BATCH_METRIC
 }
 
 // Single-grid launch of the stage kernel with NSC scalars on tile shape `shape`.

@@ -85,6 +85,34 @@ def test_batch_equals_single_runs(C):
         assert np.array_equal(q, qa), c.name
 
 
+def test_batch_with_transported_scalars(C):
+    """Grids with none, one and two scalars in one batch (three work-list
+    groups per scheme): bitwise the solves run alone, and a two-scalar member
+    within 1e-12 of the oracle."""
+    import paper_1711_09272_amd as P
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 51))
+    cases = [workloads.add_scalars(workloads.bump_case(40, rng, 9), 1, seed=1),
+             workloads.add_scalars(workloads.smooth_random_case(45, 29, 3, bc=(DIRICHLET, TRANSMISSIVE, SLIPWALL,
+                                                                                SLIPWALL), nodes=True, order=2,
+                                                                eps1=1.0, mach_ref=0.05), 2, seed=2,
+                                   k_bc=np.array([[0.5, 1.5]] * 4)),
+             workloads.bump_case(33, rng, 5),
+             workloads.add_scalars(workloads.bump_case(37, rng, 6), 2, seed=3, mode="smooth")]
+    cases[1].nsteps = 7
+    cases[3].params["time_scheme"] = 2
+    P.batch_reserve(C, 128 << 20)
+    say(f"[batch scalars] {len(cases)} solves, scalars {[c.q0.shape[0] - 4 for c in cases]}")
+    _, solves = submit_all(C, cases)
+    assert P.batch_run(C, -1) == 0
+    res = collect(C, solves)
+    for c, (q, st, rc) in zip(cases, res):
+        qa, sta = run_alone(C, c)
+        assert rc == P.OK and st["steps"] == sta["steps"] and st["t"] == sta["t"]
+        assert np.array_equal(q, qa), c.name
+    q_or, st_or = oracle.run(cases[1])
+    assert res[1][1]["steps"] == st_or["steps"] and state_error(res[1][0], q_or) <= 1e-12
+
+
 def test_batch_member_matches_oracle(C):
     import paper_1711_09272_amd as P
     cases = family()[:2]
