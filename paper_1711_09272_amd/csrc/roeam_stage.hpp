@@ -78,25 +78,57 @@ __host__ __device__ constexpr double stage_abscissa(int stage)
     return stage == 2 ? 1.0 : stage == 3 ? 0.5 : stage == 5 ? 0.25 : stage == 6 ? 1.0 / 3.0 : stage == 7 ? 0.5 : 0.0;
 }
 
+// The words of the step state a stage decides on, read through a global view
+// (global, not flat, loads: a kernel issues them before its own-cell loads and
+// waits for them without waiting for those).  None of them is written by the
+// kernel that reads them: the first stage reads parity p and publishes p^1.
+struct StepWords {
+    unsigned long long rate_bits;  // rate word `lane` of parity p (first stage)
+    double t, t_end, cfl, dt_n;
+    long long steps, steps_n, max_steps;
+    int nonphys;
+};
+
+__device__ __forceinline__ StepWords load_step_words(const Slot &zs, int p, int stage)
+{
+    typedef __attribute__((address_space(1))) const Slot GSlot;
+    GSlot &z = *(GSlot *)&zs;
+    StepWords w{};
+    w.steps = z.st[p].steps;
+    if (!first_stage(stage)) {
+        w.dt_n = z.st[p ^ 1].dt;
+        w.steps_n = z.st[p ^ 1].steps;
+        return w;
+    }
+    w.rate_bits = z.rate_bits[p][threadIdx.x & 63];
+    w.t = z.st[p].t;
+    w.t_end = z.t_end;
+    w.cfl = z.cfl;
+    w.max_steps = z.max_steps;
+    w.nonphys = z.nonphys;
+    return w;
+}
+
 // Time-step logic shared by all stage kernels of a step with parity p.
 // Returns whether the step is active and its dt.
-__device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, double &dt, double &t_next,
-                                            double &rate)
+__device__ __forceinline__ bool step_active(const StepWords &w, int stage, double &dt, double &t_next, double &rate)
 {
-    const StepState &s = z.st[p];
     if (!first_stage(stage)) {
         // the first stage has already decided: the step ran iff it advanced the count
-        const StepState &n = z.st[p ^ 1];
-        dt = n.dt;
-        return n.steps != s.steps;
+        dt = w.dt_n;
+        return w.steps_n != w.steps;
     }
-    rate = read_rate(z, p);
-    if (z.nonphys || (z.t_end > 0.0 && s.t >= z.t_end) || s.steps >= z.max_steps || !(rate > 0.0)) return false;
-    dt = z.cfl / rate;
-    t_next = s.t + dt;
-    if (z.t_end > 0.0 && s.t + dt >= z.t_end) {
-        dt = z.t_end - s.t;
-        t_next = z.t_end;
+    // max explicit rate of the state: a wave max over the 64 rate words
+    double v = __longlong_as_double((long long)w.rate_bits);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
+    rate = v;
+    if (w.nonphys || (w.t_end > 0.0 && w.t >= w.t_end) || w.steps >= w.max_steps || !(rate > 0.0)) return false;
+    dt = w.cfl / rate;
+    t_next = w.t + dt;
+    if (w.t_end > 0.0 && w.t + dt >= w.t_end) {
+        dt = w.t_end - w.t;
+        t_next = w.t_end;
     }
     return true;
 }
@@ -104,26 +136,26 @@ __device__ __forceinline__ bool step_active(const Slot &z, int p, int stage, dou
 // Start of a stage kernel's workgroup: decide whether the step is active and
 // its dt; on the first stage, workgroup 0 (first_block) publishes the next
 // step state and, unless this stage also ends the step, clears the rate words
-// that the step's last stage will reduce into.
-__device__ __forceinline__ bool begin_stage(Slot &z, int p, int stage, int last, int first_block, double &dt)
+// that the step's last stage will reduce into.  w: load_step_words(z, p, stage).
+__device__ __forceinline__ bool begin_stage(Slot &z, const StepWords &w, int p, int stage, int last, int first_block,
+                                            double &dt)
 {
     double t_next = 0.0, rate = 0.0;
-    const bool active = step_active(z, p, stage, dt, t_next, rate);
+    const bool active = step_active(w, stage, dt, t_next, rate);
     if (first_stage(stage) && first_block) {
         const int tid = threadIdx.x;
         if (tid == 0) {
-            const StepState &s = z.st[p];
             StepState &n = z.st[p ^ 1];
             if (active) {
                 n.t = t_next;
                 n.dt = dt;
-                n.steps = s.steps + 1;
+                n.steps = w.steps + 1;
                 z.dt_last = dt;
                 z.rate_last = rate;
             } else {
-                n.t = s.t;
+                n.t = w.t;
                 n.dt = 0.0;
-                n.steps = s.steps;
+                n.steps = w.steps;
             }
         }
         // multi-stage schemes: the last stage reduces into parity p^1; forward

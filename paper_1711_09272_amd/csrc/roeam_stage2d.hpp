@@ -131,9 +131,11 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     const int i0 = tx * TX, j0 = ty * TY;
     const int nx = S.nx, ny = S.ny;
 
-    // Own cells' stage input (and Q^n for stages 2-3) are loaded first so their
-    // latency is hidden behind the face work; cells outside the grid load cell
-    // (0, 0) and are never stored.
+    // The step-state words first, then the own cells' stage input (and Q^n for
+    // stages 2-3), whose latency is hidden behind the face work; cells outside
+    // the grid load cell (0, 0) and are never stored.
+    Slot &z = *S.slot;
+    const StepWords sw = stage > 0 ? load_step_words(z, p, stage) : StepWords{};
     double Qs[CPT][NC], Q0[CPT][NC];
     long long cidx[CPT];
 #pragma unroll
@@ -152,9 +154,8 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         }
     }
 
-    Slot &z = *S.slot;
     double dt = 0.0;
-    if (stage > 0 && !begin_stage(z, p, stage, last, first_block, dt)) return;
+    if (stage > 0 && !begin_stage(z, sw, p, stage, last, first_block, dt)) return;
     // time of this stage's input state (moving boundary sides): the step start
     // plus the stage abscissa, 0, 1, 1/2 (SSP-RK3) or 0, 1/4, 1/3, 1/2 (four-stage)
     const BoundaryClock clk{stage == 0 ? nullptr : &z, p, stage_abscissa(stage) * dt, S.t_res};

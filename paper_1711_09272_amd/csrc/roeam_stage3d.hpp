@@ -505,13 +505,15 @@ __global__ __launch_bounds__(NT) void k_stage3(const DevSolve3 *__restrict__ Sp,
     int i0, j0, l0;
     brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
     const double *__restrict__ qin = stage_input3(S, stage);
-    // own cells' stage input (and Q^n) first, so their latency hides behind the face work
+    // the step-state words, then the own cells' stage input (and Q^n), whose
+    // latency hides behind the face work
+    Slot &z = *S.slot;
+    const StepWords sw = stage > 0 ? load_step_words(z, p, stage) : StepWords{};
     double Qs[CPT][NR], Q0[CPT][NR];
     long long cidx[CPT];
     own_cells<NSC, TX, TY, TZ, NT>(S, stage, qin, i0, j0, l0, Qs, Q0, cidx);
-    Slot &z = *S.slot;
     double dt = 0.0;
-    if (stage > 0 && !begin_stage(z, p, stage, last, t == 0, dt)) return;
+    if (stage > 0 && !begin_stage(z, sw, p, stage, last, t == 0, dt)) return;
     // 1. brick + halo -> primitives in LDS
     halo_direct<ORDER, NSC, TX, TY, TZ, NT>(S, qin, i0, j0, l0, L.sW);
     __syncthreads();
@@ -538,6 +540,8 @@ __global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp
     const int t_end = min(nb, (xcd + 1) * chunk);
     int t = xcd * chunk + (blockIdx.x >> 3);
     const double *__restrict__ qin = stage_input3(S, stage);
+    Slot &z = *S.slot;
+    const StepWords sw = stage > 0 ? load_step_words(z, p, stage) : StepWords{};
     double Hq[NLOAD][NR];
     int Hc[NLOAD];
     int i0, j0, l0;
@@ -545,9 +549,8 @@ __global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp
         brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
         halo_prefetch<ORDER, NSC, TX, TY, TZ, NT>(S, qin, i0, j0, l0, Hq, Hc);
     }
-    Slot &z = *S.slot;
     double dt = 0.0;
-    if (stage > 0 && !begin_stage(z, p, stage, last, blockIdx.x == 0, dt)) return;
+    if (stage > 0 && !begin_stage(z, sw, p, stage, last, blockIdx.x == 0, dt)) return;
     double lmax = 0.0;
     for (; t < t_end; t += per_xcd) {
         brick_origin<TX, TY, TZ>(S, t, i0, j0, l0);
