@@ -1,8 +1,10 @@
 """Parity at the full sizes the benchmark runs, in its launch configuration:
 the fourth configuration's 256 grids through the batch engine (group shape
-chosen as in the bench), and the 2048^2 vortex of the roofline sweep through
-roeam_step with the autotuned shape.  The oracle computes a sample of grids
-(always including the largest) or the whole 2048^2 grid for a few steps."""
+chosen as in the bench), the 2048^2 vortex of the roofline sweep through
+roeam_step with the autotuned shape, and the 128^3 extruded vortex through
+roeam_step3d with the default persistent bricks (with two transported scalars:
+the fallback bricks).  The oracle computes a sample of grids (always including
+the largest) or the whole grid for a few steps."""
 import numpy as np
 import pytest
 
@@ -59,3 +61,23 @@ def test_vortex2048_full_size(C):
     say(f"[vortex 2048^2] shape {P.SHAPES[g.tile_shape(case.params)]} 2 steps err {err:.3e}")
     assert st["steps"] == 2 and abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("precision,nsc,tol", [(0, 0, 1e-12), (1, 0, 1e-6), (0, 2, 1e-12)])
+def test_vortex3d128_full_size(C, precision, nsc, tol):
+    """128^3, MUSCL + SSP-RK3, two steps in the 3-D bench's launch configuration
+    (default brick shape), against the FP64 oracle."""
+    import paper_1711_09272_amd as P
+    import torch
+    case = workloads.vortex3(128, 128, 0.01, precision=precision)
+    if nsc:
+        case = workloads.add_scalars(case, nsc, seed=61, mode="smooth")
+    g = P.Grid3.from_case(C, case)
+    q = g.to_device(case.q0)
+    st = P.step3(C, g, case.params, q, 2, 0.0, 0.0)
+    torch.cuda.synchronize()
+    q_or, st_or = oracle.run3(case, nsteps=2, params=dict(case.params, precision=0))
+    err = state_error(g.from_device(q), q_or)
+    say(f"[vortex3d 128^3] precision {precision}, {nsc} scalars, 2 steps err {err:.3e}")
+    assert st["steps"] == 2 and abs(st["t"] - st_or["t"]) <= 1e-13 * st_or["t"]
+    assert err <= tol
