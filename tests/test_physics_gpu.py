@@ -1,7 +1,8 @@
-"""Physics of the second configuration on the GPU path (no oracle run needed):
-after the vortex configuration's 1000 SSP-RK3 steps, the pressure-fluctuation
-index Ind(p) = (p_max - p_min) / p_max of Fig. 12 scales with M^2 for Roe-AM,
-and classical Roe adds O(M) fluctuations to it (Eqs. 31-32)."""
+"""Physics on the GPU path's own output (no oracle run needed): after the vortex
+configuration's 1000 SSP-RK3 steps, the pressure-fluctuation index
+Ind(p) = (p_max - p_min) / p_max of Fig. 12 scales with M^2 for Roe-AM, and
+classical Roe adds O(M) fluctuations to it (Eqs. 31-32); the expansion shock of
+Fig. 3, the near-vacuum tube of Sec. 7.1.2 and the checkerboard of Fig. 11."""
 import numpy as np
 import pytest
 
@@ -44,3 +45,83 @@ def test_pressure_fluctuation_scaling_after_1000_steps(C):
     assert 70.0 <= out[0][2] <= 130.0
     assert out[1][2] < 70.0
     assert out[1][1] > 2.0 * out[0][1]
+
+
+# --- Figures of Sec. 7.1 and Fig. 11 on the GPU's own output -----------------------
+
+def prim(q, g=1.4):
+    rho = q[0]
+    u, v = q[1] / rho, q[2] / rho
+    return rho, u, v, (g - 1) * (q[3] - 0.5 * rho * (u * u + v * v))
+
+
+def checker(q):
+    """Amplitude of the (-1)^(i+j) pressure mode."""
+    n = q.shape[1]
+    I, J = np.meshgrid(np.arange(q.shape[2]), np.arange(n))
+    p = prim(q)[3]
+    return abs(np.sum(np.where((I + J) % 2 == 0, 1, -1) * (p - p.mean()))) / p.size
+
+
+def run(c, case, **over):
+    import torch
+    import paper_1711_09272_amd as P
+    g = P.Grid.from_case(c, case)
+    q = g.to_device(case.q0)
+    st = P.step(c, g, dict(case.params, **over), q, case.nsteps, 0.0, case.t_end)
+    torch.cuda.synchronize()
+    return g.from_device(q), st
+
+
+def test_gpu_expansion_shock_fig3(C):
+    """Sec. 7.1.1: classical Roe and Roe-AM without Eq. (92) keep an expansion
+    shock at x = 0.3; the full Roe-AM opens it (largest density jump between
+    neighbouring cells near x = 0.3, against the exact solution's)."""
+    import exact_riemann as er
+    import oracle
+    x = (np.arange(200) + 0.5) / 200
+    exact_jump = np.abs(np.diff(er.sample((3, 0.9, 3), (1, 0.9, 1), x, 0.3, 0.2)[0]))[55:65].max()
+    case = workloads.expansion_shock_tube(nx=200, ny=2)
+    jumps = {}
+    for name, over in (("roe", dict(scheme=oracle.SCHEME_ROE)), ("noeq92", dict(variant=oracle.V_NO_EQ92)),
+                       ("roeam", {})):
+        q, st = run(C, case, **over)
+        assert st["t"] == 0.2 and st["nonphys"] == 0
+        jumps[name] = np.abs(np.diff(q[0, 0]))[55:65].max()
+    say(f"[Fig. 3 on the GPU] jumps {jumps}, exact {exact_jump:.3e}")
+    assert jumps["roe"] > 8 * exact_jump and jumps["noeq92"] > 8 * exact_jump
+    assert jumps["roeam"] < 3 * exact_jump
+
+
+def test_gpu_near_vacuum(C):
+    """Sec. 7.1.2: classical Roe produces a non-physical state; Roe-AM reaches
+    t = 0.15 with positive density and pressure."""
+    import paper_1711_09272_amd as P
+    import oracle
+    case = workloads.near_vacuum_tube(nx=200, ny=2)
+    with pytest.raises(P.NonPhysicalError):
+        run(C, case, scheme=oracle.SCHEME_ROE)
+    q, st = run(C, case)
+    rho, _, _, p = prim(q)
+    say(f"[near vacuum on the GPU] t {st['t']}, min rho {rho.min():.3e}, min p {p.min():.3e}")
+    assert st["t"] == 0.15 and rho.min() > 0 and p.min() > 0
+
+
+@pytest.mark.parametrize("n", [32, 256])
+def test_gpu_checkerboard_suppression_fig11(C, n):
+    """Fig. 11 on the vortex (at 32^2 and at the second configuration's 256^2):
+    the full Roe-AM removes the +-1e-6 pressure checkerboard within 20 steps,
+    dU_p = 0 keeps it, dU_p of Eq. (17) removes it only slowly."""
+    import oracle
+    case = workloads.vortex(n=n, mach=0.01)
+    case.nsteps, case.t_end = 20, 0.0
+    c0 = checker(case.q0)
+    out = {}
+    for name, var in (("roeam", 0), ("zero", oracle.V_DUP_ZERO), ("roe17", oracle.V_DUP_ROE)):
+        q, st = run(C, case, variant=var)
+        assert st["steps"] == 20 and st["nonphys"] == 0
+        out[name] = checker(q) / c0
+    say(f"[Fig. 11 on the GPU] {n}^2: checkerboard left after 20 steps {out}")
+    assert out["roeam"] < 1e-3
+    assert out["zero"] > 0.9
+    assert 0.3 < out["roe17"] < 0.99
