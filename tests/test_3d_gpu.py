@@ -214,3 +214,33 @@ def test_invalid_arguments_3d(C):
     q = g.to_device(case.q0)
     with pytest.raises(P.RoeamError):
         P.residual3(C, g, dict(case.params, order=3), q)
+
+
+def test_graph_replays_match_eager_steps_3d(C):
+    """The 3-D step's captured graph, replayed across calls with torch work and
+    host synchronisations between them, and replayed three times within one
+    call, gives the eager one-step-per-call states bit for bit."""
+    import torch
+    import paper_1711_09272_amd as P
+    case = workloads.vortex3(24, 8, 0.01, time_scheme=1)
+    g = P.Grid3.from_case(C, case)
+    q = g.to_device(case.q0)
+    t, snaps = 0.0, {}
+    for k in range(1, 111):
+        t = P.step3(C, g, case.params, q, 1, t)["t"]
+        if k % 6 == 0 or k == 110:
+            snaps[k] = (g.from_device(q), t)
+    q2 = g.to_device(case.q0)
+    t = 0.0
+    for k in (6, 12, 18):
+        t = P.step3(C, g, case.params, q2, 6, t)["t"]
+        x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+        float((x * x).sum())
+        torch.cuda.synchronize()
+        assert np.array_equal(g.from_device(q2), snaps[k][0]) and t == snaps[k][1], k
+    q3 = g.to_device(case.q0)
+    st = P.step3(C, g, case.params, q3, 110)
+    torch.cuda.synchronize()
+    say(f"[graph replays 3-D] 110 steps to t = {st['t']:.6e}")
+    assert st["steps"] == 110 and st["t"] == snaps[110][1]
+    assert np.array_equal(g.from_device(q3), snaps[110][0])

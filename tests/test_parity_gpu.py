@@ -251,3 +251,38 @@ def test_odd_even_fig6i_to_t100(C):
     say(f"[step] odd-even Fig. 6(i) to t=100: {st['steps']} steps (oracle {st_or['steps']}), err {err:.3e}")
     assert st["t"] == 100.0 and st["steps"] == st_or["steps"]
     assert err <= TOL64
+
+
+@pytest.mark.parametrize("ts", [0, 1, 2])
+def test_graph_replays_match_eager_steps(C, ts):
+    """roeam_step captures multi-step runs into a HIP graph and replays it from a
+    cache on later calls.  Against the eager path (one step per call, no graph):
+    every replay, with the program's own torch work, a residual call and host
+    synchronisations between the replays, gives the eager state bit for bit, and
+    so does one long call replaying its 50-step graph three times (the last
+    replay partly past the step budget, whose steps are inactive)."""
+    import torch
+    import paper_1711_09272_amd as P
+    case = workloads.vortex(64, 0.01, time_scheme=ts)
+    g = P.Grid.from_case(C, case)
+    q = g.to_device(case.q0)
+    t, snaps = 0.0, {}
+    for k in range(1, 111):
+        t = P.step(C, g, case.params, q, 1, t)["t"]
+        if k % 6 == 0 or k == 110:
+            snaps[k] = (g.from_device(q), t)
+    say(f"[graph replays] time scheme {ts}: eager 110 steps to t = {t:.6e}")
+    q2 = g.to_device(case.q0)
+    t = 0.0
+    for k in (6, 12, 18, 24):
+        t = P.step(C, g, case.params, q2, 6, t)["t"]
+        x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+        float((x * x).sum())
+        P.residual(C, g, case.params, g.to_device(case.q0))
+        torch.cuda.synchronize()
+        assert np.array_equal(g.from_device(q2), snaps[k][0]) and t == snaps[k][1], k
+    q3 = g.to_device(case.q0)
+    st = P.step(C, g, case.params, q3, 110)
+    torch.cuda.synchronize()
+    assert st["steps"] == 110 and st["t"] == snaps[110][1]
+    assert np.array_equal(g.from_device(q3), snaps[110][0])
