@@ -168,7 +168,7 @@ roeam_status roeam_ctx_set_stream(roeam_ctx *ctx, void *hip_stream);
 /* Text of the last error of this context (never NULL). */
 const char *roeam_last_error(const roeam_ctx *ctx);
 
-/* Create a grid of nx x ny cells (nx, ny >= 2).  bc[4] = kinds for west,
+/* Create a grid of nx x ny cells (nx, ny >= 2, nx * ny < 2^31).  bc[4] = kinds for west,
  * east, south, north; a periodic kind must be used on both sides of its
  * direction.  dirichlet_state: HOST array [4 sides][4] of conserved states,
  * used by DIRICHLET sides (NULL allowed if none).  The grid owns device
