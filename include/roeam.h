@@ -263,6 +263,18 @@ roeam_status roeam_last_stats(roeam_ctx *ctx, const roeam_grid *grid, roeam_step
  * buffer, allocated at the first call.  Asynchronous.  EINVAL: NULL argument;
  * EDEVICE. */
 roeam_status roeam_residual_norms(roeam_ctx *ctx, const roeam_grid *grid, const double *r, double *norms_out);
+/* roeam_residual_norms without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and bits as
+ * roeam_residual_norms.  Its partials live in a static device buffer of
+ * 2 x 6 rows x 1024 blocks doubles (96 KiB) that every GPU the library runs on
+ * holds until the process ends; its device address is taken when a context is
+ * created on that GPU.  All calls on one GPU share that buffer, so calls whose
+ * work overlaps on one GPU (other streams, other contexts, other host threads)
+ * race: order them on one stream.  Nothing in the buffer needs clearing (each
+ * call writes every partial it reads).  EINVAL: NULL argument, or a grid
+ * whose partials exceed the buffer (more than 6 rows); EDEVICE. */
+roeam_status roeam_residual_norms_noalloc(roeam_ctx *ctx, const roeam_grid *grid, const double *r, double *norms_out);
 
 /* ------------------------------------------------------------------------ */
 /* 3-D uniform Cartesian grids                                              */

@@ -30,7 +30,7 @@ EXPORTS = [
     "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll", "roeam_batch_attach", "roeam_residual_norms",
-    "roeam_residual_norms3d",
+    "roeam_residual_norms3d", "roeam_residual_norms_noalloc",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
     "roeam_grid3d_set_scalars", "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
@@ -107,6 +107,7 @@ def lib():
         "roeam_last_stats": (i, [vp, vp, ctypes.POINTER(StepStats)]),
         "roeam_residual_norms": (i, [vp, vp, vp, vp]),
         "roeam_residual_norms3d": (i, [vp, vp, vp, vp]),
+        "roeam_residual_norms_noalloc": (i, [vp, vp, vp, vp]),
         "roeam_profile_step": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d,
                                    ctypes.POINTER(ctypes.c_double * 4), ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_reserve": (i, [vp, ctypes.c_size_t]),
@@ -366,6 +367,22 @@ def residual_norms(ctx: Context, grid, r):
     ctx.enter()
     try:
         ctx.check(fn(ctx.h, grid.h, rp, ctypes.c_void_p(out.data_ptr())))
+    finally:
+        ctx.leave()
+    return out.view(2, rows)
+
+
+def residual_norms_noalloc(ctx: Context, grid: Grid, r, out):
+    """roeam_residual_norms_noalloc: the norms of a 2-D residual tensor into the
+    caller's float64 device tensor `out` (2 * rows elements); nothing is
+    allocated, here or in the library.  Returns `out` viewed as [2, rows]."""
+    rows = grid.rows
+    if out.dtype != __import__("torch").float64 or not out.is_cuda or out.numel() != 2 * rows \
+            or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float64 device tensor of {2 * rows} elements")
+    ctx.enter()
+    try:
+        ctx.check(lib().roeam_residual_norms_noalloc(ctx.h, grid.h, _dev_ptr(r, grid), ctypes.c_void_p(out.data_ptr())))
     finally:
         ctx.leave()
     return out.view(2, rows)

@@ -49,6 +49,11 @@ hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
 constexpr int kNormMaxBlocks = 1024;
 hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int nlines, long long pitch, double *part,
                         int max_blocks, double *out, hipStream_t st);
+// Doubles of partials launch_norms uses for these sizes.
+long long norms_partial_doubles(int rows, int nx, int nlines, int max_blocks);
+// Take the device address of the allocation-free norms scratch on `device`
+// (the current device), once per device; called when a context is created.
+hipError_t scratch_setup(int device);
 
 // 3-D uniform Cartesian grids (brick shapes 0..brick_shape_count()-1).
 int brick_shape_count();

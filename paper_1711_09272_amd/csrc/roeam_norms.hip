@@ -1,7 +1,10 @@
 // roeam_norms.hip -- residual norms (RMS and max |.| per row) of 2-D and 3-D
 // residual arrays, by a fixed-order reduction whose result does not depend on
 // timing.
+#include <mutex>
+
 #include "roeam_device.hpp"
+#include "roeam_host.hpp"
 #include "roeam_internal.hpp"
 #include "roeam_stage.hpp"
 
@@ -74,17 +77,33 @@ __global__ __launch_bounds__(kNormThreads) void k_norms_final(const double *__re
     out[t] = t < ROWS ? sqrt(a * inv_cells) : a;
 }
 
+// Partition of nlines lines of nx elements over the partial blocks: about 8
+// elements per thread per block, at most max_blocks blocks.
+static void norms_partition(int nx, int nlines, int max_blocks, long long *lines_per_block, long long *nblocks)
+{
+    long long lpb = ((long long)kNormThreads * 8 + nx - 1) / nx;
+    long long nb = (nlines + lpb - 1) / lpb;
+    if (nb > max_blocks) {
+        lpb = (nlines + max_blocks - 1) / max_blocks;
+        nb = (nlines + lpb - 1) / lpb;
+    }
+    *lines_per_block = lpb;
+    *nblocks = nb;
+}
+
+long long norms_partial_doubles(int rows, int nx, int nlines, int max_blocks)
+{
+    long long lpb = 0, nb = 0;
+    norms_partition(nx, nlines, max_blocks, &lpb, &nb);
+    return 2ll * rows * nb;
+}
+
 hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int nlines, long long pitch, double *part,
                         int max_blocks, double *out, hipStream_t st)
 {
     if (rows < 4 || rows > 7 || nx < 1 || nlines < 1) return hipErrorInvalidValue;
-    // about 8 elements per thread per block, at most max_blocks blocks
-    long long lines_per_block = ((long long)kNormThreads * 8 + nx - 1) / nx;
-    long long nb = (nlines + lines_per_block - 1) / lines_per_block;
-    if (nb > max_blocks) {
-        lines_per_block = (nlines + max_blocks - 1) / max_blocks;
-        nb = (nlines + lines_per_block - 1) / lines_per_block;
-    }
+    long long lines_per_block = 0, nb = 0;
+    norms_partition(nx, nlines, max_blocks, &lines_per_block, &nb);
     const double inv = 1.0 / ((double)nx * (double)nlines);
 #define ROEAM_NORMS(R)                                                                                            \
     case R:                                                                                                       \
@@ -97,4 +116,62 @@ hipError_t launch_norms(const double *r, int rows, long long plane, int nx, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free residual norms.  The partials of the two-pass reduction live
+// in a file-scope device array, one copy per GPU for the life of the process,
+// sized for the most rows a 2-D grid has (4 + kMaxScalars) and the most
+// partial blocks launch_norms uses.  In host code the array's name is only a
+// host-side stand-in: its device address on each GPU is taken once, with that
+// GPU current, when a context is created on it (scratch_setup), and only that
+// address is passed to kernels.  Every call on one GPU shares the array.
+// ---------------------------------------------------------------------------
+constexpr int kScratchRows = 4 + kMaxScalars;
+constexpr long long kScratchDoubles = 2ll * kScratchRows * kNormMaxBlocks;  // 96 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = (double *)p;
+    return hipSuccess;
+}
+
+static double *scratch_on(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
 } // namespace roeam
+
+extern "C" roeam_status roeam_residual_norms_noalloc(roeam_ctx *ctx, const roeam_grid *g, const double *r,
+                                                     double *norms_out)
+{
+    if (!ctx || !g || !r || !norms_out) return roeam_fail(ctx, ROEAM_EINVAL, "NULL argument");
+    if (g->ctx != ctx) return roeam_fail(ctx, ROEAM_EINVAL, "grid belongs to another context");
+    const int rows = 4 + g->nsc;
+    const long long need = roeam::norms_partial_doubles(rows, g->nx, g->ny, roeam::kNormMaxBlocks);
+    if (rows > roeam::kScratchRows || need > roeam::kScratchDoubles)
+        return roeam_fail(ctx, ROEAM_EINVAL,
+                          "residual norms need " + std::to_string(need) + " partial doubles, more than the " +
+                              std::to_string(roeam::kScratchDoubles) + " of the static scratch");
+    double *part = roeam::scratch_on(ctx->device);
+    if (!part) return roeam_fail(ctx, ROEAM_EDEVICE, "static scratch has no device address on this GPU");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = roeam::launch_norms(r, rows, (long long)g->ny * g->pitch, g->nx, g->ny, g->pitch, part, roeam::kNormMaxBlocks,
+                                norms_out, ctx->stream);
+    if (e != hipSuccess) return roeam_fail(ctx, ROEAM_EDEVICE, std::string("residual norms: ") + hipGetErrorString(e));
+    return ROEAM_OK;
+}

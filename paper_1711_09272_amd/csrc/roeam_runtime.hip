@@ -165,6 +165,7 @@ roeam_status roeam_ctx_create(int device, void *hip_stream, roeam_ctx **out)
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ROEAM_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return ROEAM_EDEVICE;
+    if (roeam::scratch_setup(device) != hipSuccess) return ROEAM_EDEVICE;
     roeam_ctx *c = new (std::nothrow) roeam_ctx;
     if (!c) return ROEAM_ENOMEM;
     c->device = device;
