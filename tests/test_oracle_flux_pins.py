@@ -335,23 +335,42 @@ def test_rotated_speed_limits():
         assert d["frr"] <= math.hypot(d["u"], d["v"]) * (1 + 1e-14)
 
 
-def test_expansion_fix_eq72_form():
-    """Eq. (72): with U = (U_R+U_L)/2, |U| < c and U_R > U_L, Eq. (70) (the f = 1 case
-    of Eq. 92) gives min(|U_L|, |U_R|) when U_L and U_R have one sign."""
-    # a face where the Roe-averaged normal velocity equals the arithmetic one:
-    # equal densities make the Roe average the arithmetic mean.
+@pytest.mark.parametrize("UL,UR,kind", [(0.2, 0.5, "eq72"), (-0.6, -0.1, "eq72"), (0.05, 0.9, "eq72"),
+                                         (0.5, 0.2, "unchanged"), (-0.1, -0.6, "unchanged"),
+                                         (2.0, 2.5, "unchanged"), (-2.5, -2.0, "unchanged"),
+                                         (-0.3, 0.4, "opposite")])
+def test_expansion_fix_eq70_eq72(UL, UR, kind):
+    """Eqs. (70)-(72).  Eq. (92) weights the correction of Eq. (70),
+    [sign(U + c) - sign(U - c)] max(0, U_R - U_L) / 4, by f(Mbar); the Eq. (73)
+    reading bit weights it by f^8(Mbar).  Recovering the unweighted correction
+    from both weights (dividing by f and f^8 of the oracle's Mbar) must give one
+    value, and Eq. (70)'s |U|' = |U| - correction must be what Eq. (72) states:
+    with U = (U_R + U_L)/2 (equal densities and pressures make the Roe average
+    arithmetic), |U| < c and U_R > U_L it is min(|U_L|, |U_R|) when U_L and U_R
+    have one sign; |U| otherwise (compression, or |U| >= c).  With opposite
+    signs Eq. (70) leaves |U| - dU/2 < 0 (reading D4: no clamp)."""
     prm = workloads.default_params(mach_ref=1.0)
-    for UL, UR in [(0.2, 0.5), (-0.6, -0.1), (0.05, 0.9)]:
-        WL = np.array([1.0, UL, 0.0, 1.0])
-        WR = np.array([1.0, UR, 0.0, 1.0])
-        _, d = oracle.face_flux(prm, WL, WR, 1.0, 0.0)
-        fMbar = oracle.f(d["Mbar"])
-        expect = abs(d["U"]) - fMbar * (UR - UL) / 2
-        assert d["absUp"] == pytest.approx(expect, rel=1e-14)
-        if fMbar == 1.0:
-            assert d["absUp"] == pytest.approx(min(abs(UL), abs(UR)), rel=1e-14)
-    # supersonic face: no change
-    WL = np.array([1.0, 2.0, 0.0, 1.0])
-    WR = np.array([1.0, 2.5, 0.0, 1.0])
+    WL = np.array([1.0, UL, 0.0, 1.0])
+    WR = np.array([1.0, UR, 0.0, 1.0])
     _, d = oracle.face_flux(prm, WL, WR, 1.0, 0.0)
-    assert d["absUp"] == abs(d["U"])
+    _, d8 = oracle.face_flux(dict(prm, variant=oracle.V_EXPFIX_F8), WL, WR, 1.0, 0.0)
+    assert d["U"] == pytest.approx(0.5 * (UL + UR), rel=1e-15, abs=1e-16)  # Eq. (71)
+    assert d8["Mbar"] == d["Mbar"] and d8["U"] == d["U"]
+    fb = oracle.f(d["Mbar"])
+    assert 0.0 < fb <= 1.0
+    corr = (abs(d["U"]) - d["absUp"]) / fb
+    corr8 = (abs(d8["U"]) - d8["absUp"]) / fb ** 8
+    # the f^8 weight is tiny at small Mbar: allow a few ulp of |U| divided by it
+    assert corr == pytest.approx(corr8, rel=1e-11, abs=4e-16 * max(1.0, abs(d["U"])) / fb ** 8)
+    eq70 = abs(d["U"]) - corr
+    subsonic = abs(d["U"]) < d["c"]
+    if kind == "eq72":
+        assert subsonic and UR > UL and UL * UR > 0  # the branch of Eq. (72) is taken
+        assert corr > 0
+        assert eq70 == pytest.approx(min(abs(UL), abs(UR)), rel=1e-13)
+    elif kind == "unchanged":
+        assert not (subsonic and UR > UL)
+        assert corr == 0.0 and d["absUp"] == abs(d["U"])
+    else:
+        assert subsonic and UR > UL and UL * UR < 0
+        assert eq70 < 0.0 and eq70 < min(abs(UL), abs(UR))

@@ -157,7 +157,7 @@ def test_nonphysical_state_is_reported(C):
 
 def test_near_vacuum_roe_am_survives(C):
     """Sec. 7.1.2 on the GPU path: Roe-AM keeps rho, p > 0 to t = 0.15."""
-    case = workloads.near_vacuum_tube(nx=200, ny=2)
+    case = workloads.near_vacuum_tube()
     q_or, st_or = oracle.run(case)
     q_gpu, st = gpu_run(C, case)
     assert st["nonphys"] == 0 and st["t"] == 0.15

@@ -111,7 +111,7 @@ def test_gpu_expansion_shock_fig3(C):
     import oracle
     x = (np.arange(200) + 0.5) / 200
     exact_jump = np.abs(np.diff(er.sample((3, 0.9, 3), (1, 0.9, 1), x, 0.3, 0.2)[0]))[55:65].max()
-    case = workloads.expansion_shock_tube(nx=200, ny=2)
+    case = workloads.expansion_shock_tube()
     jumps = {}
     for name, over in (("roe", dict(scheme=oracle.SCHEME_ROE)), ("noeq92", dict(variant=oracle.V_NO_EQ92)),
                        ("roeam", {})):
@@ -128,7 +128,7 @@ def test_gpu_near_vacuum(C):
     t = 0.15 with positive density and pressure."""
     import paper_1711_09272_amd as P
     import oracle
-    case = workloads.near_vacuum_tube(nx=200, ny=2)
+    case = workloads.near_vacuum_tube()
     with pytest.raises(P.NonPhysicalError):
         run(C, case, scheme=oracle.SCHEME_ROE)
     q, st = run(C, case)
