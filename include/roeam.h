@@ -393,20 +393,48 @@ size_t roeam_batch_footprint(const roeam_grid *grid);
  * EINVAL: bad descriptor (validated before anything is queued). */
 roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *descs,
                                 uint64_t *tickets_out);
-/* Drive the scheduler for up to `iterations` iterations (0: only admit and
- * retire; -1: until every queued solve is done).  Returns the number of
- * solves still pending in *pending (nullable). */
+/* Drive the scheduler for `iterations` iterations, rounded up to whole
+ * graphs of graph_iters (0: only admit and retire; -1: until every queued
+ * solve is done).  Every iteration advances each resident solve by one step;
+ * a solve whose budget or end time is reached idles until the status read
+ * after its graph retires it.  Returns the number of solves still pending in
+ * *pending (nullable). */
 roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending);
 /* Profiling aid (same arithmetic as roeam_batch_run): drive the scheduler
  * with every kernel launched directly (no graphs), HIP events recorded on
  * the context stream around each batched stage kernel, and the status read
- * after every iteration (a host wait per iteration), so that finished solves
- * leave at once and no timed launch is an idle one.  Waits for the stream, then writes the mean duration in
+ * after every second iteration (a host wait each time), so that finished
+ * solves leave at once and few timed launches are idle ones.  Waits for the stream, then writes the mean duration in
  * milliseconds of the batched stage kernels into stage_ms[0..3] (first to
  * fourth stage of a step; a stage that never ran reads 0) and the number of
  * timed launches into *launches (nullable).  Errors as roeam_batch_run. */
 roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pending, double stage_ms[4],
                                      long *launches);
+/* Scheduler options.  graph_iters: iterations per captured graph (even,
+ * 2..256; default 16): a finished solve is noticed after the graph it
+ * finished in.  persistent: 1 runs the batched stage kernels as resident
+ * workgroups that take the tiles of a work list in turn, 0 (default) one
+ * workgroup per tile.  policy: order in which queued solves are admitted when
+ * arena space frees up, ROEAM_ADMIT_FIFO (default) or ROEAM_ADMIT_SHORTEST
+ * (increasing cells x steps).  autotune: 1 (default) times the batched
+ * kernel on a group's real work list for every tile shape when the group
+ * first forms and keeps the fastest; 0 takes 16x7/256 below about 200k cells
+ * and 16x15/256 above (a shape forced on the group's first grid wins either
+ * way).  Applies from the next scheduler iteration.  EINVAL: out of range or
+ * no engine. */
+enum { ROEAM_ADMIT_FIFO = 0, ROEAM_ADMIT_SHORTEST = 1 };
+roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune);
+/* Counters of the batch engine: graph captures so far (one when the first
+ * group forms, then only when a group appears or empties or a work list's
+ * capacity changes: admitting and retiring solves that fit does not
+ * re-capture), graph launches, scheduler iterations, tile-shape tunings, the
+ * resident and queued solves, the options, and the tile shape of the group
+ * formed last (-1: none yet). */
+typedef struct {
+    long captures, graph_launches, iterations, tunes;
+    int resident, queued, graph_iters, persistent, policy, shape;
+} roeam_batch_stats;
+roeam_status roeam_batch_info(roeam_ctx *ctx, roeam_batch_stats *out);
 /* Non-blocking poll: *done = 1 once the solve's output is written; stats
  * (nullable) then holds its statistics.  A solve that produced a
  * non-physical state is done with return value ROEAM_ENONPHYS; the other

@@ -30,7 +30,7 @@ EXPORTS = [
     "roeam_residual", "roeam_step",
     "roeam_last_stats", "roeam_profile_step", "roeam_batch_reserve", "roeam_batch_footprint", "roeam_batch_submit",
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll", "roeam_batch_attach", "roeam_residual_norms",
-    "roeam_residual_norms3d", "roeam_residual_norms_noalloc",
+    "roeam_residual_norms3d", "roeam_residual_norms_noalloc", "roeam_batch_configure", "roeam_batch_info",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
     "roeam_grid3d_set_scalars", "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
@@ -68,6 +68,16 @@ class StepStats(ctypes.Structure):
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("captures", ctypes.c_long), ("graph_launches", ctypes.c_long), ("iterations", ctypes.c_long),
+                ("tunes", ctypes.c_long), ("resident", ctypes.c_int), ("queued", ctypes.c_int),
+                ("graph_iters", ctypes.c_int), ("persistent", ctypes.c_int), ("policy", ctypes.c_int),
+                ("shape", ctypes.c_int)]
+
+
+ADMIT_FIFO, ADMIT_SHORTEST = 0, 1
 
 
 class SolveDesc(ctypes.Structure):
@@ -118,6 +128,8 @@ def lib():
         "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 4),
                                         ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
+        "roeam_batch_configure": (i, [vp, i, i, i, i]),
+        "roeam_batch_info": (i, [vp, ctypes.POINTER(BatchStats)]),
         "roeam_grid3d_create": (i, [vp, i, i, i, d, d, d, ctypes.POINTER(ctypes.c_int * 6), vp, ctypes.POINTER(vp)]),
         "roeam_grid3d_destroy": (i, [vp]),
         "roeam_grid3d_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
@@ -463,6 +475,22 @@ def batch_attach(ctx: Context, arena):
     nbytes = arena.numel() * arena.element_size()
     ctx.check(lib().roeam_batch_attach(ctx.h, ctypes.c_void_p(arena.data_ptr()), int(nbytes)))
     ctx._arena = arena
+
+
+def batch_configure(ctx: Context, graph_iters: int = 16, persistent: bool = False, policy: int = ADMIT_FIFO,
+                    autotune: bool = True):
+    """roeam_batch_configure: iterations per captured graph, persistent batched
+    kernels, admission policy (ADMIT_FIFO / ADMIT_SHORTEST), batch tile-shape tuning."""
+    ctx.check(lib().roeam_batch_configure(ctx.h, int(graph_iters), int(bool(persistent)), int(policy),
+                                          int(bool(autotune))))
+
+
+def batch_info(ctx: Context) -> Dict:
+    """roeam_batch_info: graph captures, graph launches, iterations, tunings,
+    resident and queued solves, options and the current group tile shape."""
+    st = BatchStats()
+    ctx.check(lib().roeam_batch_info(ctx.h, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in BatchStats._fields_}
 
 
 def batch_submit(ctx: Context, solves) -> list:

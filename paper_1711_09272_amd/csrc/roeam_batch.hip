@@ -2,14 +2,21 @@
 //
 // Resident solves keep three state copies (q, qa, qb) in a device arena and a
 // Slot each.  A scheduler iteration advances every resident solve by one
-// time step: per group of solves sharing (order, precision, time scheme) one
-// batched stage kernel per Runge-Kutta stage over the flattened tile list of
-// the group.  Every solve keeps its own dt (its own Slot).  After each
-// iteration a status kernel summarises the slots and the host, one iteration
-// behind the device, retires finished solves (copying their state out) and
-// admits queued ones into the freed arena space (continuous batching).  While
-// the resident set is stable and nothing waits for admission, iterations run
-// from a captured HIP graph.
+// time step: per group of solves sharing (order, precision, time scheme,
+// metric, scalar count) one batched stage kernel per Runge-Kutta stage over
+// the group's work list of tiles.  Every solve keeps its own dt (its own
+// Slot), and a solve whose step budget or end time is reached idles (its
+// tiles exit at once) until the host retires it.
+//
+// The work lists live in device memory with a tile count the kernels read, and
+// the launches are sized to the lists' capacities, so one captured HIP graph
+// of graph_iters iterations serves every resident set that fits: admitting and
+// retiring solves only rewrites the lists (copies queued between graph
+// launches), and a graph is captured again only when a group appears or
+// disappears or a list's capacity changes.  After each graph a status kernel
+// summarises the slots; the host, one graph behind the device, retires
+// finished solves (copying their state out) and admits queued ones into the
+// freed arena space (continuous batching).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,9 +38,8 @@ namespace {
 
 constexpr int kMaxSolves = 4096;
 constexpr size_t kAlign = 256;
-constexpr int kGraphIters = 16;  // even
-constexpr int kGroups = 72;      // order (2) x precision (2) x time scheme (3) x metric (2) x scalars (3)
-constexpr int kStatusEvery = 8;  // iterations between status snapshots without a graph
+constexpr int kGroups = 72;  // order (2) x precision (2) x time scheme (3) x metric (2) x scalars (3)
+constexpr int kMinCap = 1024;  // smallest work-list capacity, tiles
 
 size_t align_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
 
@@ -78,12 +84,6 @@ struct Arena {
             }
         }
     }
-    size_t free_bytes() const
-    {
-        size_t s = 0;
-        for (auto &kv : free_) s += kv.second;
-        return s;
-    }
 };
 
 enum ReqState { QUEUED = 0, RESIDENT = 1, COPYING = 2, DONE = 3 };
@@ -94,20 +94,24 @@ struct Request {
     int idx = -1;
     size_t off = 0, bytes = 0;
     int group = -1;
+    uint64_t seq = 0;  // submission order
+    long admit_iter = 0;  // scheduler iteration at which it joined
     roeam_status rc = ROEAM_OK;
     roeam_step_stats stats{};
     hipEvent_t out_ev = nullptr;
-    long done_iter = 0;  // scheduler iteration after which its step budget is spent
 };
 
 struct Group {
-    int order = 2, precision = 0, time_scheme = 1, metric = 0, nsc = 0, shape = 0;
-    std::vector<TileEntry> tiles;
-    TileEntry *d_tiles = nullptr;
-    TileEntry *h_tiles = nullptr;  // pinned staging of the last upload
+    int order = 2, precision = 0, time_scheme = 1, metric = 0, nsc = 0;
+    int shape = -1;                // tile shape, fixed when the group first forms
+    std::vector<TileEntry> tiles;  // host copy of the work list
+    TileEntry *d_tiles = nullptr;  // device work list, cap entries
+    int *d_count = nullptr;        // device tile count
+    TileEntry *h_tiles = nullptr;  // pinned staging of the last upload (cap entries + the count after them)
     hipEvent_t up_ev = nullptr;    // recorded after that upload
-    size_t cap = 0;
+    int cap = 0;
     bool dirty = false;
+    int graph_cap = 0;             // capacity the captured graph's launches were sized for (0: not in the graph)
 };
 
 } // namespace
@@ -133,13 +137,21 @@ struct BatchEngine {
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
+    uint64_t next_seq = 0;
     long iter = 0;
-    long since_status = 0;          // iterations since the last status snapshot
     Group groups[kGroups];          // (order-1, precision, time_scheme, metric, nsc)
-    bool set_changed = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false;
+    // options (roeam_batch_configure)
+    int graph_iters = 16;           // iterations per graph (even)
+    bool persistent = false;        // persistent batched kernels instead of one workgroup per tile
+    int policy = ROEAM_ADMIT_FIFO;
+    bool autotune = true;
+    int cus = 0;                    // compute units of the device
+    // counters
+    long captures = 0, graph_launches = 0, tunes = 0;
+    int last_shape = -1;            // tile shape of the group formed last
     // profiling: event pairs around each stage launch (stage number beside)
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;
@@ -152,12 +164,20 @@ static int group_id(const roeam_params &p, int metric, int nsc)
     return (((p.order - 1) * 2 + p.precision) * 6 + p.time_scheme * 2 + metric) * 3 + nsc;
 }
 
+static void release_graph(BatchEngine *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
 static void release_engine(BatchEngine *b)
 {
     if (!b) return;
     for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    release_graph(b);
     for (auto &kv : b->reqs)
         if (kv.second.out_ev) (void)hipEventDestroy(kv.second.out_ev);
     for (int k = 0; k < 2; ++k) {
@@ -166,6 +186,7 @@ static void release_engine(BatchEngine *b)
     }
     for (auto &g : b->groups) {
         if (g.d_tiles) (void)hipFree(g.d_tiles);
+        if (g.d_count) (void)hipFree(g.d_count);
         if (g.h_tiles) (void)hipHostFree(g.h_tiles);
         if (g.up_ev) (void)hipEventDestroy(g.up_ev);
     }
@@ -189,8 +210,36 @@ static roeam_status hip_err(roeam_ctx *ctx, hipError_t e, const char *where)
         if (e_ != hipSuccess) return hip_err(ctx, e_, #call);     \
     } while (0)
 
+static int stages_of(int time_scheme) { return time_scheme == 0 ? 1 : (time_scheme == 1 ? 3 : 4); }
+
+// Workgroups of a group's batched launches: its list capacity (windowed form)
+// or, persistent, what the device holds at once; a multiple of 8.
+static int launch_blocks(const BatchEngine *b, const Group &G, int cap)
+{
+    int n = cap;
+    if (b->persistent) {
+        const int per_cu = roeam::batch_blocks_per_cu(G.order, G.precision, G.metric, G.nsc, G.shape);
+        const int resident = std::max(per_cu, 1) * std::max(b->cus, 1);
+        n = std::min(cap, resident);
+    }
+    return ((std::max(n, 1) + 7) >> 3) << 3;
+}
+
+// Tiles of resident solve idx (grid g) on the group's shape, appended to the
+// group's work list.
+static void append_tiles(Group &G, int idx, const roeam_grid *g)
+{
+    int tx, ty;
+    roeam::tile_shape(G.shape, &tx, &ty);
+    const int ntx = (g->nx + tx - 1) / tx, nty = (g->ny + ty - 1) / ty;
+    for (int j = 0; j < nty; ++j)
+        for (int i = 0; i < ntx; ++i) G.tiles.push_back(TileEntry{idx, i, j, 0});
+    G.dirty = true;
+}
+
 // Retire solve r: queue the copy of its state to q_out and free its index
-// and arena space (later work on the stream runs after the copy).
+// and arena space (later work on the stream runs after the copy).  Forward
+// Euler leaves the state of an odd step count in qa.
 static roeam_status retire(roeam_ctx *ctx, BatchEngine *b, Request &r, const SolveStatus &s)
 {
     const roeam_grid *g = r.d.grid;
@@ -200,7 +249,9 @@ static roeam_status retire(roeam_ctx *ctx, BatchEngine *b, Request &r, const Sol
     r.stats.steps = (long)s.steps;
     r.stats.nonphys = s.nonphys;
     r.rc = s.nonphys ? ROEAM_ENONPHYS : ROEAM_OK;
-    const double *q = (const double *)(b->d_arena + r.off);
+    const size_t sb = align_up(state_bytes(g));
+    const bool in_qa = r.d.params.time_scheme == 0 && (s.steps & 1);
+    const double *q = (const double *)(b->d_arena + r.off + (in_qa ? sb : 0));
     BHIP(ctx, hipMemcpyAsync(r.d.q_out, q, state_bytes(g),
                              r.d.q_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
     if (!r.out_ev) BHIP(ctx, hipEventCreateWithFlags(&r.out_ev, hipEventDisableTiming));
@@ -214,7 +265,6 @@ static roeam_status retire(roeam_ctx *ctx, BatchEngine *b, Request &r, const Sol
     G.tiles.erase(std::remove_if(G.tiles.begin(), G.tiles.end(), [idx](const TileEntry &t) { return t.solve == idx; }),
                   G.tiles.end());
     G.dirty = true;
-    b->set_changed = true;
     return ROEAM_OK;
 }
 
@@ -244,42 +294,227 @@ static roeam_status process_status(roeam_ctx *ctx, BatchEngine *b, int which, bo
     return ROEAM_OK;
 }
 
-// Tile shape of a group that forms with no forced or tuned shape on its
-// first grid, from the cells the group is about to hold (every queued solve
-// of the group): one-face-per-thread 16x7 tiles for small totals, where the
-// launch is latency-bound and needs many short workgroups; 16x15 tiles with
-// one pass per face direction above about 200k cells, where fewer halo cells
-// per tile cell pay off (measured crossover on MI355X).
-static int untuned_shape(const BatchEngine *b, int group)
+// Grow (or shrink) a group's device work list to hold `need` tiles.  Changing
+// the capacity reallocates the list and invalidates the captured graph.
+static roeam_status ensure_capacity(roeam_ctx *ctx, BatchEngine *b, Group &G, size_t need)
 {
-    long long cells = 0;
-    for (uint64_t tk : b->queue) {
-        auto it = b->reqs.find(tk);
-        if (it != b->reqs.end() && it->second.group == group)
-            cells += (long long)it->second.d.grid->nx * it->second.d.grid->ny;
-    }
-    return cells >= 200000 ? 6 : 8;
+    // an emptied list keeps its capacity (the next solves of the group may reuse
+    // the graph); one that shrinks below a third of it is reallocated
+    int want = G.cap;
+    if ((int)need > G.cap) want = (int)std::max<size_t>(kMinCap, need + need / 4);
+    else if (need > 0 && G.cap > kMinCap && (int)need < G.cap / 3)
+        want = (int)std::max<size_t>(kMinCap, need + need / 4);
+    if (want == G.cap && G.d_tiles) return ROEAM_OK;
+    want = (want + 63) & ~63;
+    BHIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (G.d_tiles) BHIP(ctx, hipFree(G.d_tiles));
+    if (G.d_count) BHIP(ctx, hipFree(G.d_count));
+    if (G.h_tiles) BHIP(ctx, hipHostFree(G.h_tiles));
+    G.d_tiles = nullptr;
+    G.d_count = nullptr;
+    G.h_tiles = nullptr;
+    BHIP(ctx, hipMalloc(&G.d_tiles, (size_t)want * sizeof(TileEntry)));
+    BHIP(ctx, hipMalloc(&G.d_count, sizeof(int)));
+    BHIP(ctx, hipHostMalloc(&G.h_tiles, ((size_t)want + 1) * sizeof(TileEntry), hipHostMallocDefault));
+    G.cap = want;
+    G.dirty = true;
+    b->graph_valid = false;
+    return ROEAM_OK;
 }
 
-// Admit queued solves that fit (first fit in submission order).
+// Upload changed work lists and their counts, in stream order (after every
+// kernel that read the old list).  The pinned staging buffer is reused only
+// after its previous upload has completed.
+static roeam_status upload_tiles(roeam_ctx *ctx, BatchEngine *b)
+{
+    for (auto &G : b->groups) {
+        if (!G.dirty) continue;
+        roeam_status rc = ensure_capacity(ctx, b, G, G.tiles.size());
+        if (rc) return rc;
+        if (!G.up_ev) BHIP(ctx, hipEventCreateWithFlags(&G.up_ev, hipEventDisableTiming));
+        else BHIP(ctx, hipEventSynchronize(G.up_ev));
+        const int n = (int)G.tiles.size();
+        if (n) std::memcpy(G.h_tiles, G.tiles.data(), (size_t)n * sizeof(TileEntry));
+        int *hc = reinterpret_cast<int *>(G.h_tiles + G.cap);
+        *hc = n;
+        if (n)
+            BHIP(ctx, hipMemcpyAsync(G.d_tiles, G.h_tiles, (size_t)n * sizeof(TileEntry), hipMemcpyHostToDevice,
+                                     ctx->stream));
+        BHIP(ctx, hipMemcpyAsync(G.d_count, hc, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        BHIP(ctx, hipEventRecord(G.up_ev, ctx->stream));
+        G.dirty = false;
+        if (G.graph_cap != 0 && G.graph_cap != G.cap) b->graph_valid = false;
+        if (G.graph_cap == 0 && n > 0) b->graph_valid = false;
+    }
+    // a group that emptied while others run leaves the graph (its launches
+    // would only start workgroups that exit)
+    bool any = false, idle = false;
+    for (auto &G : b->groups) {
+        any |= !G.tiles.empty();
+        idle |= G.graph_cap != 0 && G.tiles.empty();
+    }
+    if (any && idle) b->graph_valid = false;
+    return ROEAM_OK;
+}
+
+// One batched stage launch of group G, bracketed by profiling events when
+// profiling.
+static hipError_t stage_launch(BatchEngine *b, const Group &G, int stage, int p, int last, hipStream_t s)
+{
+    const int blocks = launch_blocks(b, G, G.cap);
+    if (!b->profiling)
+        return roeam::launch_stage_batch(b->d_solves, G.d_tiles, G.d_count, blocks, b->persistent, G.order, G.precision,
+                                         G.metric, G.nsc, G.shape, stage, p, last, s);
+    hipError_t e = hipSuccess;
+    while (e == hipSuccess && b->prof_ev.size() < b->prof_used + 2) {
+        hipEvent_t ev;
+        e = hipEventCreate(&ev);
+        if (e == hipSuccess) b->prof_ev.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used], s);
+    if (e == hipSuccess)
+        e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, G.d_count, blocks, b->persistent, G.order, G.precision,
+                                      G.metric, G.nsc, G.shape, stage, p, last, s);
+    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used + 1], s);
+    if (e == hipSuccess) {
+        b->prof_stage.push_back(stage);
+        b->prof_used += 2;
+    }
+    return e;
+}
+
+// One scheduler iteration with parity p over the groups in the graph (or, when
+// profiling, over the non-empty groups).  Forward Euler alternates stage 1
+// (q -> qa) and stage 8 (qa -> q).
+static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
+{
+    for (auto &G : b->groups) {
+        if (b->profiling ? G.tiles.empty() : G.graph_cap == 0) continue;
+        hipError_t e = hipSuccess;
+        if (G.time_scheme == 0) {
+            e = stage_launch(b, G, p ? 8 : 1, p, 1, s);
+        } else {
+            const int first = G.time_scheme == 1 ? 1 : 4, nst = stages_of(G.time_scheme);
+            for (int k = 0; k < nst && e == hipSuccess; ++k) e = stage_launch(b, G, first + k, p, k == nst - 1, s);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Snapshot the status of every index after the iterations queued so far.
+// Graphs are an even number of iterations, so the state after them sits at
+// parity 0.
+static roeam_status enqueue_status(roeam_ctx *ctx, BatchEngine *b, int which)
+{
+    const int p_after = (int)(b->iter & 1);
+    BHIP(ctx, roeam::launch_status(b->d_slots, b->hw, p_after, b->d_status, ctx->stream));
+    if (b->hw) BHIP(ctx, hipMemcpyAsync(b->h_status[which], b->d_status, sizeof(SolveStatus) * b->hw,
+                                        hipMemcpyDeviceToHost, ctx->stream));
+    BHIP(ctx, hipEventRecord(b->status_ev[which], ctx->stream));
+    b->status_pending[which] = true;
+    b->status_owner[which].assign(b->by_idx.begin(), b->by_idx.begin() + b->hw);
+    return ROEAM_OK;
+}
+
+// Tile shape of a group that forms now: time the batched stage kernel (its
+// first stage, which only reads q and writes qa; the step state it publishes
+// is written again by the real first stage) on the group's real work list for
+// every shape, best of three rounds of three launches after a warm-up, and keep
+// the fastest.  Without tuning (or with a shape forced on the first grid) the
+// first grid's forced shape, else 16x7/256 below about 200k cells and 16x15/256
+// above (measured crossover).
+static roeam_status tune_group(roeam_ctx *ctx, BatchEngine *b, Group &G, const std::vector<int> &idxs)
+{
+    long long cells = 0;
+    const roeam_grid *g0 = nullptr;
+    for (int idx : idxs) {
+        const Request &r = b->reqs[b->by_idx[idx]];
+        cells += (long long)r.d.grid->nx * r.d.grid->ny;
+        if (!g0) g0 = r.d.grid;
+    }
+    G.tiles.clear();
+    const bool forced = g0 && g0->shape_forced >= 0;
+    G.shape = forced ? g0->shape_forced : (cells >= 200000 ? 6 : 8);
+    roeam_status rc = ROEAM_OK;
+    if (!forced && b->autotune && !b->profiling && ctx->stream != nullptr && !idxs.empty()) {
+        hipStream_t s = ctx->stream;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        BHIP(ctx, hipEventCreate(&e0));
+        BHIP(ctx, hipEventCreate(&e1));
+        int best = G.shape;
+        float best_ms = 1e30f;
+        for (int sh = 0; sh < roeam::tile_shape_count() && rc == ROEAM_OK; ++sh) {
+            G.shape = sh;
+            G.tiles.clear();
+            for (int idx : idxs) append_tiles(G, idx, b->reqs[b->by_idx[idx]].d.grid);
+            if ((rc = upload_tiles(ctx, b))) break;
+            const int blocks = launch_blocks(b, G, G.cap);
+            auto launch = [&]() {
+                return roeam::launch_stage_batch(b->d_solves, G.d_tiles, G.d_count, blocks, b->persistent, G.order,
+                                                 G.precision, G.metric, G.nsc, G.shape, G.time_scheme == 2 ? 4 : 1, 0,
+                                                 G.time_scheme == 0 ? 1 : 0, s);
+            };
+            hipError_t e = launch();
+            float shape_ms = 1e30f;
+            for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+                e = hipEventRecord(e0, s);
+                for (int k = 0; k < 3 && e == hipSuccess; ++k) e = launch();
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                shape_ms = std::min(shape_ms, ms);
+            }
+            if (e != hipSuccess) rc = hip_err(ctx, e, "batch tile-shape tuning");
+            if (shape_ms < best_ms) {
+                best_ms = shape_ms;
+                best = sh;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        G.shape = best;
+        G.tiles.clear();
+        ++b->tunes;
+    }
+    // the work list of the admitted solves on the chosen shape, on every path
+    for (int idx : idxs) append_tiles(G, idx, b->reqs[b->by_idx[idx]].d.grid);
+    b->last_shape = G.shape;
+    return rc;
+}
+
+// Work of a queued request for the shortest-first policy.
+static double req_work(const Request &r)
+{
+    return (double)r.d.grid->nx * (double)r.d.grid->ny * (double)std::max(r.d.nsteps, 1L);
+}
+
+// Admit queued solves that fit: first fit in submission order (FIFO) or in
+// order of increasing work (cells x steps; ties by submission).  Groups that
+// form in this call tune their tile shape on the solves admitted into them.
 static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
 {
-    const int p = (int)(b->iter & 1);
-    for (auto it = b->queue.begin(); it != b->queue.end();) {
-        Request &r = b->reqs[*it];
+    if (b->queue.empty()) return ROEAM_OK;
+    std::vector<uint64_t> order(b->queue.begin(), b->queue.end());
+    if (b->policy == ROEAM_ADMIT_SHORTEST)
+        std::stable_sort(order.begin(), order.end(), [b](uint64_t x, uint64_t y) {
+            return req_work(b->reqs[x]) < req_work(b->reqs[y]);
+        });
+    std::vector<std::vector<int>> forming(kGroups);
+    std::vector<uint64_t> admitted;
+    for (uint64_t tk : order) {
+        Request &r = b->reqs[tk];
         if (b->free_idx.empty()) break;
         size_t off = 0;
-        if (!b->alloc.alloc(r.bytes, &off)) {
-            ++it;
-            continue;
-        }
+        if (!b->alloc.alloc(r.bytes, &off)) continue;
         const int idx = b->free_idx.back();
         b->free_idx.pop_back();
         r.idx = idx;
         r.off = off;
         r.state = RESIDENT;
-        r.done_iter = b->iter + r.d.nsteps;
-        b->by_idx[idx] = *it;
+        r.admit_iter = b->iter;
+        b->by_idx[idx] = tk;
         b->hw = std::max(b->hw, idx + 1);
         const roeam_grid *g = r.d.grid;
         const size_t sb = align_up(state_bytes(g));
@@ -293,112 +528,23 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         BHIP(ctx, hipMemcpyAsync(q, r.d.q0, state_bytes(g),
                                  r.d.q0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
         BHIP(ctx, roeam::launch_slot_init(&b->d_slots[idx], 1, 0.0, r.d.t_end, r.d.params.cfl, r.d.nsteps, ctx->stream));
-        BHIP(ctx, roeam::launch_rate(S, p, ctx->stream));
-        // tiles of the solve join its group's work list; an empty group takes
-        // the tile shape of its first solve's grid (set, autotuned, or by size)
+        BHIP(ctx, roeam::launch_rate(S, 0, ctx->stream));
         Group &G = b->groups[r.group];
-        if (G.tiles.empty()) {
-            int sh = g->shape_forced >= 0 ? g->shape_forced : g->shape_tuned[r.d.params.order - 1][r.d.params.precision];
-            if (sh < 0) sh = untuned_shape(b, r.group);
-            if (sh != G.shape) b->graph_valid = false;
-            G.shape = sh;
-        }
-        int tx, ty;
-        roeam::tile_shape(G.shape, &tx, &ty);
-        const int ntx = (g->nx + tx - 1) / tx, nty = (g->ny + ty - 1) / ty;
-        for (int j = 0; j < nty; ++j)
-            for (int i = 0; i < ntx; ++i) G.tiles.push_back(TileEntry{idx, i, j, 0});
-        G.dirty = true;
-        b->set_changed = true;
-        it = b->queue.erase(it);
+        if (G.shape < 0) forming[r.group].push_back(idx);
+        else append_tiles(G, idx, g);
+        admitted.push_back(tk);
     }
-    return ROEAM_OK;
-}
-
-// Upload changed work lists.  The device copy is overwritten in stream order
-// (after every kernel that read the old list); the pinned staging buffer is
-// reused only after its previous upload has completed.
-static roeam_status upload_tiles(roeam_ctx *ctx, BatchEngine *b)
-{
-    for (auto &G : b->groups) {
-        if (!G.dirty) continue;
-        if (G.tiles.size() > G.cap) {
-            BHIP(ctx, hipStreamSynchronize(ctx->stream));
-            if (G.d_tiles) BHIP(ctx, hipFree(G.d_tiles));
-            if (G.h_tiles) BHIP(ctx, hipHostFree(G.h_tiles));
-            G.d_tiles = nullptr;
-            G.h_tiles = nullptr;
-            G.cap = std::max<size_t>(G.tiles.size() * 2, 1024);
-            BHIP(ctx, hipMalloc(&G.d_tiles, G.cap * sizeof(TileEntry)));
-            BHIP(ctx, hipHostMalloc(&G.h_tiles, G.cap * sizeof(TileEntry), hipHostMallocDefault));
-        }
-        if (!G.up_ev) BHIP(ctx, hipEventCreateWithFlags(&G.up_ev, hipEventDisableTiming));
-        else BHIP(ctx, hipEventSynchronize(G.up_ev));
-        if (!G.tiles.empty()) {
-            std::memcpy(G.h_tiles, G.tiles.data(), G.tiles.size() * sizeof(TileEntry));
-            BHIP(ctx, hipMemcpyAsync(G.d_tiles, G.h_tiles, G.tiles.size() * sizeof(TileEntry), hipMemcpyHostToDevice,
-                                     ctx->stream));
-        }
-        BHIP(ctx, hipEventRecord(G.up_ev, ctx->stream));
-        G.dirty = false;
+    if (!admitted.empty()) {
+        std::vector<uint64_t> rest;
+        for (uint64_t tk : b->queue)
+            if (b->reqs[tk].state == QUEUED) rest.push_back(tk);
+        b->queue.assign(rest.begin(), rest.end());
     }
-    return ROEAM_OK;
-}
-
-// One batched stage launch, bracketed by profiling events when profiling.
-static hipError_t stage_launch(BatchEngine *b, const Group &G, int n, int stage, int p, int last, hipStream_t s)
-{
-    if (!b->profiling)
-        return roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.nsc, G.shape, stage,
-                                         p, last, s);
-    hipError_t e = hipSuccess;
-    while (e == hipSuccess && b->prof_ev.size() < b->prof_used + 2) {
-        hipEvent_t ev;
-        e = hipEventCreate(&ev);
-        if (e == hipSuccess) b->prof_ev.push_back(ev);
+    for (int gi = 0; gi < kGroups; ++gi) {
+        if (forming[gi].empty()) continue;
+        roeam_status rc = tune_group(ctx, b, b->groups[gi], forming[gi]);
+        if (rc) return rc;
     }
-    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used], s);
-    if (e == hipSuccess)
-        e = roeam::launch_stage_batch(b->d_solves, G.d_tiles, n, G.order, G.precision, G.metric, G.nsc, G.shape, stage, p,
-                                      last, s);
-    if (e == hipSuccess) e = hipEventRecord(b->prof_ev[b->prof_used + 1], s);
-    if (e == hipSuccess) {
-        b->prof_stage.push_back(stage);
-        b->prof_used += 2;
-    }
-    return e;
-}
-
-static hipError_t enqueue_iteration(BatchEngine *b, int p, hipStream_t s)
-{
-    for (auto &G : b->groups) {
-        const int n = (int)G.tiles.size();
-        if (!n) continue;
-        hipError_t e;
-        if (G.time_scheme == 0) {
-            e = stage_launch(b, G, n, 1, p, 1, s);
-            if (e == hipSuccess) e = roeam::launch_copy_back_batch(b->d_solves, G.d_tiles, n, G.shape, p, s);
-        } else {
-            const int first = G.time_scheme == 1 ? 1 : 4, nst = G.time_scheme == 1 ? 3 : 4;
-            e = hipSuccess;
-            for (int k = 0; k < nst && e == hipSuccess; ++k) e = stage_launch(b, G, n, first + k, p, k == nst - 1, s);
-        }
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-// Snapshot the status of every index after the iterations queued so far.
-// The state after iteration k sits at parity (k + 1) & 1 = iter & 1.
-static roeam_status enqueue_status(roeam_ctx *ctx, BatchEngine *b, int which)
-{
-    const int p_after = (int)(b->iter & 1);
-    BHIP(ctx, roeam::launch_status(b->d_slots, b->hw, p_after, b->d_status, ctx->stream));
-    if (b->hw) BHIP(ctx, hipMemcpyAsync(b->h_status[which], b->d_status, sizeof(SolveStatus) * b->hw,
-                                        hipMemcpyDeviceToHost, ctx->stream));
-    BHIP(ctx, hipEventRecord(b->status_ev[which], ctx->stream));
-    b->status_pending[which] = true;
-    b->status_owner[which].assign(b->by_idx.begin(), b->by_idx.begin() + b->hw);
     return ROEAM_OK;
 }
 
@@ -407,6 +553,27 @@ static int resident_count(const BatchEngine *b)
     int n = 0;
     for (int i = 0; i < b->hw; ++i) n += b->by_idx[i] != 0;
     return n;
+}
+
+// Capture the graph of graph_iters iterations over the groups with tiles,
+// each launch sized to its list's capacity.
+static roeam_status capture_graph(roeam_ctx *ctx, BatchEngine *b)
+{
+    release_graph(b);
+    bool any = false;
+    for (auto &G : b->groups) any |= !G.tiles.empty();
+    for (auto &G : b->groups) G.graph_cap = (G.tiles.empty() && any) || G.cap == 0 ? 0 : G.cap;
+    hipStream_t s = ctx->stream;
+    BHIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < b->graph_iters && e == hipSuccess; ++k) e = enqueue_iteration(b, k & 1, s);
+    hipError_t e2 = hipStreamEndCapture(s, &b->graph);
+    if (e != hipSuccess) return hip_err(ctx, e, "capture batch iteration");
+    if (e2 != hipSuccess) return hip_err(ctx, e2, "hipStreamEndCapture");
+    BHIP(ctx, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->graph_valid = true;
+    ++b->captures;
+    return ROEAM_OK;
 }
 
 extern "C" {
@@ -433,22 +600,37 @@ static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes
     if (arena_bytes < kAlign) return roeam_fail(ctx, ROEAM_EINVAL, "arena too small");
     if (arena && ((uintptr_t)arena % kAlign) != 0) return roeam_fail(ctx, ROEAM_EINVAL, "arena not 256-byte aligned");
     BHIP(ctx, hipSetDevice(ctx->device));
+    BatchEngine keep;  // options survive a re-reserve
+    bool have_old = false;
     if (ctx->batch) {
         BatchEngine *b = ctx->batch;
         if (!b->queue.empty() || resident_count(b)) return roeam_fail(ctx, ROEAM_EBUSY, "batch engine has work");
         BHIP(ctx, hipStreamSynchronize(ctx->stream));
+        keep.graph_iters = b->graph_iters;
+        keep.persistent = b->persistent;
+        keep.policy = b->policy;
+        keep.autotune = b->autotune;
+        have_old = true;
         release_engine(b);
         ctx->batch = nullptr;
     }
     BatchEngine *b = new (std::nothrow) BatchEngine;
     if (!b) return roeam_fail(ctx, ROEAM_ENOMEM, "host allocation");
+    if (have_old) {
+        b->graph_iters = keep.graph_iters;
+        b->persistent = keep.persistent;
+        b->policy = keep.policy;
+        b->autotune = keep.autotune;
+    }
     b->device = ctx->device;
-    hipError_t e = hipSuccess;
-    if (arena) {
-        b->d_arena = (char *)arena;
-        b->owns_arena = false;
-    } else {
-        e = hipMalloc(&b->d_arena, arena_bytes);
+    hipError_t e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e == hipSuccess) {
+        if (arena) {
+            b->d_arena = (char *)arena;
+            b->owns_arena = false;
+        } else {
+            e = hipMalloc(&b->d_arena, arena_bytes);
+        }
     }
     if (e == hipSuccess) e = hipMalloc(&b->d_solves, sizeof(DevSolve) * kMaxSolves);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_solves, sizeof(DevSolve) * kMaxSolves, hipHostMallocDefault);
@@ -474,7 +656,6 @@ static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes
         G.time_scheme = (g / 2) % 3;
         G.metric = g & 1;
         G.nsc = gidx % 3;
-        G.shape = 0;
     }
     ctx->batch = b;
     return ROEAM_OK;
@@ -486,6 +667,45 @@ roeam_status roeam_batch_attach(roeam_ctx *ctx, void *arena, size_t arena_bytes)
 {
     if (!arena) return roeam_fail(ctx, ROEAM_EINVAL, "arena is NULL");
     return setup_engine(ctx, arena, arena_bytes);
+}
+
+roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune)
+{
+    if (!ctx) return ROEAM_EINVAL;
+    BatchEngine *b = ctx->batch;
+    if (!b) return roeam_fail(ctx, ROEAM_EINVAL, "call roeam_batch_reserve first");
+    if (graph_iters < 2 || graph_iters > 256 || (graph_iters & 1))
+        return roeam_fail(ctx, ROEAM_EINVAL, "graph_iters must be even, 2 .. 256");
+    if (persistent != 0 && persistent != 1) return roeam_fail(ctx, ROEAM_EINVAL, "persistent must be 0 or 1");
+    if (policy != ROEAM_ADMIT_FIFO && policy != ROEAM_ADMIT_SHORTEST)
+        return roeam_fail(ctx, ROEAM_EINVAL, "policy must be ROEAM_ADMIT_FIFO or ROEAM_ADMIT_SHORTEST");
+    if (autotune != 0 && autotune != 1) return roeam_fail(ctx, ROEAM_EINVAL, "autotune must be 0 or 1");
+    if (b->graph_iters != graph_iters || b->persistent != (persistent != 0)) b->graph_valid = false;
+    b->graph_iters = graph_iters;
+    b->persistent = persistent != 0;
+    b->policy = policy;
+    b->autotune = autotune != 0;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_batch_info(roeam_ctx *ctx, roeam_batch_stats *out)
+{
+    if (!ctx || !out) return roeam_fail(ctx, ROEAM_EINVAL, "bad argument");
+    BatchEngine *b = ctx->batch;
+    if (!b) return roeam_fail(ctx, ROEAM_EINVAL, "call roeam_batch_reserve first");
+    out->captures = b->captures;
+    out->graph_launches = b->graph_launches;
+    out->iterations = b->iter;
+    out->tunes = b->tunes;
+    out->resident = resident_count(b);
+    int queued = 0;
+    for (auto &kv : b->reqs) queued += kv.second.state == QUEUED;
+    out->queued = queued;
+    out->graph_iters = b->graph_iters;
+    out->persistent = b->persistent ? 1 : 0;
+    out->policy = b->policy;
+    out->shape = b->last_shape;
+    return ROEAM_OK;
 }
 
 roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *descs, uint64_t *tickets_out)
@@ -509,6 +729,7 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
         r.d = descs[i];
         r.bytes = roeam_batch_footprint(descs[i].grid);
         r.group = group_id(descs[i].params, descs[i].grid->metric, descs[i].grid->nsc);
+        r.seq = b->next_seq++;
         b->reqs.emplace(tk, r);
         b->queue.push_back(tk);
         tickets_out[i] = tk;
@@ -526,7 +747,7 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
     long done_iters = 0;
     roeam_status rc;
     for (;;) {
-        // retire what finished (status one iteration behind), then admit
+        // retire what finished (status one graph behind), then admit
         for (int w = 0; w < 2; ++w)
             if ((rc = process_status(ctx, b, w, false))) return rc;
         if ((rc = admit(ctx, b))) return rc;
@@ -535,64 +756,51 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         if (iterations >= 0 && done_iters >= iterations) break;
         if (resident == 0) {
             if (b->queue.empty()) break;
-            // queued solves wait for space held by nothing resident: cannot happen,
-            // every queued solve fits the empty arena
+            // every queued solve fits the empty arena (checked at submission)
             return roeam_fail(ctx, ROEAM_ENOMEM, "queued solve does not fit the arena");
         }
-        // iterations of the resident set; a stable set with nothing waiting runs
-        // kGraphIters iterations from one captured graph, unless a resident
-        // solve spends its step budget sooner: then single iterations run up to
-        // that iteration and the status is snapshot right after it, so the
-        // solve leaves without waiting for the regular snapshot cadence
-        long next_done = LONG_MAX;
-        for (int i = 0; i < b->hw; ++i)
-            if (b->by_idx[i]) next_done = std::min(next_done, b->reqs[b->by_idx[i]].done_iter);
-        const bool stable = !b->set_changed && b->queue.empty() && (b->iter & 1) == 0 &&
-                            (iterations < 0 || iterations - done_iters >= kGraphIters) &&
-                            next_done - b->iter >= kGraphIters;
-        long ran;
-        if (stable && s != nullptr && !b->profiling) {
-            if (!b->graph_valid) {
-                if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-                if (b->graph) (void)hipGraphDestroy(b->graph);
-                b->gexec = nullptr;
-                b->graph = nullptr;
-                BHIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-                hipError_t e = hipSuccess;
-                for (int k = 0; k < kGraphIters && e == hipSuccess; ++k) e = enqueue_iteration(b, k & 1, s);
-                hipError_t e2 = hipStreamEndCapture(s, &b->graph);
-                if (e != hipSuccess) return hip_err(ctx, e, "capture batch iteration");
-                if (e2 != hipSuccess) return hip_err(ctx, e2, "hipStreamEndCapture");
-                BHIP(ctx, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
-                b->graph_valid = true;
-            }
+        // every resident solve has spent its step budget (each ran one step per
+        // iteration since it joined): nothing left to compute, so wait for the
+        // newest status snapshot (taken after the last iteration) instead
+        bool spent = true;
+        size_t tiles = 0;
+        for (auto &G : b->groups) tiles += G.tiles.size();
+        for (int i = 0; i < b->hw && spent; ++i) {
+            if (!b->by_idx[i]) continue;
+            const Request &r = b->reqs[b->by_idx[i]];
+            spent = r.state != RESIDENT || b->iter - r.admit_iter >= std::max(r.d.nsteps, 1L);
+        }
+        if (spent) {
+            for (int w = 0; w < 2; ++w)
+                if ((rc = process_status(ctx, b, w, true))) return rc;
+            if (resident_count(b) < resident) continue;
+            // the snapshot after the last iteration has been read: a solve past
+            // its step budget that it did not report done is an engine fault
+            return roeam_fail(ctx, ROEAM_EDEVICE, "batch engine: a solve past its step budget is not reported done");
+        }
+        if (tiles == 0) return roeam_fail(ctx, ROEAM_EDEVICE, "batch engine: resident solves without work-list tiles");
+        // graph_iters iterations: the captured graph, or (profiling, or the
+        // null stream, which cannot be captured) the same launches directly;
+        // profiling reads the status after every second iteration (solves join
+        // at even iterations: forward Euler's buffer follows the step parity)
+        // so that few timed launches are idle ones
+        const int run_iters = b->profiling ? 2 : b->graph_iters;
+        if (!b->profiling && s != nullptr) {
+            if (!b->graph_valid && (rc = capture_graph(ctx, b))) return rc;
             BHIP(ctx, hipGraphLaunch(b->gexec, s));
-            ran = kGraphIters;
+            ++b->graph_launches;
         } else {
-            BHIP(ctx, enqueue_iteration(b, (int)(b->iter & 1), s));
-            ran = 1;
+            for (auto &G : b->groups) G.graph_cap = G.tiles.empty() ? 0 : G.cap;
+            for (int k = 0; k < run_iters; ++k) BHIP(ctx, enqueue_iteration(b, (int)((b->iter + k) & 1), s));
         }
-        if (b->set_changed) {
-            b->graph_valid = false;
-            b->set_changed = false;
-        }
-        b->iter += ran;
-        done_iters += ran;
-        b->since_status += ran;
-        // snapshot the status after every graph, or every kStatusEvery single
-        // iterations, or when the caller's iteration budget ends; the buffer's
-        // previous snapshot (two back) is read first
-        const bool budget_end = iterations >= 0 && done_iters >= iterations;
-        // (profiling snapshots and reads the status after every iteration, so
-        // finished solves leave at once and no timed launch is an idle one)
-        const bool budget_spent = b->iter == next_done;
-        if (ran > 1 || b->since_status >= kStatusEvery || budget_end || budget_spent || b->profiling) {
-            const int which = (int)(b->status_seq++ & 1);
-            if ((rc = process_status(ctx, b, which, true))) return rc;
-            if ((rc = enqueue_status(ctx, b, which))) return rc;
-            if (b->profiling && (rc = process_status(ctx, b, which, true))) return rc;
-            b->since_status = 0;
-        }
+        b->iter += run_iters;
+        done_iters += run_iters;
+        // snapshot the status after these iterations; the buffer's previous
+        // snapshot (two back) is read first
+        const int which = (int)(b->status_seq++ & 1);
+        if ((rc = process_status(ctx, b, which, true))) return rc;
+        if ((rc = enqueue_status(ctx, b, which))) return rc;
+        if (b->profiling && (rc = process_status(ctx, b, which, true))) return rc;
     }
     if (iterations < 0) {
         // drain: retire everything still reported
@@ -618,6 +826,7 @@ roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pendi
     b->prof_stage.clear();
     roeam_status rc = roeam_batch_run(ctx, iterations, pending);
     b->profiling = false;
+    b->graph_valid = false;
     if (rc) return rc;
     BHIP(ctx, hipStreamSynchronize(ctx->stream));
     double sum[4] = {0.0, 0.0, 0.0, 0.0};
@@ -626,7 +835,8 @@ roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pendi
         float ms = 0.f;
         BHIP(ctx, hipEventElapsedTime(&ms, b->prof_ev[2 * k], b->prof_ev[2 * k + 1]));
         const int code = b->prof_stage[k];
-        const int st = code >= 4 ? code - 4 : code - 1;  // position of the stage within its step
+        // position of the stage within its step (forward Euler's stage 8 is a first stage)
+        const int st = code == 8 ? 0 : (code >= 4 ? code - 4 : code - 1);
         sum[st] += ms;
         cnt[st] += 1;
     }

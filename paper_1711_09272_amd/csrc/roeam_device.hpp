@@ -32,8 +32,12 @@ constexpr int kMaxScalars = 2;
 // id modulo kRateSlots) so that thousands of workgroups do not serialize on
 // one device-scope atomic; readers take the max over the words.  Each word is
 // the bit pattern of a non-negative double, which atomicMax on the unsigned
-// 64-bit integer orders correctly.
+// 64-bit integer orders correctly.  The rate of the state after n steps sits
+// in word set n mod 3: step n reads set n, reduces the new state into set
+// n + 1 and clears set n + 2 (read by the previous step, reduced into by the
+// next one), so no kernel between steps has to clear anything.
 constexpr int kRateSlots = 64;
+constexpr int kRateSets = 3;
 
 struct StepState {
     double t;                      // time of the state at this parity
@@ -43,7 +47,7 @@ struct StepState {
 };
 
 struct alignas(64) Slot {
-    unsigned long long rate_bits[2][kRateSlots];  // per parity
+    unsigned long long rate_bits[kRateSets][kRateSlots];  // per step count mod 3
     StepState st[2];
     double t_end, cfl;
     long long max_steps;
@@ -142,8 +146,14 @@ __device__ __forceinline__ double sqrtR(double x) { return x * rsq_nr1(x); }
 __device__ __forceinline__ float rcpR(float b) { return __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ float rsqR(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
-// square root of a non-negative operand (zero allowed)
-__device__ __forceinline__ double sqrt0R(double x) { return x > 0.0 ? x * rsq_nr1(x) : 0.0; }
+// square root of a non-negative operand (zero allowed): evaluated at
+// x + 1e-300, which equals x for every x above about 1e-284 and keeps rsq off
+// zero (the result for smaller x is below 1e-142 either way)
+__device__ __forceinline__ double sqrt0R(double x)
+{
+    const double y = x + 1e-300;
+    return y * rsq_nr1(y);
+}
 __device__ __forceinline__ float sqrt0R(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Eq. (98): f(phi) = min(phi sqrt(4 + (1 - phi^2)^2) / (1 + phi^2), 1), with
@@ -436,11 +446,17 @@ __device__ __forceinline__ void roe_classic(const DevSolve &S, const double *WL,
 // Roe-AM numerical flux, Eqs. (85)-(109), per unit face length.
 // R is the precision of the dissipation coefficients; the side quantities,
 // the central term, the jumps of Eq. (85) and the final assembly stay FP64.
+// AXIS: the face normal is n = (1, 0) (the caller passes the states in the
+// face's frame); the products with the normal's components are left out.
 // ---------------------------------------------------------------------------
-template <typename R, int NSC = 0>
+template <typename R, int NSC = 0, bool AXIS = false>
 __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, const double *WR, double nx,
                                            double ny, double s1d, double *F)
 {
+    if (AXIS) {
+        nx = 1.0;
+        ny = 0.0;
+    }
     if (__builtin_expect(S.scheme != SCHEME_ROEAM, 0)) {
         roe_classic<R, NSC>(S, WL, WR, nx, ny, F);
         return;
@@ -451,7 +467,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     // side quantities, Eq. (4); H = gamma/(gamma-1) p/rho + |V|^2/2
     const double iL = rcp_nr(rL), iR = rcp_nr(rR);
     const double qL = uL * uL + vL * vL, qR = uR * uR + vR * vR;
-    const double UL = nx * uL + ny * vL, UR = nx * uR + ny * vR;
+    const double UL = AXIS ? uL : nx * uL + ny * vL, UR = AXIS ? uR : nx * uR + ny * vR;
     const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
     const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
     const double PsiL1 = rL * uL, PsiL2 = rL * vL, PsiL3 = rL * HL;
@@ -470,7 +486,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     const R c2 = (R)S.gm1 * (H - (R)0.5 * (u * u + v * v));
     const R ic = rsqR(c2);
     const R c = c2 * ic;
-    const R U = (R)nx * u + (R)ny * v;
+    const R U = AXIS ? u : (R)nx * u + (R)ny * v;
     const R dU = (R)dUd, dp = (R)dpd;
     const R s1 = (R)s1d;
 
@@ -515,9 +531,9 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
         const bool use_n = dV2 < (R)S.dv_min2 || dV2 == (R)0;
         const R idV = rsqR(use_n ? (R)1 : dV2);
         const R n1x = use_n ? (R)nx : du * idV, n1y = use_n ? (R)ny : dv * idV;
-        const R a1U1 = (n1x * (R)nx + n1y * (R)ny) * (n1x * u + n1y * v);
+        const R a1U1 = (AXIS ? n1x : n1x * (R)nx + n1y * (R)ny) * (n1x * u + n1y * v);
         // unit n2 along (n1 x n) x n1 = s (-n1y, n1x): alpha2 U2 = |s| (n1x v - n1y u) up to sign
-        const R sz = n1x * (R)ny - n1y * (R)nx;
+        const R sz = AXIS ? -n1y : n1x * (R)ny - n1y * (R)nx;
         const R a2U2 = sz * (n1x * v - n1y * u);
         const R frr = rabs(a1U1) + rabs(a2U2);
         const R xi_fix = (R)S.eps1 * ((R)1 - f8Mbar) * f8M * rmin(fef, frr);
@@ -547,10 +563,17 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     const double xid = (double)xi, pd = (double)(dpp + dpu), dUpd = (double)dUp, dUud = (double)dUu;
     const double rhod = (double)rho;
     F[0] = 0.5 * (UL * rL + UR * rR) - 0.5 * (xid * (rR - rL) + dUpd * rhod + dUud * (rR + rL));
-    F[1] = 0.5 * ((UL * PsiL1 + pL * nx) + (UR * PsiR1 + pR * nx))
-         - 0.5 * (xid * (PsiR1 - PsiL1) + pd * nx + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
-    F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
-         - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+    if (AXIS) {
+        F[1] = 0.5 * ((UL * PsiL1 + pL) + (UR * PsiR1 + pR))
+             - 0.5 * (xid * (PsiR1 - PsiL1) + pd + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
+        F[2] = 0.5 * (UL * PsiL2 + UR * PsiR2)
+             - 0.5 * (xid * (PsiR2 - PsiL2) + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+    } else {
+        F[1] = 0.5 * ((UL * PsiL1 + pL * nx) + (UR * PsiR1 + pR * nx))
+             - 0.5 * (xid * (PsiR1 - PsiL1) + pd * nx + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
+        F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
+             - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+    }
     F[3] = 0.5 * (UL * PsiL3 + UR * PsiR3)
          - 0.5 * (xid * (PsiR3 - PsiL3) + dUpd * (rhod * (double)H) + dUud * (PsiR3 + PsiL3));
     // transported scalars (rho k rows of Eq. 85): Psi = rho k, Psi^ = rho^ k^

@@ -33,16 +33,25 @@ hipError_t launch_stage_single_sc(const DevSolve *dS, const DevSolve &S, int sha
                                   double *r_out, hipStream_t st);
 // Batched stage kernel over the tiles of one group (solves that share order,
 // precision, metric and scalar count nsc); nsc > 0 in roeam_kernels_sc.hip.
-hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st);
-hipError_t launch_stage_batch_sc(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                                 int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st);
-hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st);
+// The kernels read the tile count from device memory (*count); `blocks` (a
+// multiple of 8) workgroups of the windowed form (one tile each, the rest
+// exit) or of the persistent form (resident workgroups taking tiles in turn).
+hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, const int *count, int blocks,
+                              bool persistent, int order, int precision, int metric, int nsc, int shape, int stage,
+                              int p, int last, hipStream_t st);
+hipError_t launch_stage_batch_sc(const DevSolve *solves, const TileEntry *tiles, const int *count, int blocks,
+                                 bool persistent, int order, int precision, int metric, int nsc, int shape, int stage,
+                                 int p, int last, hipStream_t st);
+// Resident workgroups per CU of the persistent batched kernel.
+int batch_blocks_per_cu(int order, int precision, int metric, int nsc, int shape);
+int batch_blocks_per_cu_sc(int order, int precision, int metric, int nsc, int shape);
+// Explicit rate of S's state q into rate-word set `set` (0 for a fresh slot).
+hipError_t launch_rate(const DevSolve &S, int set, hipStream_t st);
 hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipStream_t st);
-hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,
-                                  hipStream_t st);
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st);
-hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st);
+// Forward Euler: copy qa into q when the step state at parity p counts an odd
+// number of steps (the state then sits in qa).
+hipError_t launch_fe_finish(const DevSolve &S, int p, hipStream_t st);
 hipError_t launch_rate_out(const Slot *s, double *out, hipStream_t st);
 // RMS and max |.| per row of r[k][line][pitch] (rows 4..7, nx valid per line)
 // into out[2 rows]; part: scratch of 2 rows doubles per block, max_blocks blocks.
@@ -65,6 +74,6 @@ hipError_t launch_stage3_sc(const DevSolve3 *dS, const DevSolve3 &S, int shape, 
 hipError_t launch_stage3(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last, double *r_out,
                          hipStream_t st);
 hipError_t launch_rate3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);
-hipError_t launch_copy_back3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);
+hipError_t launch_fe_finish3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st);
 
 } // namespace roeam

@@ -20,9 +20,9 @@
 
 namespace roeam {
 
-// Explicit rate of a state (sets dt of the first step of a run) into the
-// rate words of parity p.
-__global__ __launch_bounds__(256) void k_rate(DevSolve S, int p)
+// Explicit rate of a state (sets dt of the first step of a run) into rate-word
+// set `set`.
+__global__ __launch_bounds__(256) void k_rate(DevSolve S, int set)
 {
     __shared__ double sRed[4];
     double lmax = 0.0;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_rate(DevSolve S, int p)
         }
     }
     const double m = block_max<256>(lmax, sRed);
-    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, p, m);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, set, m);
 }
 
 __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps)
@@ -51,8 +51,9 @@ __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl,
         z.st[q].dt = 0.0;
         z.st[q].steps = 0;
         z.st[q].pad = 0;
-        for (int w = 0; w < kRateSlots; ++w) z.rate_bits[q][w] = 0ull;
     }
+    for (int q = 0; q < kRateSets; ++q)
+        for (int w = 0; w < kRateSlots; ++w) z.rate_bits[q][w] = 0ull;
     z.t_end = t_end;
     z.cfl = cfl;
     z.max_steps = max_steps;
@@ -61,14 +62,11 @@ __global__ void k_slot_init(Slot *s, int n, double t0, double t_end, double cfl,
     z.nonphys = 0;
 }
 
-// Forward Euler: copy the stage result back into q when the step ran, and
-// clear the rate accumulator that the next step's stage will use.
-__global__ void k_copy_back(DevSolve S, int p)
+// Forward Euler alternates q -> qa and qa -> q: after an odd number of steps
+// (the step state at parity p) the result is in qa and is copied into q.
+__global__ void k_fe_finish(DevSolve S, int p)
 {
-    Slot &z = *S.slot;
-    const bool ran = z.st[p ^ 1].steps != z.st[p].steps;
-    if (blockIdx.x == 0 && threadIdx.x < kRateSlots) z.rate_bits[p][threadIdx.x] = 0ull;
-    if (!ran) return;
+    if ((S.slot->st[p].steps & 1) == 0) return;
     const long long n = (long long)S.nx * S.ny;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
         const int j = (int)(c / S.nx), i = (int)(c - (long long)j * S.nx);
@@ -112,15 +110,24 @@ hipError_t launch_stage_single(const DevSolve *dS, const DevSolve &S, int shape,
     return hipGetLastError();
 }
 
-hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                              int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st)
+hipError_t launch_stage_batch(const DevSolve *solves, const TileEntry *tiles, const int *count, int blocks,
+                              bool persistent, int order, int precision, int metric, int nsc, int shape, int stage,
+                              int p, int last, hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
-    if (shape < 0 || shape >= kNumShapes) return hipErrorInvalidValue;
+    if (blocks <= 0) return hipSuccess;
+    if (shape < 0 || shape >= kNumShapes || (blocks & 7)) return hipErrorInvalidValue;
     if (nsc != 0)
-        return launch_stage_batch_sc(solves, tiles, ntiles, order, precision, metric, nsc, shape, stage, p, last, st);
-    launch_batch_nsc<0>(solves, tiles, ntiles, order, precision, metric, shape, stage, p, last, st);
+        return launch_stage_batch_sc(solves, tiles, count, blocks, persistent, order, precision, metric, nsc, shape,
+                                     stage, p, last, st);
+    launch_batch_nsc<0>(solves, tiles, count, blocks, persistent, order, precision, metric, shape, stage, p, last, st);
     return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int order, int precision, int metric, int nsc, int shape)
+{
+    if (shape < 0 || shape >= kNumShapes) return 0;
+    if (nsc != 0) return batch_blocks_per_cu_sc(order, precision, metric, nsc, shape);
+    return batch_blocks_per_cu_nsc<0>(order, precision, metric, shape);
 }
 
 static int small_grid(long long n)
@@ -129,9 +136,9 @@ static int small_grid(long long n)
     return (int)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
 }
 
-hipError_t launch_rate(const DevSolve &S, int p, hipStream_t st)
+hipError_t launch_rate(const DevSolve &S, int set, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rate, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, p);
+    hipLaunchKernelGGL(k_rate, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, set);
     return hipGetLastError();
 }
 
@@ -160,51 +167,15 @@ hipError_t launch_status(const Slot *slots, int n, int p, SolveStatus *out, hipS
     return hipGetLastError();
 }
 
-// Forward Euler in a batch: copy each tile of qa back into q when the solve's
-// step ran; the rate words of parity p are cleared by each solve's first tile.
-template <int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_copy_back_batch(const DevSolve *__restrict__ solves,
-                                                        const TileEntry *__restrict__ tiles, int ntiles, int p)
-{
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    if (t >= ntiles) return;
-    const TileEntry te = tiles[t];
-    const DevSolve &S = solves[te.solve];
-    Slot &z = *S.slot;
-    const bool ran = z.st[p ^ 1].steps != z.st[p].steps;
-    if (te.tx == 0 && te.ty == 0 && threadIdx.x < kRateSlots) z.rate_bits[p][threadIdx.x] = 0ull;
-    if (!ran) return;
-    for (int c = threadIdx.x; c < TX * TY; c += NT) {
-        const int cj = c / TX, ci = c - cj * TX;
-        const int gi = te.tx * TX + ci, gj = te.ty * TY + cj;
-        if (gi >= S.nx || gj >= S.ny) continue;
-        const long long idx = (long long)gj * S.pitch + gi;
-        for (int k = 0; k < 4 + S.nsc; ++k) S.q[k * S.plane + idx] = S.qa[k * S.plane + idx];
-    }
-}
-
-hipError_t launch_copy_back_batch(const DevSolve *solves, const TileEntry *tiles, int ntiles, int shape, int p,
-                                  hipStream_t st)
-{
-    if (ntiles <= 0) return hipSuccess;
-    const int blocks = ((ntiles + 7) >> 3) << 3;
-#define ROEAM_COPY_CASE(ID, TX, TY, NT, SPLIT)                                                                 \
-    case ID: hipLaunchKernelGGL((k_copy_back_batch<TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, solves, tiles, ntiles, \
-                                p); break;
-    switch (shape) { ROEAM_SHAPES(ROEAM_COPY_CASE) }
-#undef ROEAM_COPY_CASE
-    return hipGetLastError();
-}
-
 hipError_t launch_slot_init(Slot *s, int n, double t0, double t_end, double cfl, long long max_steps, hipStream_t st)
 {
     hipLaunchKernelGGL(k_slot_init, dim3((n + 63) / 64), dim3(64), 0, st, s, n, t0, t_end, cfl, max_steps);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_back(const DevSolve &S, int p, hipStream_t st)
+hipError_t launch_fe_finish(const DevSolve &S, int p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_copy_back, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, p);
+    hipLaunchKernelGGL(k_fe_finish, dim3(small_grid((long long)S.nx * S.ny)), dim3(256), 0, st, S, p);
     return hipGetLastError();
 }
 

@@ -5,8 +5,8 @@
 
 namespace roeam {
 
-// Explicit rate of the state q into the rate words of parity p.
-__global__ __launch_bounds__(256) void k_rate3(const DevSolve3 *__restrict__ Sp, int p)
+// Explicit rate of the state q into rate-word set `set`.
+__global__ __launch_bounds__(256) void k_rate3(const DevSolve3 *__restrict__ Sp, int set)
 {
     const DevSolve3 &S = *Sp;
     __shared__ double sRed[4];
@@ -21,18 +21,15 @@ __global__ __launch_bounds__(256) void k_rate3(const DevSolve3 *__restrict__ Sp,
         else lmax = rmax(lmax, cell_rate3(S, W, rcp_nr(W[0])));
     }
     const double m = block_max<256>(lmax, sRed);
-    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, p, m);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(*S.slot, set, m);
 }
 
-// Forward Euler: copy the stage result back into q when the step ran and clear
-// the rate words the next step's stage reduces into.
-__global__ __launch_bounds__(256) void k_copy_back3(const DevSolve3 *__restrict__ Sp, int p)
+// Forward Euler alternates q -> qa and qa -> q: after an odd number of steps
+// (the step state at parity p) the result is in qa and is copied into q.
+__global__ __launch_bounds__(256) void k_fe_finish3(const DevSolve3 *__restrict__ Sp, int p)
 {
     const DevSolve3 &S = *Sp;
-    Slot &z = *S.slot;
-    const bool ran = z.st[p ^ 1].steps != z.st[p].steps;
-    if (blockIdx.x == 0 && threadIdx.x < kRateSlots) z.rate_bits[p][threadIdx.x] = 0ull;
-    if (!ran) return;
+    if ((S.slot->st[p].steps & 1) == 0) return;
     const long long n = (long long)S.nx * S.ny * S.nz;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
         const long long r = c / S.nx;
@@ -75,9 +72,9 @@ hipError_t launch_rate3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_copy_back3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st)
+hipError_t launch_fe_finish3(const DevSolve3 *dS, const DevSolve3 &S, int p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_copy_back3, dim3(grid_blocks3(S)), dim3(256), 0, st, dS, p);
+    hipLaunchKernelGGL(k_fe_finish3, dim3(grid_blocks3(S)), dim3(256), 0, st, dS, p);
     return hipGetLastError();
 }
 

@@ -15,14 +15,24 @@ hipError_t launch_stage_single_sc(const DevSolve *dS, const DevSolve &S, int sha
     return hipGetLastError();
 }
 
-hipError_t launch_stage_batch_sc(const DevSolve *solves, const TileEntry *tiles, int ntiles, int order, int precision,
-                                 int metric, int nsc, int shape, int stage, int p, int last, hipStream_t st)
+hipError_t launch_stage_batch_sc(const DevSolve *solves, const TileEntry *tiles, const int *count, int blocks,
+                                 bool persistent, int order, int precision, int metric, int nsc, int shape, int stage,
+                                 int p, int last, hipStream_t st)
 {
     if (shape < 0 || shape >= tile_shape_count()) return hipErrorInvalidValue;
-    if (nsc == 1) launch_batch_nsc<1>(solves, tiles, ntiles, order, precision, metric, shape, stage, p, last, st);
-    else if (nsc == 2) launch_batch_nsc<2>(solves, tiles, ntiles, order, precision, metric, shape, stage, p, last, st);
+    if (nsc == 1)
+        launch_batch_nsc<1>(solves, tiles, count, blocks, persistent, order, precision, metric, shape, stage, p, last, st);
+    else if (nsc == 2)
+        launch_batch_nsc<2>(solves, tiles, count, blocks, persistent, order, precision, metric, shape, stage, p, last, st);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+int batch_blocks_per_cu_sc(int order, int precision, int metric, int nsc, int shape)
+{
+    if (nsc == 1) return batch_blocks_per_cu_nsc<1>(order, precision, metric, shape);
+    if (nsc == 2) return batch_blocks_per_cu_nsc<2>(order, precision, metric, shape);
+    return 0;
 }
 
 } // namespace roeam

@@ -413,17 +413,13 @@ roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *g, const roeam_par
 }
 
 // One time step with parity p: one kernel per stage (the first stage also
-// sets dt), plus the copy back for forward Euler.
+// sets dt); forward Euler goes q -> qa on even and qa -> q on odd steps.
 static hipError_t enqueue_step(const roeam_grid *g, const DevSolve &S, int shape, int time_scheme, int p,
                                hipStream_t st)
 {
     hipError_t e;
     const DevSolve *d = g->d_solve;
-    if (time_scheme == 0) {
-        e = roeam::launch_stage_single(d, S, shape, 1, p, 1, nullptr, st);
-        if (e == hipSuccess) e = roeam::launch_copy_back(S, p, st);
-        return e;
-    }
+    if (time_scheme == 0) return roeam::launch_stage_single(d, S, shape, p ? 8 : 1, p, 1, nullptr, st);
     // stage codes 1-3 (SSP-RK3) or 4-7 (four-stage scheme)
     const int first = time_scheme == 1 ? 1 : 4, nst = time_scheme == 1 ? 3 : 4;
     e = hipSuccess;
@@ -479,8 +475,11 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
         int chunk = (int)(nsteps < kStepsPerGraph ? nsteps : kStepsPerGraph);
         chunk += chunk & 1;  // even: every launch of the graph starts at parity 0
         GraphCache &G = g->gc;
-        if (!G.valid || G.q != q || G.stream != s || G.chunk != chunk || G.shape != shape ||
-            std::memcmp(&G.params, p, sizeof *p) != 0) {
+        // the graph's kernels read q and every parameter from the grid's device
+        // descriptor; it depends only on the stream, its length, the tile shape
+        // and what selects the kernels and stages
+        if (!G.valid || G.stream != s || G.chunk != chunk || G.shape != shape || G.params.order != p->order ||
+            G.params.precision != p->precision || G.params.time_scheme != p->time_scheme) {
             G.release();
             HIP_OK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             hipError_t e = hipSuccess;
@@ -512,6 +511,7 @@ roeam_status roeam_step(roeam_ctx *ctx, const roeam_grid *gc, const roeam_params
         }
     }
     g->final_parity = (int)(launched & 1);
+    if (p->time_scheme == 0) HIP_OK(ctx, roeam::launch_fe_finish(S, g->final_parity, s));
     if (stats) return fill_stats(ctx, g, stats);
     return ROEAM_OK;
 }
@@ -544,13 +544,14 @@ roeam_status roeam_profile_step(roeam_ctx *ctx, const roeam_grid *gc, const roea
         for (int stg = 1; stg <= nst && e == hipSuccess; ++stg) {
             hipEvent_t *pair = &ev[(size_t)(2 * (k * nst + stg - 1))];
             e = hipEventRecord(pair[0], s);
+            const int code = nst == 1 && par ? 8 : first + stg - 1;
             if (e == hipSuccess)
-                e = roeam::launch_stage_single(g->d_solve, S, shape, first + stg - 1, par, stg == nst ? 1 : 0, nullptr, s);
+                e = roeam::launch_stage_single(g->d_solve, S, shape, code, par, stg == nst ? 1 : 0, nullptr, s);
             if (e == hipSuccess) e = hipEventRecord(pair[1], s);
         }
-        if (e == hipSuccess && nst == 1) e = roeam::launch_copy_back(S, par, s);
     }
     g->final_parity = (int)(nsteps & 1);
+    if (e == hipSuccess && nst == 1) e = roeam::launch_fe_finish(S, g->final_parity, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(ctx, e, "profile step");
     double sum[4] = {0, 0, 0, 0};

@@ -134,17 +134,13 @@ static roeam_status ensure_stage_buffers3(roeam_ctx *ctx, roeam_grid3d *g)
     return ROEAM_OK;
 }
 
-// One time step with parity p: one kernel per stage, plus the copy back for
-// forward Euler.
+// One time step with parity p: one kernel per stage; forward Euler goes
+// q -> qa on even and qa -> q on odd steps.
 static hipError_t enqueue_step3(const roeam_grid3d *g, const DevSolve3 &S, int time_scheme, int p, hipStream_t st)
 {
     const DevSolve3 *d = g->d_solve;
     const int shape = stage_shape3(g, S.order);
-    if (time_scheme == 0) {
-        hipError_t e = roeam::launch_stage3(d, S, shape, 1, p, 1, nullptr, st);
-        if (e == hipSuccess) e = roeam::launch_copy_back3(d, S, p, st);
-        return e;
-    }
+    if (time_scheme == 0) return roeam::launch_stage3(d, S, shape, p ? 8 : 1, p, 1, nullptr, st);
     const int first = time_scheme == 1 ? 1 : 4, nst = time_scheme == 1 ? 3 : 4;
     hipError_t e = hipSuccess;
     for (int k = 0; k < nst && e == hipSuccess; ++k)
@@ -361,6 +357,7 @@ roeam_status roeam_step3d(roeam_ctx *ctx, const roeam_grid3d *gc, const roeam_pa
         }
     }
     g->final_parity = (int)(launched & 1);
+    if (p->time_scheme == 0) HIP_OK(ctx, roeam::launch_fe_finish3(g->d_solve, S, g->final_parity, s));
     if (stats) return fill_stats3(ctx, g, stats);
     return ROEAM_OK;
 }

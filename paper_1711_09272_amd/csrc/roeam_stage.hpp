@@ -32,21 +32,24 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return m;
 }
 
-// Max explicit rate of the state at parity p: lane k of every wave reads rate
-// word k, then a wave max.  Every lane of every wave ends with the same value.
-__device__ __forceinline__ double read_rate(const Slot &z, int p)
+// Rate-word set of the state after n steps.
+__host__ __device__ __forceinline__ int rate_set(long long n) { return (int)(n % kRateSets); }
+
+// Max explicit rate in word set `set`: lane k of every wave reads rate word k,
+// then a wave max.  Every lane of every wave ends with the same value.
+__device__ __forceinline__ double read_rate(const Slot &z, int set)
 {
     static_assert(kRateSlots == 64, "one rate word per lane");
     const int lane = threadIdx.x & 63;
-    double v = __longlong_as_double((long long)z.rate_bits[p][lane]);
+    double v = __longlong_as_double((long long)z.rate_bits[set][lane]);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
     return v;
 }
 
-__device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
+__device__ __forceinline__ void reduce_rate(Slot &z, int set, double v)
 {
-    atomicMax(&z.rate_bits[p][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
+    atomicMax(&z.rate_bits[set][blockIdx.x & (kRateSlots - 1)], (unsigned long long)__double_as_longlong(v));
 }
 
 // Workgroup reduction of the rate of the new state, then one device-scope
@@ -54,28 +57,44 @@ __device__ __forceinline__ void reduce_rate(Slot &z, int p, double v)
 // wave instead (no barrier) measured 25% slower on the last stage of a 2048^2
 // grid: the atomics on the 64 words contend.  red: NT/64 doubles of LDS.
 template <int NT>
-__device__ __forceinline__ void reduce_rate_block(Slot &z, int p, double v, double *red)
+__device__ __forceinline__ void reduce_rate_block(Slot &z, int set, double v, double *red)
 {
     const double m = block_max<NT>(v, red);
-    if (threadIdx.x == 0 && m > 0.0) reduce_rate(z, p, m);
+    if (threadIdx.x == 0 && m > 0.0) reduce_rate(z, set, m);
 }
 
-// Stage codes of the stage kernel: 0 residual only; 1 forward Euler or the
-// first SSP-RK3 stage; 2, 3 the second and third SSP-RK3 stages; 4-7 the four
-// stages of the four-stage scheme.  The buffers each stage reads (stencil) and
+// Stage codes of the stage kernel: 0 residual only; 1 forward Euler (steps
+// of even parity) or the first SSP-RK3 stage; 2, 3 the second and third
+// SSP-RK3 stages; 4-7 the four stages of the four-stage scheme; 8 forward
+// Euler on steps of odd parity.  The buffers each stage reads (stencil) and
 // writes, and whether it also reads Q^n at its own cells:
 //   1: q -> qa     2: qa -> qb (+Q^n)   3: qb -> q (+Q^n)
 //   4: q -> qa     5: qa -> qb (+Q^n)   6: qb -> qa (+Q^n)   7: qa -> q (+Q^n)
+//   8: qa -> q
 // (a stage that writes q reads its stencil from another buffer, and its
-// pointwise read of Q^n is the cell it writes).
-__host__ __device__ constexpr bool first_stage(int stage) { return stage == 1 || stage == 4; }
+// pointwise read of Q^n is the cell it writes).  Forward Euler alternates
+// q -> qa and qa -> q, so after an odd number of steps the state is in qa.
+__host__ __device__ constexpr bool first_stage(int stage) { return stage == 1 || stage == 4 || stage == 8; }
+// buffer a stage reads its stencil from / writes: 0 q, 1 qa, 2 qb
+__host__ __device__ constexpr int stage_in_buf(int stage)
+{
+    return (stage <= 1 || stage == 4) ? 0 : ((stage == 3 || stage == 6) ? 2 : 1);
+}
+__host__ __device__ constexpr int stage_out_buf(int stage)
+{
+    return (stage == 3 || stage == 7 || stage == 8) ? 0 : ((stage == 2 || stage == 5) ? 2 : 1);
+}
+__host__ __device__ constexpr bool stage_reads_qn(int stage)
+{
+    return stage == 2 || stage == 3 || stage == 5 || stage == 6 || stage == 7;
+}
 
 // Fraction of dt at which a stage's input state lies (the abscissae c of the
 // schemes): stage codes 1-3 are SSP-RK3 (0, 1, 1/2), 4-7 the four-stage scheme
 // (0, 1/4, 1/3, 1/2).
 __host__ __device__ constexpr double stage_abscissa(int stage)
 {
-    return stage == 2 ? 1.0 : stage == 3 ? 0.5 : stage == 5 ? 0.25 : stage == 6 ? 1.0 / 3.0 : stage == 7 ? 0.5 : 0.0;
+    return stage == 2 ? 1.0 : stage == 3 ? 0.5 : stage == 5 ? 0.25 : stage == 6 ? 1.0 / 3.0 : stage == 7 ? 0.5 : 0.0;  // 8: 0
 }
 
 // The words of the step state a stage decides on, read through a global view
@@ -83,7 +102,7 @@ __host__ __device__ constexpr double stage_abscissa(int stage)
 // waits for them without waiting for those).  None of them is written by the
 // kernel that reads them: the first stage reads parity p and publishes p^1.
 struct StepWords {
-    unsigned long long rate_bits;  // rate word `lane` of parity p (first stage)
+    unsigned long long rate_bits;  // rate word `lane` of the input state's set (first stage)
     double t, t_end, cfl, dt_n;
     long long steps, steps_n, max_steps;
     int nonphys;
@@ -100,7 +119,12 @@ __device__ __forceinline__ StepWords load_step_words(const Slot &zs, int p, int 
         w.steps_n = z.st[p ^ 1].steps;
         return w;
     }
-    w.rate_bits = z.rate_bits[p][threadIdx.x & 63];
+    // all three sets are read, and the input state's one kept, so that no
+    // load waits for the step count
+    const unsigned long long r0 = z.rate_bits[0][threadIdx.x & 63], r1 = z.rate_bits[1][threadIdx.x & 63],
+                             r2 = z.rate_bits[2][threadIdx.x & 63];
+    const int set = rate_set(w.steps);
+    w.rate_bits = set == 0 ? r0 : (set == 1 ? r1 : r2);
     w.t = z.st[p].t;
     w.t_end = z.t_end;
     w.cfl = z.cfl;
@@ -118,7 +142,7 @@ __device__ __forceinline__ bool step_active(const StepWords &w, int stage, doubl
         dt = w.dt_n;
         return w.steps_n != w.steps;
     }
-    // max explicit rate of the state: a wave max over the 64 rate words
+    // max explicit rate of the state: a wave max over its 64 rate words
     double v = __longlong_as_double((long long)w.rate_bits);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = rmax(v, __shfl_xor(v, o, 64));
@@ -135,8 +159,8 @@ __device__ __forceinline__ bool step_active(const StepWords &w, int stage, doubl
 
 // Start of a stage kernel's workgroup: decide whether the step is active and
 // its dt; on the first stage, workgroup 0 (first_block) publishes the next
-// step state and, unless this stage also ends the step, clears the rate words
-// that the step's last stage will reduce into.  w: load_step_words(z, p, stage).
+// step state and clears the rate words of the step after this one (set
+// n + 2 for input step count n).  w: load_step_words(z, p, stage).
 __device__ __forceinline__ bool begin_stage(Slot &z, const StepWords &w, int p, int stage, int last, int first_block,
                                             double &dt)
 {
@@ -158,9 +182,10 @@ __device__ __forceinline__ bool begin_stage(Slot &z, const StepWords &w, int p, 
                 n.steps = w.steps;
             }
         }
-        // multi-stage schemes: the last stage reduces into parity p^1; forward
-        // Euler reduces in this kernel, so its words were cleared earlier.
-        if (!last && tid < kRateSlots) z.rate_bits[p ^ 1][tid] = 0ull;
+        // set n + 1 (this step's result) was cleared by the previous step;
+        // set n was read by this step's workgroups and stays until step n + 1
+        (void)last;
+        if (tid < kRateSlots) z.rate_bits[rate_set(w.steps + 2)][tid] = 0ull;
     }
     return active;
 }

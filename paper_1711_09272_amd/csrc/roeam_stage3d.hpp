@@ -194,7 +194,8 @@ struct StageLds {
 // positivity check and the rate read the flow rows only.
 __device__ __forceinline__ const double *stage_input3(const DevSolve3 &S, int stage)
 {
-    return (stage <= 1 || stage == 4) ? S.q : ((stage == 3 || stage == 6) ? S.qb : S.qa);
+    const int b = stage_in_buf(stage);
+    return b == 0 ? S.q : (b == 2 ? S.qb : S.qa);
 }
 
 // Origin of brick t.  Bricks are numbered x fastest, then z, then y: the
@@ -221,7 +222,7 @@ __device__ __forceinline__ void own_cells(const DevSolve3 &S, int stage, const d
                                           int l0, double (*Qs)[5 + NSC], double (*Q0)[5 + NSC], long long *cidx)
 {
     constexpr int NC = TX * TY * TZ, CPT = (NC + NT - 1) / NT, NR = 5 + NSC;
-    const bool reads_qn = stage >= 2 && stage != 4;
+    const bool reads_qn = stage_reads_qn(stage);
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = threadIdx.x + m * NT;
@@ -479,7 +480,8 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             switch (stage) {
-            case 1: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
+            case 1:
+            case 8: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
             case 2: Qn[k] = 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k]); break;
             case 3: Qn[k] = (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]); break;
             case 4: Qn[k] = Qs[m][k] + (0.25 * dt) * Rv[k]; break;
@@ -488,7 +490,8 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
             default: Qn[k] = Q0[m][k] + dt * Rv[k]; break;
             }
         }
-        double *__restrict__ qo = (stage == 3 || stage == 7) ? S.q : ((stage == 2 || stage == 5) ? S.qb : S.qa);
+        const int bout = stage_out_buf(stage);
+        double *__restrict__ qo = bout == 0 ? S.q : (bout == 2 ? S.qb : S.qa);
 #pragma unroll
         for (int k = 0; k < NR; ++k) gptr(qo)[k * S.plane + idx] = Qn[k];
         double W[5];
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(NT) void k_stage3(const DevSolve3 *__restrict__ Sp,
     __syncthreads();
     double lmax = 0.0;
     brick_body<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, L, stage, last, dt, i0, j0, l0, Qs, Q0, cidx, r_out, lmax);
-    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, L.sRed);
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : rate_set(sw.steps + 1), lmax, L.sRed);
 }
 
 // Persistent form: gridDim.x (a multiple of 8) resident workgroups; those of
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp
         }
         brick_body<ORDER, PREC, NSC, TX, TY, TZ, NT>(S, L, stage, last, dt, i0, j0, l0, Qs, Q0, cidx, r_out, lmax);
     }
-    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : (p ^ 1), lmax, L.sRed);
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : rate_set(sw.steps + 1), lmax, L.sRed);
 }
 
 // Brick shapes: id, TX, TY, TZ, threads, persistent.  Shapes 4-9 give every

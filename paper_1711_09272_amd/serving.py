@@ -34,11 +34,15 @@ class Server:
     """One context's batch engine driven as a request loop.
 
     arena_bytes bounds the device memory held by resident solves (three state
-    copies each); requests that do not fit wait in the engine's queue."""
+    copies each); requests that do not fit wait in the engine's queue.
+    graph_iters: scheduler iterations per captured graph (a finished request
+    is noticed after the graph it finished in); policy: admission order of
+    queued requests (P.ADMIT_FIFO or P.ADMIT_SHORTEST)."""
 
-    def __init__(self, ctx: "P.Context", arena_bytes: int):
+    def __init__(self, ctx: "P.Context", arena_bytes: int, graph_iters: int = 8, policy: int = P.ADMIT_FIFO):
         self.ctx = ctx
         P.batch_reserve(ctx, arena_bytes)
+        P.batch_configure(ctx, graph_iters=graph_iters, policy=policy)
         self.outstanding: List[Request] = []
         self.done: List[Request] = []
 

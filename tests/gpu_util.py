@@ -36,6 +36,18 @@ def residual_error(r_gpu, r_or, scale):
     return np.array([np.abs(r_gpu[k] - r_or[k]).max() / scale[k].max() for k in range(4)])
 
 
+def residual_error_cell(r_gpu, r_or, scale, floor=1e-6):
+    """The same cell by cell: max over cells of |dR| / the cell's own flux
+    scale, the scale floored at `floor` times the row's largest (a cell at rest
+    carries no mass flux at all).  Catches errors in quiet regions that the
+    row-wide norm weights down by the ratio of the scales."""
+    out = []
+    for k in range(r_or.shape[0]):
+        s = np.maximum(scale[k], floor * scale[k].max())
+        out.append((np.abs(r_gpu[k] - r_or[k]) / s).max())
+    return np.array(out)
+
+
 def gpu_run(c, case, nsteps=None, t_end=None, params=None, q0=None):
     import torch
     import paper_1711_09272_amd as P

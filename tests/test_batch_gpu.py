@@ -134,12 +134,16 @@ def test_continuous_admission_and_arena_pressure(C):
     grids = [P.Grid.from_case(C, c) for c in cases]
     big = max(g.footprint() for g in grids)
     P.batch_reserve(C, 2 * big + 4096)
-    _, first = submit_all(C, cases[:3], grids[:3])
-    P.batch_run(C, 3)
-    _, second = submit_all(C, cases[3:], grids[3:])
-    P.batch_run(C, 2)
-    _, third = submit_all(C, cases[:2], grids[:2])  # the same solves again, mid-flight
-    assert P.batch_run(C, -1) == 0
+    P.batch_configure(C, graph_iters=2)  # short graphs: later solves join mid-flight
+    try:
+        _, first = submit_all(C, cases[:3], grids[:3])
+        P.batch_run(C, 3)
+        _, second = submit_all(C, cases[3:], grids[3:])
+        P.batch_run(C, 2)
+        _, third = submit_all(C, cases[:2], grids[:2])  # the same solves again, mid-flight
+        assert P.batch_run(C, -1) == 0
+    finally:
+        P.batch_configure(C)
     res = collect(C, first + second + third)
     alone = [run_alone(C, c)[0] for c in cases]
     for k, (q, st, rc) in enumerate(res):
@@ -230,3 +234,104 @@ def test_batch_profile_run_matches_batch_run(C):
     assert launches == 3 * 6 and all(t > 0.0 for t in stage_ms[:3]) and stage_ms[3] == 0.0, (stage_ms, launches)
     for (qa, sa, ca), (qb, sb, cb) in zip(ra, rb):
         assert ca == cb == P.OK and sa == sb and np.array_equal(qa, qb)
+
+
+def test_graph_survives_admissions_and_retirements(C):
+    """The work lists live in device memory and the graph's launches are sized
+    to their capacity: after the first capture, solves admitted and retired
+    within that capacity run from the same graph instance (capture counter
+    unchanged), and every result is bitwise the solve run alone."""
+    import paper_1711_09272_amd as P
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 52))
+    waves = [[workloads.bump_case(n, rng, s) for n, s in ((64, 20), (48, 9), (80, 31))],
+             [workloads.bump_case(n, rng, s) for n, s in ((56, 12), (40, 25))],
+             [workloads.bump_case(n, rng, s) for n, s in ((72, 7), (64, 18), (32, 40))]]
+    P.batch_reserve(C, 256 << 20)
+    P.batch_configure(C, graph_iters=4)
+    try:
+        _, first = submit_all(C, waves[0])
+        P.batch_run(C, 4)
+        info0 = P.batch_info(C)
+        assert info0["captures"] == 1 and info0["resident"] == 3, info0
+        solves = list(first)
+        for w in waves[1:]:
+            _, more = submit_all(C, w)
+            solves += more
+            P.batch_run(C, 8)
+        assert P.batch_run(C, -1) == 0
+        info = P.batch_info(C)
+    finally:
+        P.batch_configure(C)
+    say(f"[graph reuse] {info}")
+    assert info["captures"] == 1 and info["graph_launches"] >= 10, info
+    cases = [c for w in waves for c in w]
+    for c, (q, st, rc) in zip(cases, collect(C, solves)):
+        qa, sta = run_alone(C, c)
+        assert rc == P.OK and st["steps"] == c.nsteps == sta["steps"]
+        assert np.array_equal(q, qa), c.name
+
+
+@pytest.mark.parametrize("tune", [True, False])
+def test_persistent_kernels_equal_windowed(C, tune):
+    """The persistent batched kernels (resident workgroups taking tiles in
+    turn) give bitwise the results of one workgroup per tile, with or without
+    the batch tile-shape tuning."""
+    import paper_1711_09272_amd as P
+    cases = family()
+    out = {}
+    for persistent in (False, True):
+        P.batch_reserve(C, 256 << 20)
+        P.batch_configure(C, persistent=persistent, autotune=tune)
+        try:
+            _, solves = submit_all(C, cases)
+            assert P.batch_run(C, -1) == 0
+            assert P.batch_info(C)["persistent"] == int(persistent)
+        finally:
+            P.batch_configure(C)
+        out[persistent] = collect(C, solves)
+    for c, (qa, sa, ca), (qb, sb, cb) in zip(cases, out[False], out[True]):
+        assert ca == cb == P.OK and sa == sb and np.array_equal(qa, qb), c.name
+
+
+def test_shortest_first_admission(C):
+    """With room for one solve at a time, ROEAM_ADMIT_SHORTEST admits the
+    queued solve of least work (cells x steps) first, FIFO the first
+    submitted; results are bitwise the solves run alone either way."""
+    import paper_1711_09272_amd as P
+    rng = np.random.Generator(np.random.PCG64(workloads.SEED_BASE + 53))
+    big, small = workloads.bump_case(96, rng, 30), workloads.bump_case(40, rng, 6)
+    grids = [P.Grid.from_case(C, c) for c in (big, small)]
+    for policy, first_done in ((P.ADMIT_FIFO, 0), (P.ADMIT_SHORTEST, 1)):
+        P.batch_reserve(C, grids[0].footprint() + 4096)
+        P.batch_configure(C, graph_iters=2, policy=policy)
+        try:
+            _, solves = submit_all(C, [big, small], grids)
+            order = []
+            while len(order) < 2:
+                P.batch_run(C, 2)
+                for k, s in enumerate(solves):
+                    if k not in order and P.batch_poll(C, s.ticket)[0]:
+                        order.append(k)
+        finally:
+            P.batch_configure(C)
+        assert order[0] == first_done, (policy, order)
+        for k, c in enumerate((big, small)):
+            assert np.array_equal(solves[k].q_out[:, :, : c.nx], run_alone(C, c)[0])
+
+
+@pytest.mark.parametrize("nsteps", [7, 8])
+def test_forward_euler_odd_and_even_step_counts(C, nsteps):
+    """Forward Euler alternates q -> qa and qa -> q with no copy between steps:
+    after an odd or an even number of steps the result (single grid and
+    batched) is the oracle's."""
+    import paper_1711_09272_amd as P
+    case = workloads.sod(nx=100, ny=3)
+    case.nsteps, case.t_end = nsteps, 0.0
+    q_or, st_or = oracle.run(case)
+    qa, sta = run_alone(C, case)
+    assert sta["steps"] == nsteps and state_error(qa, q_or) <= 1e-13
+    P.batch_reserve(C, 16 << 20)
+    _, solves = submit_all(C, [case])
+    assert P.batch_run(C, -1) == 0
+    (q, st, rc), = collect(C, solves)
+    assert rc == P.OK and st["steps"] == nsteps and np.array_equal(q, qa)

@@ -12,13 +12,18 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import ctx, gpu_residual, gpu_run, residual_error, say, state_error
+from gpu_util import ctx, gpu_residual, gpu_run, residual_error, residual_error_cell, say, state_error
 from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+# cell by cell, each cell against its own flux scale (floored at 1e-6 of the
+# row's largest): the largest seen is 1.06e-12 on the M = 0.01 vortex, whose
+# row-norm error (5.9e-13) is the conditioning of the pressure-jump term at
+# 1/theta = 1e4 (the other cases stay below 1e-14)
+TOL64_CELL = 2e-12
 
 
 @pytest.fixture(scope="module")
@@ -66,8 +71,10 @@ def test_residual_fp64(C, name, case):
     r_or, scale = oracle.residual(case, with_scale=True)
     r_gpu, rate = gpu_residual(C, case, rate=True)
     err = residual_error(r_gpu, r_or, scale)
-    say(f"    err per row {err}")
+    errc = residual_error_cell(r_gpu, r_or, scale)
+    say(f"    err per row {err}, per cell {errc}")
     assert np.all(err <= TOL64), err
+    assert np.all(errc <= TOL64_CELL), errc
     rate_or = oracle.max_rate(case)
     assert abs(rate - rate_or) <= 1e-14 * rate_or
 
