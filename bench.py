@@ -233,110 +233,266 @@ def percentile(xs, q):
 
 def one_at_a_time(ctx, items, precision):
     """Run each (grid, params, q0_tensor, steps) alone through roeam_step in
-    order; returns per-item GPU-serial completion times (s from start) and total."""
+    order; returns per-item GPU-serial completion times (s from start) and total.
+    Tile shapes are tuned and the step graphs captured beforehand (a run of up
+    to 50 steps of each item on its own working buffer, which the timed run
+    reuses), so the timed runs only replay graphs."""
     import torch
     import paper_1711_09272_amd as P
-    # tune tile shapes first (zero-step runs), outside the timing
+    bufs = []
     for g, prm, q0, n in items:
         p = dict(prm)
         p["precision"] = precision
-        P.step(ctx, g, p, q0.clone(), 0)
+        b = q0.clone()
+        P.step(ctx, g, p, b, min(n, 50), sync=True)
+        bufs.append(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = []
-    for g, prm, q0, n in items:
+    for (g, prm, q0, n), b in zip(items, bufs):
         p = dict(prm)
         p["precision"] = precision
-        q = q0.clone()
-        P.step(ctx, g, p, q, n, sync=True)
+        b.copy_(q0)
+        P.step(ctx, g, p, b, n, sync=True)
         done.append(time.perf_counter() - t0)
     return done, time.perf_counter() - t0
 
 
-def bench_batch(args):
-    """Fourth configuration: 256 seeded grids of sides log-uniform 32..512, 200
-    SSP-RK3 steps each, FP32 coefficients / FP64 state, all submitted at once
-    and advanced together (graph-replayed batched stage kernels)."""
-    import torch
-    import paper_1711_09272_amd as P
+def batch_cases(n_grids: int, prec: int):
+    """The fourth configuration's grids: 256 bump-family periodic grids, sides
+    log-uniform 32..512 (seeded), MUSCL + SSP-RK3, 200 steps each."""
     import workloads
-    prec = 1 if args.precision is None else args.precision
-    cases = workloads.batch_family(args.batch_grids, nsteps=args.steps, precision=prec)
-    ctx = P.Context(0)
-    grids = [P.Grid.from_case(ctx, c) for c in cases]
-    if args.batch_shape >= 0:
-        for g in grids:
-            g.set_tile_shape(args.batch_shape)
-    q0 = [g.to_device(c.q0) for g, c in zip(grids, cases)]
-    cells = sum(c.nx * c.ny for c in cases)
-    P.batch_reserve(ctx, sum(g.footprint() for g in grids) + (64 << 20))
-    spin_up_generic(args.spin_up_s)
+    return workloads.batch_family(n_grids, nsteps=BATCH_STEPS, precision=prec)
 
-    def run(nsteps):
-        outs = [g.empty_state() for g in grids]
-        solves = [P.Solve(g, c.params, q, nsteps, 0.0, o) for g, c, q, o in zip(grids, cases, q0, outs)]
+
+BATCH_STEPS = 200
+BATCH_GRAPH_ITERS = 20  # 200 steps = 10 graphs
+
+
+class BatchRunner:
+    """The fourth configuration on the batch engine: all grids submitted at
+    once and advanced together until every one is done; one `run` is one
+    bench step (the whole batch, 200 SSP-RK3 steps of each grid)."""
+
+    def __init__(self, ctx, cases, persistent=False, reserve_extra=64 << 20):
+        import paper_1711_09272_amd as P
+        self.P, self.ctx, self.cases = P, ctx, cases
+        self.grids = [P.Grid.from_case(ctx, c) for c in cases]
+        self.q0 = [g.to_device(c.q0) for g, c in zip(self.grids, cases)]
+        self.out = [g.empty_state() for g in self.grids]
+        self.cells = sum(c.nx * c.ny for c in cases)
+        P.batch_reserve(ctx, sum(g.footprint() for g in self.grids) + reserve_extra)
+        P.batch_configure(ctx, graph_iters=BATCH_GRAPH_ITERS, persistent=persistent)
+
+    def run(self, nsteps=BATCH_STEPS):
+        """Submit every grid, drive the engine until all are done; returns the
+        latency of each solve (s, submission to the poll that saw it done)."""
+        P = self.P
+        solves = [P.Solve(g, c.params, q, nsteps, 0.0, o)
+                  for g, c, q, o in zip(self.grids, self.cases, self.q0, self.out)]
         t0 = time.perf_counter()
-        P.batch_submit(ctx, solves)
+        P.batch_submit(self.ctx, solves)
         fin = {}
         while len(fin) < len(solves):
-            P.batch_run(ctx, 16)
+            P.batch_run(self.ctx, BATCH_GRAPH_ITERS)
             now = time.perf_counter()
             for s in solves:
                 if s.ticket not in fin:
-                    done, st, rc = P.batch_poll(ctx, s.ticket)
+                    done, st, rc = P.batch_poll(self.ctx, s.ticket)
                     if done:
                         if rc != P.OK or st["steps"] != nsteps:
                             raise SystemExit(f"batched solve failed: {st} {rc}")
                         fin[s.ticket] = now - t0
         return [fin[s.ticket] for s in solves]
 
-    run(2)  # warm-up: kernels, graphs
+    def profile(self, nsteps=BATCH_STEPS):
+        """The same batch once more with HIP events around every batched stage
+        launch (direct launches, no graph): (mean stage ms, launches)."""
+        P = self.P
+        solves = [P.Solve(g, c.params, q, nsteps, 0.0, o)
+                  for g, c, q, o in zip(self.grids, self.cases, self.q0, self.out)]
+        P.batch_submit(self.ctx, solves)
+        stage_ms, launches = P.batch_profile_run(self.ctx, -1)
+        for s in solves:
+            done, st, rc = P.batch_poll(self.ctx, s.ticket)
+            if not done or rc != P.OK or st["steps"] != nsteps:
+                raise SystemExit(f"batched profile run failed: {done} {st} {rc}")
+        return stage_ms, launches
+
+
+def timed_repeats(fn, k, stream):
+    """GPU seconds (HIP events on torch's stream, which waits for the library's
+    stream before the end event) and wall seconds of k calls of fn; also the
+    list of fn's results."""
+    import torch
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
     ev0.record(stream)
-    lat = run(args.steps)
+    res = [fn() for _ in range(k)]
     ev1.record(stream)
     torch.cuda.synchronize()
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    updates = cells * 3 * args.steps
-    items = [(g, c.params, q, args.steps) for g, c, q in zip(grids, cases, q0)]
-    alone64, total64 = one_at_a_time(ctx, items, 0)
-    aloneP, totalP = (alone64, total64) if prec == 0 else one_at_a_time(ctx, items, prec)
+    return ev0.elapsed_time(ev1) / 1e3, time.perf_counter() - t0, res
+
+
+def single_grid_point(ctx, n, steps, precision, stream):
+    """One n x n vortex grid through roeam_step (autotuned shape, graph
+    replay): Gcell-stage/s and the HBM fraction of the stage kernel."""
+    import torch
+    import paper_1711_09272_amd as P
+    import workloads
+    case = workloads.vortex(n, 0.01)
+    case.params["precision"] = precision
+    g = P.Grid.from_case(ctx, case)
+    q = g.to_device(case.q0)
+    P.step(ctx, g, case.params, q, 20, sync=True)  # tunes the shape, captures the graph
+    gpu_s, wall, _ = timed_repeats(lambda: P.step(ctx, g, case.params, q, steps, sync=False), 1, stream)
+    st = P.last_stats(ctx, g)
+    if st["nonphys"] or st["steps"] != steps:
+        raise SystemExit(f"single-grid run failed: {st}")
+    cells = n * n
+    launch_ms = gpu_s * 1e3 / (3 * steps)
+    bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    shape = g.tile_shape(case.params)
+    return {"workload": f"low-Mach vortex {n}x{n} periodic, M=0.01, MUSCL + SSP-RK3, Roe-AM (detector, eps1=1)",
+            "dtype": "f64" if precision == 0 else "f32-flux/f64-state", "steps": steps,
+            "value": round(cells * 3 * steps / gpu_s / 1e9, 4), "unit": "Gcell-updates/s",
+            "ms_per_step": round(gpu_s * 1e3 / steps, 5), "tile_shape": P.SHAPES[shape] if shape >= 0 else None,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(achieved / PEAK_HBM_GBS, 5), "launch_ms": round(launch_ms, 6),
+                         "algorithmic_bytes_per_launch": bytes_per_launch}}
+
+
+def bench_batch(args):
+    """Fourth configuration (the default line): 256 seeded grids of sides
+    log-uniform 32..512, 200 SSP-RK3 steps each, FP32 flux coefficients with
+    FP64 state, all submitted at once and advanced together through the batch
+    engine (graph-replayed batched stage kernels).  A bench step is the whole
+    batch; --steps and --warmup count whole batches."""
+    import torch
+    import paper_1711_09272_amd as P
+    prec = 1 if args.precision is None else args.precision
+    cases = batch_cases(args.batch_grids, prec)
+    ctx = P.Context(0)
+    stream = torch.cuda.current_stream()
+    runner = BatchRunner(ctx, cases, persistent=args.batch_persistent)
+    cells = runner.cells
+    updates_per_step = cells * 3 * BATCH_STEPS
+    bytes_per_launch = cells * sum(BYTES_PER_CELL_STAGE.values()) / 3.0
+    if args.counter_run:
+        stage_ms, launches = runner.profile(args.profile_steps)
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": "batch256", "cells": cells, "profile_steps": args.profile_steps,
+                          "copy_bytes": src.numel() * 8, "info": P.batch_info(ctx)}), flush=True)
+        return
+    spin_up(lambda: runner.run(20), args.spin_up_s)
+    for _ in range(max(args.warmup, 1)):  # the first forms the group: tile-shape tuning, graph capture
+        runner.run()
+    info0 = P.batch_info(ctx)
+    gpu_s, wall, lats = timed_repeats(runner.run, args.steps, stream)
+    info = P.batch_info(ctx)
+    lat = [x for rep in lats for x in rep]
+    launches_per_step = 3 * BATCH_STEPS
+    launch_ms = gpu_s * 1e3 / (args.steps * launches_per_step)
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    stage_ms, plaunches = runner.profile()
+    tag = "batch256"
+    traffic = measured_traffic(tag, prec)
+    valu = measured_valu(tag, prec)
+    alu = None
+    if valu is not None:
+        lane_rate = valu * cells / (launch_ms / 1e3)
+        alu = {"bound": "alu", "achieved": round(lane_rate / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 3),
+               "unit": "T VALU lane-instr/s", "frac": round(lane_rate / PEAK_VALU_LANE_INSTR, 4),
+               "valu_lane_instr_per_cell_stage": valu}
+    shape = info["shape"]
+    kform = "k_stage_batch_p" if args.batch_persistent else "k_stage_batch"
     out = {
-        "metric": "Gcell-updates/s per RK stage (batched)",
-        "value": round(updates / gpu_s / 1e9, 4),
+        "metric": "Gcell-updates/s per RK stage",
+        "value": round(updates_per_step * args.steps / gpu_s / 1e9, 4),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_s * 1e3 / args.steps, 4),
         "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32-flux/f64-state",
         "data": "synthetic",
-        "config": {"workload": f"{len(cases)} bump-family grids, sides log-uniform 32..512, "
-                               f"{args.steps} SSP-RK3 steps each, submitted together",
-                   "cells": cells, "cell_stage_updates": updates, "tile_shape": args.batch_shape},
-        "makespan_s": round(gpu_s, 4),
-        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
-        "one_at_a_time": {
-            "same_precision": {"value": round(updates / totalP / 1e9, 4), "makespan_s": round(totalP, 4),
-                               "p50_s": percentile(aloneP, 50), "p99_s": percentile(aloneP, 99)},
-            "fp64": {"value": round(updates / total64 / 1e9, 4), "makespan_s": round(total64, 4),
-                     "p50_s": percentile(alone64, 50), "p99_s": percentile(alone64, 99)},
+        "config": {"workload": f"{len(cases)} bump-family periodic grids, sides log-uniform 32..512 (seeded), "
+                               f"{BATCH_STEPS} SSP-RK3 steps each, MUSCL-minmod, Roe-AM (detector, eps1=1), "
+                               "submitted together, continuous-batching engine; one bench step = the whole batch",
+                   "grids": len(cases), "cells": cells, "rk_steps_per_grid": BATCH_STEPS,
+                   "cell_stage_updates_per_step": updates_per_step,
+                   "tile_shape": P.SHAPES[shape] if shape >= 0 else None,
+                   "kernel_form": "persistent" if args.batch_persistent else "one workgroup per tile",
+                   "graph_iters": BATCH_GRAPH_ITERS, "graph_captures_in_timed_region": info["captures"] - info0["captures"],
+                   "wall_s": round(wall, 4)},
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat),
+                      "what": "per solve, submission to completion, every solve of every timed batch"},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5),
+            "traffic": traffic,
+            "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
+            "alu": alu,
+            "kernel": "%s<order 2, FP%s, uniform, %s>" % (kform, "64" if prec == 0 else "32-coef",
+                                                         P.SHAPES[shape] if shape >= 0 else "?"),
+            "kernel_grid": f"{len(cases)} grids, {cells} cells",
+            "launch_ms": round(launch_ms, 6),
+            "timed_region_launches": args.steps * launches_per_step,
+            "event_bracketed_stage_ms": [round(x, 5) for x in stage_ms[:3]],
+            "event_bracketed_launches": plaunches,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
         },
     }
+    if not args.no_extra_legs:
+        # the same batch in FP64
+        cases64 = batch_cases(args.batch_grids, 0)
+        r64 = BatchRunner(ctx, cases64, persistent=args.batch_persistent)
+        r64.run()
+        k64 = max(1, args.steps // 4)
+        g64, _, lats64 = timed_repeats(r64.run, k64, stream)
+        lat64 = [x for rep in lats64 for x in rep]
+        out["fp64"] = {"value": round(updates_per_step * k64 / g64 / 1e9, 4), "ms_per_step": round(g64 * 1e3 / k64, 4),
+                       "repeats": k64, "latency_p50_s": percentile(lat64, 50), "latency_p99_s": percentile(lat64, 99),
+                       "hbm_frac": round(bytes_per_launch / (g64 / (k64 * launches_per_step)) / 1e9 / PEAK_HBM_GBS, 5)}
+        del r64
+        # one grid at a time through roeam_step, shapes tuned and graphs captured beforehand
+        items = [(g, c.params, q, BATCH_STEPS) for g, c, q in zip(runner.grids, cases, runner.q0)]
+        legs = {}
+        for name, pr in (("fp64", 0), ("same_precision", prec)):
+            done, total = one_at_a_time(ctx, items, pr)
+            legs[name] = {"value": round(updates_per_step / total / 1e9, 4), "makespan_s": round(total, 4),
+                          "p50_s": percentile(done, 50), "p99_s": percentile(done, 99)}
+        out["one_at_a_time"] = legs
+        # the single-grid FP64 path at 2048^2
+        out["single_grid_fp64_2048"] = single_grid_point(ctx, 2048, args.single_steps, 0, stream)
     if not args.no_cpu_baseline:
-        # the oracle on a bounded sample: the first 16 grids, all their steps
+        # the oracle on a bounded sample: the first 16 grids, all their steps, FP64
         import oracle
         sample = cases[:16]
         t0 = time.perf_counter()
         upd = 0
         for c in sample:
-            _, st = oracle.run(c, nsteps=args.steps)
+            prm = dict(c.params)
+            prm["precision"] = 0
+            _, st = oracle.run(c, params=prm, nsteps=BATCH_STEPS)
             upd += c.nx * c.ny * 3 * st["steps"]
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": upd / dt / 1e9, "unit": "Gcell-updates/s per RK stage",
                                "cores": oracle.max_threads(), "kind": "oracle",
-                               "sample": f"the first {len(sample)} of the {len(cases)} grids, {args.steps} steps each, "
-                                         f"FP64 ({upd} cell-stage updates, {dt:.1f} s)"}
+                               "sample": f"the first {len(sample)} of the {len(cases)} grids, {BATCH_STEPS} steps each, "
+                                         f"FP64 ({upd} cell-stage updates, {dt:.1f} s, "
+                                         f"{oracle.max_threads()} OpenMP threads over rows)"}
     print(json.dumps(out), flush=True)
 
 
@@ -404,15 +560,18 @@ def bench_to_t_end(args):
 
 def bench_serve(args):
     """Fifth configuration: Poisson arrivals (rates swept) of solves with grid
-    sides log-uniform 64..2048 and 50..2000 steps, bump-family states built on
-    the device; served with continuous batching vs one at a time (FP64)."""
+    sides log-uniform 64..2048 and 50..2000 steps, bump-family states; served
+    with continuous batching vs one at a time through roeam_step.  Initial
+    states are built on the device before each trace starts; the
+    one-at-a-time leg has every grid size's tile shape tuned and step graph
+    captured beforehand, so neither leg pays set-up inside a latency."""
     import torch
     import paper_1711_09272_amd as P
     import workloads
     from paper_1711_09272_amd.serving import Server
     prec = 0 if args.precision is None else args.precision
     ctx = P.Context(0)
-    grid_cache = {}
+    grid_cache, buf_cache = {}, {}
 
     def grid(n):
         if n not in grid_cache:
@@ -421,59 +580,96 @@ def bench_serve(args):
 
     spin_up_generic(args.spin_up_s)
     results = []
+    work_total = 0.0
     for rate in [float(r) for r in args.rates.split(",")]:
         trace = workloads.serving_trace(rate, args.duration)
-        server = Server(ctx, args.arena_gb << 30)
-        t0 = time.perf_counter()
-        k = 0
-        reqs = []
-        while k < len(trace) or server.outstanding:
-            now = time.perf_counter() - t0
-            while k < len(trace) and trace[k]["arrival_s"] <= now:
-                tr = trace[k]
-                g = grid(tr["n"])
-                q0 = workloads.bump_state_device(tr["n"], tr["spec"], g.pitch)
-                prm = workloads.bump_params(tr["spec"]["mach"], precision=prec)
-                r = server.submit(g, prm, q0, tr["steps"], tag=k)
-                r.arrival = t0 + tr["arrival_s"]
-                reqs.append(r)
-                k += 1
-            if server.outstanding:
-                for r in server.pump(8):
-                    r.solve.q0 = r.solve.q_out = None  # release device memory
+        states = [workloads.bump_state_device(tr["n"], tr["spec"], grid(tr["n"]).pitch) for tr in trace]
+        prms = [workloads.bump_params(tr["spec"]["mach"], precision=prec) for tr in trace]
+        # one-at-a-time set-up, outside any latency: tune each size's tile shape
+        # and capture its step graph on a working buffer of that size
+        for tr, q0, prm in zip(trace, states, prms):
+            n = tr["n"]
+            if n not in buf_cache:
+                buf_cache[n] = q0.clone()
+                P.step(ctx, grid(n), prm, buf_cache[n], 50, sync=True)
+        torch.cuda.synchronize()
+        legs = {}
+        for leg in ("served", "one_at_a_time"):
+            t0 = time.perf_counter()
+            lat, done_at = [], []
+            if leg == "served":
+                server = Server(ctx, args.arena_gb << 30, graph_iters=args.serve_graph_iters, policy=args.serve_policy)
+                k = 0
+                reqs = []
+                while k < len(trace) or server.outstanding:
+                    now = time.perf_counter() - t0
+                    while k < len(trace) and trace[k]["arrival_s"] <= now:
+                        r = server.submit(grid(trace[k]["n"]), prms[k], states[k], trace[k]["steps"], tag=k)
+                        r.arrival = t0 + trace[k]["arrival_s"]
+                        reqs.append(r)
+                        k += 1
+                    if server.outstanding:
+                        for r in server.pump(args.serve_graph_iters):
+                            r.solve.q_out = None  # release device memory
+                    else:
+                        time.sleep(0.0005)
+                lat = [r.finished - r.arrival for r in reqs]
+                done_at = [r.finished for r in reqs]
+                bad = [r for r in reqs if r.code != P.OK or r.stats["steps"] != r.solve.nsteps]
+                if bad:
+                    raise SystemExit(f"served request failed: {bad[0].stats} {bad[0].code}")
+                del server
             else:
-                time.sleep(0.0005)
-        wall = time.perf_counter() - t0
-        lat = [r.finished - r.arrival for r in reqs]
-        updates = sum(r.cells * 3 * r.solve.nsteps for r in reqs)
-        span = max(r.finished for r in reqs) - (t0 + trace[0]["arrival_s"])
-        # one at a time, FIFO, in real time: each request runs alone when the previous finished
-        t1 = time.perf_counter()
-        lat1 = []
-        for tr in trace:
-            wait = t1 + tr["arrival_s"] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
-            g = grid(tr["n"])
-            q = workloads.bump_state_device(tr["n"], tr["spec"], g.pitch)
-            P.step(ctx, g, workloads.bump_params(tr["spec"]["mach"], precision=0), q, tr["steps"], sync=True)
-            lat1.append(time.perf_counter() - (t1 + tr["arrival_s"]))
-        span1 = time.perf_counter() - (t1 + trace[0]["arrival_s"])
-        results.append({
-            "rate_per_s": rate, "requests": len(trace), "duration_s": args.duration,
-            "served": {"gcell_updates_per_s": round(updates / span / 1e9, 4), "p50_s": percentile(lat, 50),
-                       "p99_s": percentile(lat, 99), "wall_s": round(wall, 3)},
-            "one_at_a_time_fp64": {"gcell_updates_per_s": round(updates / span1 / 1e9, 4),
-                                   "p50_s": percentile(lat1, 50), "p99_s": percentile(lat1, 99)},
-        })
+                for tr, q0, prm in zip(trace, states, prms):
+                    wait = t0 + tr["arrival_s"] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    b = buf_cache[tr["n"]]
+                    b.copy_(q0)
+                    st = P.step(ctx, grid(tr["n"]), prm, b, tr["steps"], sync=True)
+                    if st["nonphys"] or st["steps"] != tr["steps"]:
+                        raise SystemExit(f"one-at-a-time request failed: {st}")
+                    now = time.perf_counter()
+                    lat.append(now - (t0 + tr["arrival_s"]))
+                    done_at.append(now)
+            updates = sum(tr["n"] * tr["n"] * 3 * tr["steps"] for tr in trace)
+            span = max(done_at) - (t0 + trace[0]["arrival_s"])
+            legs[leg] = {"gcell_updates_per_s": round(updates / span / 1e9, 4), "p50_s": percentile(lat, 50),
+                         "p99_s": percentile(lat, 99), "mean_s": sum(lat) / len(lat), "span_s": round(span, 3)}
+        work = sum(tr["n"] * tr["n"] * 3 * tr["steps"] for tr in trace)
+        work_total += work
+        results.append({"rate_per_s": rate, "requests": len(trace), "duration_s": args.duration,
+                        "cell_stage_updates": work, "served": legs["served"],
+                        "one_at_a_time": legs["one_at_a_time"]})
         print(json.dumps({"serve_rate": rate, **results[-1]}), file=sys.stderr, flush=True)
+        del states
         torch.cuda.synchronize()
     out = {"metric": "served p50/p99 latency and Gcell-updates/s", "n_gpus": 1,
            "dtype": "f64" if prec == 0 else "f32-flux/f64-state", "data": "synthetic",
            "config": {"workload": "Poisson requests, sides log-uniform 64..2048, steps log-uniform 50..2000, "
-                                  "bump-family states, SSP-RK3 + MUSCL, continuous batching",
-                      "arena_gb": args.arena_gb},
+                                  "bump-family states, SSP-RK3 + MUSCL; continuous batching vs one request at a time",
+                      "arena_gb": args.arena_gb, "graph_iters": args.serve_graph_iters,
+                      "admission": "shortest-first" if args.serve_policy == P.ADMIT_SHORTEST else "fifo"},
            "rates": results}
+    if not args.no_cpu_baseline:
+        # the oracle's per-cell-stage cost on a sample of the same state family
+        # (the first 4 grids of the batched configuration, 200 steps, FP64),
+        # extrapolated to each trace's work: an extrapolation, not a run
+        import oracle
+        sample = batch_cases(4, 0)
+        t0 = time.perf_counter()
+        upd = 0
+        for c in sample:
+            _, st = oracle.run(c, nsteps=BATCH_STEPS)
+            upd += c.nx * c.ny * 3 * st["steps"]
+        dt = time.perf_counter() - t0
+        rate_or = upd / dt
+        out["cpu_baseline"] = {"value": rate_or / 1e9, "unit": "Gcell-updates/s per RK stage",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"4 grids of the bump family (sides {[c.nx for c in sample]}), "
+                                         f"{BATCH_STEPS} steps each, FP64 ({upd} cell-stage updates, {dt:.1f} s)",
+                               "extrapolated_trace_s": {str(r["rate_per_s"]): round(r["cell_stage_updates"] / rate_or, 1)
+                                                        for r in results}}
     print(json.dumps(out), flush=True)
 
 
@@ -601,17 +797,86 @@ def bench_3d(args):
     print(json.dumps(out), flush=True)
 
 
+def summarize_counters(args):
+    """Write a counter summary for profiles/ from rocprofv3 --pmc CSV output
+    (counter_collection.csv of the runs named by --pmc-csv): HBM bytes per
+    stage-kernel launch from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by
+    what the counter reads for the run's plain 256 MiB copy, or the VALU work
+    per cell-stage from an SQ pass.  Prints the summary; the caller saves it."""
+    import csv
+    import collections
+
+    def load(path):
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        names = {}
+        for r in csv.DictReader(open(path)):
+            key = r["Dispatch_Id"]
+            per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+            names[key] = r["Kernel_Name"]
+        return per, names
+
+    cmd = args.pmc_command or "(command not given)"
+    lines = []
+    if args.pmc_kind == "traffic":
+        lines.append(f"# HBM traffic per stage-kernel launch, {args.workload} (rocprofv3 --pmc, one pass per counter)")
+        out = {}
+        for path, ctr, what in zip(args.pmc_csv, ("FETCH_SIZE", "WRITE_SIZE"), ("read", "written")):
+            lines.append(f"# {ctr} pass: {cmd.replace('<COUNTER>', ctr)}")
+            per, names = load(path)
+            stage = [per[k][ctr] for k in per if "k_stage" in names[k]]
+            copies = [per[k][ctr] for k in per if "copy" in names[k].lower() and "k_stage" not in names[k]]
+            kname = next(names[k] for k in per if "k_stage" in names[k])
+            copy_kib = max(copies)
+            scale = (256 << 20) / 1024.0 / copy_kib
+            kib = sum(stage) / len(stage)
+            c = ctr.lower()
+            out[c] = (kib, len(stage), copy_kib, scale, kib * 1024 * scale)
+        lines.append("# counters are KiB per dispatch; each is scaled by what it reads for a plain copy of 268435456 B")
+        lines.append(f"kernel_source_hash {kernel_source_hash()}")
+        lines.append(f"kernel {kname.replace(' ', '')}")
+        for c, (kib, n, ck, sc, b) in out.items():
+            lines += [f"{c}_kib_per_dispatch {kib:.1f}", f"{c}_dispatches {n}", f"{c}_copy_kib {ck:.1f}",
+                      f"{c}_scale {sc:.4f}", f"{c}_bytes_per_launch {b:.0f}"]
+        lines.append(f"hbm_bytes_per_launch {out['fetch_size'][4] + out['write_size'][4]:.0f}")
+    else:
+        lines.append(f"# VALU work of the stage kernel per launch, {args.workload} (rocprofv3 --pmc, SQ block, whole-GPU sums)")
+        lines.append(f"# command: {cmd}")
+        lines.append("# SQ_INSTS_VALU counts wave64 instructions; x 64 / cells = lane-instructions per cell-stage")
+        lines.append("# valu_busy_fraction = SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES")
+        per, names = load(args.pmc_csv[0])
+        keys = [k for k in per if "k_stage" in names[k]]
+        tot = collections.defaultdict(float)
+        for k in keys:
+            for c, v in per[k].items():
+                tot[c] += v
+        n = len(keys)
+        lines.append(f"kernel_source_hash {kernel_source_hash()}")
+        lines.append(f"kernel {names[keys[0]].replace(' ', '')}")
+        lines.append(f"dispatches {n}")
+        lines.append(f"cells {args.pmc_cells}")
+        for c in sorted(tot):
+            lines.append(f"{c.lower()}_per_dispatch {tot[c] / n:.0f}")
+        lines.append(f"valu_lane_instr_per_cell_stage {tot['SQ_INSTS_VALU'] / n * 64 / args.pmc_cells:.1f}")
+        if tot.get("SQ_BUSY_CU_CYCLES"):
+            lines.append(f"valu_busy_fraction {tot['SQ_ACTIVE_INST_VALU'] / tot['SQ_BUSY_CU_CYCLES']:.3f}")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed bench steps: whole batches for batch256 (default 10), time steps for the "
+                         "single-grid workloads (default 1000)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed bench steps before them (default 2 batches, or 50 time steps)")
     ap.add_argument("--spin-up-s", type=float, default=2.0,
                     help="seconds of the workload's own untimed GPU work before the warm-up steps, "
                          "so that the timed region runs at sustained clocks (0: none)")
-    ap.add_argument("--workload", default="vortex256pair",
-                    help="vortex256pair (both Mach numbers, batched; the default line), vortexN (one "
-                         "N x N grid), batch256 (fourth configuration), serve (fifth configuration), "
+    ap.add_argument("--workload", default="batch256",
+                    help="batch256 (fourth configuration, the default line: 256 grids, 200 steps each, one "
+                         "bench step = the whole batch), vortex256pair (the low-Mach vortex at both Mach "
+                         "numbers, batched), vortexN (one N x N grid), serve (fifth configuration), "
                          "vortex3dNxNZ (one 3-D N x N x NZ grid), sod and oddeven (first and third "
                          "configurations, each run to its end time)")
     ap.add_argument("--precision", type=int, default=None, choices=[0, 1],
@@ -623,9 +888,17 @@ def main():
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="stage-kernel tile shape index for the vortex workloads (-1: autotune)")
     ap.add_argument("--batch-grids", type=int, default=256)
-    ap.add_argument("--batch-shape", type=int, default=-1)
-    ap.add_argument("--rates", default="2,5,10")
-    ap.add_argument("--duration", type=float, default=15.0)
+    ap.add_argument("--batch-persistent", action="store_true",
+                    help="batch256: persistent batched stage kernels instead of one workgroup per tile")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="batch256: only the headline batch (no FP64 batch, one-at-a-time or 2048^2 legs)")
+    ap.add_argument("--single-steps", type=int, default=100,
+                    help="batch256: SSP-RK3 steps of the single-grid FP64 2048^2 leg")
+    ap.add_argument("--rates", default="5,10,20")
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--serve-graph-iters", type=int, default=8)
+    ap.add_argument("--serve-policy", type=int, default=0, choices=[0, 1],
+                    help="admission order of queued requests: 0 FIFO, 1 shortest first (cells x steps)")
     ap.add_argument("--arena-gb", type=int, default=48)
     ap.add_argument("--profile-steps", type=int, default=100,
                     help="steps timed kernel by kernel with HIP events for the roofline object")
@@ -635,11 +908,24 @@ def main():
     ap.add_argument("--counter-run", action="store_true",
                     help="for rocprofv3 --pmc: only --profile-steps steps of directly launched stage "
                          "kernels, then a plain 256 MiB device copy as the counter reference; no timing")
+    ap.add_argument("--summarize-pmc", dest="pmc_kind", choices=["traffic", "valu"], default=None,
+                    help="no run: print a profiles/ counter summary from rocprofv3 CSV files (--pmc-csv)")
+    ap.add_argument("--pmc-csv", nargs="+", default=[],
+                    help="counter_collection.csv of the FETCH_SIZE then WRITE_SIZE passes (traffic), or of the SQ pass")
+    ap.add_argument("--pmc-cells", type=int, default=0, help="cells per stage launch (valu summary)")
+    ap.add_argument("--pmc-command", default="", help="the rocprofv3 command, <COUNTER> for the counter name")
     args = ap.parse_args()
+    if args.pmc_kind:
+        return summarize_counters(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the Roe-AM step here is a single-GPU build "
               "(multi-GPU sharding is described, not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    batch_like = args.workload == "batch256"
+    if args.steps is None:
+        args.steps = 10 if batch_like else 1000
+    if args.warmup is None:
+        args.warmup = 2 if batch_like else 50
     if args.counter_run:
         args.spin_up_s = 0.0  # counters do not depend on clocks
     # half the spin-up before anything else (the tile-shape autotuner then times
