@@ -127,3 +127,28 @@ def test_gpu_cylinder_pressure_fluctuation_index(C):
         assert 70 < ind[0, hi] / ind[0, lo] < 200, (hi, lo, ind)
     assert ind[1, 0.01] / ind[1, 0.001] < 40, ind
     assert ind[1, 0.001] > 4 * ind[0, 0.001], ind
+
+
+def test_gpu_carbuncle_fig10(C):
+    """Sec. 7.5 / Fig. 10 on the GPU: from the same seeded grid (interior nodes
+    moved radially by 1e-3 of the spacing), classical Roe grows the carbuncle
+    and Roe-AM keeps the bow shock at Billig's stand-off.  Each scheme matches
+    the oracle over its first 200 steps, then runs to t = 2 on the GPU, and the
+    oracle pin's checks are applied to the GPU's states."""
+    from test_oracle_solver_pins import carbuncle_case, check_carbuncle
+    c = carbuncle_case()
+    out = {}
+    for scheme in (oracle.SCHEME_ROE, oracle.SCHEME_ROEAM):
+        prm = dict(c.params, scheme=scheme)
+        q_or, st_or = oracle.run(c, params=prm, nsteps=200)
+        q_gpu, st = gpu_run(C, c, nsteps=200, params=prm)
+        err = state_error(q_gpu, q_or)
+        say(f"[carbuncle] scheme {scheme}: 200 steps err {err:.3e}")
+        assert st["steps"] == 200 and err <= TOL64
+        q, st = gpu_run(C, c, params=prm)
+        assert st["t"] == 2.0 and st["nonphys"] == 0
+        out[scheme] = q
+    roe, am = check_carbuncle(c, out[oracle.SCHEME_ROE], out[oracle.SCHEME_ROEAM])
+    mid = c.nx // 2
+    say(f"    shock radius next to the stagnation line: Roe {roe[mid - 1]:.3f} {roe[mid]:.3f}, "
+        f"Roe-AM {am[mid - 1]:.3f} {am[mid]:.3f} (Billig {1.0 + 0.386 * math.exp(4.67 / 400.0):.3f})")

@@ -427,6 +427,66 @@ def test_cylinder_bow_shock_standoff_billig():
         assert abs(shock - billig) <= 0.05, (shock, billig)
 
 
+def bow_shock_radii(c, q):
+    """Radius of the bow shock on every ray of the half O-grid: the mid-point
+    between the last compressed cell (p > 100; post-shock p ~ 400-500) and the
+    next one out (free stream, p = 1); the outer radius where the compressed
+    gas reaches the far field."""
+    _, _, _, p = prim(q)
+    X, Y = workloads._node_centres(c.xn, c.yn)
+    R = np.hypot(X, Y)
+    r_out = np.hypot(c.xn[-1], c.yn[-1])
+    out = np.full(c.nx, np.nan)
+    for i in range(c.nx):
+        js = np.where(p[:, i] > 100.0)[0]
+        if not len(js):
+            continue
+        j = js.max()
+        out[i] = 0.5 * (R[j, i] + R[j + 1, i]) if j + 1 < c.ny else r_out[i]
+    return out
+
+
+BILLIG = 1.0 + 0.386 * math.exp(4.67 / 400.0)  # Billig's stand-off for cylinders at Mach 20, r / R
+
+
+def carbuncle_case(**over):
+    """Sec. 7.5 / Fig. 10 set-up: the Mach-20 half O-grid, first order, forward
+    Euler, with the interior nodes moved radially by a seeded 1e-3 of the radial
+    spacing (the seed of the instability), run to t = 2."""
+    c = workloads.cylinder_carbuncle(jitter=1e-3, **over)
+    c.nsteps, c.t_end = 10 ** 7, 2.0
+    return c
+
+
+def check_carbuncle(c, q_roe, q_am):
+    """Fig. 10: classical Roe's bow shock ahead of the stagnation point bulges
+    upstream (the carbuncle): on the rays next to the stagnation line it
+    stands more than four radial cells (0.2 R) beyond Billig's stand-off, and
+    over the 40 central rays its radius varies by more than ten cells.
+    Roe-AM's stays within one cell (0.05 R) of Billig's on those rays and
+    varies by at most one cell over the central rays."""
+    mid = c.nx // 2
+    roe, am = bow_shock_radii(c, q_roe), bow_shock_radii(c, q_am)
+    for i in (mid - 1, mid):
+        assert roe[i] > BILLIG + 0.2, (roe[i], BILLIG)
+        assert abs(am[i] - BILLIG) <= 0.05, (am[i], BILLIG)
+    core = slice(mid - 20, mid + 20)
+    assert np.nanmax(roe[core]) - np.nanmin(roe[core]) > 0.5
+    assert np.nanmax(am[core]) - np.nanmin(am[core]) <= 0.05 + 1e-3  # one cell, plus the node jitter
+    return roe, am
+
+
+def test_carbuncle_fig10():
+    """Sec. 7.5 / Fig. 10 on the oracle: the carbuncle with classical Roe, none
+    with Roe-AM (both to t = 2 from the same seeded grid)."""
+    c = carbuncle_case()
+    q_roe, st = oracle.run(c, params=dict(c.params, scheme=oracle.SCHEME_ROE))
+    assert st["t"] == 2.0
+    q_am, st = oracle.run(c)
+    assert st["t"] == 2.0
+    check_carbuncle(c, q_roe, q_am)
+
+
 def test_cylinder_low_mach_residual_scaling_fig12():
     """Sec. 7.6 / Fig. 12 on the 100 x 72 O-grid: for the incompressible
     potential flow (pressure fluctuation ~ M^2) the momentum residual of Roe-AM
