@@ -95,7 +95,7 @@ def measured_valu(workload: str, precision: int):
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 
 
-def make_cases(workload: str, precision: int, order=None, eps1=None):
+def make_cases(workload: str, precision: int, order=None, eps1=None, time_scheme=None):
     """The grids of a workload (list) and whether they run as one batch
     (order / eps1: overrides of the workload's MUSCL order and eps1)."""
     import workloads
@@ -113,6 +113,8 @@ def make_cases(workload: str, precision: int, order=None, eps1=None):
             c.params["order"] = order
         if eps1 is not None:
             c.params["eps1"] = eps1
+        if time_scheme is not None:
+            c.params["time_scheme"] = time_scheme
     return cases, batched
 
 
@@ -568,7 +570,7 @@ def bench_serve(args):
     import torch
     import paper_1711_09272_amd as P
     import workloads
-    from paper_1711_09272_amd.serving import Server
+    from paper_1711_09272_amd.serving import Server, SplitServer
     prec = 0 if args.precision is None else args.precision
     ctx = P.Context(0)
     grid_cache, buf_cache = {}, {}
@@ -594,10 +596,32 @@ def bench_serve(args):
                 P.step(ctx, grid(n), prm, buf_cache[n], 50, sync=True)
         torch.cuda.synchronize()
         legs = {}
-        for leg in ("served", "one_at_a_time"):
+        for leg in ("served_split", "served", "one_at_a_time"):
             t0 = time.perf_counter()
             lat, done_at = [], []
-            if leg == "served":
+            if leg == "served_split":
+                srv = SplitServer(0, args.arena_gb << 30, split_cells=args.split_cells,
+                                  graph_iters=args.serve_graph_iters)
+                k = 0
+                reqs = []
+                while k < len(trace) or srv.outstanding:
+                    now = time.perf_counter() - t0
+                    while k < len(trace) and trace[k]["arrival_s"] <= now:
+                        r = srv.submit(grid(trace[k]["n"]), prms[k], states[k], trace[k]["steps"], tag=k)
+                        r.arrival = t0 + trace[k]["arrival_s"]
+                        reqs.append(r)
+                        k += 1
+                    time.sleep(0.0005)
+                srv.close()
+                lat = [r.finished - r.arrival for r in reqs]
+                done_at = [r.finished for r in reqs]
+                bad = [r for r in reqs if r.code != P.OK or r.stats["steps"] != r.solve.nsteps]
+                if bad:
+                    raise SystemExit(f"served request failed: {bad[0].stats} {bad[0].code}")
+                for r in reqs:
+                    r.solve.q_out = None
+                del srv
+            elif leg == "served":
                 server = Server(ctx, args.arena_gb << 30, graph_iters=args.serve_graph_iters, policy=args.serve_policy)
                 k = 0
                 reqs = []
@@ -639,15 +663,17 @@ def bench_serve(args):
         work = sum(tr["n"] * tr["n"] * 3 * tr["steps"] for tr in trace)
         work_total += work
         results.append({"rate_per_s": rate, "requests": len(trace), "duration_s": args.duration,
-                        "cell_stage_updates": work, "served": legs["served"],
-                        "one_at_a_time": legs["one_at_a_time"]})
+                        "cell_stage_updates": work, "served_two_lanes": legs["served_split"],
+                        "served_one_engine": legs["served"], "one_at_a_time": legs["one_at_a_time"]})
         print(json.dumps({"serve_rate": rate, **results[-1]}), file=sys.stderr, flush=True)
         del states
         torch.cuda.synchronize()
     out = {"metric": "served p50/p99 latency and Gcell-updates/s", "n_gpus": 1,
            "dtype": "f64" if prec == 0 else "f32-flux/f64-state", "data": "synthetic",
            "config": {"workload": "Poisson requests, sides log-uniform 64..2048, steps log-uniform 50..2000, "
-                                  "bump-family states, SSP-RK3 + MUSCL; continuous batching vs one request at a time",
+                                  "bump-family states, SSP-RK3 + MUSCL; continuous batching (two lanes: solves "
+                                  f"below {args.split_cells} cells batched together, larger ones one at a time beside "
+                                  "them; and one engine for all) vs one request at a time",
                       "arena_gb": args.arena_gb, "graph_iters": args.serve_graph_iters,
                       "admission": "shortest-first" if args.serve_policy == P.ADMIT_SHORTEST else "fifo"},
            "rates": results}
@@ -885,6 +911,9 @@ def main():
                     help="override the reconstruction order of the vortex workloads (roofline sweep)")
     ap.add_argument("--eps1", type=float, default=None, choices=[0.0, 1.0],
                     help="override eps1 of the vortex workloads (roofline sweep)")
+    ap.add_argument("--time-scheme", type=int, default=None, choices=[0, 1, 2],
+                    help="override the time scheme of the vortex workloads (counter runs only: the bench's "
+                         "rates assume three stages per step)")
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="stage-kernel tile shape index for the vortex workloads (-1: autotune)")
     ap.add_argument("--batch-grids", type=int, default=256)
@@ -897,6 +926,9 @@ def main():
     ap.add_argument("--rates", default="5,10,20")
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--serve-graph-iters", type=int, default=8)
+    ap.add_argument("--split-cells", type=int, default=512 * 512,
+                    help="serve: requests below this many cells go to the batched lane, larger ones to the "
+                         "one-at-a-time lane")
     ap.add_argument("--serve-policy", type=int, default=0, choices=[0, 1],
                     help="admission order of queued requests: 0 FIFO, 1 shortest first (cells x steps)")
     ap.add_argument("--arena-gb", type=int, default=48)
@@ -951,7 +983,9 @@ def main():
     import torch
     import paper_1711_09272_amd as P
 
-    cases, batched = make_cases(args.workload, args.precision, args.order, args.eps1)
+    if args.time_scheme is not None and not args.counter_run:
+        raise SystemExit("--time-scheme is for counter runs (--counter-run)")
+    cases, batched = make_cases(args.workload, args.precision, args.order, args.eps1, args.time_scheme)
     cells = sum(c.nx * c.ny for c in cases)
     ctx = P.Context(0)
     grids = [P.Grid.from_case(ctx, c) for c in cases]

@@ -386,7 +386,9 @@ roeam_status roeam_batch_reserve(roeam_ctx *ctx, size_t arena_bytes);
 roeam_status roeam_batch_attach(roeam_ctx *ctx, void *arena, size_t arena_bytes);
 /* Bytes of arena a solve on this grid occupies while resident. */
 size_t roeam_batch_footprint(const roeam_grid *grid);
-/* Queue n solves; tickets_out[n] receives their tickets.  Solves are
+/* Queue n solves; tickets_out[n] receives their tickets.  A descriptor's grid
+ * may belong to any context on this context's device (the engine reads it,
+ * and it must outlive the solve).  Solves are
  * admitted when arena memory is free and then advance together, one step of
  * every resident solve per scheduler iteration, with solves that arrive
  * later joining at the next iteration (continuous batching).
@@ -420,10 +422,12 @@ roeam_status roeam_batch_profile_run(roeam_ctx *ctx, long iterations, int *pendi
  * kernel on a group's real work list for every tile shape when the group
  * first forms and keeps the fastest; 0 takes 16x7/256 below about 200k cells
  * and 16x15/256 above (a shape forced on the group's first grid wins either
- * way).  Applies from the next scheduler iteration.  EINVAL: out of range or
- * no engine. */
+ * way).  max_resident: at most this many solves resident at once (0: as many
+ * as the arena holds; 1 runs the queue one solve at a time).  Applies from
+ * the next scheduler iteration.  EINVAL: out of range or no engine. */
 enum { ROEAM_ADMIT_FIFO = 0, ROEAM_ADMIT_SHORTEST = 1 };
-roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune);
+roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune,
+                                   int max_resident);
 /* Counters of the batch engine: graph captures so far (one when the first
  * group forms, then only when a group appears or empties or a work list's
  * capacity changes: admitting and retiring solves that fit does not
@@ -432,7 +436,7 @@ roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persiste
  * formed last (-1: none yet). */
 typedef struct {
     long captures, graph_launches, iterations, tunes;
-    int resident, queued, graph_iters, persistent, policy, shape;
+    int resident, queued, graph_iters, persistent, policy, shape, max_resident;
 } roeam_batch_stats;
 roeam_status roeam_batch_info(roeam_ctx *ctx, roeam_batch_stats *out);
 /* Non-blocking poll: *done = 1 once the solve's output is written; stats

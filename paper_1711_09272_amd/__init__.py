@@ -74,7 +74,7 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("captures", ctypes.c_long), ("graph_launches", ctypes.c_long), ("iterations", ctypes.c_long),
                 ("tunes", ctypes.c_long), ("resident", ctypes.c_int), ("queued", ctypes.c_int),
                 ("graph_iters", ctypes.c_int), ("persistent", ctypes.c_int), ("policy", ctypes.c_int),
-                ("shape", ctypes.c_int)]
+                ("shape", ctypes.c_int), ("max_resident", ctypes.c_int)]
 
 
 ADMIT_FIFO, ADMIT_SHORTEST = 0, 1
@@ -128,7 +128,7 @@ def lib():
         "roeam_batch_profile_run": (i, [vp, ctypes.c_long, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double * 4),
                                         ctypes.POINTER(ctypes.c_long)]),
         "roeam_batch_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(StepStats)]),
-        "roeam_batch_configure": (i, [vp, i, i, i, i]),
+        "roeam_batch_configure": (i, [vp, i, i, i, i, i]),
         "roeam_batch_info": (i, [vp, ctypes.POINTER(BatchStats)]),
         "roeam_grid3d_create": (i, [vp, i, i, i, d, d, d, ctypes.POINTER(ctypes.c_int * 6), vp, ctypes.POINTER(vp)]),
         "roeam_grid3d_destroy": (i, [vp]),
@@ -478,11 +478,12 @@ def batch_attach(ctx: Context, arena):
 
 
 def batch_configure(ctx: Context, graph_iters: int = 16, persistent: bool = False, policy: int = ADMIT_FIFO,
-                    autotune: bool = True):
+                    autotune: bool = True, max_resident: int = 0):
     """roeam_batch_configure: iterations per captured graph, persistent batched
-    kernels, admission policy (ADMIT_FIFO / ADMIT_SHORTEST), batch tile-shape tuning."""
+    kernels, admission policy (ADMIT_FIFO / ADMIT_SHORTEST), batch tile-shape
+    tuning, limit on resident solves (0: none)."""
     ctx.check(lib().roeam_batch_configure(ctx.h, int(graph_iters), int(bool(persistent)), int(policy),
-                                          int(bool(autotune))))
+                                          int(bool(autotune)), int(max_resident)))
 
 
 def batch_info(ctx: Context) -> Dict:

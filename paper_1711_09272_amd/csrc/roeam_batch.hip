@@ -148,6 +148,7 @@ struct BatchEngine {
     bool persistent = false;        // persistent batched kernels instead of one workgroup per tile
     int policy = ROEAM_ADMIT_FIFO;
     bool autotune = true;
+    int max_resident = 0;           // 0: as many solves as the arena holds
     int cus = 0;                    // compute units of the device
     // counters
     long captures = 0, graph_launches = 0, tunes = 0;
@@ -503,9 +504,12 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         });
     std::vector<std::vector<int>> forming(kGroups);
     std::vector<uint64_t> admitted;
+    int resident = 0;
+    for (int i = 0; i < b->hw; ++i) resident += b->by_idx[i] != 0;
     for (uint64_t tk : order) {
         Request &r = b->reqs[tk];
         if (b->free_idx.empty()) break;
+        if (b->max_resident > 0 && resident >= b->max_resident) break;
         size_t off = 0;
         if (!b->alloc.alloc(r.bytes, &off)) continue;
         const int idx = b->free_idx.back();
@@ -513,6 +517,7 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         r.idx = idx;
         r.off = off;
         r.state = RESIDENT;
+        ++resident;
         r.admit_iter = b->iter;
         b->by_idx[idx] = tk;
         b->hw = std::max(b->hw, idx + 1);
@@ -610,6 +615,7 @@ static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes
         keep.persistent = b->persistent;
         keep.policy = b->policy;
         keep.autotune = b->autotune;
+        keep.max_resident = b->max_resident;
         have_old = true;
         release_engine(b);
         ctx->batch = nullptr;
@@ -621,6 +627,7 @@ static roeam_status setup_engine(roeam_ctx *ctx, void *arena, size_t arena_bytes
         b->persistent = keep.persistent;
         b->policy = keep.policy;
         b->autotune = keep.autotune;
+        b->max_resident = keep.max_resident;
     }
     b->device = ctx->device;
     hipError_t e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -669,7 +676,8 @@ roeam_status roeam_batch_attach(roeam_ctx *ctx, void *arena, size_t arena_bytes)
     return setup_engine(ctx, arena, arena_bytes);
 }
 
-roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune)
+roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persistent, int policy, int autotune,
+                                   int max_resident)
 {
     if (!ctx) return ROEAM_EINVAL;
     BatchEngine *b = ctx->batch;
@@ -680,11 +688,14 @@ roeam_status roeam_batch_configure(roeam_ctx *ctx, int graph_iters, int persiste
     if (policy != ROEAM_ADMIT_FIFO && policy != ROEAM_ADMIT_SHORTEST)
         return roeam_fail(ctx, ROEAM_EINVAL, "policy must be ROEAM_ADMIT_FIFO or ROEAM_ADMIT_SHORTEST");
     if (autotune != 0 && autotune != 1) return roeam_fail(ctx, ROEAM_EINVAL, "autotune must be 0 or 1");
+    if (max_resident < 0 || max_resident > kMaxSolves)
+        return roeam_fail(ctx, ROEAM_EINVAL, "max_resident must be 0 (no limit) .. 4096");
     if (b->graph_iters != graph_iters || b->persistent != (persistent != 0)) b->graph_valid = false;
     b->graph_iters = graph_iters;
     b->persistent = persistent != 0;
     b->policy = policy;
     b->autotune = autotune != 0;
+    b->max_resident = max_resident;
     return ROEAM_OK;
 }
 
@@ -704,6 +715,7 @@ roeam_status roeam_batch_info(roeam_ctx *ctx, roeam_batch_stats *out)
     out->graph_iters = b->graph_iters;
     out->persistent = b->persistent ? 1 : 0;
     out->policy = b->policy;
+    out->max_resident = b->max_resident;
     out->shape = b->last_shape;
     return ROEAM_OK;
 }
@@ -715,7 +727,10 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
     if (!b) return roeam_fail(ctx, ROEAM_EINVAL, "call roeam_batch_reserve first");
     for (int i = 0; i < n; ++i) {
         const roeam_solve_desc &d = descs[i];
-        if (!d.grid || d.grid->ctx != ctx) return roeam_fail(ctx, ROEAM_EINVAL, "descriptor grid invalid");
+        // a grid only describes sizes, metrics and sides (its device arrays are
+        // read, never written): one created on any context of this device will do
+        if (!d.grid || !d.grid->ctx || d.grid->ctx->device != ctx->device)
+            return roeam_fail(ctx, ROEAM_EINVAL, "descriptor grid invalid (NULL, or of another device)");
         roeam_status st = roeam_check_params(ctx, &d.params, true);
         if (st) return st;
         if (!d.q0 || !d.q_out) return roeam_fail(ctx, ROEAM_EINVAL, "q0 and q_out are required");

@@ -84,3 +84,93 @@ class Server:
             P.batch_run(self.ctx, -1)
             out.extend(self.poll())
         return out
+
+
+class _Lane:
+    """One batch engine (its own context, stream and arena) pumped by its own
+    host thread; requests reach it through an inbox so that only that thread
+    calls into its context."""
+
+    def __init__(self, device: int, arena_bytes: int, graph_iters: int, max_resident: int):
+        import collections
+        import threading
+        self.server = Server(P.Context(device), arena_bytes, graph_iters=graph_iters)
+        if max_resident:
+            P.batch_configure(self.server.ctx, graph_iters=graph_iters, max_resident=max_resident)
+        self.graph_iters = graph_iters
+        self.inbox = collections.deque()
+        self.done: List[Request] = []
+        self.error: Optional[BaseException] = None
+        self._stop = False
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+
+    def _run(self):
+        try:
+            while not self._stop or self.inbox or self.server.outstanding:
+                while self.inbox:
+                    req, grid, prm, q0, nsteps, t_end, q_out = self.inbox.popleft()
+                    if q_out is None:
+                        q_out = grid.empty_state()
+                    req.solve = P.Solve(grid, prm, q0, nsteps, t_end, q_out)
+                    P.batch_submit(self.server.ctx, [req.solve])
+                    self.server.outstanding.append(req)
+                if self.server.outstanding:
+                    self.done.extend(self.server.pump(self.graph_iters))
+                else:
+                    time.sleep(0.0002)
+        except BaseException as e:  # surfaced by the caller's next call
+            self.error = e
+
+    def stop(self):
+        self._stop = True
+        self._thread.join()
+
+
+class SplitServer:
+    """Requests served on two batch engines of one GPU, each on its own stream
+    and pumped by its own host thread: solves of fewer than `split_cells`
+    cells run batched together in the small lane; larger ones queue for the
+    large lane, which holds at most `large_resident` of them at a time (one:
+    the large solves run one after another, nearly alone).  The lanes' graphs
+    run side by side on the device, so a small solve is no longer paced by the
+    step time of the largest grid resident with it (in one engine every
+    resident solve takes one step per iteration), and a large solve shares the
+    device only with small ones.  Results are bitwise those of the solves run
+    alone (same kernels)."""
+
+    def __init__(self, device: int, arena_bytes: int, split_cells: int = 512 * 512, large_resident: int = 1,
+                 graph_iters: int = 8):
+        self.split_cells = split_cells
+        self.small = _Lane(device, arena_bytes // 2, graph_iters, 0)
+        self.large = _Lane(device, arena_bytes // 2, graph_iters, large_resident)
+        self.requests: List[Request] = []
+
+    def submit(self, grid: "P.Grid", prm: Dict, q0, nsteps: int, t_end: float = 0.0, q_out=None,
+               tag=None) -> Request:
+        for lane in (self.small, self.large):
+            if lane.error:
+                raise lane.error
+        lane = self.small if grid.nx * grid.ny < self.split_cells else self.large
+        r = Request(None, grid.nx * grid.ny, time.perf_counter(), tag)
+        lane.inbox.append((r, grid, prm, q0, nsteps, t_end, q_out))
+        self.requests.append(r)
+        return r
+
+    @property
+    def outstanding(self) -> int:
+        for lane in (self.small, self.large):
+            if lane.error:
+                raise lane.error
+        return len(self.requests) - len(self.small.done) - len(self.large.done)
+
+    def drain(self, poll_s: float = 0.0005):
+        while self.outstanding:
+            time.sleep(poll_s)
+
+    def close(self):
+        self.small.stop()
+        self.large.stop()
+        for lane in (self.small, self.large):
+            if lane.error:
+                raise lane.error

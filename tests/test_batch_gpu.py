@@ -335,3 +335,36 @@ def test_forward_euler_odd_and_even_step_counts(C, nsteps):
     assert P.batch_run(C, -1) == 0
     (q, st, rc), = collect(C, solves)
     assert rc == P.OK and st["steps"] == nsteps and np.array_equal(q, qa)
+
+
+def test_split_server_lanes(C):
+    """Two engines on two streams: small requests batched together, large
+    ones one at a time beside them, each lane pumped by its own host thread;
+    every result bitwise the solve run alone."""
+    import torch
+    import paper_1711_09272_amd as P
+    from paper_1711_09272_amd.serving import SplitServer
+    trace = workloads.serving_trace(100.0, 0.1, seed=workloads.SEED_BASE + 60, n_lo=24, n_hi=160, s_lo=3, s_hi=40)
+    assert len(trace) >= 6
+    srv = SplitServer(0, 512 << 20, split_cells=64 * 64, graph_iters=4)
+    grids, reqs, refs = {}, [], []
+    try:
+        for k, tr in enumerate(trace):
+            n = tr["n"]
+            if n not in grids:
+                grids[n] = P.Grid(C, n, n, dx=1.0 / n, dy=1.0 / n, bc=(PERIODIC,) * 4)
+            g = grids[n]
+            prm = workloads.bump_params(tr["spec"]["mach"])
+            q0 = workloads.bump_state_device(n, tr["spec"], g.pitch)
+            refs.append((g, prm, q0.clone(), tr["steps"]))
+            reqs.append(srv.submit(g, prm, q0, tr["steps"], tag=k))
+        srv.drain()
+    finally:
+        srv.close()
+    lanes = {n * n < 64 * 64 for n in grids}
+    assert lanes == {True, False}, "both lanes used"
+    for r, (g, prm, q, n) in zip(reqs, refs):
+        assert r.code == P.OK and r.stats["steps"] == n, r.tag
+        P.step(C, g, prm, q, n)
+        torch.cuda.synchronize()
+        assert torch.equal(r.solve.q_out[:, :, : g.nx], q[:, :, : g.nx]), r.tag
