@@ -413,12 +413,13 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 }
 
 // Minimum waves per SIMD asked of the register allocator: the uniform-grid
-// FP32-coefficient kernels of the one-pass 256-thread shapes fit five waves
-// without spills (measured 4% faster at 2048^2); the FP64 and node-grid ones
-// would spill, so they keep the default (as do the kernels with scalars).
+// kernels of the one-pass 256-thread shapes fit five waves in 96 VGPRs with a
+// few spilled dwords (FP32 coefficients one, FP64 five), measured faster than
+// four waves without spills (FP64: 1-3% at 512^2 and 2048^2); the node-grid
+// ones and those with scalars keep the default.
 constexpr int stage_min_waves(int prec, int metric, int nt, bool split, int nsc)
 {
-    return (prec == 1 && metric == 0 && nt == 256 && !split && nsc == 0) ? 5 : 1;
+    return (prec >= 0 && metric == 0 && nt == 256 && !split && nsc == 0) ? 5 : 1;
 }
 
 template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
