@@ -842,6 +842,7 @@ def summarize_counters(args):
         return per, names
 
     cmd = args.pmc_command or "(command not given)"
+    source_hash = kernel_source_hash(KERNEL_SOURCES_3D if is_3d(args.workload) else KERNEL_SOURCES)
     lines = []
     if args.pmc_kind == "traffic":
         lines.append(f"# HBM traffic per stage-kernel launch, {args.workload} (rocprofv3 --pmc, one pass per counter)")
@@ -858,7 +859,7 @@ def summarize_counters(args):
             c = ctr.lower()
             out[c] = (kib, len(stage), copy_kib, scale, kib * 1024 * scale)
         lines.append("# counters are KiB per dispatch; each is scaled by what it reads for a plain copy of 268435456 B")
-        lines.append(f"kernel_source_hash {kernel_source_hash()}")
+        lines.append(f"kernel_source_hash {source_hash}")
         lines.append(f"kernel {kname.replace(' ', '')}")
         for c, (kib, n, ck, sc, b) in out.items():
             lines += [f"{c}_kib_per_dispatch {kib:.1f}", f"{c}_dispatches {n}", f"{c}_copy_kib {ck:.1f}",
@@ -876,7 +877,7 @@ def summarize_counters(args):
             for c, v in per[k].items():
                 tot[c] += v
         n = len(keys)
-        lines.append(f"kernel_source_hash {kernel_source_hash()}")
+        lines.append(f"kernel_source_hash {source_hash}")
         lines.append(f"kernel {names[keys[0]].replace(' ', '')}")
         lines.append(f"dispatches {n}")
         lines.append(f"cells {args.pmc_cells}")
