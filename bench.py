@@ -736,7 +736,7 @@ def bench_3d(args):
     cells = case.cells
     ctx = P.Context(0)
     grid = P.Grid3.from_case(ctx, case)
-    shape = args.tile_shape if args.tile_shape >= 0 else 8
+    shape = args.tile_shape if args.tile_shape >= 0 else 10
     grid.set_tile_shape(shape)
     q = grid.to_device(case.q0)
     prm = case.params

@@ -326,12 +326,16 @@ roeam_status roeam_grid3d_set_scalars(roeam_grid3d *grid, int nscalars, const do
 /* Brick shape of the 3-D stage kernel (cells per workgroup / threads):
  * 0 = 8x8x4/256, 1 = 8x4x4/128, 2 = 16x8x4/512, 3 = 16x4x4/256,
  * 4 = 8x8x4/320, 5 = 8x4x4/192, 6 = 16x8x4/640, 7 = 8x8x8/576
- * (4-7: one thread per face of each direction), 8 = 16x8x4/512 (default) and
+ * (4-7: one thread per face of each direction), 8 = 16x8x4/512 and
  * 9 = 8x8x8/512 persistent (as many workgroups as the GPU holds, each taking a
  * band of bricks in turn and loading the next brick's halo while it computes
- * the current one).  Every shape computes bitwise the same result.  With two
- * transported scalars the 16x8x4 bricks (2, 6, 8) exceed the LDS of a
- * workgroup; such a grid runs shape 9 instead.  EINVAL: shape outside 0..9. */
+ * the current one).  10-12: z-marching column tiles of 16x15 cells with 256
+ * threads, each workgroup walking a run of 4 (10, the default), 8 (11) or
+ * 16 (12) planes upward with one plane and its x-y halo in LDS while the
+ * next plane's footprint loads into registers (three workgroups per CU).
+ * Every shape computes bitwise the same result.  With two transported
+ * scalars the 16x8x4 bricks (2, 6, 8) exceed the LDS of a workgroup; such a
+ * grid runs shape 9 instead.  EINVAL: shape outside 0..12. */
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
 /* Residual R = dQ/dt = -(1/V) sum over the cell's six faces of F A (Eq. 85
  * per unit area times the face area).  q: device, 3-D state layout, read

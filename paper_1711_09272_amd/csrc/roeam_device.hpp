@@ -597,10 +597,14 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
     const double M2 = (W[1] * W[1] + W[2] * W[2]) * rcp_nr(c2);
     const double theta = rmin(rmax(S.mr2, M2), 1.0);
     const double ce = c2 * rsq_nr(c2 * theta);
-    double six, siy, sjx, sjy, li, lj;
     if (METRIC == 0) {
-        six = S.dy; siy = 0.0; sjx = 0.0; sjy = S.dx; li = S.dy; lj = S.dx;
-    } else {
+        // faces along the axes: |u| dy + |v| dx (the zero products of the
+        // general form left out; equal to it for finite states)
+        const double sum = fabs(W[1]) * S.dy + ce * S.dy + fabs(W[2]) * S.dx + ce * S.dx;
+        return sum * S.inv_area;
+    }
+    double six, siy, sjx, sjy, li, lj;
+    {
         double ax, ay, bx, by;
         xface_vec<METRIC>(S, i, j, ax, ay);
         xface_vec<METRIC>(S, i + 1, j, bx, by);
@@ -613,7 +617,7 @@ __device__ __forceinline__ double cell_rate(const DevSolve &S, const double W[4]
         lj = lj2 * rsq_nr(lj2);
     }
     const double sum = fabs(W[1] * six + W[2] * siy) + ce * li + fabs(W[1] * sjx + W[2] * sjy) + ce * lj;
-    return METRIC == 0 ? sum * S.inv_area : sum * rcp_nr(cell_area<METRIC>(S, i, j));
+    return sum * rcp_nr(cell_area<METRIC>(S, i, j));
 }
 
 __device__ __forceinline__ bool physical(const double W[4])

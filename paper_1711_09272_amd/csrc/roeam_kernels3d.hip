@@ -48,7 +48,7 @@ bool brick_shape_fits(int shape, int order, int nsc)
 {
     if (shape < 0 || shape >= kNumShapes3) return false;
     const BrickShape &sh = kShapes3[shape];
-    return stage3_lds_bytes(order, nsc, sh.tx, sh.ty, sh.tz, sh.nt) <= kLdsBytes3;
+    return shape3_lds_bytes(order, nsc, sh.tx, sh.ty, sh.tz, sh.nt, sh.persistent) <= kLdsBytes3;
 }
 
 hipError_t launch_stage3(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last, double *r_out,

@@ -26,7 +26,7 @@ struct roeam_grid3d {
     DevSolve3 *h_solve = nullptr;     // pinned staging copy of the last descriptor sent
     bool solve_valid = false;
     GraphCache gc;
-    int shape = 8;                    // persistent 16x8x4/512 bricks (fastest measured on 128^3)
+    int shape = 10;                   // z-marching 16x15 column tiles, runs of 4 planes (fastest measured on 128^3)
     double *d_norm_part = nullptr;    // scratch of roeam_residual_norms3d
     int final_parity = 0;
     int nsc = 0;                      // transported scalars (rows 5 .. 4 + nsc of q)

@@ -161,6 +161,17 @@ __device__ __forceinline__ bool step_active(const StepWords &w, int stage, doubl
 // its dt; on the first stage, workgroup 0 (first_block) publishes the next
 // step state and clears the rate words of the step after this one (set
 // n + 2 for input step count n).  w: load_step_words(z, p, stage).
+// A value that is the same in every lane of the wave, moved to scalar
+// registers (the compiler cannot tell that a value read from memory by every
+// lane at the same address is uniform).
+__device__ __forceinline__ double wave_uniform(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ bool begin_stage(Slot &z, const StepWords &w, int p, int stage, int last, int first_block,
                                             double &dt)
 {
@@ -187,6 +198,7 @@ __device__ __forceinline__ bool begin_stage(Slot &z, const StepWords &w, int p, 
         (void)last;
         if (tid < kRateSlots) z.rate_bits[rate_set(w.steps + 2)][tid] = 0ull;
     }
+    dt = wave_uniform(dt);  // every lane read the same step words
     return active;
 }
 

@@ -88,46 +88,61 @@ __device__ __forceinline__ double face_detector(const double *__restrict__ sP, i
     }
 }
 
+// MUSCL-minmod: the limited slope of a cell from its two neighbours along an
+// axis, and the values half a cell above and below its centre.
+__device__ __forceinline__ double slope3(double lo, double mid, double hi) { return minmod(mid - lo, hi - mid); }
+__device__ __forceinline__ double extrap_up(double w, double s) { return fma(0.5, s, w); }
+__device__ __forceinline__ double extrap_dn(double w, double s) { return fma(-0.5, s, w); }
+
+// Row of the primitive state that goes into face-frame row k of a face of
+// axis AXIS: rho, the normal velocity, the two others in cyclic order, p, k_m.
+template <int AXIS>
+__device__ __forceinline__ constexpr int frame_row(int k)
+{
+    return k == 1 ? 1 + AXIS : (k == 2 ? 1 + (AXIS + 1) % 3 : (k == 3 ? 1 + (AXIS + 2) % 3 : k));
+}
+
+// Flux times area of a face of axis AXIS from its face-frame states, rows
+// scattered back to global order (rho, rho u, rho v, rho w, rho E, rho k_m).
+template <int PREC, int AXIS, int NSC>
+__device__ __forceinline__ void frame_flux3(const DevSolve3 &S, const double *WL, const double *WR, double s1, double *F)
+{
+    constexpr int NR = 5 + NSC;
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    double Ff[NR];
+    roeam_flux3<R, NSC>(S, WL, WR, s1, Ff);
+    const double area = AXIS == 0 ? S.ax : (AXIS == 1 ? S.ay : S.az);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) F[frame_row<AXIS>(k)] = Ff[k] * area;
+}
+
 // Flux times area of the face of axis AXIS whose upper cell is brick cell
-// (i, j, l), rows in global order (rho, rho u, rho v, rho w, rho E, rho k_m).
+// (i, j, l), rows in global order.
 template <int ORDER, int PREC, int AXIS, int NSC, class B>
 __device__ __forceinline__ void brick_face(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
                                            int i, int j, int l, double *F)
 {
     constexpr int NR = 5 + NSC;
-    using R = typename std::conditional<PREC == 0, double, float>::type;
     constexpr int PL = B::LX * B::LY * B::LZ;                     // one row of sW
     constexpr int ST = AXIS == 0 ? 1 : (AXIS == 1 ? B::LX : B::LX * B::LY);
-    // face frame: rho, normal velocity, the two others in cyclic order, p
-    constexpr int RN = 1 + AXIS, RT1 = 1 + (AXIS + 1) % 3, RT2 = 1 + (AXIS + 2) % 3;
     const int c = B::cell(i, j, l);
     double WL[NR], WR[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-        const int row = k == 1 ? RN : (k == 2 ? RT1 : (k == 3 ? RT2 : k));
-        const double *r = sW + row * PL;
+        const double *r = sW + frame_row<AXIS>(k) * PL;
         const double m1 = r[c - ST], p0 = r[c];
         if (ORDER == 1) {
             WL[k] = m1;
             WR[k] = p0;
         } else {
             const double m2 = r[c - 2 * ST], p1 = r[c + ST];
-            const double d1 = p0 - m1;
-            WL[k] = m1 + 0.5 * minmod(m1 - m2, d1);
-            WR[k] = p0 - 0.5 * minmod(d1, p1 - p0);
+            WL[k] = extrap_up(m1, slope3(m2, m1, p0));
+            WR[k] = extrap_dn(p0, slope3(m1, p0, p1));
         }
     }
     double s1 = 1.0;
     if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) s1 = pow8(fswitch(face_detector<AXIS, B>(sP, i, j, l)));
-    double Ff[NR];
-    roeam_flux3<R, NSC>(S, WL, WR, s1, Ff);
-    const double area = AXIS == 0 ? S.ax : (AXIS == 1 ? S.ay : S.az);
-    F[0] = Ff[0] * area;
-    F[RN] = Ff[1] * area;
-    F[RT1] = Ff[2] * area;
-    F[RT2] = Ff[3] * area;
-#pragma unroll
-    for (int k = 4; k < NR; ++k) F[k] = Ff[k] * area;
+    frame_flux3<PREC, AXIS, NSC>(S, WL, WR, s1, F);
 }
 
 // All faces of one axis into sF.
@@ -383,6 +398,38 @@ __device__ __forceinline__ void halo_commit(const DevSolve3 &S, const double (*H
     }
 }
 
+// Stage update of one cell at idx from its residual Rv, stage input Qs and
+// Q^n (Q0): the new state, its positivity check and (last stage) its rate.
+template <int NR>
+__device__ __forceinline__ void stage_update3(const DevSolve3 &S, int stage, int last, double dt, const double *Rv,
+                                              const double *Qs, const double *Q0, long long idx, double &lmax)
+{
+    // each combination written as the fused multiply-adds it rounds with, so
+    // that every kernel form that inlines it rounds the same way
+    double Qn[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        switch (stage) {
+        case 1:
+        case 8: Qn[k] = fma(dt, Rv[k], Qs[k]); break;
+        case 2: Qn[k] = fma(0.75, Q0[k], 0.25 * fma(dt, Rv[k], Qs[k])); break;
+        case 3: Qn[k] = fma(1.0 / 3.0, Q0[k], (2.0 / 3.0) * fma(dt, Rv[k], Qs[k])); break;
+        case 4: Qn[k] = fma(0.25 * dt, Rv[k], Qs[k]); break;
+        case 5: Qn[k] = fma((1.0 / 3.0) * dt, Rv[k], Q0[k]); break;
+        case 6: Qn[k] = fma(0.5 * dt, Rv[k], Q0[k]); break;
+        default: Qn[k] = fma(dt, Rv[k], Q0[k]); break;
+        }
+    }
+    const int bout = stage_out_buf(stage);
+    double *__restrict__ qo = bout == 0 ? S.q : (bout == 2 ? S.qb : S.qa);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) gptr(qo)[k * S.plane + idx] = Qn[k];
+    double W[5];
+    const double ir = to_prim3(S.gm1, Qn, W);
+    if (!physical3(W)) atomicOr(&S.slot->nonphys, 1);
+    else if (last) lmax = rmax(lmax, cell_rate3(S, W, ir));
+}
+
 // Detector ratios, faces, residual and stage update of one brick whose
 // primitives are in LDS (the caller has synchronised after staging them);
 // the rate of the new state goes into lmax.
@@ -454,7 +501,6 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
     }
 
     // 4. R = -(sum of face fluxes times areas) / V and the stage update
-    Slot &z = *S.slot;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = tid + m * NT;
@@ -476,28 +522,7 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
             }
             continue;
         }
-        double Qn[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            switch (stage) {
-            case 1:
-            case 8: Qn[k] = Qs[m][k] + dt * Rv[k]; break;
-            case 2: Qn[k] = 0.75 * Q0[m][k] + 0.25 * (Qs[m][k] + dt * Rv[k]); break;
-            case 3: Qn[k] = (1.0 / 3.0) * Q0[m][k] + (2.0 / 3.0) * (Qs[m][k] + dt * Rv[k]); break;
-            case 4: Qn[k] = Qs[m][k] + (0.25 * dt) * Rv[k]; break;
-            case 5: Qn[k] = Q0[m][k] + ((1.0 / 3.0) * dt) * Rv[k]; break;
-            case 6: Qn[k] = Q0[m][k] + (0.5 * dt) * Rv[k]; break;
-            default: Qn[k] = Q0[m][k] + dt * Rv[k]; break;
-            }
-        }
-        const int bout = stage_out_buf(stage);
-        double *__restrict__ qo = bout == 0 ? S.q : (bout == 2 ? S.qb : S.qa);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) gptr(qo)[k * S.plane + idx] = Qn[k];
-        double W[5];
-        const double ir = to_prim3(S.gm1, Qn, W);
-        if (!physical3(W)) atomicOr(&z.nonphys, 1);
-        else if (last) lmax = rmax(lmax, cell_rate3(S, W, ir));
+        stage_update3<NR>(S, stage, last, dt, Rv, Qs[m], Q0[m], idx, lmax);
     }
 }
 
@@ -580,11 +605,444 @@ __global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp
     if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : rate_set(sw.steps + 1), lmax, L.sRed);
 }
 
-// Brick shapes: id, TX, TY, TZ, threads, persistent.  Shapes 4-9 give every
+// ---------------------------------------------------------------------------
+// z-marching form (2.5-D blocking)
+// ---------------------------------------------------------------------------
+// A workgroup owns a column tile of TX x TY cells and a run of planes of it,
+// and walks up the run one plane at a time.  LDS holds one plane of
+// primitives with its x-y halo (the plane whose x- and y-faces are being
+// evaluated), p and rho of the plane above it, the detector ratios of the
+// faces in and between the two planes, and one flux buffer; the next
+// plane's footprint is loaded into registers while the current one is
+// worked on.  Thread c < TX TY owns column c: its z-faces come from its own
+// registers (the reconstructed upper state of the plane below and the flux
+// through the plane's lower face carry over from one plane to the next).
+// Every face of the run is evaluated once, the run's lowest z-face once more
+// by the run below; each plane's footprint is loaded once per run.  Same
+// arithmetic as the brick kernels, bitwise the same result.
+template <int TX, int TY, int HL>
+struct ZPlane {
+    static constexpr int LX = TX + 2 * HL, LY = TY + 2 * HL, PL = LX * LY;  // the staged plane
+    static constexpr int NI = TX * TY;                                       // interior cells
+    static constexpr int RX = TX + 2, RP = RX * (TY + 2);                    // one-layer footprint
+    static constexpr int NPX = (TX + 1) * (TY + 2), NPY = (TX + 2) * (TY + 1);
+    static constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    static constexpr int NFB = NFX > NFY ? NFX : NFY;
+    // staged-plane offset of cell (i, j), -HL <= i < TX + HL, -HL <= j < TY + HL
+    static __device__ __forceinline__ int cell(int i, int j) { return (j + HL) * LX + i + HL; }
+    // one-layer footprint offset of cell (i, j), -1 <= i <= TX, -1 <= j <= TY
+    static __device__ __forceinline__ int rc(int i, int j) { return (j + 1) * RX + i + 1; }
+    // ratio of the x-face at fi (0..TX) in row j (-1..TY); of the y-face at fj (0..TY) in column i (-1..TX)
+    static __device__ __forceinline__ int px(int fi, int j) { return (j + 1) * (TX + 1) + fi; }
+    static __device__ __forceinline__ int py(int i, int fj) { return NPX + fj * (TX + 2) + i + 1; }
+    // footprint slot e -> staged-plane position (lx, ly): the interior first
+    // (x fastest, so that slot c is column c's own cell), then the rows below,
+    // the rows above and the side columns of the halo
+    static __device__ __forceinline__ void slot_xy(int e, int &lx, int &ly)
+    {
+        if (e < NI) {
+            lx = HL + e % TX;
+            ly = HL + e / TX;
+            return;
+        }
+        int r = e - NI;
+        if (r < HL * LX) {
+            lx = r % LX;
+            ly = r / LX;
+            return;
+        }
+        r -= HL * LX;
+        if (r < HL * LX) {
+            lx = r % LX;
+            ly = TY + HL + r / LX;
+            return;
+        }
+        r -= HL * LX;
+        const int c = r % (2 * HL);
+        lx = c < HL ? c : TX + c;
+        ly = HL + r / (2 * HL);
+    }
+};
+
+template <int ORDER, int NSC, int TX, int TY, int NT>
+struct ZStageLds {
+    using P = ZPlane<TX, TY, ORDER>;
+    static constexpr int NR = 5 + NSC;
+    double sW[NR * P::PL];           // primitives of the plane whose x- and y-faces are evaluated
+    double sPR[2 * P::RP];           // p, then rho, of the plane above it
+    double sPxy[2][P::NPX + P::NPY]; // x- and y-face ratios of a plane, by plane parity
+    double sPz[2][P::RP];            // z-face ratios below a plane, by plane parity
+    double sF[NR][P::NFB];
+    // each thread's footprint slots past the first (slot e >= NT at e - NT):
+    // the current plane's primitives, kept by the thread for the next plane's
+    // staging (private to the thread, so no barrier guards them)
+    double sKeep[NR][P::PL > NT ? P::PL - NT : 1];
+    double sRed[NT / 64];
+};
+constexpr long long zstage3_lds_bytes(int order, int nsc, int tx, int ty, int nt)
+{
+    const long long pl = (long long)(tx + 2 * order) * (ty + 2 * order), rp = (long long)(tx + 2) * (ty + 2);
+    const long long npxy = (long long)(tx + 1) * (ty + 2) + (long long)(tx + 2) * (ty + 1);
+    const long long nfb = (tx + 1) * ty > tx * (ty + 1) ? (long long)(tx + 1) * ty : (long long)tx * (ty + 1);
+    const long long keep = pl > nt ? pl - nt : 1;
+    return 8 * ((5 + nsc) * pl + 2 * rp + 2 * npxy + 2 * rp + (5 + nsc) * nfb + (5 + nsc) * keep + nt / 64);
+}
+
+// Issue the loads of footprint slots SLO..SHI-1 of plane l (own cells only
+// when own_only) into Fq, with the source code of each slot in Fc as
+// halo_prefetch gives it (-1: no slot).
+template <int ORDER, int NSC, int TX, int TY, int NT, int SLO, int SHI>
+__device__ __forceinline__ void zplane_load(const DevSolve3 &S, const double *__restrict__ qin, int tid, int i0, int j0,
+                                            int l, bool own_only, double (*Fq)[5 + NSC], int *Fc)
+{
+    using P = ZPlane<TX, TY, ORDER>;
+    constexpr int HL = ORDER, NR = 5 + NSC;
+    const bool inner = i0 - HL >= 0 && i0 + TX + HL <= S.nx && j0 - HL >= 0 && j0 + TY + HL <= S.ny && l >= 0 &&
+                       l < S.nz;
+#pragma unroll
+    for (int s = SLO; s < SHI; ++s) {
+        const int e = tid + s * NT;
+        Fc[s] = -1;
+        if (e >= P::PL || (own_only && e >= P::NI)) continue;
+        int lx, ly;
+        P::slot_xy(e, lx, ly);
+        long long idx = 0;
+        int code = 0;
+        if (inner) {
+            idx = (long long)l * S.slab + (long long)(j0 - HL + ly) * S.pitch + (i0 - HL + lx);
+        } else {
+            // cells past the ghost layers of a ragged tile feed no face on the grid
+            const int gi = min(i0 - HL + lx, S.nx + 1), gj = min(j0 - HL + ly, S.ny + 1);
+            code = map_cell3(S, gi, gj, l, idx);
+        }
+        Fc[s] = code;
+        if ((code & 7) == 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Fq[s][k] = gptr(qin)[k * S.plane + idx];
+        }
+    }
+}
+
+// Primitives of a loaded footprint slot (bitwise what halo_commit stages).
+template <int NSC>
+__device__ __forceinline__ void zslot_prim(const DevSolve3 &S, const double *Q, int code, double *W)
+{
+    if ((code & 7) == 0) {
+        const double ir = to_prim3(S.gm1, Q, W);
+#pragma unroll
+        for (int m = 0; m < NSC; ++m) W[5 + m] = Q[5 + m] * ir;
+    } else {
+        dirichlet3<NSC>(S, (code & 7) - 1, W);
+    }
+    if (code & 8) W[1] = -W[1];
+    if (code & 16) W[2] = -W[2];
+    if (code & 32) W[3] = -W[3];
+}
+
+// x- (AXIS 0) or y-face (AXIS 1) of the staged plane whose upper cell is (i, j):
+// flux times area in global row order.  cur: the plane's own x-y ratios; lo,
+// hi: the z-face ratios below and above it (the nine faces of Eq. 96, as
+// face_detector takes them).
+template <int ORDER, int PREC, int AXIS, int NSC, class P>
+__device__ __forceinline__ void zplane_face(const DevSolve3 &S, const double *__restrict__ sW,
+                                            const double *__restrict__ cur, const double *__restrict__ lo,
+                                            const double *__restrict__ hi, int i, int j, double *F)
+{
+    constexpr int NR = 5 + NSC;
+    constexpr int ST = AXIS == 0 ? 1 : P::LX;
+    const int c = P::cell(i, j);
+    double WL[NR], WR[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const double *r = sW + frame_row<AXIS>(k) * P::PL;
+        const double m1 = r[c - ST], p0 = r[c];
+        if (ORDER == 1) {
+            WL[k] = m1;
+            WR[k] = p0;
+        } else {
+            const double m2 = r[c - 2 * ST], p1 = r[c + ST];
+            WL[k] = extrap_up(m1, slope3(m2, m1, p0));
+            WR[k] = extrap_dn(p0, slope3(m1, p0, p1));
+        }
+    }
+    double s1 = 1.0;
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) {
+        double dmin;
+        if (AXIS == 0) {
+            dmin = rmin(rmin(rmin(cur[P::px(i, j)], cur[P::py(i - 1, j)]), rmin(cur[P::py(i - 1, j + 1)], cur[P::py(i, j)])),
+                        rmin(rmin(cur[P::py(i, j + 1)], lo[P::rc(i - 1, j)]),
+                             rmin(hi[P::rc(i - 1, j)], rmin(lo[P::rc(i, j)], hi[P::rc(i, j)]))));
+        } else {
+            dmin = rmin(rmin(rmin(cur[P::py(i, j)], cur[P::px(i, j - 1)]), rmin(cur[P::px(i + 1, j - 1)], cur[P::px(i, j)])),
+                        rmin(rmin(cur[P::px(i + 1, j)], lo[P::rc(i, j - 1)]),
+                             rmin(hi[P::rc(i, j - 1)], rmin(lo[P::rc(i, j)], hi[P::rc(i, j)]))));
+        }
+        s1 = pow8(fswitch(dmin));
+    }
+    frame_flux3<PREC, AXIS, NSC>(S, WL, WR, s1, F);
+}
+
+// A column owner's part of plane step m: the own cell of plane m + 1 into
+// primitives (order 2), the z-face between planes m - 1 and m, and from the
+// run's second plane on the residual and stage update of plane m - 1.  H0:
+// the own cell of plane m; F0, c0: that of plane m + 1 as loaded; d: the
+// plane's x- and y-face sums; Wup and zlo carry to the next plane.
+template <int ORDER, int PREC, int NSC, int TX, int TY, int NT>
+__device__ __forceinline__ void column_z(const DevSolve3 &S, ZStageLds<ORDER, NSC, TX, TY, NT> &L, int stage, int last,
+                                         double dt, int m, int z0, int i0, int j0, int ci, int cj, bool col,
+                                         bool reads_qn, bool detect, const double *__restrict__ qin, double *r_out,
+                                         const double *H0, double *F0, int c0, const double *d, double *Wup,
+                                         double *zlo, double &lmax)
+{
+    using P = ZPlane<TX, TY, ORDER>;
+    constexpr int NR = 5 + NSC;
+    const int cur = m & 1, prv = cur ^ 1;
+    if (ORDER == 2) {
+        double W[NR];
+        zslot_prim<NSC>(S, F0, c0, W);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) F0[k] = W[k];
+    }
+    if (m < z0) {
+        // below the run: only the reconstructed upper state of plane z0 - 1
+        if (ORDER == 2) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Wup[k] = extrap_up(H0[k], slope3(Wup[k], H0[k], F0[k]));
+        }
+        return;
+    }
+    const int cb = P::cell(ci, cj);
+    double WL[NR], WR[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int row = frame_row<2>(k);
+        if (ORDER == 1) {
+            WL[k] = L.sW[row * P::PL + cb];
+            WR[k] = H0[row];
+        } else {
+            const double sl = slope3(L.sW[row * P::PL + cb], H0[row], F0[row]);
+            WL[k] = Wup[row];
+            WR[k] = extrap_dn(H0[row], sl);
+            Wup[row] = extrap_up(H0[row], sl);
+        }
+    }
+    double s1 = 1.0;
+    if (detect) {
+        const double *bl = L.sPxy[prv], *ab = L.sPxy[cur];
+        const double dmin =
+            rmin(rmin(rmin(L.sPz[cur][P::rc(ci, cj)], bl[P::px(ci, cj)]), rmin(bl[P::px(ci + 1, cj)], ab[P::px(ci, cj)])),
+                 rmin(rmin(ab[P::px(ci + 1, cj)], bl[P::py(ci, cj)]),
+                      rmin(bl[P::py(ci, cj + 1)], rmin(ab[P::py(ci, cj)], ab[P::py(ci, cj + 1)]))));
+        s1 = pow8(fswitch(dmin));
+    }
+    double zf[NR];
+    frame_flux3<PREC, 2, NSC>(S, WL, WR, s1, zf);
+    if (col && m > z0) {
+        // R = -(sum of face fluxes times areas) / V of plane m - 1 and its stage update
+        const long long idx = (long long)(m - 1) * S.slab + (long long)(j0 + cj) * S.pitch + (i0 + ci);
+        double Rv[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) Rv[k] = -(d[k] + (zf[k] - zlo[k])) * S.inv_vol;
+        if (stage == 0) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) gptr(r_out)[k * S.plane + idx] = Rv[k];
+            if (last) {
+                double W[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) W[k] = L.sW[k * P::PL + cb];
+                lmax = rmax(lmax, cell_rate3(S, W, rcp_nr(W[0])));
+            }
+        } else {
+            double Qs[NR], Q0[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) Qs[k] = gptr(qin)[k * S.plane + idx];
+            if (reads_qn) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) Q0[k] = gptr(S.q)[k * S.plane + idx];
+            }
+            stage_update3<NR>(S, stage, last, dt, Rv, Qs, Q0, idx, lmax);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) zlo[k] = zf[k];
+}
+
+template <int ORDER, int PREC, int NSC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__ Sp, int stage, int p, int last,
+                                                   double *r_out, int zc)
+{
+    using P = ZPlane<TX, TY, ORDER>;
+    constexpr int NR = 5 + NSC, NS = (P::PL + NT - 1) / NT;
+    static_assert(P::NI <= NT && P::NFX <= NT && P::NFY <= NT, "one column, one x-face and one y-face per thread");
+    const DevSolve3 &S = *Sp;
+    __shared__ ZStageLds<ORDER, NSC, TX, TY, NT> L;
+    const int tid = threadIdx.x;
+    const int ntx = (S.nx + TX - 1) / TX, nty = (S.ny + TY - 1) / TY, nzc = (S.nz + zc - 1) / zc;
+    const int nb = ntx * nty * nzc;
+    // runs numbered column tile fastest: each XCD takes a slab of whole
+    // layers of runs, so the runs it holds at once are x- and y-neighbours at
+    // the same height (their shared halo lines are read from its L2 once)
+    // and a run's successor above starts as it ends (the planes they share
+    // are still in that L2)
+    const int t = xcd_tile(blockIdx.x, nb);
+    if (t >= nb) return;
+    const int ct = t % (ntx * nty);
+    const int i0 = (ct % ntx) * TX, j0 = (ct / ntx) * TY;
+    const int z0 = (t / (ntx * nty)) * zc, z1 = min(z0 + zc, S.nz);
+    const double *__restrict__ qin = stage_input3(S, stage);
+    Slot &z = *S.slot;
+    const StepWords sw = stage > 0 ? load_step_words(z, p, stage) : StepWords{};
+    const bool reads_qn = stage_reads_qn(stage);
+    const bool detect = S.s1_mode == 0 && S.scheme == SCHEME_ROEAM;
+    const bool own = tid < P::NI;
+
+    double Fq[NS][NR];  // the next plane's footprint as loaded; slot 0 of a column owner in primitives (order 2)
+    int Fc[NS];
+    double H0[NR];      // the current plane's footprint slot 0, primitives (slots past it: sKeep)
+    double Wup[NR];     // order 2: the own cell of the plane below, reconstructed at its upper face
+    double zlo[NR];     // flux through the lower z-face of the plane being finished
+    if (ORDER == 2) {
+        // own cell two planes below the run, then the footprint of the plane below it
+        zplane_load<ORDER, NSC, TX, TY, NT, 0, 1>(S, qin, tid, i0, j0, z0 - 2, true, Fq, Fc);
+        if (own) zslot_prim<NSC>(S, Fq[0], Fc[0], Wup);
+    }
+    zplane_load<ORDER, NSC, TX, TY, NT, 0, NS>(S, qin, tid, i0, j0, z0 - 1, false, Fq, Fc);
+    if (ORDER == 2 && own) {
+        double W[NR];
+        zslot_prim<NSC>(S, Fq[0], Fc[0], W);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) Fq[0][k] = W[k];
+    }
+    double dt = 0.0;
+    if (stage > 0 && !begin_stage(z, sw, p, stage, last, t == 0, dt)) return;
+    double lmax = 0.0;
+
+    for (int m = z0 - 1; m <= z1; ++m) {
+        const int cur = m & 1, prv = cur ^ 1;
+        // the thread's indices.  With FP64 coefficients they are derived
+        // anew in each plane step from a copy of the thread id the compiler
+        // cannot see through: hoisted out of the loop they would hold
+        // registers the face work needs, and spill (measured 7% slower); the
+        // FP32-coefficient kernel has the registers to keep them (4% faster)
+        int tq = tid;
+        if constexpr (PREC == 0) asm volatile("" : "+v"(tq));
+        const int ci = tq % TX, cj = tq / TX;
+        const bool col = own && i0 + ci < S.nx && j0 + cj < S.ny;
+        // plane m - 1 into the staged plane, plane m's primitives from the
+        // loaded footprint, its p and rho into the one-layer footprint.  No
+        // barrier first: the last plane's other readers of these arrays
+        // passed the barrier after its y-faces (its ratios one before), and
+        // a thread's own cell, which the column step reads after it, is
+        // written by the thread itself.
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = tq + s * NT;
+            if (e >= P::PL) continue;
+            int lx, ly;
+            P::slot_xy(e, lx, ly);
+            if (m >= z0) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k)
+                    L.sW[k * P::PL + ly * P::LX + lx] = s == 0 ? H0[k] : L.sKeep[k][e - NT];
+            }
+            double W[NR];
+            if (ORDER == 2 && s == 0 && own) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) W[k] = Fq[0][k];
+            } else {
+                zslot_prim<NSC>(S, Fq[s], Fc[s], W);
+            }
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (s == 0) H0[k] = W[k];
+                else L.sKeep[k][e - NT] = W[k];
+            }
+            const int i = lx - ORDER, j = ly - ORDER;
+            if (i >= -1 && i <= TX && j >= -1 && j <= TY) {
+                L.sPR[P::rc(i, j)] = W[4];
+                L.sPR[P::RP + P::rc(i, j)] = W[0];
+            }
+        }
+        // the plane above: slot 0 now (a column owner's is its z-stencil; at
+        // the top of the run only those are loaded), the other slots once the
+        // detector ratios are in LDS
+        if (m < z1 || ORDER == 2) zplane_load<ORDER, NSC, TX, TY, NT, 0, 1>(S, qin, tq, i0, j0, m + 1, m == z1, Fq, Fc);
+        __syncthreads();
+
+        // detector ratios, Eq. (97): x- and y-faces of plane m, z-faces between m - 1 and m
+        if (detect) {
+            const double *pP = L.sPR, *pR = L.sPR + P::RP;
+            double *rxy = L.sPxy[cur];
+            const int ne = P::NPX + P::NPY + (m >= z0 ? P::RP : 0);
+            for (int e = tq; e < ne; e += NT) {
+                if (e < P::NPX) {
+                    const int fi = e % (TX + 1), j = e / (TX + 1) - 1;
+                    const int a = P::rc(fi - 1, j), b = P::rc(fi, j);
+                    rxy[e] = detector_P(pP[a], pR[a], pP[b], pR[b]);
+                } else if (e < P::NPX + P::NPY) {
+                    const int f = e - P::NPX;
+                    const int i = f % (TX + 2) - 1, fj = f / (TX + 2);
+                    const int a = P::rc(i, fj - 1), b = P::rc(i, fj);
+                    rxy[e] = detector_P(pP[a], pR[a], pP[b], pR[b]);
+                } else {
+                    const int f = e - P::NPX - P::NPY;
+                    const int c = P::cell(f % (TX + 2) - 1, f / (TX + 2) - 1);
+                    L.sPz[cur][f] = detector_P(L.sW[4 * P::PL + c], L.sW[c], pP[f], pR[f]);
+                }
+            }
+        }
+        __syncthreads();
+
+        if (m < z1) zplane_load<ORDER, NSC, TX, TY, NT, 1, NS>(S, qin, tq, i0, j0, m + 1, false, Fq, Fc);
+        // x- and y-faces of plane m - 1, residual sums (x) + (y)
+        double d[NR];
+        if (m > z0) {
+            const double *cxy = L.sPxy[prv], *zl = L.sPz[prv], *zh = L.sPz[cur];
+            if (tq < P::NFX) {
+                const int fi = tq % (TX + 1), j = tq / (TX + 1);
+                if (i0 + fi <= S.nx && j0 + j < S.ny) {
+                    double F[NR];
+                    zplane_face<ORDER, PREC, 0, NSC, P>(S, L.sW, cxy, zl, zh, fi, j, F);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) L.sF[k][tq] = F[k];
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int lo = cj * (TX + 1) + ci;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) d[k] = L.sF[k][lo + 1] - L.sF[k][lo];
+            }
+            __syncthreads();
+            if (tq < P::NFY) {
+                const int i = tq % TX, fj = tq / TX;
+                if (i0 + i < S.nx && j0 + fj <= S.ny) {
+                    double F[NR];
+                    zplane_face<ORDER, PREC, 1, NSC, P>(S, L.sW, cxy, zl, zh, i, fj, F);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) L.sF[k][tq] = F[k];
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int lo = cj * TX + ci;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) d[k] += L.sF[k][lo + TX] - L.sF[k][lo];
+            }
+        }
+
+        if (own) column_z<ORDER, PREC, NSC, TX, TY, NT>(S, L, stage, last, dt, m, z0, i0, j0, ci, cj, col, reads_qn,
+                                                         detect, qin, r_out, H0, Fq[0], Fc[0], d, Wup, zlo, lmax);
+    }
+    if (last) reduce_rate_block<NT>(z, stage == 0 ? 0 : rate_set(sw.steps + 1), lmax, L.sRed);
+}
+
+// Brick shapes: id, TX, TY, TZ, threads, form.  Shapes 4-9 give every
 // face of a sweep its own thread (threads >= the largest face count of one
-// axis), so each sweep is a single pass; 8 and 9 are persistent (resident
-// workgroups that prefetch the next brick's halo into registers; 512 threads
-// leave room for them).
+// axis), so each sweep is a single pass; 8 and 9 are persistent (form 1:
+// resident workgroups that prefetch the next brick's halo into registers;
+// 512 threads leave room for them).  Form 2 is the z-marching kernel on
+// TX x TY column tiles with runs of TZ planes (three waves per SIMD).
 #define ROEAM_SHAPES3(X)      \
     X(0, 8, 8, 4, 256, 0)     \
     X(1, 8, 4, 4, 128, 0)     \
@@ -595,10 +1053,13 @@ __global__ __launch_bounds__(NT) void k_stage3p(const DevSolve3 *__restrict__ Sp
     X(6, 16, 8, 4, 640, 0)    \
     X(7, 8, 8, 8, 576, 0)     \
     X(8, 16, 8, 4, 512, 1)    \
-    X(9, 8, 8, 8, 512, 1)
+    X(9, 8, 8, 8, 512, 1)     \
+    X(10, 16, 15, 4, 256, 2)  \
+    X(11, 16, 15, 8, 256, 2)  \
+    X(12, 16, 15, 16, 256, 2)
 
 struct BrickShape {
-    int tx, ty, tz, nt, persistent;
+    int tx, ty, tz, nt, persistent;  // form: 0 brick, 1 persistent brick, 2 z-marching
 };
 #define ROEAM_SHAPE3_ENTRY(ID, TX, TY, TZ, NT, PE) {TX, TY, TZ, NT, PE},
 static const BrickShape kShapes3[] = {ROEAM_SHAPES3(ROEAM_SHAPE3_ENTRY)};
@@ -628,12 +1089,25 @@ static int persistent_blocks(K kernel, int nt, long long nb)
     return (int)(((want + 7) >> 3) << 3);
 }
 
+// LDS of a shape's kernel.
+constexpr long long shape3_lds_bytes(int order, int nsc, int tx, int ty, int tz, int nt, int form)
+{
+    return form == 2 ? zstage3_lds_bytes(order, nsc, tx, ty, nt)
+                     : stage3_lds_bytes(order, nsc, tx, ty, tz, nt, stage3_double_buffer(order, nsc, tx, ty, tz, nt));
+}
+
 template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT, int PE>
 static hipError_t launch3_one(const DevSolve3 *dS, long long nb, int stage, int p, int last, double *r_out,
                               hipStream_t st)
 {
-    if constexpr (stage3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT, StageLds<ORDER, NSC, TX, TY, TZ, NT>::DB) > kLdsBytes3) {
+    if constexpr (shape3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT, PE) > kLdsBytes3) {
         return hipErrorInvalidValue;
+    } else if constexpr (PE == 2) {
+        // one workgroup per run of TZ planes of a column tile
+        const int blocks = (int)(((nb + 7) >> 3) << 3);
+        hipLaunchKernelGGL((k_stage3z<ORDER, PREC, NSC, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, dS, stage, p,
+                           last, r_out, TZ);
+        return hipSuccess;
     } else if constexpr (PE) {
         auto kernel = k_stage3p<ORDER, PREC, NSC, TX, TY, TZ, NT>;
         const int blocks = persistent_blocks(kernel, NT, nb);

@@ -11,6 +11,7 @@ import pytest
 import oracle
 import workloads
 from gpu_util import ctx, say
+from paper_1711_09272_amd import SHAPES3
 from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
 
 pytestmark = pytest.mark.gpu
@@ -106,7 +107,11 @@ def test_residual3_fp32_flux(C, name):
     assert np.all(err <= TOL32), err
 
 
-@pytest.mark.parametrize("shape", range(10))
+# the z-marching shapes (column tiles walking runs of planes)
+ZSHAPES = [k for k, name in enumerate(SHAPES3) if "z" in name]
+
+
+@pytest.mark.parametrize("shape", range(len(SHAPES3)))
 def test_every_brick_shape_is_bitwise_identical(C, shape):
     """All brick shapes evaluate the same faces with the same arithmetic."""
     case = workloads.rough_case3(37, 19, 13, 15, bc=ALL_WALLS, order=2, eps1=1.0, mach_ref=0.05)
@@ -118,13 +123,26 @@ def test_every_brick_shape_is_bitwise_identical(C, shape):
     assert np.all(rerr(r, r_or, scale) <= TOL64)
 
 
-@pytest.mark.parametrize("shape", [8, 9])
+@pytest.mark.parametrize("name,case", CASES, ids=[n for n, _ in CASES])
+@pytest.mark.parametrize("shape", [ZSHAPES[0], ZSHAPES[-1]])
+def test_zmarch_residual_every_case(C, shape, name, case):
+    """The z-marching kernel on every residual case (boundary kinds, orders,
+    schemes, variants, the 2-cell grids): bitwise the brick kernel's result,
+    rate included."""
+    say(f"[z-march shape {shape}] {name} {case.nx}x{case.ny}x{case.nz}")
+    r0, rate0 = gpu_residual3(C, case, shape=0)
+    r, rate = gpu_residual3(C, case, shape=shape)
+    assert np.array_equal(r, r0) and rate == rate0
+
+
+@pytest.mark.parametrize("shape", [8, 9] + ZSHAPES)
 @pytest.mark.parametrize("ts,steps", [(0, 3), (1, 2), (2, 2)])
 def test_persistent_bricks_steps(C, shape, ts, steps):
-    """The persistent shapes on a grid with more bricks than resident workgroups
-    (64^3: 512 bricks, each workgroup takes several and prefetches the next):
-    every stage code, the step state and the rate reduction, bitwise equal to
-    the one-brick-per-workgroup kernel and within 1e-12 of the oracle."""
+    """The persistent and z-marching shapes on a grid with more bricks or runs
+    than resident workgroups (64^3: 512 bricks; 20 column tiles x 16, 8 or 4
+    runs): every stage code, the step state and the rate reduction, bitwise
+    equal to the one-brick-per-workgroup kernel and within 1e-12 of the
+    oracle."""
     case = workloads.smooth_random_case3(64, 64, 64, 30, bc=ALL_WALLS, order=2, eps1=1.0, mach_ref=0.05,
                                          time_scheme=ts, cfl=0.4)
     say(f"[persistent shape {shape}] time scheme {ts}, {steps} steps, 64^3")
@@ -210,7 +228,7 @@ def test_invalid_arguments_3d(C):
     case = workloads.smooth_random_case3(4, 4, 4, 19)
     g = P.Grid3.from_case(C, case)
     with pytest.raises(P.RoeamError):
-        g.set_tile_shape(10)
+        g.set_tile_shape(len(SHAPES3))
     q = g.to_device(case.q0)
     with pytest.raises(P.RoeamError):
         P.residual3(C, g, dict(case.params, order=3), q)

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads
+from paper_1711_09272_amd import SHAPES3
 from gpu_util import ctx, say
 from workloads import DIRICHLET, PERIODIC, SLIPWALL, TRANSMISSIVE
 
@@ -119,7 +120,7 @@ def test_unit_scalar_follows_the_mass_row_3d(C):
 
 
 @pytest.mark.parametrize("ns", [1, 2])
-@pytest.mark.parametrize("shape", range(10))
+@pytest.mark.parametrize("shape", range(len(SHAPES3)))
 def test_every_brick_shape_with_scalars(C, shape, ns):
     """Every shape computes the same bits; with two scalars the 16x8x4 bricks do
     not fit the LDS and run the fallback shape (persistent 8x8x8), again the
