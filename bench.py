@@ -779,6 +779,7 @@ def bench_3d(args):
         alu = {"bound": "alu", "achieved": round(lane_rate / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 3),
                "unit": "T VALU lane-instr/s", "frac": round(lane_rate / PEAK_VALU_LANE_INSTR, 4),
                "valu_lane_instr_per_cell_stage": valu}
+    kform3 = "p" if P.SHAPES3[shape].endswith("p") else ("z" if "z" in P.SHAPES3[shape] else "")
     out = {
         "metric": "Gcell-updates/s per RK stage",
         "value": round(value, 4),
@@ -810,8 +811,8 @@ def bench_3d(args):
             "traffic": traffic,
             "traffic_frac": round(traffic / (launch_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
             "alu": alu,
-            "kernel": "k_stage3%s<order 2, FP%s, %s>" % ("p" if P.SHAPES3[shape].endswith("p") else "",
-                                                         "64" if args.precision == 0 else "32-coef", P.SHAPES3[shape]),
+            "kernel": "k_stage3%s<order 2, FP%s, %s>" % (kform3, "64" if args.precision == 0 else "32-coef",
+                                                         P.SHAPES3[shape]),
             "kernel_grid": f"{n}x{n}x{nz}",
             "launch_ms": round(launch_ms, 6),
             "timed_region_launches": 3 * args.steps,
