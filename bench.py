@@ -736,8 +736,8 @@ def bench_3d(args):
     cells = case.cells
     ctx = P.Context(0)
     grid = P.Grid3.from_case(ctx, case)
-    shape = args.tile_shape if args.tile_shape >= 0 else 10
-    grid.set_tile_shape(shape)
+    grid.set_tile_shape(args.tile_shape)  # -1: the shape chosen for the grid's size
+    shape = grid.tile_shape(case.params["order"])
     q = grid.to_device(case.q0)
     prm = case.params
     stream = torch.cuda.current_stream()

@@ -330,13 +330,19 @@ roeam_status roeam_grid3d_set_scalars(roeam_grid3d *grid, int nscalars, const do
  * 9 = 8x8x8/512 persistent (as many workgroups as the GPU holds, each taking a
  * band of bricks in turn and loading the next brick's halo while it computes
  * the current one).  10-12: z-marching column tiles of 16x15 cells with 256
- * threads, each workgroup walking a run of 4 (10, the default), 8 (11) or
- * 16 (12) planes upward with one plane and its x-y halo in LDS while the
- * next plane's footprint loads into registers (three workgroups per CU).
- * Every shape computes bitwise the same result.  With two transported
- * scalars the 16x8x4 bricks (2, 6, 8) exceed the LDS of a workgroup; such a
- * grid runs shape 9 instead.  EINVAL: shape outside 0..12. */
+ * threads, each workgroup walking a run of 4 (10), 8 (11) or 16 (12)
+ * planes upward with one plane and its x-y halo in LDS while the next
+ * plane's footprint loads into registers (three workgroups per CU).  -1
+ * (default): the z-marching shape with the longest run whose workgroups
+ * still number at least nine per CU of the device (else runs of 4).  Every
+ * shape computes bitwise the same result.  With two transported scalars the
+ * 16x8x4 bricks (2, 6, 8) exceed the LDS of a workgroup; such a grid runs
+ * shape 9 instead.  EINVAL: shape outside -1..12. */
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
+/* The shape the stage kernel runs with for MUSCL order `order` (1 or 2),
+ * the default's choice and the scalar fallback applied.  EINVAL: NULL
+ * argument, bad order. */
+roeam_status roeam_grid3d_tile_shape(const roeam_grid3d *grid, int order, int *shape);
 /* Residual R = dQ/dt = -(1/V) sum over the cell's six faces of F A (Eq. 85
  * per unit area times the face area).  q: device, 3-D state layout, read
  * only; r: device, same layout, written.  max_rate_out: nullable DEVICE

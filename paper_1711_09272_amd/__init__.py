@@ -32,6 +32,7 @@ EXPORTS = [
     "roeam_batch_run", "roeam_batch_profile_run", "roeam_batch_poll", "roeam_batch_attach", "roeam_residual_norms",
     "roeam_residual_norms3d", "roeam_residual_norms_noalloc", "roeam_batch_configure", "roeam_batch_info",
     "roeam_grid3d_create", "roeam_grid3d_destroy", "roeam_grid3d_layout", "roeam_grid3d_set_tile_shape",
+    "roeam_grid3d_tile_shape",
     "roeam_grid3d_set_scalars", "roeam_residual3d", "roeam_step3d", "roeam_last_stats3d",
 ]
 # 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
@@ -137,6 +138,7 @@ def lib():
         "roeam_grid3d_layout": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                     ctypes.POINTER(ctypes.c_long)]),
         "roeam_grid3d_set_tile_shape": (i, [vp, i]),
+        "roeam_grid3d_tile_shape": (i, [vp, i, ctypes.POINTER(i)]),
         "roeam_grid3d_set_scalars": (i, [vp, i, vp]),
         "roeam_residual3d": (i, [vp, vp, ctypes.POINTER(Params), vp, vp, vp]),
         "roeam_step3d": (i, [vp, vp, ctypes.POINTER(Params), vp, ctypes.c_long, d, d, ctypes.POINTER(StepStats)]),
@@ -610,8 +612,14 @@ class Grid3:
         return t[..., : self.nx].detach().cpu().numpy().copy()
 
     def set_tile_shape(self, shape: int):
-        """Brick shape (see SHAPES3)."""
+        """Shape of the 3-D stage kernel (see SHAPES3; -1: chosen for the grid's size)."""
         self.ctx.check(lib().roeam_grid3d_set_tile_shape(self.h, int(shape)))
+
+    def tile_shape(self, order: int = 2) -> int:
+        """The shape the stage kernel runs with for this MUSCL order."""
+        out = ctypes.c_int(-1)
+        self.ctx.check(lib().roeam_grid3d_tile_shape(self.h, int(order), ctypes.byref(out)))
+        return out.value
 
     def close(self):
         if getattr(self, "h", None):

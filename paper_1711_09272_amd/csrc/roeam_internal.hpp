@@ -69,6 +69,7 @@ int brick_shape_count();
 // Whether a brick shape's stage kernel fits the LDS of a workgroup for the given
 // MUSCL order and scalar count (16x8x4 bricks do not with two scalars).
 bool brick_shape_fits(int shape, int order, int nsc);
+int zmarch_auto_shape(int nx, int ny, int nz, int cus);
 hipError_t launch_stage3_sc(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last,
                             double *r_out, hipStream_t st);
 hipError_t launch_stage3(const DevSolve3 *dS, const DevSolve3 &S, int shape, int stage, int p, int last, double *r_out,

@@ -44,6 +44,22 @@ __global__ __launch_bounds__(256) void k_fe_finish3(const DevSolve3 *__restrict_
 // ---------------------------------------------------------------------------
 int brick_shape_count() { return kNumShapes3; }
 
+// The z-marching shape for a grid: the longest run whose workgroups still
+// make three rounds of the three a CU holds (longer runs load fewer planes
+// twice; more workgroups keep the chip full), else the shortest run.
+int zmarch_auto_shape(int nx, int ny, int nz, int cus)
+{
+    int best = -1, best_tz = 0, shortest = -1, shortest_tz = 1 << 30;
+    for (int s = 0; s < kNumShapes3; ++s) {
+        const BrickShape &sh = kShapes3[s];
+        if (sh.persistent != 2) continue;
+        const long long wgs = (long long)((nx + sh.tx - 1) / sh.tx) * ((ny + sh.ty - 1) / sh.ty) * ((nz + sh.tz - 1) / sh.tz);
+        if (wgs >= 9ll * cus && sh.tz > best_tz) best = s, best_tz = sh.tz;
+        if (sh.tz < shortest_tz) shortest = s, shortest_tz = sh.tz;
+    }
+    return best >= 0 ? best : shortest;
+}
+
 bool brick_shape_fits(int shape, int order, int nsc)
 {
     if (shape < 0 || shape >= kNumShapes3) return false;

@@ -26,21 +26,36 @@ struct roeam_grid3d {
     DevSolve3 *h_solve = nullptr;     // pinned staging copy of the last descriptor sent
     bool solve_valid = false;
     GraphCache gc;
-    int shape = 10;                   // z-marching 16x15 column tiles, runs of 4 planes (fastest measured on 128^3)
+    int shape = -1;                   // -1: the z-marching shape chosen for the grid's size
     double *d_norm_part = nullptr;    // scratch of roeam_residual_norms3d
     int final_parity = 0;
     int nsc = 0;                      // transported scalars (rows 5 .. 4 + nsc of q)
     double bcs[6][roeam::kMaxScalars] = {}; // Dirichlet rho k_m per side
 };
 
-// Brick shape the stage kernel runs with: the grid's, or persistent 8x8x8
-// bricks with 512 threads where the grid's does not fit the LDS with its
-// scalars (fastest measured with two scalars on 128^3: 350 us per stage, the
-// 8x8x4/320 brick 561).
+// Compute units of a device (queried once per device).
+static int device_cus(int dev)
+{
+    constexpr int kMaxDevices = 64;
+    static int cached[kMaxDevices];  // 0: not queried yet
+    if (dev < 0 || dev >= kMaxDevices) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+// Shape the stage kernel runs with: the grid's; by default the z-marching
+// shape for the grid's size; persistent 8x8x8 bricks with 512 threads where
+// the grid's does not fit the LDS with its scalars (fastest measured with two
+// scalars on 128^3 among the bricks: 350 us per stage, the 8x8x4/320 brick 561).
 constexpr int kFallbackShape3 = 9;
 static int stage_shape3(const roeam_grid3d *g, int order)
 {
-    return roeam::brick_shape_fits(g->shape, order, g->nsc) ? g->shape : kFallbackShape3;
+    const int shape = g->shape >= 0 ? g->shape : roeam::zmarch_auto_shape(g->nx, g->ny, g->nz, device_cus(g->ctx->device));
+    return roeam::brick_shape_fits(shape, order, g->nsc) ? shape : kFallbackShape3;
 }
 
 static roeam_status fail(roeam_ctx *ctx, roeam_status st, const std::string &msg) { return roeam_fail(ctx, st, msg); }
@@ -272,8 +287,15 @@ roeam_status roeam_grid3d_set_scalars(roeam_grid3d *g, int nscalars, const doubl
 
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *g, int shape)
 {
-    if (!g || shape < 0 || shape >= roeam::brick_shape_count()) return ROEAM_EINVAL;
+    if (!g || shape < -1 || shape >= roeam::brick_shape_count()) return ROEAM_EINVAL;
     g->shape = shape;
+    return ROEAM_OK;
+}
+
+roeam_status roeam_grid3d_tile_shape(const roeam_grid3d *g, int order, int *shape)
+{
+    if (!g || !shape || (order != 1 && order != 2)) return ROEAM_EINVAL;
+    *shape = stage_shape3(g, order);
     return ROEAM_OK;
 }
 

@@ -158,6 +158,29 @@ def test_persistent_bricks_steps(C, shape, ts, steps):
     assert np.array_equal(r, r6) and rate == rate6
 
 
+def test_default_shape_follows_the_grid_size(C):
+    """By default a 3-D grid runs the z-marching shape with the longest run
+    whose workgroups number at least nine per CU (three rounds of the three a
+    CU holds), else the shortest run; a set shape is kept."""
+    import torch
+    import paper_1711_09272_amd as P
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    runs = {k: int(name.split("z")[1].split("/")[0]) for k, name in enumerate(SHAPES3) if "z" in name}
+
+    def expected(n, nz):
+        tiles = -(-n // 16) * -(-n // 15)
+        fit = [k for k, zc in runs.items() if tiles * -(-nz // zc) >= 9 * cus]
+        return max(fit, key=runs.get) if fit else min(runs, key=runs.get)
+
+    for n, nz in ((32, 8), (128, 128), (256, 256), (512, 64)):
+        g = P.Grid3(C, n, n, nz, 0.1, 0.1, 0.1)
+        assert g.tile_shape(2) == expected(n, nz), (n, nz, g.tile_shape(2))
+        g.set_tile_shape(8)
+        assert g.tile_shape(2) == 8
+        g.close()
+    say(f"[default 3-D shape] {cus} CUs: 128^3 -> {SHAPES3[expected(128, 128)]}, 256^3 -> {SHAPES3[expected(256, 256)]}")
+
+
 def test_extruded_2d_case_matches_the_2d_oracle(C):
     """A 2-D case repeated along a periodic z: every z-slice of the 3-D GPU
     residual is the 2-D oracle residual and the w row is zero."""
