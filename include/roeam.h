@@ -407,7 +407,7 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
                                 uint64_t *tickets_out);
 /* Drive the scheduler for `iterations` iterations, rounded up to whole
  * graphs of graph_iters (0: only admit and retire; -1: until every queued
- * solve is done).  Every iteration advances each resident solve by one step;
+ * solve is done, its state copied out: polls then report it done).  Every iteration advances each resident solve by one step;
  * a solve whose budget or end time is reached idles until the status read
  * after its graph retires it.  Returns the number of solves still pending in
  * *pending (nullable). */

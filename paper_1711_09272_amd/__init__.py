@@ -498,9 +498,18 @@ def batch_info(ctx: Context) -> Dict:
     return {k: getattr(st, k) for k, _ in BatchStats._fields_}
 
 
-def batch_submit(ctx: Context, solves) -> list:
+def batch_descs(solves):
+    """The descriptor array of these solves, to submit the same set again
+    without rebuilding it (batch_submit(..., descs=))."""
     solves = list(solves)
-    arr = (SolveDesc * len(solves))(*[s.desc() for s in solves])
+    return (SolveDesc * len(solves))(*[s.desc() for s in solves])
+
+
+def batch_submit(ctx: Context, solves, descs=None) -> list:
+    solves = list(solves)
+    arr = batch_descs(solves) if descs is None else descs
+    if len(arr) != len(solves):
+        raise ValueError("descs must describe the solves")
     tk = (ctypes.c_uint64 * len(solves))()
     ctx.enter()  # initial states written by the caller's stream are read at admission
     ctx.check(lib().roeam_batch_submit(ctx.h, len(solves), arr, tk))

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libroeam.so")
 SOURCES = ["roeam_kernels.hip", "roeam_kernels_sc.hip", "roeam_norms.hip", "roeam_runtime.hip", "roeam_batch.hip",
-           "roeam_kernels3d.hip", "roeam_kernels3d_sc.hip", "roeam_runtime3d.hip"]
+           "roeam_batch_kernels.hip", "roeam_kernels3d.hip", "roeam_kernels3d_sc.hip", "roeam_runtime3d.hip"]
 HEADERS = ["roeam_device.hpp", "roeam_internal.hpp", "roeam_stage.hpp", "roeam_stage2d.hpp", "roeam_device3d.hpp",
            "roeam_stage3d.hpp", "roeam_host.hpp"]
 

@@ -16,7 +16,9 @@
 // disappears or a list's capacity changes.  After each graph a status kernel
 // summarises the slots; the host, one graph behind the device, retires
 // finished solves (copying their state out) and admits queued ones into the
-// freed arena space (continuous batching).
+// freed arena space (continuous batching).  The solves retired or admitted in
+// one round are moved by one upload and two kernel launches, whatever their
+// number (roeam_batch_kernels.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +27,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -88,6 +91,16 @@ struct Arena {
 
 enum ReqState { QUEUED = 0, RESIDENT = 1, COPYING = 2, DONE = 3 };
 
+// An event shared by the solves retired in one round: recorded after their
+// copies, destroyed with the last of them.
+struct SharedEvent {
+    hipEvent_t ev = nullptr;
+    ~SharedEvent()
+    {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
 struct Request {
     roeam_solve_desc d{};
     int state = QUEUED;
@@ -95,10 +108,11 @@ struct Request {
     size_t off = 0, bytes = 0;
     int group = -1;
     uint64_t seq = 0;  // submission order
+    uint64_t ticket = 0;
     long admit_iter = 0;  // scheduler iteration at which it joined
     roeam_status rc = ROEAM_OK;
     roeam_step_stats stats{};
-    hipEvent_t out_ev = nullptr;
+    std::shared_ptr<SharedEvent> out_ev;  // its copy out is complete when this has passed
 };
 
 struct Group {
@@ -153,6 +167,13 @@ struct BatchEngine {
     // counters
     long captures = 0, graph_launches = 0, tunes = 0;
     int last_shape = -1;            // tile shape of the group formed last
+    // the round's pending admissions and state moves, staged through one upload
+    std::vector<roeam::AdmitInit> pend_init;
+    std::vector<roeam::StateMove> pend_moves;
+    std::vector<uint64_t> pend_retired;  // tickets whose copy out is among the moves
+    char *d_stage = nullptr, *h_stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t stage_ev = nullptr;  // recorded after the last staging upload
     // profiling: event pairs around each stage launch (stage number beside)
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;
@@ -179,8 +200,10 @@ static void release_engine(BatchEngine *b)
     if (!b) return;
     for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
     release_graph(b);
-    for (auto &kv : b->reqs)
-        if (kv.second.out_ev) (void)hipEventDestroy(kv.second.out_ev);
+    b->reqs.clear();  // their shared events
+    if (b->stage_ev) (void)hipEventDestroy(b->stage_ev);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
     for (int k = 0; k < 2; ++k) {
         if (b->status_ev[k]) (void)hipEventDestroy(b->status_ev[k]);
         if (b->h_status[k]) (void)hipHostFree(b->h_status[k]);
@@ -238,9 +261,77 @@ static void append_tiles(Group &G, int idx, const roeam_grid *g)
     G.dirty = true;
 }
 
-// Retire solve r: queue the copy of its state to q_out and free its index
-// and arena space (later work on the stream runs after the copy).  Forward
-// Euler leaves the state of an odd step count in qa.
+// The move of grid g's state from src to dst.
+static roeam::StateMove state_move(const roeam_grid *g, const double *src, double *dst, int solve)
+{
+    roeam::StateMove m{};
+    m.src = src;
+    m.dst = dst;
+    m.plane = (long long)g->ny * g->pitch;
+    m.pitch = g->pitch;
+    m.nx = g->nx;
+    m.ny = g->ny;
+    m.rows = 4 + g->nsc;
+    m.solve = solve;
+    return m;
+}
+
+// Upload the round's pending admissions and moves in one copy and launch
+// them (descriptors and slots first, then the moves); the solves retired in
+// the round share one event recorded after their copies.  The pinned staging
+// buffer is rewritten only after its previous upload has completed.
+static roeam_status flush_moves(roeam_ctx *ctx, BatchEngine *b)
+{
+    if (b->pend_init.empty() && b->pend_moves.empty() && b->pend_retired.empty()) return ROEAM_OK;
+    std::vector<roeam::MoveChunk> chunks;
+    for (int m = 0; m < (int)b->pend_moves.size(); ++m) {
+        const long long n = (long long)b->pend_moves[m].nx * b->pend_moves[m].ny;
+        for (long long c0 = 0; c0 < n; c0 += roeam::kMoveChunk) chunks.push_back(roeam::MoveChunk{m, (int)c0});
+    }
+    const size_t bi = align_up(b->pend_init.size() * sizeof(roeam::AdmitInit));
+    const size_t bm = align_up(b->pend_moves.size() * sizeof(roeam::StateMove));
+    const size_t bytes = bi + bm + chunks.size() * sizeof(roeam::MoveChunk);
+    if (bytes > b->stage_cap) {
+        BHIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (b->d_stage) BHIP(ctx, hipFree(b->d_stage));
+        if (b->h_stage) BHIP(ctx, hipHostFree(b->h_stage));
+        b->d_stage = b->h_stage = nullptr;
+        b->stage_cap = 0;
+        const size_t cap = align_up(bytes + bytes / 2);
+        BHIP(ctx, hipMalloc(&b->d_stage, cap));
+        BHIP(ctx, hipHostMalloc(&b->h_stage, cap, hipHostMallocDefault));
+        b->stage_cap = cap;
+    } else if (b->stage_ev) {
+        BHIP(ctx, hipEventSynchronize(b->stage_ev));
+    }
+    if (bytes) {
+        std::memcpy(b->h_stage, b->pend_init.data(), b->pend_init.size() * sizeof(roeam::AdmitInit));
+        std::memcpy(b->h_stage + bi, b->pend_moves.data(), b->pend_moves.size() * sizeof(roeam::StateMove));
+        std::memcpy(b->h_stage + bi + bm, chunks.data(), chunks.size() * sizeof(roeam::MoveChunk));
+        BHIP(ctx, hipMemcpyAsync(b->d_stage, b->h_stage, bytes, hipMemcpyHostToDevice, ctx->stream));
+        if (!b->stage_ev) BHIP(ctx, hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming));
+        BHIP(ctx, hipEventRecord(b->stage_ev, ctx->stream));
+        BHIP(ctx, roeam::launch_admit_init((const roeam::AdmitInit *)b->d_stage, (int)b->pend_init.size(), b->d_solves,
+                                           ctx->stream));
+        BHIP(ctx, roeam::launch_moves((const roeam::StateMove *)(b->d_stage + bi),
+                                      (const roeam::MoveChunk *)(b->d_stage + bi + bm), (int)chunks.size(),
+                                      b->d_solves, ctx->stream));
+    }
+    if (!b->pend_retired.empty()) {
+        auto ev = std::make_shared<SharedEvent>();
+        BHIP(ctx, hipEventCreateWithFlags(&ev->ev, hipEventDisableTiming));
+        BHIP(ctx, hipEventRecord(ev->ev, ctx->stream));
+        for (uint64_t tk : b->pend_retired) b->reqs[tk].out_ev = ev;
+    }
+    b->pend_init.clear();
+    b->pend_moves.clear();
+    b->pend_retired.clear();
+    return ROEAM_OK;
+}
+
+// Retire solve r: queue the copy of its state to q_out (flush_moves issues
+// it, before anything later on the stream) and free its index and arena
+// space.  Forward Euler leaves the state of an odd step count in qa.
 static roeam_status retire(roeam_ctx *ctx, BatchEngine *b, Request &r, const SolveStatus &s)
 {
     const roeam_grid *g = r.d.grid;
@@ -253,10 +344,9 @@ static roeam_status retire(roeam_ctx *ctx, BatchEngine *b, Request &r, const Sol
     const size_t sb = align_up(state_bytes(g));
     const bool in_qa = r.d.params.time_scheme == 0 && (s.steps & 1);
     const double *q = (const double *)(b->d_arena + r.off + (in_qa ? sb : 0));
-    BHIP(ctx, hipMemcpyAsync(r.d.q_out, q, state_bytes(g),
-                             r.d.q_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
-    if (!r.out_ev) BHIP(ctx, hipEventCreateWithFlags(&r.out_ev, hipEventDisableTiming));
-    BHIP(ctx, hipEventRecord(r.out_ev, ctx->stream));
+    if (r.d.q_out_on_device) b->pend_moves.push_back(state_move(g, q, r.d.q_out, -1));
+    else BHIP(ctx, hipMemcpyAsync(r.d.q_out, q, state_bytes(g), hipMemcpyDeviceToHost, ctx->stream));
+    b->pend_retired.push_back(r.ticket);
     r.state = COPYING;
     b->alloc.release(r.off, r.bytes);
     b->by_idx[r.idx] = 0;
@@ -292,7 +382,7 @@ static roeam_status process_status(roeam_ctx *ctx, BatchEngine *b, int which, bo
         roeam_status rc = retire(ctx, b, r, st[i]);
         if (rc) return rc;
     }
-    return ROEAM_OK;
+    return flush_moves(ctx, b);
 }
 
 // Grow (or shrink) a group's device work list to hold `need` tiles.  Changing
@@ -528,12 +618,21 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
         double *qb = (double *)(b->d_arena + off + 2 * sb);
         DevSolve S = roeam_make_solve(g, &r.d.params, q, qa, qb, &b->d_slots[idx]);
         b->h_solves[idx] = S;
-        BHIP(ctx, hipMemcpyAsync(&b->d_solves[idx], &b->h_solves[idx], sizeof(DevSolve), hipMemcpyHostToDevice,
-                                 ctx->stream));
-        BHIP(ctx, hipMemcpyAsync(q, r.d.q0, state_bytes(g),
-                                 r.d.q0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
-        BHIP(ctx, roeam::launch_slot_init(&b->d_slots[idx], 1, 0.0, r.d.t_end, r.d.params.cfl, r.d.nsteps, ctx->stream));
-        BHIP(ctx, roeam::launch_rate(S, 0, ctx->stream));
+        // descriptor, fresh slot, the initial state into the arena and its
+        // rate: queued, issued for the whole round by flush_moves
+        roeam::AdmitInit ai{};
+        ai.S = S;
+        ai.t_end = r.d.t_end;
+        ai.cfl = r.d.params.cfl;
+        ai.nsteps = r.d.nsteps;
+        ai.idx = idx;
+        b->pend_init.push_back(ai);
+        if (r.d.q0_on_device) {
+            b->pend_moves.push_back(state_move(g, r.d.q0, q, idx));
+        } else {
+            BHIP(ctx, hipMemcpyAsync(q, r.d.q0, state_bytes(g), hipMemcpyHostToDevice, ctx->stream));
+            b->pend_moves.push_back(state_move(g, q, q, idx));
+        }
         Group &G = b->groups[r.group];
         if (G.shape < 0) forming[r.group].push_back(idx);
         else append_tiles(G, idx, g);
@@ -545,6 +644,8 @@ static roeam_status admit(roeam_ctx *ctx, BatchEngine *b)
             if (b->reqs[tk].state == QUEUED) rest.push_back(tk);
         b->queue.assign(rest.begin(), rest.end());
     }
+    roeam_status frc = flush_moves(ctx, b);  // before any launch reads the new solves
+    if (frc) return frc;
     for (int gi = 0; gi < kGroups; ++gi) {
         if (forming[gi].empty()) continue;
         roeam_status rc = tune_group(ctx, b, b->groups[gi], forming[gi]);
@@ -745,6 +846,7 @@ roeam_status roeam_batch_submit(roeam_ctx *ctx, int n, const roeam_solve_desc *d
         r.bytes = roeam_batch_footprint(descs[i].grid);
         r.group = group_id(descs[i].params, descs[i].grid->metric, descs[i].grid->nsc);
         r.seq = b->next_seq++;
+        r.ticket = tk;
         b->reqs.emplace(tk, r);
         b->queue.push_back(tk);
         tickets_out[i] = tk;
@@ -818,9 +920,11 @@ roeam_status roeam_batch_run(roeam_ctx *ctx, long iterations, int *pending)
         if (b->profiling && (rc = process_status(ctx, b, which, true))) return rc;
     }
     if (iterations < 0) {
-        // drain: retire everything still reported
+        // drain: retire everything still reported, and return once every
+        // retired solve's copy out has completed (its poll reports it done)
         for (int w = 0; w < 2; ++w)
             if ((rc = process_status(ctx, b, w, true))) return rc;
+        BHIP(ctx, hipStreamSynchronize(s));
     }
     if (pending) {
         int n = 0;
@@ -869,7 +973,8 @@ roeam_status roeam_batch_poll(roeam_ctx *ctx, uint64_t ticket, int *done, roeam_
     if (it == b->reqs.end()) return roeam_fail(ctx, ROEAM_ENOTFOUND, "unknown ticket");
     Request &r = it->second;
     if (r.state == COPYING) {
-        hipError_t q = hipEventQuery(r.out_ev);
+        if (!r.out_ev) return roeam_fail(ctx, ROEAM_EDEVICE, "retired solve without a copy event");
+        hipError_t q = hipEventQuery(r.out_ev->ev);
         if (q == hipSuccess) r.state = DONE;
         else if (q != hipErrorNotReady) return hip_err(ctx, q, "hipEventQuery");
     }
@@ -878,7 +983,6 @@ roeam_status roeam_batch_poll(roeam_ctx *ctx, uint64_t ticket, int *done, roeam_
     // reported done: the ticket is forgotten (a server's request table does not grow)
     if (stats) *stats = r.stats;
     const roeam_status rc = r.rc;
-    if (r.out_ev) (void)hipEventDestroy(r.out_ev);
     b->reqs.erase(it);
     if (rc == ROEAM_ENONPHYS) return roeam_fail(ctx, ROEAM_ENONPHYS, "solve produced a non-physical state");
     return ROEAM_OK;

@@ -21,6 +21,34 @@ struct SolveStatus {
     int nonphys, done;
 };
 
+// Batched state moves of the batch engine: one solve's state copied between
+// a caller's buffer and the arena (src == dst: in place), and, on admission,
+// the explicit rate of the moved state reduced into the solve's fresh slot.
+struct StateMove {
+    const double *src;
+    double *dst;
+    long long plane, pitch;  // elements per row of the state; per grid line
+    int nx, ny, rows;
+    int solve;               // index of the solve whose initial rate it sets (-1: copy only)
+};
+// Cells [c0, c0 + kMoveChunk) of move `move`: one workgroup each.
+struct MoveChunk {
+    int move, c0;
+};
+constexpr int kMoveChunk = 2048;
+// A solve entering the batch: its descriptor and its slot's initial state.
+struct AdmitInit {
+    DevSolve S;
+    double t_end, cfl;
+    long long nsteps;
+    int idx, pad;
+};
+// Descriptors into solves[], fresh slots; then the moves (after the
+// descriptors: a moving state's rate reads its solve's descriptor).
+hipError_t launch_admit_init(const AdmitInit *inits, int n, DevSolve *solves, hipStream_t st);
+hipError_t launch_moves(const StateMove *moves, const MoveChunk *chunks, int nchunks, const DevSolve *solves,
+                        hipStream_t st);
+
 // Tile shapes of the stage kernel: 0 = 32x15 cells / 256 threads,
 // 1 = 16x15 / 128, 2 = 8x7 / 64.
 void tile_shape(int shape, int *tx, int *ty);
