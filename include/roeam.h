@@ -228,8 +228,9 @@ roeam_status roeam_grid_tile_shape(const roeam_grid *grid, const roeam_params *p
  * Roe-AM flux of Eq. (85) (Sec. 2.2: finite-volume cell faces).
  * q: device, state layout, read only; r: device, state layout, written.
  * max_rate_out: nullable DEVICE pointer to one double that receives the
- * largest explicit rate of q (time-step rule above).  Asynchronous.
- * EINVAL: NULL q/r, bad params; EDEVICE. */
+ * largest explicit rate of q (time-step rule above).  Runs the grid's set
+ * tile shape, else the one tuned for these parameters, else 16x15/256 (it
+ * does not tune).  Asynchronous.  EINVAL: NULL q/r, bad params; EDEVICE. */
 roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *grid, const roeam_params *params,
                             const double *q, double *r, double *max_rate_out);
 

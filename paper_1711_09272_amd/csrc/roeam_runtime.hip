@@ -403,7 +403,10 @@ roeam_status roeam_residual(roeam_ctx *ctx, const roeam_grid *g, const roeam_par
     if (st) return st;
     HIP_OK(ctx, hipSetDevice(ctx->device));
     DevSolve S = make_solve(g, p, const_cast<double *>(q));
-    const int shape = g->shape_forced >= 0 ? g->shape_forced : 0;
+    // the caller's shape, else the one tuned for these parameters, else
+    // 16x15/256 (the fastest from 512^2 up); every shape gives the same bits
+    const int tuned = g->shape_tuned[p->order - 1][p->precision];
+    const int shape = g->shape_forced >= 0 ? g->shape_forced : (tuned >= 0 ? tuned : 6);
     roeam_grid *gm = const_cast<roeam_grid *>(g);
     HIP_OK(ctx, upload_solve(gm, S, ctx->stream));
     if (max_rate_out) HIP_OK(ctx, roeam::launch_slot_init(g->d_slot, 1, 0.0, 0.0, p->cfl, 0, ctx->stream));
