@@ -333,12 +333,15 @@ roeam_status roeam_grid3d_set_scalars(roeam_grid3d *grid, int nscalars, const do
  * the current one).  10-12: z-marching column tiles of 16x15 cells with 256
  * threads, each workgroup walking a run of 4 (10), 8 (11) or 16 (12)
  * planes upward with one plane and its x-y halo in LDS while the next
- * plane's footprint loads into registers (three workgroups per CU).  -1
+ * plane's footprint loads into registers (three workgroups per CU); 13: the
+ * same with every tile's height cut into as many equal runs as one round of
+ * workgroups allows (not chosen by default: faster at 128^3, but it reads
+ * more, and larger grids leave part of the round empty).  -1
  * (default): the z-marching shape with the longest run whose workgroups
  * still number at least nine per CU of the device (else runs of 4).  Every
  * shape computes bitwise the same result.  With two transported scalars the
  * 16x8x4 bricks (2, 6, 8) exceed the LDS of a workgroup; such a grid runs
- * shape 9 instead.  EINVAL: shape outside -1..12. */
+ * shape 9 instead.  EINVAL: shape outside -1..13. */
 roeam_status roeam_grid3d_set_tile_shape(roeam_grid3d *grid, int shape);
 /* The shape the stage kernel runs with for MUSCL order `order` (1 or 2),
  * the default's choice and the scalar fallback applied.  EINVAL: NULL

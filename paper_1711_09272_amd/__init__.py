@@ -38,8 +38,9 @@ EXPORTS = [
 # 3-D stage-kernel brick shapes: cells x cells x cells / threads per workgroup
 SHAPES3 = ["8x8x4/256", "8x4x4/128", "16x8x4/512", "16x4x4/256", "8x8x4/320", "8x4x4/192", "16x8x4/640",
            "8x8x8/576", "16x8x4/512p", "8x8x8/512p",  # p: persistent, prefetching the next brick's halo
-           # z: z-marching column tiles TX x TY walking runs of TZ planes
-           "16x15z4/256", "16x15z8/256", "16x15z16/256"]
+           # z: z-marching column tiles TX x TY walking runs of TZ planes (z*: one round of workgroups,
+           # each tile's height cut into balanced runs)
+           "16x15z4/256", "16x15z8/256", "16x15z16/256", "16x15z*/256"]
 
 
 class RoeamError(RuntimeError):

@@ -52,7 +52,7 @@ int zmarch_auto_shape(int nx, int ny, int nz, int cus)
     int best = -1, best_tz = 0, shortest = -1, shortest_tz = 1 << 30;
     for (int s = 0; s < kNumShapes3; ++s) {
         const BrickShape &sh = kShapes3[s];
-        if (sh.persistent != 2) continue;
+        if (sh.persistent != 2 || sh.tz <= 0) continue;  // fixed-length runs only
         const long long wgs = (long long)((nx + sh.tx - 1) / sh.tx) * ((ny + sh.ty - 1) / sh.ty) * ((nz + sh.tz - 1) / sh.tz);
         if (wgs >= 9ll * cus && sh.tz > best_tz) best = s, best_tz = sh.tz;
         if (sh.tz < shortest_tz) shortest = s, shortest_tz = sh.tz;

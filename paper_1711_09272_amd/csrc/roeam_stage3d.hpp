@@ -877,18 +877,36 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
     const DevSolve3 &S = *Sp;
     __shared__ ZStageLds<ORDER, NSC, TX, TY, NT> L;
     const int tid = threadIdx.x;
-    const int ntx = (S.nx + TX - 1) / TX, nty = (S.ny + TY - 1) / TY, nzc = (S.nz + zc - 1) / zc;
-    const int nb = ntx * nty * nzc;
+    const int ntx = (S.nx + TX - 1) / TX, nty = (S.ny + TY - 1) / TY, nt = ntx * nty;
     // runs numbered column tile fastest: each XCD takes a slab of whole
     // layers of runs, so the runs it holds at once are x- and y-neighbours at
     // the same height (their shared halo lines are read from its L2 once)
     // and a run's successor above starts as it ends (the planes they share
     // are still in that L2)
-    const int t = xcd_tile(blockIdx.x, nb);
-    if (t >= nb) return;
-    const int ct = t % (ntx * nty);
+    int ct, z0, z1, t;
+    if (zc > 0) {
+        // runs of zc planes
+        const int nb = nt * ((S.nz + zc - 1) / zc);
+        t = xcd_tile(blockIdx.x, nb);
+        if (t >= nb) return;
+        ct = t % nt;
+        z0 = (t / nt) * zc;
+        z1 = min(z0 + zc, S.nz);
+    } else {
+        // -zc runs in all (nt <= -zc <= nt nz): every tile takes q or q + 1
+        // of them (the first -zc mod nt tiles the extra one) and its height
+        // is cut into its runs as evenly as whole planes allow; layer k holds
+        // the k-th run of every tile that has one
+        const int nb = -zc, q = nb / nt, rem = nb % nt;
+        t = xcd_tile(blockIdx.x, nb);
+        if (t >= nb) return;
+        const int k = t < q * nt ? t / nt : q;
+        ct = t < q * nt ? t % nt : t - q * nt;
+        const int runs = q + (ct < rem ? 1 : 0);
+        z0 = (int)((long long)S.nz * k / runs);
+        z1 = (int)((long long)S.nz * (k + 1) / runs);
+    }
     const int i0 = (ct % ntx) * TX, j0 = (ct / ntx) * TY;
-    const int z0 = (t / (ntx * nty)) * zc, z1 = min(z0 + zc, S.nz);
     const double *__restrict__ qin = stage_input3(S, stage);
     Slot &z = *S.slot;
     const StepWords sw = stage > 0 ? load_step_words(z, p, stage) : StepWords{};
@@ -1042,7 +1060,9 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
 // axis), so each sweep is a single pass; 8 and 9 are persistent (form 1:
 // resident workgroups that prefetch the next brick's halo into registers;
 // 512 threads leave room for them).  Form 2 is the z-marching kernel on
-// TX x TY column tiles with runs of TZ planes (three waves per SIMD).
+// TX x TY column tiles with runs of TZ planes (three waves per SIMD); TZ = 0:
+// one round of workgroups (as many as the GPU holds at once), each tile's
+// height cut into balanced runs.
 #define ROEAM_SHAPES3(X)      \
     X(0, 8, 8, 4, 256, 0)     \
     X(1, 8, 4, 4, 128, 0)     \
@@ -1056,7 +1076,8 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
     X(9, 8, 8, 8, 512, 1)     \
     X(10, 16, 15, 4, 256, 2)  \
     X(11, 16, 15, 8, 256, 2)  \
-    X(12, 16, 15, 16, 256, 2)
+    X(12, 16, 15, 16, 256, 2) \
+    X(13, 16, 15, 0, 256, 2)
 
 struct BrickShape {
     int tx, ty, tz, nt, persistent;  // form: 0 brick, 1 persistent brick, 2 z-marching
@@ -1067,10 +1088,10 @@ static const BrickShape kShapes3[] = {ROEAM_SHAPES3(ROEAM_SHAPE3_ENTRY)};
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
 // Workgroups of a persistent kernel: as many as the GPU holds at once (CUs
-// times workgroups per CU from the occupancy query, cached per device), a
-// multiple of 8, and no more than the bricks need.
-template <class K>
-static int persistent_blocks(K kernel, int nt, long long nb)
+// times workgroups per CU from the occupancy query, cached per kernel and
+// device), a multiple of 8, and no more than the bricks need.
+template <auto Kernel>
+static int persistent_blocks(int nt, long long nb)
 {
     constexpr int kMaxDevices = 64;
     static int cached[kMaxDevices];  // 0: not queried yet
@@ -1079,7 +1100,7 @@ static int persistent_blocks(K kernel, int nt, long long nb)
     if (cached[dev] == 0) {
         int cus = 0, per_cu = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), nt, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(Kernel), nt, 0) !=
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -1097,20 +1118,34 @@ constexpr long long shape3_lds_bytes(int order, int nsc, int tx, int ty, int tz,
 }
 
 template <int ORDER, int PREC, int NSC, int TX, int TY, int TZ, int NT, int PE>
-static hipError_t launch3_one(const DevSolve3 *dS, long long nb, int stage, int p, int last, double *r_out,
-                              hipStream_t st)
+static hipError_t launch3_one(const DevSolve3 *dS, const DevSolve3 &S, long long nb, int stage, int p, int last,
+                              double *r_out, hipStream_t st)
 {
     if constexpr (shape3_lds_bytes(ORDER, NSC, TX, TY, TZ, NT, PE) > kLdsBytes3) {
         return hipErrorInvalidValue;
     } else if constexpr (PE == 2) {
-        // one workgroup per run of TZ planes of a column tile
-        const int blocks = (int)(((nb + 7) >> 3) << 3);
+        // one workgroup per run of TZ planes of a column tile; TZ = 0: the same
+        // number of runs for every tile, as many as the GPU holds workgroups
+        // at once allows (at least one, and runs no shorter than four planes
+        // where the grid allows)
+        int zc = TZ;
+        long long runs = nb;
+        if constexpr (TZ == 0) {
+            const long long nt = (long long)((S.nx + TX - 1) / TX) * ((S.ny + TY - 1) / TY);
+            const long long per_tile_max = S.nz >= 8 ? S.nz / 4 : 1;
+            const long long slots = persistent_blocks<k_stage3z<ORDER, PREC, NSC, TX, TY, NT>>(NT, nt * per_tile_max);
+            long long per_tile = slots / nt;
+            per_tile = per_tile < 1 ? 1 : (per_tile > per_tile_max ? per_tile_max : per_tile);
+            runs = nt * per_tile;
+            zc = (int)-runs;
+        }
+        const int blocks = (int)(((runs + 7) >> 3) << 3);
         hipLaunchKernelGGL((k_stage3z<ORDER, PREC, NSC, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, dS, stage, p,
-                           last, r_out, TZ);
+                           last, r_out, zc);
         return hipSuccess;
     } else if constexpr (PE) {
         auto kernel = k_stage3p<ORDER, PREC, NSC, TX, TY, TZ, NT>;
-        const int blocks = persistent_blocks(kernel, NT, nb);
+        const int blocks = persistent_blocks<k_stage3p<ORDER, PREC, NSC, TX, TY, TZ, NT>>(NT, nb);
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(NT), 0, st, dS, stage, p, last, r_out);
         return hipSuccess;
     } else {
@@ -1126,9 +1161,11 @@ static hipError_t launch3_shape(const DevSolve3 *dS, const DevSolve3 &S, int sha
                                 double *r_out, hipStream_t st)
 {
     const BrickShape &sh = kShapes3[shape];
-    const long long nb = (long long)((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty) * ((S.nz + sh.tz - 1) / sh.tz);
+    const long long nb = sh.tz > 0 ? (long long)((S.nx + sh.tx - 1) / sh.tx) * ((S.ny + sh.ty - 1) / sh.ty) *
+                                         ((S.nz + sh.tz - 1) / sh.tz)
+                                   : 0;
 #define ROEAM_SHAPE3_CASE(ID, TX, TY, TZ, NT, PE) \
-    case ID: return launch3_one<ORDER, PREC, NSC, TX, TY, TZ, NT, PE>(dS, nb, stage, p, last, r_out, st);
+    case ID: return launch3_one<ORDER, PREC, NSC, TX, TY, TZ, NT, PE>(dS, S, nb, stage, p, last, r_out, st);
     switch (shape) { ROEAM_SHAPES3(ROEAM_SHAPE3_CASE) }
 #undef ROEAM_SHAPE3_CASE
     return hipErrorInvalidValue;

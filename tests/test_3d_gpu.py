@@ -165,7 +165,7 @@ def test_default_shape_follows_the_grid_size(C):
     import torch
     import paper_1711_09272_amd as P
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    runs = {k: int(name.split("z")[1].split("/")[0]) for k, name in enumerate(SHAPES3) if "z" in name}
+    runs = {k: int(name.split("z")[1].split("/")[0]) for k, name in enumerate(SHAPES3) if "z" in name and "*" not in name}
 
     def expected(n, nz):
         tiles = -(-n // 16) * -(-n // 15)
