@@ -3,6 +3,7 @@
 // graph-captured step loop (same step state and stage codes as 2-D grids).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -37,14 +38,14 @@ struct roeam_grid3d {
 static int device_cus(int dev)
 {
     constexpr int kMaxDevices = 64;
-    static int cached[kMaxDevices];  // 0: not queried yet
+    static std::atomic<int> cached[kMaxDevices];  // 0: not queried yet (threads may race to fill it alike)
     if (dev < 0 || dev >= kMaxDevices) return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-        cached[dev] = cus;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+        cached[dev].store(v, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return v;
 }
 
 // Shape the stage kernel runs with: the grid's; by default the z-marching

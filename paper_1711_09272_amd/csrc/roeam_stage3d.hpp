@@ -14,6 +14,7 @@
 // state).  One kernel per Runge-Kutta stage.
 #pragma once
 
+#include <atomic>
 #include <type_traits>
 
 #include "roeam_device3d.hpp"
@@ -1094,19 +1095,21 @@ template <auto Kernel>
 static int persistent_blocks(int nt, long long nb)
 {
     constexpr int kMaxDevices = 64;
-    static int cached[kMaxDevices];  // 0: not queried yet
+    static std::atomic<int> cached[kMaxDevices];  // 0: not queried yet (threads may race to fill it alike)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
-    if (cached[dev] == 0) {
+    int held = cached[dev].load(std::memory_order_relaxed);
+    if (held == 0) {
         int cus = 0, per_cu = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(Kernel), nt, 0) !=
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        cached[dev] = cus * per_cu;
+        held = cus * per_cu;
+        cached[dev].store(held, std::memory_order_relaxed);
     }
-    const long long want = nb < cached[dev] ? nb : cached[dev];
+    const long long want = nb < held ? nb : held;
     return (int)(((want + 7) >> 3) << 3);
 }
 
