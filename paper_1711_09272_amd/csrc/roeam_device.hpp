@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace roeam {
 
 // BC_MOVING (uniform grids): the side's Dirichlet state where the cell-centre
@@ -465,24 +467,43 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     const double rR = WR[0], uR = WR[1], vR = WR[2], pR = WR[3];
 
     // side quantities, Eq. (4); H = gamma/(gamma-1) p/rho + |V|^2/2
-    const double iL = rcp_nr(rL), iR = rcp_nr(rR);
     const double qL = uL * uL + vL * vL, qR = uR * uR + vR * vR;
     const double UL = AXIS ? uL : nx * uL + ny * vL, UR = AXIS ? uR : nx * uR + ny * vR;
-    const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
-    const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
-    const double PsiL1 = rL * uL, PsiL2 = rL * vL, PsiL3 = rL * HL;
-    const double PsiR1 = rR * uR, PsiR2 = rR * vR, PsiR3 = rR * HR;
+    const double PsiL1 = rL * uL, PsiL2 = rL * vL;
+    const double PsiR1 = rR * uR, PsiR2 = rR * vR;
+    double PsiL3, PsiR3;   // rho H, FP64 (central flux and jump)
+    R iLr, iRr, HLr, HRr;  // 1/rho and H of the sides, for the coefficients
+    if constexpr (std::is_same<R, float>::value) {
+        // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 needs no 1/rho, so the
+        // reciprocals feed only the FP32 coefficients and are taken in FP32
+        PsiL3 = S.g_gm1 * pL + 0.5 * rL * qL;
+        PsiR3 = S.g_gm1 * pR + 0.5 * rR * qR;
+        iLr = rcpR((R)rL);
+        iRr = rcpR((R)rR);
+        HLr = (R)PsiL3 * iLr;
+        HRr = (R)PsiR3 * iRr;
+    } else {
+        const double iL = rcp_nr(rL), iR = rcp_nr(rR);
+        const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
+        const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
+        PsiL3 = rL * HL;
+        PsiR3 = rR * HR;
+        iLr = iL;
+        iRr = iR;
+        HLr = HL;
+        HRr = HR;
+    }
 
     // jumps stay FP64 (low-Mach pressure differences cancel otherwise)
     const double dUd = UR - UL, dpd = pR - pL;
 
     // Roe averages (sqrt(rho) weights)
-    const R rr = sqrtR((R)(rR * iL));
+    const R rr = sqrtR((R)rR * iLr);
     const R w1 = rcpR((R)1 + rr);
     const R rho = rr * (R)rL;
     const R u = ((R)uL + rr * (R)uR) * w1;
     const R v = ((R)vL + rr * (R)vR) * w1;
-    const R H = ((R)HL + rr * (R)HR) * w1;
+    const R H = (HLr + rr * HRr) * w1;
     const R c2 = (R)S.gm1 * (H - (R)0.5 * (u * u + v * v));
     const R ic = rsqR(c2);
     const R c = c2 * ic;
@@ -492,7 +513,9 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
 
 
     // Mach numbers, Eqs. (93)-(94): M_K = |V_K| / c_K, c_K^2 = gamma p_K / rho_K
-    const R c2L = (R)(S.gamma * pL * iL), c2R = (R)(S.gamma * pR * iR);
+    constexpr bool F32 = std::is_same<R, float>::value;
+    const R c2L = F32 ? (R)S.gamma * (R)pL * iLr : (R)(S.gamma * pL * iLr);
+    const R c2R = F32 ? (R)S.gamma * (R)pR * iRr : (R)(S.gamma * pR * iRr);
     const R icLR = rcpR(c2L * c2R);
     const R M = (R)0.5 * (sqrt0R((R)qL * c2R * icLR) + sqrt0R((R)qR * c2L * icLR));
     const R absU = rabs(U);
@@ -526,7 +549,10 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     if (S.eps1 != 0.0) {
         // modified entropy fix f_ef (Eq. 102) and rotated speed f_rr (Eqs. 103-109)
         const R fef = (R)S.eps2 * c;
-        const R du = (R)(uR - uL), dv = (R)(vR - vL);
+        // the velocity jumps only steer n1 (Eq. 103): FP32 differences of the
+        // rounded velocities suffice there
+        const R du = F32 ? (R)uR - (R)uL : (R)(uR - uL);
+        const R dv = F32 ? (R)vR - (R)vL : (R)(vR - vL);
         const R dV2 = du * du + dv * dv;
         const bool use_n = dV2 < (R)S.dv_min2 || dV2 == (R)0;
         const R idV = rsqR(use_n ? (R)1 : dV2);

@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "roeam_device.hpp"
 
 namespace roeam {
@@ -205,22 +207,42 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     const double rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
 
     // side quantities, Eq. (4); U_L = u_L, U_R = u_R in the face frame
-    const double iL = rcp_nr(rL), iR = rcp_nr(rR);
     const double qL = uL * uL + vL * vL + wL * wL, qR = uR * uR + vR * vR + wR * wR;
-    const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
-    const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
-    const double PL1 = rL * uL, PL2 = rL * vL, PL3 = rL * wL, PL4 = rL * HL;
-    const double PR1 = rR * uR, PR2 = rR * vR, PR3 = rR * wR, PR4 = rR * HR;
+    const double PL1 = rL * uL, PL2 = rL * vL, PL3 = rL * wL;
+    const double PR1 = rR * uR, PR2 = rR * vR, PR3 = rR * wR;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    double PL4, PR4;       // rho H, FP64 (central flux and jump)
+    R iLr, iRr, HLr, HRr;  // 1/rho and H of the sides, for the coefficients
+    if constexpr (F32) {
+        // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 needs no 1/rho, so the
+        // reciprocals feed only the FP32 coefficients and are taken in FP32
+        PL4 = S.g_gm1 * pL + 0.5 * rL * qL;
+        PR4 = S.g_gm1 * pR + 0.5 * rR * qR;
+        iLr = rcpR((R)rL);
+        iRr = rcpR((R)rR);
+        HLr = (R)PL4 * iLr;
+        HRr = (R)PR4 * iRr;
+    } else {
+        const double iL = rcp_nr(rL), iR = rcp_nr(rR);
+        const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
+        const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
+        PL4 = rL * HL;
+        PR4 = rR * HR;
+        iLr = iL;
+        iRr = iR;
+        HLr = HL;
+        HRr = HR;
+    }
     const double dUd = uR - uL, dpd = pR - pL;
 
     // Roe averages
-    const R rr = sqrtR((R)(rR * iL));
+    const R rr = sqrtR((R)rR * iLr);
     const R w1 = rcpR((R)1 + rr);
     const R rho = rr * (R)rL;
     const R u = ((R)uL + rr * (R)uR) * w1;
     const R v = ((R)vL + rr * (R)vR) * w1;
     const R w = ((R)wL + rr * (R)wR) * w1;
-    const R H = ((R)HL + rr * (R)HR) * w1;
+    const R H = (HLr + rr * HRr) * w1;
     const R c2 = (R)S.gm1 * (H - (R)0.5 * (u * u + v * v + w * w));
     const R ic = rsqR(c2);
     const R c = c2 * ic;
@@ -229,7 +251,8 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     const R s1 = (R)s1d;
 
     // Mach numbers, Eqs. (93)-(94)
-    const R c2L = (R)(S.gamma * pL * iL), c2R = (R)(S.gamma * pR * iR);
+    const R c2L = F32 ? (R)S.gamma * (R)pL * iLr : (R)(S.gamma * pL * iLr);
+    const R c2R = F32 ? (R)S.gamma * (R)pR * iRr : (R)(S.gamma * pR * iRr);
     const R icLR = rcpR(c2L * c2R);
     const R M = (R)0.5 * (sqrt0R((R)qL * c2R * icLR) + sqrt0R((R)qR * c2L * icLR));
     const R absU = rabs(U);
@@ -265,7 +288,10 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
         // alpha2 U2 = ((n1 x n) x n1) . V, which for n = e_1 and unit n1 is
         // (n1y^2 + n1z^2) u - n1x (n1y v + n1z w).
         const R fef = (R)S.eps2 * c;
-        const R du = (R)(uR - uL), dv = (R)(vR - vL), dw = (R)(wR - wL);
+        // the velocity jumps only steer n1 (Eq. 103)
+        const R du = F32 ? (R)uR - (R)uL : (R)(uR - uL);
+        const R dv = F32 ? (R)vR - (R)vL : (R)(vR - vL);
+        const R dw = F32 ? (R)wR - (R)wL : (R)(wR - wL);
         const R dV2 = du * du + dv * dv + dw * dw;
         const bool use_n = dV2 < (R)S.dv_min2 || dV2 == (R)0;
         const R idV = rsqR(use_n ? (R)1 : dV2);
