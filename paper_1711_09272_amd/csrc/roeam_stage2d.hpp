@@ -412,18 +412,24 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     }
 }
 
-// Minimum waves per SIMD asked of the register allocator: the uniform-grid
-// kernels of the one-pass 256-thread shapes fit five waves in 96 VGPRs with a
-// few spilled dwords (FP32 coefficients one, FP64 five), measured faster than
-// four waves without spills (FP64: 1-3% at 512^2 and 2048^2); the node-grid
-// ones and those with scalars keep the default.
-constexpr int stage_min_waves(int prec, int metric, int nt, bool split, int nsc)
+// Minimum waves per SIMD asked of the register allocator, for the uniform-grid
+// kernels of the one-pass 256-thread shapes without scalars: FP64 five (96
+// VGPRs; measured faster than four, 1-3% at 512^2 and 2048^2; six spills forty
+// dwords and loses 8-40%); FP32 coefficients six where the tile's LDS (25 KB
+// for 240 cells or fewer) lets six workgroups share a CU: 80 VGPRs, six dwords
+// spilled, 3.5% faster than five waves on the 256-grid batch and at 2048^2.
+// The persistent batched form keeps five (it spills more); the node-grid
+// kernels and those with scalars keep the default.
+constexpr int stage_min_waves(int prec, int metric, int tx, int ty, int nt, bool split, int nsc,
+                              bool persistent = false)
 {
-    return (prec >= 0 && metric == 0 && nt == 256 && !split && nsc == 0) ? 5 : 1;
+    return (metric == 0 && nt == 256 && !split && nsc == 0)
+               ? ((prec == 1 && tx * ty <= 240 && !persistent) ? 6 : 5)
+               : 1;
 }
 
 template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
+__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, TX, TY, NT, SPLIT, NSC)) void k_stage_single(const DevSolve *__restrict__ Sp, int stage, int p, int last,
                                                      double *r_out)
 {
     const DevSolve &S = *Sp;
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) 
 // graph serves any count up to it; the XCD-aware map (xcd_tile) spreads the
 // first ceil(count / 8) * 8 workgroups over the tiles and the rest exit.
 template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) void k_stage_batch(const DevSolve *__restrict__ solves,
+__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, TX, TY, NT, SPLIT, NSC)) void k_stage_batch(const DevSolve *__restrict__ solves,
                                                     const TileEntry *__restrict__ tiles, const int *__restrict__ count,
                                                     int stage, int p, int last)
 {
@@ -458,7 +464,7 @@ __global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) 
 // band [x c, (x + 1) c), c = ceil(count / 8), so that neighbouring tiles share
 // that XCD's L2.
 template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
-__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, NT, SPLIT, NSC)) void k_stage_batch_p(const DevSolve *__restrict__ solves,
+__global__ __launch_bounds__(NT, stage_min_waves(PREC, METRIC, TX, TY, NT, SPLIT, NSC, true)) void k_stage_batch_p(const DevSolve *__restrict__ solves,
                                                     const TileEntry *__restrict__ tiles, const int *__restrict__ count,
                                                     int stage, int p, int last)
 {
