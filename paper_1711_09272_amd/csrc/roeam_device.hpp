@@ -585,31 +585,34 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     }
     const R dUu = (R)0.5 * sU * mUc * dU * ic;
 
-    // Eq. (85): F = central - (1/2){xi dPsi + (dpp + dpu)(0, n, 0) + dUp PsiHat + dUu (Psi_R + Psi_L)}
-    const double xid = (double)xi, pd = (double)(dpp + dpu), dUpd = (double)dUp, dUud = (double)dUu;
-    const double rhod = (double)rho;
-    F[0] = 0.5 * (UL * rL + UR * rR) - 0.5 * (xid * (rR - rL) + dUpd * rhod + dUud * (rR + rL));
+    // Eq. (85): F = central - (1/2){xi dPsi + (dpp + dpu)(0, n, 0) + dUp PsiHat + dUu (Psi_R + Psi_L)}.
+    // Each row's side terms are gathered per side, U_L Psi_L + U_R Psi_R -
+    // xi (Psi_R - Psi_L) - dUu (Psi_R + Psi_L) = aL Psi_L + aR Psi_R with
+    // aL = U_L + xi - dUu and aR = U_R - xi - dUu, and the Psi^ term is
+    // (dUp rho^) times (1, u^, v^, H^)
+    // (xi and dUu are widened to FP64 before they are combined: with FP32
+    // coefficients their rounding then enters as in Eq. (85) written out,
+    // times the jump Psi_R - Psi_L, and not times Psi itself)
+    const double xid = (double)xi, dUud = (double)dUu;
+    const double aL = UL + (xid - dUud), aR = UR - (xid + dUud);
+    const R g = dUp * rho;
+    const double pc = (pL + pR) - (double)(dpp + dpu);
+    F[0] = 0.5 * fma(rR, aR, fma(rL, aL, -(double)g));
     if (AXIS) {
-        F[1] = 0.5 * ((UL * PsiL1 + pL) + (UR * PsiR1 + pR))
-             - 0.5 * (xid * (PsiR1 - PsiL1) + pd + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
-        F[2] = 0.5 * (UL * PsiL2 + UR * PsiR2)
-             - 0.5 * (xid * (PsiR2 - PsiL2) + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+        F[1] = 0.5 * fma(PsiR1, aR, fma(PsiL1, aL, pc - (double)(g * u)));
     } else {
-        F[1] = 0.5 * ((UL * PsiL1 + pL * nx) + (UR * PsiR1 + pR * nx))
-             - 0.5 * (xid * (PsiR1 - PsiL1) + pd * nx + dUpd * (rhod * (double)u) + dUud * (PsiR1 + PsiL1));
-        F[2] = 0.5 * ((UL * PsiL2 + pL * ny) + (UR * PsiR2 + pR * ny))
-             - 0.5 * (xid * (PsiR2 - PsiL2) + pd * ny + dUpd * (rhod * (double)v) + dUud * (PsiR2 + PsiL2));
+        F[1] = 0.5 * fma(PsiR1, aR, fma(PsiL1, aL, fma(pc, nx, -(double)(g * u))));
     }
-    F[3] = 0.5 * (UL * PsiL3 + UR * PsiR3)
-         - 0.5 * (xid * (PsiR3 - PsiL3) + dUpd * (rhod * (double)H) + dUud * (PsiR3 + PsiL3));
+    F[2] = 0.5 * fma(PsiR2, aR, fma(PsiL2, aL, AXIS ? -(double)(g * v) : fma(pc, ny, -(double)(g * v))));
+    F[3] = 0.5 * fma(PsiR3, aR, fma(PsiL3, aL, -(double)(g * H)));
     // transported scalars (rho k rows of Eq. 85): Psi = rho k, Psi^ = rho^ k^
     // with the Roe average of k, no pressure term
 #pragma unroll
     for (int m = 0; m < NSC; ++m) {
         const double kL = WL[4 + m], kR = WR[4 + m];
         const double PL = rL * kL, PR = rR * kR;
-        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
-        F[4 + m] = 0.5 * (UL * PL + UR * PR) - 0.5 * (xid * (PR - PL) + dUpd * (rhod * khat) + dUud * (PR + PL));
+        const R khat = ((R)kL + rr * (R)kR) * w1;
+        F[4 + m] = 0.5 * fma(PR, aR, fma(PL, aL, -(double)(g * khat)));
     }
 }
 

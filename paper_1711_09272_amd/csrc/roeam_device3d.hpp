@@ -320,22 +320,29 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     }
     const R dUu = (R)0.5 * sU * mUc * dU * ic;
 
-    // Eq. (85)
-    const double xid = (double)xi, pd = (double)(dpp + dpu), dUpd = (double)dUp, dUud = (double)dUu;
-    const double rhod = (double)rho;
-    F[0] = 0.5 * (uL * rL + uR * rR) - 0.5 * (xid * (rR - rL) + dUpd * rhod + dUud * (rR + rL));
-    F[1] = 0.5 * ((uL * PL1 + pL) + (uR * PR1 + pR))
-         - 0.5 * (xid * (PR1 - PL1) + pd + dUpd * (rhod * (double)u) + dUud * (PR1 + PL1));
-    F[2] = 0.5 * (uL * PL2 + uR * PR2) - 0.5 * (xid * (PR2 - PL2) + dUpd * (rhod * (double)v) + dUud * (PR2 + PL2));
-    F[3] = 0.5 * (uL * PL3 + uR * PR3) - 0.5 * (xid * (PR3 - PL3) + dUpd * (rhod * (double)w) + dUud * (PR3 + PL3));
-    F[4] = 0.5 * (uL * PL4 + uR * PR4) - 0.5 * (xid * (PR4 - PL4) + dUpd * (rhod * (double)H) + dUud * (PR4 + PL4));
+    // Eq. (85), each row's side terms gathered per side: u_L Psi_L + u_R Psi_R -
+    // xi (Psi_R - Psi_L) - dUu (Psi_R + Psi_L) = aL Psi_L + aR Psi_R with
+    // aL = u_L + xi - dUu, aR = u_R - xi - dUu; the Psi^ term is (dUp rho^)
+    // times (1, u^, v^, w^, H^)
+    // (xi and dUu are widened to FP64 before they are combined: with FP32
+    // coefficients their rounding then enters as in Eq. (85) written out,
+    // times the jump Psi_R - Psi_L, and not times Psi itself)
+    const double xid = (double)xi, dUud = (double)dUu;
+    const double aL = uL + (xid - dUud), aR = uR - (xid + dUud);
+    const R g = dUp * rho;
+    const double pc = (pL + pR) - (double)(dpp + dpu);
+    F[0] = 0.5 * fma(rR, aR, fma(rL, aL, -(double)g));
+    F[1] = 0.5 * fma(PR1, aR, fma(PL1, aL, pc - (double)(g * u)));
+    F[2] = 0.5 * fma(PR2, aR, fma(PL2, aL, -(double)(g * v)));
+    F[3] = 0.5 * fma(PR3, aR, fma(PL3, aL, -(double)(g * w)));
+    F[4] = 0.5 * fma(PR4, aR, fma(PL4, aL, -(double)(g * H)));
     // transported scalars: Psi = rho k, Psi^ = rho^ k^ (Roe average of k), no pressure term
 #pragma unroll
     for (int m = 0; m < NSC; ++m) {
         const double kL = WL[5 + m], kR = WR[5 + m];
         const double PL = rL * kL, PR = rR * kR;
-        const double khat = (double)(((R)kL + rr * (R)kR) * w1);
-        F[5 + m] = 0.5 * (uL * PL + uR * PR) - 0.5 * (xid * (PR - PL) + dUpd * (rhod * khat) + dUud * (PR + PL));
+        const R khat = ((R)kL + rr * (R)kR) * w1;
+        F[5 + m] = 0.5 * fma(PR, aR, fma(PL, aL, -(double)(g * khat)));
     }
 }
 

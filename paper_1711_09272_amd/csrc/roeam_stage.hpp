@@ -11,10 +11,11 @@
 namespace roeam {
 
 // minmod(a, b): 0 when the slopes differ in sign, else the one nearer zero,
-// written as max(0, min(a, b)) + min(0, max(a, b)) (four min/max and an add).
+// which is the median of a, b and 0: max(min(a, b), min(max(a, b), 0)) (four
+// min/max).
 __device__ __forceinline__ double minmod(double a, double b)
 {
-    return rmax(0.0, rmin(a, b)) + rmin(0.0, rmax(a, b));
+    return rmax(rmin(a, b), rmin(rmax(a, b), 0.0));
 }
 
 template <int NT>

@@ -418,14 +418,17 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
 // dwords and loses 8-40%); FP32 coefficients six where the tile's LDS (25 KB
 // for 240 cells or fewer) lets six workgroups share a CU: 80 VGPRs, six dwords
 // spilled, 3.5% faster than five waves on the 256-grid batch and at 2048^2.
-// The persistent batched form keeps five (it spills more); the node-grid
+// Tiles of more cells (32x15: 47 KB of LDS) fit three workgroups per CU, so
+// three is asked there (the persistent batched form of those takes what the
+// allocator chooses: two waves without spills). The persistent batched form
+// of the smaller tiles keeps five (it spills more at six); the node-grid
 // kernels and those with scalars keep the default.
 constexpr int stage_min_waves(int prec, int metric, int tx, int ty, int nt, bool split, int nsc,
                               bool persistent = false)
 {
-    return (metric == 0 && nt == 256 && !split && nsc == 0)
-               ? ((prec == 1 && tx * ty <= 240 && !persistent) ? 6 : 5)
-               : 1;
+    if (metric != 0 || nt != 256 || split || nsc != 0) return 1;
+    if (tx * ty > 240) return persistent ? 1 : 3;
+    return (prec == 1 && !persistent) ? 6 : 5;
 }
 
 template <int ORDER, int PREC, int METRIC, int TX, int TY, int NT, bool SPLIT, int NSC>
