@@ -175,6 +175,14 @@ template <typename R> __device__ __forceinline__ R pow8(R x)
     R x4 = x2 * x2;
     return x4 * x4;
 }
+// The detector's s1 = f^8(a), Eq. (95), from the face's smallest ratio a,
+// taken in the precision of the dissipation coefficients it scales (PREC 1:
+// FP32; the value is then exact in FP32 when the flux narrows it).
+template <int PREC> __device__ __forceinline__ double detector_s1(double a)
+{
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    return (double)pow8(fswitch((R)a));
+}
 
 // Global-memory views of the state and metric arrays.  The descriptor holds
 // generic pointers; accesses through these views are global_* instructions
@@ -526,10 +534,11 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     // preconditioning, Eqs. (99)-(101)
     const R theta = rmin(rmax((R)S.mr2, M * M), (R)1);
     const R omt = (R)1 - theta;
-    const R X = (R)4 * c2 * theta + omt * omt * U * U;
+    const R omtU = omt * U;
+    const R X = omtU * omtU + (R)4 * c2 * theta;
     const R rX = rsqR(X);
     const R ct = (R)0.5 * X * rX;  // c~ of Eq. (99)
-    const R U_2ct = U * rX;        // U / (2 c~)
+    const R aU_2ct = absU * rX;    // |U| / (2 c~)
     const R Ut = (R)0.5 * ((R)1 + theta) * U;
 
     // expansion-shock fix, Eq. (92); sign(U + c) - sign(U - c) is 2 for |U| < c,
@@ -571,9 +580,11 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     // Eqs. (87)-(91)
     const R sU = sgn(U);
     const R mUc = rmin(absUp, c);
-    const R dpp = sU * mUc * dp * ic;
+    const R sMc = sU * mUc * ic;  // sgn(U) min(|U|', c^) / c^, shared by dpp and dUu
+    const R dpp = sMc * dp;
     const R dpu = ((R)1 - s1 + s1 * fM) * rmax((R)0, c - absUp) * rho * dU;
-    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(rabs(Ut), ct));
+    // U~ = (1 + theta) U / 2 has the sign of U, so U / (2 c~) sgn(U~) = |U| / (2 c~)
+    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - aU_2ct * rmin(rabs(Ut), ct));
     R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
     // ablations of Sec. 7: xi of Eq. (46) (no velocity positivity) or of
     // Eq. (13); dU_p of classical Roe, Eq. (17), or none
@@ -583,7 +594,7 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
         if (S.variant & V_DUP_ROE) dUp = rmax((R)0, c - absU) * dp * rcpR(rho * c2);
         if (S.variant & V_DUP_ZERO) dUp = (R)0;
     }
-    const R dUu = (R)0.5 * sU * mUc * dU * ic;
+    const R dUu = (R)0.5 * sMc * dU;
 
     // Eq. (85): F = central - (1/2){xi dPsi + (dpp + dpu)(0, n, 0) + dUp PsiHat + dUu (Psi_R + Psi_L)}.
     // Each row's side terms are gathered per side, U_L Psi_L + U_R Psi_R -

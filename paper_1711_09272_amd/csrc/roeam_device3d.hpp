@@ -263,10 +263,11 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     // preconditioning, Eqs. (99)-(101)
     const R theta = rmin(rmax((R)S.mr2, M * M), (R)1);
     const R omt = (R)1 - theta;
-    const R X = (R)4 * c2 * theta + omt * omt * U * U;
+    const R omtU = omt * U;
+    const R X = omtU * omtU + (R)4 * c2 * theta;
     const R rX = rsqR(X);
     const R ct = (R)0.5 * X * rX;
-    const R U_2ct = U * rX;
+    const R aU_2ct = absU * rX;  // |U| / (2 c~)
     const R Ut = (R)0.5 * ((R)1 + theta) * U;
 
     // expansion-shock fix, Eq. (92)
@@ -308,9 +309,11 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     // Eqs. (87)-(91)
     const R sU = sgn(U);
     const R mUc = rmin(absUp, c);
-    const R dpp = sU * mUc * dp * ic;
+    const R sMc = sU * mUc * ic;  // sgn(U) min(|U|', c^) / c^, shared by dpp and dUu
+    const R dpp = sMc * dp;
     const R dpu = ((R)1 - s1 + s1 * fM) * rmax((R)0, c - absUp) * rho * dU;
-    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - U_2ct * sgn(Ut) * rmin(rabs(Ut), ct));
+    // U~ = (1 + theta) U / 2 has the sign of U, so U / (2 c~) sgn(U~) = |U| / (2 c~)
+    const R bracket = rmax((R)0, ct - absUp) + omt * (absUp - aU_2ct * rmin(rabs(Ut), ct));
     R dUp = s1 * ((R)1 - f8M) * bracket * dp * rcpR(rho * theta * c2);
     if (__builtin_expect((S.variant & (V_XI_EQ46 | V_XI_ROE | V_DUP_ROE | V_DUP_ZERO)) != 0, 0)) {
         if (S.variant & V_XI_EQ46) xi = (R)rabs(0.5 * (uR + uL));
@@ -318,7 +321,7 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
         if (S.variant & V_DUP_ROE) dUp = rmax((R)0, c - absU) * dp * rcpR(rho * c2);
         if (S.variant & V_DUP_ZERO) dUp = (R)0;
     }
-    const R dUu = (R)0.5 * sU * mUc * dU * ic;
+    const R dUu = (R)0.5 * sMc * dU;
 
     // Eq. (85), each row's side terms gathered per side: u_L Psi_L + u_R Psi_R -
     // xi (Psi_R - Psi_L) - dUu (Psi_R + Psi_L) = aL Psi_L + aR Psi_R with

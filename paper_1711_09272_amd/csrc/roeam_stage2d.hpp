@@ -110,7 +110,7 @@ __device__ __forceinline__ void tile_face(const DevSolve &S,
         } else {
             a = rmin(rmin(sPy[fj][fi + 1], sPx[fj][fi]), rmin(sPx[fj][fi + 1], rmin(sPx[fj + 1][fi], sPx[fj + 1][fi + 1])));
         }
-        s1 = pow8(fswitch(a));
+        s1 = detector_s1<PREC>(a);
     }
     if (AXIS) {
         roeam_flux<R, NSC, true>(S, WL, WR, 1.0, 0.0, s1, F);
@@ -205,7 +205,8 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     // plus the stage abscissa, 0, 1, 1/2 (SSP-RK3) or 0, 1/4, 1/3, 1/2 (four-stage)
     const BoundaryClock clk{stage == 0 ? nullptr : &z, p, stage_abscissa(stage) * dt, S.t_res};
 
-    // 1. tile + halo -> primitives in LDS (and 1/p, 1/rho for the detector).
+    // 1. tile + halo -> primitives in LDS (and 1/p, 1/rho for the detector;
+    // 1/p with one Newton step, as for the other dissipation coefficients).
     // Interior tiles issue every load of the thread first (lanes past the
     // staged box load the box's first cell, which is on the grid) and convert
     // afterwards, so that all loads are in flight together; tiles at the
@@ -235,7 +236,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
             if (detector) {
                 sIR[e] = ir;
-                sIP[e] = rcp_nr(W[3]);
+                sIP[e] = rcp_nr1(W[3]);
             }
         }
     } else {
@@ -252,7 +253,7 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
             for (int k = 0; k < NC; ++k) sW[k][ly][lx] = W[k];
             if (detector) {
                 sIR[e] = rcp_nr(W[0]);
-                sIP[e] = rcp_nr(W[3]);
+                sIP[e] = rcp_nr1(W[3]);
             }
         }
     }

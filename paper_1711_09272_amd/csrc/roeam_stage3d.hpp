@@ -142,7 +142,7 @@ __device__ __forceinline__ void brick_face(const DevSolve3 &S, const double *__r
         }
     }
     double s1 = 1.0;
-    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) s1 = pow8(fswitch(face_detector<AXIS, B>(sP, i, j, l)));
+    if (S.s1_mode == 0 && S.scheme == SCHEME_ROEAM) s1 = detector_s1<PREC>(face_detector<AXIS, B>(sP, i, j, l));
     frame_flux3<PREC, AXIS, NSC>(S, WL, WR, s1, F);
 }
 
@@ -778,7 +778,7 @@ __device__ __forceinline__ void zplane_face(const DevSolve3 &S, const double *__
                         rmin(rmin(cur[P::px(i + 1, j)], lo[P::rc(i, j - 1)]),
                              rmin(hi[P::rc(i, j - 1)], rmin(lo[P::rc(i, j)], hi[P::rc(i, j)]))));
         }
-        s1 = pow8(fswitch(dmin));
+        s1 = detector_s1<PREC>(dmin);
     }
     frame_flux3<PREC, AXIS, NSC>(S, WL, WR, s1, F);
 }
@@ -834,7 +834,7 @@ __device__ __forceinline__ void column_z(const DevSolve3 &S, ZStageLds<ORDER, NS
             rmin(rmin(rmin(L.sPz[cur][P::rc(ci, cj)], bl[P::px(ci, cj)]), rmin(bl[P::px(ci + 1, cj)], ab[P::px(ci, cj)])),
                  rmin(rmin(ab[P::px(ci + 1, cj)], bl[P::py(ci, cj)]),
                       rmin(bl[P::py(ci, cj + 1)], rmin(ab[P::py(ci, cj)], ab[P::py(ci, cj + 1)]))));
-        s1 = pow8(fswitch(dmin));
+        s1 = detector_s1<PREC>(dmin);
     }
     double zf[NR];
     frame_flux3<PREC, 2, NSC>(S, WL, WR, s1, zf);

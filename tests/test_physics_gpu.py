@@ -52,8 +52,8 @@ def test_pressure_fluctuation_scaling_after_1000_steps(C):
 def test_fp32_coefficients_keep_the_low_mach_pressure_field(C):
     """The FP32-coefficient path keeps the O(M^2) pressure field: after 1000
     SSP-RK3 steps of the 256^2 vortex its pressure differs from the FP64 path's
-    by a tiny fraction of the field's own fluctuation (measured 7e-10 at
-    M = 0.01, 2e-9 at M = 0.001), so Ind(p) still scales with M^2."""
+    by a tiny fraction of the field's own fluctuation (measured 1.1e-8 at
+    M = 0.01, 1.7e-8 at M = 0.001), so Ind(p) still scales with M^2."""
     import torch
     import paper_1711_09272_amd as P
     ind32 = {}
