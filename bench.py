@@ -305,13 +305,16 @@ class BatchRunner:
         while len(fin) < len(solves):
             P.batch_run(self.ctx, BATCH_GRAPH_ITERS)
             now = time.perf_counter()
+            n0 = len(fin)
             for s in solves:
                 if s.ticket not in fin:
-                    done, st, rc = P.batch_poll(self.ctx, s.ticket)
+                    done, st, rc = P.batch_poll(self.ctx, s.ticket, leave=False)
                     if done:
                         if rc != P.OK or st["steps"] != nsteps:
                             raise SystemExit(f"batched solve failed: {st} {rc}")
                         fin[s.ticket] = now - t0
+            if len(fin) > n0:
+                self.ctx.leave()  # the finished solves' outputs, handed to torch's stream once
         return [fin[s.ticket] for s in solves]
 
     def profile(self, nsteps=BATCH_STEPS):

@@ -544,15 +544,18 @@ def batch_profile_run(ctx: Context, iterations: int = -1):
     return list(out), n.value
 
 
-def batch_poll(ctx: Context, ticket: int):
+def batch_poll(ctx: Context, ticket: int, leave: bool = True):
     """(done, stats dict or None, status code); a solve that went non-physical
-    is done with code ENONPHYS."""
+    is done with code ENONPHYS.  leave=False skips the hand-off of a done
+    solve's output to torch's current stream: a caller polling many solves
+    calls ctx.leave() once afterwards instead (one hand-off covers every
+    output the library's stream has written)."""
     done = ctypes.c_int()
     st = StepStats()
     rc = lib().roeam_batch_poll(ctx.h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(st))
     if rc not in (OK, ENONPHYS):
         ctx.check(rc)
-    if done.value:
+    if done.value and leave:
         ctx.leave()  # outputs written by the library's stream are read after this
     return bool(done.value), (st.as_dict() if done.value else None), rc
 

@@ -113,15 +113,14 @@ __device__ __forceinline__ void tile_face(const DevSolve &S,
         s1 = detector_s1<PREC>(a);
     }
     if (AXIS) {
+        // flux per unit length: the face length (dy or dx) enters the
+        // residual with 1 / Omega, once per cell instead of once per face row
         roeam_flux<R, NSC, true>(S, WL, WR, 1.0, 0.0, s1, F);
         if (!XDIR) {
             const double t = F[1];
             F[1] = F[2];
             F[2] = t;
         }
-        const double len = XDIR ? S.dy : S.dx;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) F[k] *= len;
     } else {
         double sx, sy, nxv, nyv, len;
         if (XDIR) xface_vec<METRIC>(S, gi, gj, sx, sy);
@@ -355,7 +354,10 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
     const double(&sJ)[NC][SPLIT ? NFY : NFB] = *reinterpret_cast<const double(*)[NC][SPLIT ? NFY : NFB]>(SPLIT ? &sG[0][0] : &sF[0][0]);
 
     // 4. conservative residual R = -((F_e - F_w) + (G_n - G_s)) / Omega and the stage update
+    // (uniform grids: the faces hold fluxes per unit length, so R = -((F_e - F_w) dy / Omega
+    // + (G_n - G_s) dx / Omega))
     double lmax = 0.0;
+    const double cxi = S.dy * S.inv_area, cyi = S.dx * S.inv_area;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = tid + m * NT;
@@ -365,7 +367,10 @@ __device__ __forceinline__ void stage_tile(const DevSolve &S, int tx, int ty, in
         const double iom = METRIC == 0 ? S.inv_area : rcp_nr(cell_area<METRIC>(S, gi, gj));
         double Rv[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) Rv[k] = -(dfx[m][k] + (sJ[k][(cj + 1) * TX + ci] - sJ[k][cj * TX + ci])) * iom;
+        for (int k = 0; k < NC; ++k) {
+            const double dj = sJ[k][(cj + 1) * TX + ci] - sJ[k][cj * TX + ci];
+            Rv[k] = METRIC == 0 ? -fma(dfx[m][k], cxi, dj * cyi) : -(dfx[m][k] + dj) * iom;
+        }
         const long long idx = cidx[m];
         if (stage == 0) {
 #pragma unroll
