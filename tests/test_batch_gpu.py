@@ -85,6 +85,49 @@ def test_batch_equals_single_runs(C):
         assert np.array_equal(q, qa), c.name
 
 
+def test_poll_without_handoff_then_one_leave(C):
+    """The bench's polling loop: finite batch_run calls (the outputs are still
+    being written on the library's stream when a poll first reports them
+    done), batch_poll(..., leave=False) for every solve and one ctx.leave()
+    per loop that saw a solve finish; the outputs read on torch's stream
+    afterwards are bitwise those of the solves run alone."""
+    import paper_1711_09272_amd as P
+    cases = family()[:4]
+    P.batch_reserve(C, 128 << 20)
+    P.batch_configure(C, graph_iters=2)
+    try:
+        grids = [P.Grid.from_case(C, c) for c in cases]
+        solves = [P.Solve(g, c.params, g.to_device(c.q0), c.nsteps, c.t_end, g.empty_state())
+                  for g, c in zip(grids, cases)]
+        P.batch_submit(C, solves)
+        fin = {}
+        for _ in range(200):
+            if len(fin) == len(solves):
+                break
+            P.batch_run(C, 2)
+            n0 = len(fin)
+            for s in solves:
+                if s.ticket not in fin:
+                    done, st, rc = P.batch_poll(C, s.ticket, leave=False)
+                    if done:
+                        fin[s.ticket] = (st, rc)
+            if len(fin) > n0:
+                C.leave()
+                for s in solves:
+                    if s.ticket in fin and len(fin[s.ticket]) == 2:
+                        fin[s.ticket] = fin[s.ticket] + (s.q_out[:, :, : s.grid.nx].clone(),)
+        assert len(fin) == len(solves)
+        assert P.batch_run(C, -1) == 0
+    finally:
+        P.batch_configure(C)
+    say(f"[batch poll, one hand-off] {len(cases)} solves")
+    for c, s in zip(cases, solves):
+        st, rc, q = fin[s.ticket]
+        qa, sta = run_alone(C, c)
+        assert rc == P.OK and st["steps"] == sta["steps"] and st["t"] == sta["t"]
+        assert np.array_equal(q.cpu().numpy(), qa), c.name
+
+
 def test_batch_with_transported_scalars(C):
     """Grids with none, one and two scalars in one batch (three work-list
     groups per scheme): bitwise the solves run alone, and a two-scalar member
