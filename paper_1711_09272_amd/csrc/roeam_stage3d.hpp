@@ -103,8 +103,9 @@ __device__ __forceinline__ constexpr int frame_row(int k)
     return k == 1 ? 1 + AXIS : (k == 2 ? 1 + (AXIS + 1) % 3 : (k == 3 ? 1 + (AXIS + 2) % 3 : k));
 }
 
-// Flux times area of a face of axis AXIS from its face-frame states, rows
-// scattered back to global order (rho, rho u, rho v, rho w, rho E, rho k_m).
+// Flux per unit area of a face of axis AXIS from its face-frame states, rows
+// scattered back to global order (rho, rho u, rho v, rho w, rho E, rho k_m);
+// the face area enters the residual with 1 / V (axis_factor).
 template <int PREC, int AXIS, int NSC>
 __device__ __forceinline__ void frame_flux3(const DevSolve3 &S, const double *WL, const double *WR, double s1, double *F)
 {
@@ -112,12 +113,19 @@ __device__ __forceinline__ void frame_flux3(const DevSolve3 &S, const double *WL
     using R = typename std::conditional<PREC == 0, double, float>::type;
     double Ff[NR];
     roeam_flux3<R, NSC>(S, WL, WR, s1, Ff);
-    const double area = AXIS == 0 ? S.ax : (AXIS == 1 ? S.ay : S.az);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) F[frame_row<AXIS>(k)] = Ff[k] * area;
+    for (int k = 0; k < NR; ++k) F[frame_row<AXIS>(k)] = Ff[k];
 }
 
-// Flux times area of the face of axis AXIS whose upper cell is brick cell
+// Face area over cell volume of axis AXIS: R = -(dFx ax/V + dFy ay/V + dFz az/V),
+// summed as dFx (ax/V), then fma(dFy, ay/V, .), then fma(dFz, az/V, .) by
+// every kernel form, so that they give the same bits.
+template <int AXIS> __device__ __forceinline__ double axis_factor(const DevSolve3 &S)
+{
+    return (AXIS == 0 ? S.ax : (AXIS == 1 ? S.ay : S.az)) * S.inv_vol;
+}
+
+// Flux per unit area of the face of axis AXIS whose upper cell is brick cell
 // (i, j, l), rows in global order.
 template <int ORDER, int PREC, int AXIS, int NSC, class B>
 __device__ __forceinline__ void brick_face(const DevSolve3 &S, const double *__restrict__ sW, const double *__restrict__ sP,
@@ -165,11 +173,12 @@ __device__ __forceinline__ void faces_axis(const DevSolve3 &S, const double *__r
     }
 }
 
-// Add the face differences of one axis (from sF) to the cells' residual sums d
-// (in registers), in the order x, y, z.
+// Add the face differences of one axis (from sF), times the axis factor, to
+// the cells' residual sums d (in registers), in the order x, y, z.
 template <int AXIS, int NSC, int TX, int TY, int TZ, int NT, class B>
-__device__ __forceinline__ void acc_axis(const double (&sF)[5 + NSC][B::NFB], double (*d)[5 + NSC])
+__device__ __forceinline__ void acc_axis(const DevSolve3 &S, const double (&sF)[5 + NSC][B::NFB], double (*d)[5 + NSC])
 {
+    const double ca = axis_factor<AXIS>(S);
     constexpr int NR = 5 + NSC;
     constexpr int FX = TX + (AXIS == 0), FY = TY + (AXIS == 1);
     constexpr int CPT = (TX * TY * TZ + NT - 1) / NT;
@@ -183,7 +192,7 @@ __device__ __forceinline__ void acc_axis(const double (&sF)[5 + NSC][B::NFB], do
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const double df = sF[k][lo + up] - sF[k][lo];
-            d[m][k] = AXIS == 0 ? df : d[m][k] + df;
+            d[m][k] = AXIS == 0 ? df * ca : fma(df, ca, d[m][k]);
         }
     }
 }
@@ -475,33 +484,33 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
         __syncthreads();
     }
 
-    // 3. x-, y- and z-faces, each exactly once; residual sums ((x) + (y)) + (z)
+    // 3. x-, y- and z-faces, each exactly once; residual sums in the order x, y, z
     double d[CPT][NR];
     faces_axis<ORDER, PREC, 0, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
     __syncthreads();
     if constexpr (StageLds<ORDER, NSC, TX, TY, TZ, NT>::DB) {
         // x sums while the y-faces go to the second buffer, y sums while the
         // z-faces go to the first (whose readers passed the barrier between)
-        acc_axis<0, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        acc_axis<0, NSC, TX, TY, TZ, NT, B>(S, L.sF, d);
         faces_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF2, i0, j0, l0);
         __syncthreads();
-        acc_axis<1, NSC, TX, TY, TZ, NT, B>(L.sF2, d);
+        acc_axis<1, NSC, TX, TY, TZ, NT, B>(S, L.sF2, d);
         faces_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
         __syncthreads();
-        acc_axis<2, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        acc_axis<2, NSC, TX, TY, TZ, NT, B>(S, L.sF, d);
     } else {
-        acc_axis<0, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        acc_axis<0, NSC, TX, TY, TZ, NT, B>(S, L.sF, d);
         __syncthreads();
         faces_axis<ORDER, PREC, 1, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
         __syncthreads();
-        acc_axis<1, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        acc_axis<1, NSC, TX, TY, TZ, NT, B>(S, L.sF, d);
         __syncthreads();
         faces_axis<ORDER, PREC, 2, NSC, TX, TY, TZ, NT, B>(S, sW, sP, L.sF, i0, j0, l0);
         __syncthreads();
-        acc_axis<2, NSC, TX, TY, TZ, NT, B>(L.sF, d);
+        acc_axis<2, NSC, TX, TY, TZ, NT, B>(S, L.sF, d);
     }
 
-    // 4. R = -(sum of face fluxes times areas) / V and the stage update
+    // 4. R = -(sum of face flux differences times area / V) and the stage update
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int c = tid + m * NT;
@@ -509,7 +518,7 @@ __device__ __forceinline__ void brick_body(const DevSolve3 &S, StageLds<ORDER, N
         if (c >= NC || i0 + ci >= nx || j0 + cj >= ny || l0 + cl >= nz) continue;
         double Rv[NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) Rv[k] = -d[m][k] * S.inv_vol;
+        for (int k = 0; k < NR; ++k) Rv[k] = -d[m][k];
         const long long idx = cidx[m];
         if (stage == 0) {
 #pragma unroll
@@ -741,7 +750,7 @@ __device__ __forceinline__ void zslot_prim(const DevSolve3 &S, const double *Q, 
 }
 
 // x- (AXIS 0) or y-face (AXIS 1) of the staged plane whose upper cell is (i, j):
-// flux times area in global row order.  cur: the plane's own x-y ratios; lo,
+// flux per unit area in global row order.  cur: the plane's own x-y ratios; lo,
 // hi: the z-face ratios below and above it (the nine faces of Eq. 96, as
 // face_detector takes them).
 template <int ORDER, int PREC, int AXIS, int NSC, class P>
@@ -787,7 +796,8 @@ __device__ __forceinline__ void zplane_face(const DevSolve3 &S, const double *__
 // primitives (order 2), the z-face between planes m - 1 and m, and from the
 // run's second plane on the residual and stage update of plane m - 1.  H0:
 // the own cell of plane m; F0, c0: that of plane m + 1 as loaded; d: the
-// plane's x- and y-face sums; Wup and zlo carry to the next plane.
+// plane's x- and y-face sums (each difference times its axis factor); Wup
+// and zlo carry to the next plane.
 template <int ORDER, int PREC, int NSC, int TX, int TY, int NT>
 __device__ __forceinline__ void column_z(const DevSolve3 &S, ZStageLds<ORDER, NSC, TX, TY, NT> &L, int stage, int last,
                                          double dt, int m, int z0, int i0, int j0, int ci, int cj, bool col,
@@ -839,11 +849,11 @@ __device__ __forceinline__ void column_z(const DevSolve3 &S, ZStageLds<ORDER, NS
     double zf[NR];
     frame_flux3<PREC, 2, NSC>(S, WL, WR, s1, zf);
     if (col && m > z0) {
-        // R = -(sum of face fluxes times areas) / V of plane m - 1 and its stage update
+        // R = -(sum of face flux differences times area / V) of plane m - 1 and its stage update
         const long long idx = (long long)(m - 1) * S.slab + (long long)(j0 + cj) * S.pitch + (i0 + ci);
         double Rv[NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) Rv[k] = -(d[k] + (zf[k] - zlo[k])) * S.inv_vol;
+        for (int k = 0; k < NR; ++k) Rv[k] = -fma(zf[k] - zlo[k], axis_factor<2>(S), d[k]);
         if (stage == 0) {
 #pragma unroll
             for (int k = 0; k < NR; ++k) gptr(r_out)[k * S.plane + idx] = Rv[k];
@@ -1013,7 +1023,7 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
         __syncthreads();
 
         if (m < z1) zplane_load<ORDER, NSC, TX, TY, NT, 1, NS>(S, qin, tq, i0, j0, m + 1, false, Fq, Fc);
-        // x- and y-faces of plane m - 1, residual sums (x) + (y)
+        // x- and y-faces of plane m - 1, residual sums x, then y
         double d[NR];
         if (m > z0) {
             const double *cxy = L.sPxy[prv], *zl = L.sPz[prv], *zh = L.sPz[cur];
@@ -1030,7 +1040,7 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
             if (own) {
                 const int lo = cj * (TX + 1) + ci;
 #pragma unroll
-                for (int k = 0; k < NR; ++k) d[k] = L.sF[k][lo + 1] - L.sF[k][lo];
+                for (int k = 0; k < NR; ++k) d[k] = (L.sF[k][lo + 1] - L.sF[k][lo]) * axis_factor<0>(S);
             }
             __syncthreads();
             if (tq < P::NFY) {
@@ -1046,7 +1056,7 @@ __global__ __launch_bounds__(NT, 3) void k_stage3z(const DevSolve3 *__restrict__
             if (own) {
                 const int lo = cj * TX + ci;
 #pragma unroll
-                for (int k = 0; k < NR; ++k) d[k] += L.sF[k][lo + TX] - L.sF[k][lo];
+                for (int k = 0; k < NR; ++k) d[k] = fma(L.sF[k][lo + TX] - L.sF[k][lo], axis_factor<1>(S), d[k]);
             }
         }
 
