@@ -479,28 +479,13 @@ __device__ __forceinline__ void roeam_flux(const DevSolve &S, const double *WL, 
     const double UL = AXIS ? uL : nx * uL + ny * vL, UR = AXIS ? uR : nx * uR + ny * vR;
     const double PsiL1 = rL * uL, PsiL2 = rL * vL;
     const double PsiR1 = rR * uR, PsiR2 = rR * vR;
-    double PsiL3, PsiR3;   // rho H, FP64 (central flux and jump)
-    R iLr, iRr, HLr, HRr;  // 1/rho and H of the sides, for the coefficients
-    if constexpr (std::is_same<R, float>::value) {
-        // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 needs no 1/rho, so the
-        // reciprocals feed only the FP32 coefficients and are taken in FP32
-        PsiL3 = S.g_gm1 * pL + 0.5 * rL * qL;
-        PsiR3 = S.g_gm1 * pR + 0.5 * rR * qR;
-        iLr = rcpR((R)rL);
-        iRr = rcpR((R)rR);
-        HLr = (R)PsiL3 * iLr;
-        HRr = (R)PsiR3 * iRr;
-    } else {
-        const double iL = rcp_nr(rL), iR = rcp_nr(rR);
-        const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
-        const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
-        PsiL3 = rL * HL;
-        PsiR3 = rR * HR;
-        iLr = iL;
-        iRr = iR;
-        HLr = HL;
-        HRr = HR;
-    }
+    // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 (FP64: central flux and jump)
+    // needs no 1/rho, so the sides' reciprocals feed only the coefficients and
+    // are taken in their precision (FP64: one Newton step, as the others)
+    const double PsiL3 = S.g_gm1 * pL + 0.5 * rL * qL;
+    const double PsiR3 = S.g_gm1 * pR + 0.5 * rR * qR;
+    const R iLr = rcpR((R)rL), iRr = rcpR((R)rR);  // 1/rho of the sides
+    const R HLr = (R)PsiL3 * iLr, HRr = (R)PsiR3 * iRr;
 
     // jumps stay FP64 (low-Mach pressure differences cancel otherwise)
     const double dUd = UR - UL, dpd = pR - pL;

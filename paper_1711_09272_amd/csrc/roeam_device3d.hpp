@@ -211,28 +211,13 @@ __device__ __forceinline__ void roeam_flux3(const DevSolve3 &S, const double *WL
     const double PL1 = rL * uL, PL2 = rL * vL, PL3 = rL * wL;
     const double PR1 = rR * uR, PR2 = rR * vR, PR3 = rR * wR;
     constexpr bool F32 = std::is_same<R, float>::value;
-    double PL4, PR4;       // rho H, FP64 (central flux and jump)
-    R iLr, iRr, HLr, HRr;  // 1/rho and H of the sides, for the coefficients
-    if constexpr (F32) {
-        // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 needs no 1/rho, so the
-        // reciprocals feed only the FP32 coefficients and are taken in FP32
-        PL4 = S.g_gm1 * pL + 0.5 * rL * qL;
-        PR4 = S.g_gm1 * pR + 0.5 * rR * qR;
-        iLr = rcpR((R)rL);
-        iRr = rcpR((R)rR);
-        HLr = (R)PL4 * iLr;
-        HRr = (R)PR4 * iRr;
-    } else {
-        const double iL = rcp_nr(rL), iR = rcp_nr(rR);
-        const double HL = S.g_gm1 * pL * iL + 0.5 * qL;
-        const double HR = S.g_gm1 * pR * iR + 0.5 * qR;
-        PL4 = rL * HL;
-        PR4 = rR * HR;
-        iLr = iL;
-        iRr = iR;
-        HLr = HL;
-        HRr = HR;
-    }
+    // rho H = gamma/(gamma-1) p + rho |V|^2 / 2 (FP64: central flux and jump)
+    // needs no 1/rho, so the sides' reciprocals feed only the coefficients and
+    // are taken in their precision (FP64: one Newton step, as the others)
+    const double PL4 = S.g_gm1 * pL + 0.5 * rL * qL;
+    const double PR4 = S.g_gm1 * pR + 0.5 * rR * qR;
+    const R iLr = rcpR((R)rL), iRr = rcpR((R)rR);  // 1/rho of the sides
+    const R HLr = (R)PL4 * iLr, HRr = (R)PR4 * iRr;
     const double dUd = uR - uL, dpd = pR - pL;
 
     // Roe averages
